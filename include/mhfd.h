@@ -1,0 +1,214 @@
+/*
+ * mhfd.h -- C ABI of libmhfd: the scale-normalised Laplacian-of-Gaussian
+ * (LoG) blob detector used as a focus criterion for serial-section electron
+ * microscopy ("Ultrafast Focus Detection for Automated Microscopy",
+ * Multi-scale Histologic Feature Detection), written in HIP for AMD MI355X
+ * (gfx950).
+ *
+ * What the library computes, for an image I and scales sigma_1 < ... < sigma_K
+ * (section 2.2: Gaussian G, scale space L = G_t * I with t the standard
+ * deviation, scale grid t_i = min_t + (i-1) delta_t):
+ *
+ *   R_k(y,x)  = s * sigma_k^2 * Lap(G_sigma_k * I)(y,x)        the stack
+ *     sampled Gaussian taps g over |j| <= floor(truncate*sigma + 0.5),
+ *     normalised to unit sum; second-derivative taps h_j = (j^2 - V) g_j /
+ *     sigma^4 with V the variance of the truncated kernel (zero sum); borders
+ *     extended half-sample symmetrically (... x1 x0 | x0 x1 ...); s = -1 for
+ *     bright blobs (default), +1 for dark.  This is the scale-normalised
+ *     Laplacian t^2 Lap L that section 2.2 approximates by a difference of
+ *     Gaussians.
+ *   candidates: voxels (y, x, k) equal to the maximum of their 3x3x3
+ *     scale-space window (windows clipped at the volume's faces) with
+ *     R_k(y,x) > threshold -- the maxpool-equality test of section 3
+ *     (equation "argmax"), taken local in scale as well as in space;
+ *   pruning: a candidate b is dropped when some other candidate a dominates
+ *     it (larger k, or equal k and smaller (y, x)) and the discs of radius
+ *     sqrt(2)*sigma around them overlap by more than `overlap` of the
+ *     smaller disc's area (one-shot rule, FP64 geometry);
+ *   focus criterion: the number of surviving blobs, |C| (section 3,
+ *     Algorithm 1's output); its density per megapixel compares tiles of
+ *     different sizes.
+ *
+ * Soft focus score (differentiable form):
+ *   S_b = 1/(K H W) sum_k sum_{y,x} softplus(beta * (|r_k(y,x)| - tau)),
+ *   r_k = sigma_k^2 Lap(G_sigma_k * I_b), with its gradient with respect to
+ *   every image and every sigma.
+ *
+ * Conventions shared by every call:
+ *   - All pointers named d_* are device pointers on the device that was
+ *     current when the plan was created; the caller owns and allocates them.
+ *     Host pointers are named without the prefix.
+ *   - Images are row-major; `pitch` is the distance between rows in elements
+ *     (>= w).  Float images hold any finite values; 8-bit images are read as
+ *     u / 255.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Every call that
+ *     takes a stream only enqueues work on it and returns without waiting;
+ *     results are valid once the stream has reached that point.
+ *   - Argument and size errors are found on the host before anything is
+ *     enqueued and reported as a status; nothing is written then.  A failing
+ *     HIP call gives MHFD_ERR_HIP.  mhfd_last_error() returns a description
+ *     of the last failure on the calling thread.
+ *   - Calls on one plan may run concurrently on different streams as long as
+ *     they use different workspaces and outputs; a plan is read-only after
+ *     creation.
+ */
+#ifndef MHFD_H
+#define MHFD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MHFD_MAX_SCALES 32   /* largest K */
+#define MHFD_MAX_RADIUS 64   /* largest kernel radius floor(truncate*sigma + 0.5) */
+
+typedef enum mhfd_status {
+    MHFD_OK = 0,
+    MHFD_ERR_INVALID_ARG = 1, /* null pointer, bad size, bad configuration */
+    MHFD_ERR_UNSUPPORTED = 2, /* valid request outside what this build supports */
+    MHFD_ERR_WORKSPACE = 3,   /* workspace smaller than the size query returned */
+    MHFD_ERR_HIP = 4,         /* a HIP runtime call failed */
+    MHFD_ERR_OOM = 5          /* device allocation for the plan failed */
+} mhfd_status;
+
+typedef enum mhfd_dtype { MHFD_F32 = 0, MHFD_U8 = 1 } mhfd_dtype;
+typedef enum mhfd_polarity { MHFD_BRIGHT = 0, MHFD_DARK = 1 } mhfd_polarity;
+
+/* One detected blob (20 bytes).  Lists are in ascending (y, x, k) order. */
+typedef struct mhfd_blob {
+    int32_t y, x;      /* pixel position */
+    int32_t k;         /* scale index, 0-based */
+    float sigma;       /* sigma_k */
+    float response;    /* R_k(y, x) */
+} mhfd_blob;
+
+/* Summary of one detection, written by the device. */
+typedef struct mhfd_result {
+    int64_t n_blobs;       /* blobs after pruning: the focus criterion |C| */
+    int64_t n_candidates;  /* window maxima above the threshold, before pruning */
+    int32_t flags;         /* MHFD_FLAG_* */
+    int32_t reserved;
+} mhfd_result;
+
+/* n_blobs exceeds the caller's capacity: only the first `capacity` blobs of
+ * the canonical order were written (n_blobs is still the true count). */
+#define MHFD_FLAG_BLOB_OVERFLOW 1
+/* n_candidates exceeds the plan's max_candidates: pruning could not see every
+ * candidate and n_blobs and the list are not valid. */
+#define MHFD_FLAG_CAND_OVERFLOW 2
+
+typedef struct mhfd_config {
+    int32_t n_scales;        /* K, 1..MHFD_MAX_SCALES */
+    float sigma_min;         /* linear grid sigma_k = min + k (max - min)/(K - 1), */
+    float sigma_max;         /*   computed in double and rounded to float       */
+    const float *sigmas;     /* optional host array of K strictly increasing
+                                positive sigmas; overrides min/max when set    */
+    float truncate;          /* kernel radius floor(truncate * sigma + 0.5); 4  */
+    float threshold;         /* candidate iff R > threshold                     */
+    float overlap;           /* pruning threshold in [0, 1]; >= 1 disables it   */
+    int32_t polarity;        /* mhfd_polarity                                   */
+    int32_t in_dtype;        /* mhfd_dtype of the images given to detect        */
+    int32_t max_h, max_w;    /* largest image the plan will see                 */
+    int64_t max_candidates;  /* candidate capacity of a detection workspace
+                                (0: max(65536, max_h*max_w/64))                 */
+} mhfd_config;
+
+typedef struct mhfd_plan_s *mhfd_plan;
+
+/* Build a plan: validates the configuration, derives every scale's kernel
+ * radius and taps in double precision on the host and copies the float taps
+ * to the current device (a few kilobytes, owned by the plan).  *out is set
+ * only on success.  Host call; synchronous. */
+mhfd_status mhfd_create_plan(const mhfd_config *cfg, mhfd_plan *out);
+
+/* Release the plan and its device table.  The caller must make sure no
+ * enqueued work still uses it.  NULL is accepted. */
+mhfd_status mhfd_destroy_plan(mhfd_plan plan);
+
+/* Read back the plan's scales (sigmas[K]) and radii (radii[K]); either
+ * pointer may be NULL.  Returns K, or -1 for a NULL plan. */
+int32_t mhfd_plan_scales(mhfd_plan plan, float *sigmas, int32_t *radii);
+
+/* Workspace bytes mhfd_detect needs for an h x w image (0 on bad input). */
+size_t mhfd_detect_workspace_size(mhfd_plan plan, int32_t h, int32_t w);
+
+/*
+ * Detect blobs in one image (section 3's criterion with the readings above).
+ *   d_img     h x w image of the plan's dtype, row pitch `pitch` elements.
+ *   d_blobs   room for `capacity` (>= 0) blobs; the first
+ *             min(n_blobs, capacity) are written in ascending (y, x, k).
+ *   d_result  one mhfd_result, always written.
+ *   d_stack   optional K x h x w float array (plane k at k*h*w) that receives
+ *             the LoG stack R; NULL keeps the stack inside the workspace.
+ *   d_ws      workspace of at least mhfd_detect_workspace_size(plan, h, w)
+ *             bytes, 256-byte aligned; its contents need no initialisation
+ *             and are scratch after the call.
+ * Requires 1 <= h <= max_h, 1 <= w <= max_w, pitch >= w.
+ */
+mhfd_status mhfd_detect(mhfd_plan plan, const void *d_img, int32_t h, int32_t w, int64_t pitch,
+                        mhfd_blob *d_blobs, int32_t capacity, mhfd_result *d_result,
+                        float *d_stack, void *d_ws, size_t ws_bytes, void *stream);
+
+/*
+ * The LoG stack alone -- the first step of mhfd_detect: writes
+ * R_k(y, x) for k < K into d_stack (K x h x w floats, plane k at k*h*w).
+ * Needs no workspace.  Same image requirements as mhfd_detect.
+ */
+mhfd_status mhfd_log_stack(mhfd_plan plan, const void *d_img, int32_t h, int32_t w, int64_t pitch,
+                           float *d_stack, void *stream);
+
+/*
+ * The rest of mhfd_detect on a stack the caller already holds (as written by
+ * mhfd_log_stack): maxima, threshold, canonical list, pruning, count.
+ * mhfd_log_stack followed by mhfd_detect_stack gives exactly what
+ * mhfd_detect gives.  d_ws as for mhfd_detect (its stack region is unused).
+ */
+mhfd_status mhfd_detect_stack(mhfd_plan plan, const float *d_stack, int32_t h, int32_t w,
+                              mhfd_blob *d_blobs, int32_t capacity, mhfd_result *d_result,
+                              void *d_ws, size_t ws_bytes, void *stream);
+
+/* Workspace bytes mhfd_focus_score and mhfd_focus_score_backward need for a
+ * batch of b images of h x w (0 on bad input). */
+size_t mhfd_focus_workspace_size(mhfd_plan plan, int32_t b, int32_t h, int32_t w);
+
+/*
+ * Soft focus score of b float images (b x h x w, dense).
+ *   d_sigmas  K device floats, the current (trainable) scales.  The kernel
+ *             radius of scale k stays the plan's: the support is frozen and
+ *             the score is smooth in sigma for that support.  Each sigma
+ *             must be positive; a non-positive or non-finite sigma makes every
+ *             score NaN.
+ *   d_scores  b floats, overwritten with S_b.
+ * Requires 1 <= h <= max_h, 1 <= w <= max_w, b >= 1; beta > 0.
+ */
+mhfd_status mhfd_focus_score(mhfd_plan plan, const float *d_imgs, int32_t b, int32_t h, int32_t w,
+                             const float *d_sigmas, float beta, float tau, float *d_scores,
+                             void *d_ws, size_t ws_bytes, void *stream);
+
+/*
+ * Gradient of sum_b d_grad_scores[b] * S_b.
+ *   d_grad_imgs    b x h x w floats, overwritten with the image gradient.
+ *   d_grad_sigmas  K floats, overwritten with the sigma gradient.
+ * The stack is recomputed per scale; nothing from the forward call is kept.
+ * Same arguments and requirements as mhfd_focus_score.
+ */
+mhfd_status mhfd_focus_score_backward(mhfd_plan plan, const float *d_imgs, int32_t b, int32_t h,
+                                      int32_t w, const float *d_sigmas, float beta, float tau,
+                                      const float *d_grad_scores, float *d_grad_imgs,
+                                      float *d_grad_sigmas, void *d_ws, size_t ws_bytes,
+                                      void *stream);
+
+/* Static text for a status code. */
+const char *mhfd_status_string(mhfd_status status);
+
+/* Description of the last failure on the calling thread ("" if none). */
+const char *mhfd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MHFD_H */

@@ -1,0 +1,176 @@
+"""Python face of libmhfd: plans, detection and the soft focus score.
+
+PyTorch provides device memory and streams; every step of the detector runs
+in the HIP kernels of libmhfd, reached through the C ABI in ``_lib``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+
+
+def _stream_ptr(stream) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None) -> int | None:
+    return None if t is None else int(t.data_ptr())
+
+
+@dataclass
+class Detection:
+    """Blobs of one image.  ``yxk`` int32 [n, 3], ``sigma`` and ``response``
+    float32 [n] (device tensors, canonical ascending (y, x, k) order);
+    ``count`` is the focus criterion |C| (blobs after pruning)."""
+    yxk: torch.Tensor
+    sigma: torch.Tensor
+    response: torch.Tensor
+    count: int
+    n_candidates: int
+    flags: int
+    stack: torch.Tensor | None = None
+
+    @property
+    def density(self) -> float:
+        """Blobs per megapixel (set by Plan.detect)."""
+        return self._density
+
+    def numpy(self):
+        return (self.yxk.cpu().numpy(), self.sigma.cpu().numpy(), self.response.cpu().numpy())
+
+
+def split_blobs(raw: torch.Tensor, n: int):
+    """View an int32 [cap, 5] buffer of mhfd_blob records as (yxk, sigma, response)."""
+    r = raw[:n]
+    return r[:, :3], r[:, 3].view(torch.float32), r[:, 4].view(torch.float32)
+
+
+class Plan:
+    """A detector configuration bound to the current device (mhfd_create_plan).
+
+    Scales follow section 2.2's linear grid (sigma_min .. sigma_max, K = n+1
+    values) unless ``sigmas`` is given.  ``threshold`` is the strict lower
+    bound on the response of a candidate, ``overlap`` the pruning threshold
+    (>= 1 disables pruning)."""
+
+    def __init__(self, n_scales: int = 10, sigma_min: float = 1.0, sigma_max: float = 10.0,
+                 sigmas=None, truncate: float = 4.0, threshold: float = 0.1,
+                 overlap: float = 0.5, polarity: str = "bright", dtype: str = "f32",
+                 max_h: int = 4096, max_w: int = 4096, max_candidates: int = 0):
+        self._L = _lib.load()
+        self._handle = None
+        cfg = _lib.Config()
+        cfg.n_scales = int(n_scales if sigmas is None else len(sigmas))
+        cfg.sigma_min = float(sigma_min)
+        cfg.sigma_max = float(sigma_max)
+        self._sig_arr = None
+        if sigmas is not None:
+            self._sig_arr = (C.c_float * len(sigmas))(*[float(s) for s in sigmas])
+            cfg.sigmas = C.cast(self._sig_arr, C.POINTER(C.c_float))
+        cfg.truncate = float(truncate)
+        cfg.threshold = float(threshold)
+        cfg.overlap = float(overlap)
+        cfg.polarity = {"bright": _lib.MHFD_BRIGHT, "dark": _lib.MHFD_DARK}[polarity]
+        cfg.in_dtype = {"f32": _lib.MHFD_F32, "u8": _lib.MHFD_U8}[dtype]
+        cfg.max_h, cfg.max_w = int(max_h), int(max_w)
+        cfg.max_candidates = int(max_candidates)
+        h = C.c_void_p()
+        _lib.check(self._L.mhfd_create_plan(C.byref(cfg), C.byref(h)), "mhfd_create_plan")
+        self._handle = h
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        K = self._L.mhfd_plan_scales(h, None, None)
+        sig = (C.c_float * K)()
+        rad = (C.c_int32 * K)()
+        self._L.mhfd_plan_scales(h, sig, rad)
+        self.sigmas = [float(v) for v in sig]
+        self.radii = [int(v) for v in rad]
+        self.K = K
+        self.dtype = dtype
+        self.threshold, self.overlap, self.truncate = float(threshold), float(overlap), float(truncate)
+        self.max_h, self.max_w = int(max_h), int(max_w)
+        self._ws = {}
+
+    def close(self):
+        if self._handle is not None:
+            self._L.mhfd_destroy_plan(self._handle)
+            self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- workspace
+    def detect_workspace_bytes(self, h: int, w: int) -> int:
+        n = int(self._L.mhfd_detect_workspace_size(self._handle, int(h), int(w)))
+        if n == 0:
+            raise _lib.MHFDError(1, "mhfd_detect_workspace_size",
+                                 f"a {h} x {w} image is empty or exceeds the plan's "
+                                 f"{self.max_h} x {self.max_w}")
+        return n
+
+    def _workspace(self, key, nbytes: int) -> torch.Tensor:
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < nbytes:
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            if ws.data_ptr() % 256:
+                raise RuntimeError("workspace allocation not 256-byte aligned")
+            self._ws[key] = ws
+        return ws
+
+    # ---------------------------------------------------------------- detect
+    def detect_into(self, img: torch.Tensor, blobs_raw: torch.Tensor, result: torch.Tensor,
+                    stack: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
+                    stream=None) -> None:
+        """Enqueue mhfd_detect without synchronising.  ``blobs_raw`` is an
+        int32 [capacity, 5] tensor, ``result`` an int64 [3] tensor
+        (n_blobs, n_candidates, flags)."""
+        if img.dim() != 2:
+            raise ValueError("image must be 2-D")
+        want = torch.uint8 if self.dtype == "u8" else torch.float32
+        if img.dtype != want or img.device != self.device:
+            raise ValueError(f"image must be {want} on {self.device}")
+        if img.stride(1) != 1:
+            raise ValueError("image rows must be contiguous")
+        h, w = img.shape
+        if blobs_raw.dtype != torch.int32 or blobs_raw.dim() != 2 or blobs_raw.shape[1] != 5:
+            raise ValueError("blobs_raw must be int32 [capacity, 5]")
+        if result.dtype != torch.int64 or result.numel() < 3:
+            raise ValueError("result must be int64 [3]")
+        if stack is not None and (stack.dtype != torch.float32 or not stack.is_contiguous()
+                                  or stack.numel() != self.K * h * w):
+            raise ValueError("stack must be a contiguous float32 [K, h, w] tensor")
+        nbytes = self.detect_workspace_bytes(h, w)
+        ws = workspace if workspace is not None else self._workspace(("detect", h, w), nbytes)
+        st = self._L.mhfd_detect(self._handle, _ptr(img), h, w, img.stride(0), _ptr(blobs_raw),
+                                 blobs_raw.shape[0], _ptr(result), _ptr(stack), _ptr(ws),
+                                 ws.numel(), _stream_ptr(stream))
+        _lib.check(st, "mhfd_detect")
+
+    def detect(self, img: torch.Tensor, capacity: int | None = None,
+               return_stack: bool = False, stream=None) -> Detection:
+        """Detect blobs in one device image and wait for the result."""
+        h, w = img.shape
+        if capacity is None:
+            capacity = max(1024, h * w // 64)
+        raw = torch.empty((capacity, 5), dtype=torch.int32, device=self.device)
+        res = torch.zeros(3, dtype=torch.int64, device=self.device)
+        stack = (torch.empty((self.K, h, w), dtype=torch.float32, device=self.device)
+                 if return_stack else None)
+        self.detect_into(img, raw, res, stack, stream=stream)
+        r = res.cpu().tolist()
+        n_blobs, n_cand, flags = int(r[0]), int(r[1]), int(r[2]) & 0xFFFFFFFF
+        if flags & _lib.MHFD_FLAG_CAND_OVERFLOW:
+            raise RuntimeError(f"{n_cand} candidates exceed the plan's candidate capacity; "
+                               "create the plan with a larger max_candidates")
+        n = min(n_blobs, capacity)
+        yxk, sig, resp = split_blobs(raw, n)
+        d = Detection(yxk, sig, resp, n_blobs, n_cand, flags, stack)
+        d._density = n_blobs * 1e6 / (h * w)
+        return d

@@ -1,0 +1,411 @@
+// Host side of libmhfd: plan construction (scale grid and taps in double on
+// the host), argument checks, workspace layout and the C entry points.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "mhfd_internal.h"
+
+struct mhfd_plan_s {
+    int device = 0;
+    int K = 0;
+    std::vector<float> sigmas;   // sigma_k as float
+    std::vector<int> radii;      // floor(truncate * sigma_k + 0.5)
+    std::vector<int> padded;     // radius rounded up to the instantiation quantum
+    std::vector<int> tap_off;    // float offset of scale k's tap block
+    float truncate = 4.0f, threshold = 0.0f, overlap = 1.0f;
+    int polarity = MHFD_BRIGHT, dtype = MHFD_F32;
+    int max_h = 0, max_w = 0;
+    int64_t max_cand = 0;
+    int reach = 0;               // floor(2 sqrt(2) sigma_max): prune row reach
+    float* d_taps = nullptr;     // device tap table
+    float* d_sigmas = nullptr;   // device copy of sigmas (float)
+    size_t tap_floats = 0;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+mhfd_status fail(mhfd_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+mhfd_status fail(mhfd_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+mhfd_status hip_fail(hipError_t e, const char* what) {
+    return fail(MHFD_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Segment height (rows per workgroup) of the strip kernel: a multiple of the
+// 32-row chunk aiming at about 1024 workgroups per scale.
+int strip_segment_rows(int h, int w) {
+    const int strips = (w + 63) / 64;
+    long long seg = (static_cast<long long>(h) * strips + 1023) / 1024;
+    seg = (seg + 31) / 32 * 32;
+    if (seg < 32) seg = 32;
+    if (seg > 1024) seg = 1024;
+    return static_cast<int>(seg);
+}
+
+// Taps of one scale in double, then rounded to float into `dst`
+// (layout documented with tap_block_floats).
+void synth_taps(double sigma, int R, int P, int polarity, float* dst) {
+    std::vector<double> g(R + 1), h(R + 1);
+    double z = 0.0;
+    for (int j = 0; j <= R; ++j) {
+        g[j] = exp(-static_cast<double>(j) * j / (2.0 * sigma * sigma));
+        z += j == 0 ? g[j] : 2.0 * g[j];
+    }
+    double var = 0.0;
+    for (int j = 0; j <= R; ++j) {
+        g[j] /= z;
+        var += (j == 0 ? 0.0 : 2.0) * static_cast<double>(j) * j * g[j];
+    }
+    const double s4 = sigma * sigma * sigma * sigma;
+    for (int j = 0; j <= R; ++j) h[j] = (static_cast<double>(j) * j - var) * g[j] / s4;
+    const double norm = (polarity == MHFD_BRIGHT ? -1.0 : 1.0) * sigma * sigma;
+    for (int j = 0; j <= P; ++j) {
+        const bool in = j <= R;
+        dst[j] = in ? static_cast<float>(g[j]) : 0.0f;
+        dst[(P + 1) + j] = in ? static_cast<float>(h[j]) : 0.0f;
+        dst[2 * (P + 1) + j] = in ? static_cast<float>(norm * g[j]) : 0.0f;
+        dst[3 * (P + 1) + j] = in ? static_cast<float>(norm * h[j]) : 0.0f;
+    }
+}
+
+struct DetectLayout {
+    size_t stack, blk_n, blk_o, blk_off, pool, cand, keep, keep_off, ctr, total;
+    int n_blk, bpr;
+};
+
+DetectLayout detect_layout(const mhfd_plan_s* p, int h, int w) {
+    DetectLayout L{};
+    L.bpr = mhfd::nms_blocks_per_row(w);
+    L.n_blk = h * L.bpr;
+    const size_t cap = static_cast<size_t>(p->max_cand);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    L.stack = take(sizeof(float) * static_cast<size_t>(p->K) * h * w);
+    L.blk_n = take(sizeof(int32_t) * L.n_blk);
+    L.blk_o = take(sizeof(int32_t) * L.n_blk);
+    L.blk_off = take(sizeof(int32_t) * (L.n_blk + 1));
+    L.pool = take(sizeof(mhfd::Cand) * cap);
+    L.cand = take(sizeof(mhfd::Cand) * cap);
+    L.keep = take(sizeof(int32_t) * cap);
+    L.keep_off = take(sizeof(int32_t) * (cap + 1));
+    L.ctr = take(sizeof(mhfd::DetectCounters));
+    L.total = off;
+    return L;
+}
+
+mhfd_status check_device(const mhfd_plan_s* p) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev != p->device)
+        return fail(MHFD_ERR_INVALID_ARG, "plan lives on device %d but device %d is current",
+                    p->device, dev);
+    return MHFD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mhfd_status_string(mhfd_status st) {
+    switch (st) {
+        case MHFD_OK: return "ok";
+        case MHFD_ERR_INVALID_ARG: return "invalid argument";
+        case MHFD_ERR_UNSUPPORTED: return "unsupported";
+        case MHFD_ERR_WORKSPACE: return "workspace too small";
+        case MHFD_ERR_HIP: return "HIP error";
+        case MHFD_ERR_OOM: return "out of device memory";
+    }
+    return "unknown status";
+}
+
+const char* mhfd_last_error(void) { return g_last_error.c_str(); }
+
+mhfd_status mhfd_create_plan(const mhfd_config* cfg, mhfd_plan* out) {
+    g_last_error.clear();
+    if (!cfg || !out) return fail(MHFD_ERR_INVALID_ARG, "null config or output pointer");
+    const int K = cfg->n_scales;
+    if (K < 1 || K > MHFD_MAX_SCALES)
+        return fail(MHFD_ERR_INVALID_ARG, "n_scales %d outside [1, %d]", K, MHFD_MAX_SCALES);
+    if (!(cfg->truncate > 0.0f) || !isfinite(cfg->truncate))
+        return fail(MHFD_ERR_INVALID_ARG, "truncate must be positive and finite");
+    if (!isfinite(cfg->threshold)) return fail(MHFD_ERR_INVALID_ARG, "threshold must be finite");
+    if (!(cfg->overlap >= 0.0f) || !isfinite(cfg->overlap))
+        return fail(MHFD_ERR_INVALID_ARG, "overlap must be >= 0 and finite");
+    if (cfg->polarity != MHFD_BRIGHT && cfg->polarity != MHFD_DARK)
+        return fail(MHFD_ERR_INVALID_ARG, "unknown polarity %d", cfg->polarity);
+    if (cfg->in_dtype != MHFD_F32 && cfg->in_dtype != MHFD_U8)
+        return fail(MHFD_ERR_INVALID_ARG, "unknown input dtype %d", cfg->in_dtype);
+    if (cfg->max_h < 1 || cfg->max_w < 1)
+        return fail(MHFD_ERR_INVALID_ARG, "max_h and max_w must be >= 1");
+    if (static_cast<int64_t>(cfg->max_h) * cfg->max_w > (int64_t(1) << 31) / 4)
+        return fail(MHFD_ERR_UNSUPPORTED, "max_h * max_w above 2^29 pixels");
+    if (cfg->max_candidates < 0) return fail(MHFD_ERR_INVALID_ARG, "max_candidates < 0");
+
+    std::vector<float> sig(K);
+    if (cfg->sigmas) {
+        for (int k = 0; k < K; ++k) sig[k] = cfg->sigmas[k];
+    } else if (K == 1) {
+        sig[0] = cfg->sigma_min;
+    } else {
+        // section 2.2: t_i = min_t + (i - 1) delta_t, delta_t = (max_t - min_t) / n, K = n + 1
+        const double a = cfg->sigma_min, b = cfg->sigma_max;
+        const double dt = (b - a) / (K - 1);
+        for (int k = 0; k < K; ++k) sig[k] = static_cast<float>(a + k * dt);
+    }
+    for (int k = 0; k < K; ++k) {
+        if (!(sig[k] > 0.0f) || !isfinite(sig[k]))
+            return fail(MHFD_ERR_INVALID_ARG, "sigma[%d] = %g is not positive and finite", k,
+                        static_cast<double>(sig[k]));
+        if (k > 0 && !(sig[k] > sig[k - 1]))
+            return fail(MHFD_ERR_INVALID_ARG, "sigmas must be strictly increasing (sigma[%d])", k);
+    }
+
+    mhfd_plan_s* p = new (std::nothrow) mhfd_plan_s();
+    if (!p) return fail(MHFD_ERR_OOM, "host allocation of the plan failed");
+    p->K = K;
+    p->sigmas = sig;
+    p->truncate = cfg->truncate;
+    p->threshold = cfg->threshold;
+    p->overlap = cfg->overlap;
+    p->polarity = cfg->polarity;
+    p->dtype = cfg->in_dtype;
+    p->max_h = cfg->max_h;
+    p->max_w = cfg->max_w;
+    int64_t dc = static_cast<int64_t>(cfg->max_h) * cfg->max_w / 64;
+    p->max_cand = cfg->max_candidates > 0 ? cfg->max_candidates : (dc > 65536 ? dc : 65536);
+    if (p->max_cand > (int64_t(1) << 30)) {
+        delete p;
+        return fail(MHFD_ERR_UNSUPPORTED, "max_candidates above 2^30");
+    }
+    size_t off = 0;
+    for (int k = 0; k < K; ++k) {
+        const int R = static_cast<int>(floor(static_cast<double>(p->truncate) * sig[k] + 0.5));
+        if (R > MHFD_MAX_RADIUS) {
+            delete p;
+            return fail(MHFD_ERR_UNSUPPORTED, "radius %d of sigma %g exceeds %d", R,
+                        static_cast<double>(sig[k]), MHFD_MAX_RADIUS);
+        }
+        const int P = mhfd::padded_radius(R < 1 ? 1 : R);
+        p->radii.push_back(R);
+        p->padded.push_back(P);
+        p->tap_off.push_back(static_cast<int>(off));
+        off += mhfd::tap_block_floats(P);
+    }
+    p->tap_floats = off;
+    p->reach = static_cast<int>(floor(2.0 * 1.4142135623730951 * sig[K - 1]));
+    std::vector<float> host(off, 0.0f);
+    for (int k = 0; k < K; ++k)
+        synth_taps(static_cast<double>(sig[k]), p->radii[k], p->padded[k], p->polarity,
+                   host.data() + p->tap_off[k]);
+
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+        delete p;
+        return hip_fail(e, "hipGetDevice");
+    }
+    e = hipMalloc(reinterpret_cast<void**>(&p->d_taps), sizeof(float) * off);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->d_sigmas), sizeof(float) * K);
+    if (e != hipSuccess) {
+        hipFree(p->d_taps);
+        delete p;
+        return fail(MHFD_ERR_OOM, "plan tables: %s", hipGetErrorString(e));
+    }
+    e = hipMemcpy(p->d_taps, host.data(), sizeof(float) * off, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(p->d_sigmas, sig.data(), sizeof(float) * K, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        hipFree(p->d_taps);
+        hipFree(p->d_sigmas);
+        delete p;
+        return hip_fail(e, "copy of the plan tables");
+    }
+    *out = p;
+    return MHFD_OK;
+}
+
+mhfd_status mhfd_destroy_plan(mhfd_plan p) {
+    if (!p) return MHFD_OK;
+    hipFree(p->d_taps);
+    hipFree(p->d_sigmas);
+    delete p;
+    return MHFD_OK;
+}
+
+int32_t mhfd_plan_scales(mhfd_plan p, float* sigmas, int32_t* radii) {
+    if (!p) return -1;
+    for (int k = 0; k < p->K; ++k) {
+        if (sigmas) sigmas[k] = p->sigmas[k];
+        if (radii) radii[k] = p->radii[k];
+    }
+    return p->K;
+}
+
+size_t mhfd_detect_workspace_size(mhfd_plan p, int32_t h, int32_t w) {
+    if (!p || h < 1 || w < 1 || h > p->max_h || w > p->max_w) return 0;
+    return detect_layout(p, h, w).total;
+}
+
+}  // extern "C"
+
+namespace {
+
+mhfd_status check_image(const mhfd_plan_s* p, const void* d_img, int32_t h, int32_t w,
+                        int64_t pitch) {
+    if (!p) return fail(MHFD_ERR_INVALID_ARG, "null plan");
+    if (!d_img) return fail(MHFD_ERR_INVALID_ARG, "null image");
+    if (h < 1 || w < 1) return fail(MHFD_ERR_INVALID_ARG, "image %d x %d is empty", h, w);
+    if (h > p->max_h || w > p->max_w)
+        return fail(MHFD_ERR_INVALID_ARG, "image %d x %d exceeds the plan's %d x %d", h, w,
+                    p->max_h, p->max_w);
+    if (pitch < w) return fail(MHFD_ERR_INVALID_ARG, "pitch %lld < width %d", (long long)pitch, w);
+    if (p->dtype == MHFD_F32 && reinterpret_cast<uintptr_t>(d_img) % 4)
+        return fail(MHFD_ERR_INVALID_ARG, "float image not 4-byte aligned");
+    return MHFD_OK;
+}
+
+mhfd_status check_outputs(const mhfd_plan_s* p, int32_t h, int32_t w, const mhfd_blob* d_blobs,
+                          int32_t capacity, const mhfd_result* d_result, const void* d_ws,
+                          size_t ws_bytes, DetectLayout* L) {
+    if (!d_result || !d_ws) return fail(MHFD_ERR_INVALID_ARG, "null result or workspace");
+    if (capacity < 0) return fail(MHFD_ERR_INVALID_ARG, "capacity < 0");
+    if (capacity > 0 && !d_blobs) return fail(MHFD_ERR_INVALID_ARG, "null blob buffer");
+    if (reinterpret_cast<uintptr_t>(d_ws) % kAlign)
+        return fail(MHFD_ERR_INVALID_ARG, "workspace not %zu-byte aligned", kAlign);
+    *L = detect_layout(p, h, w);
+    if (ws_bytes < L->total)
+        return fail(MHFD_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, L->total);
+    return MHFD_OK;
+}
+
+mhfd_status enqueue_log_stack(const mhfd_plan_s* p, const void* d_img, int h, int w,
+                              int64_t pitch, float* stack, hipStream_t s) {
+    const int seg = strip_segment_rows(h, w);
+    const size_t plane = static_cast<size_t>(h) * w;
+    for (int k = 0; k < p->K; ++k) {
+        hipError_t e = mhfd::launch_log_scale(p->padded[k], p->dtype, d_img, h, w, pitch,
+                                              p->d_taps + p->tap_off[k], stack + k * plane, w, seg,
+                                              s);
+        if (e != hipSuccess) return hip_fail(e, "LoG strip launch");
+    }
+    return MHFD_OK;
+}
+
+mhfd_status enqueue_tail(const mhfd_plan_s* p, const float* stack, int h, int w,
+                         const DetectLayout& L, char* base, mhfd_blob* d_blobs, int capacity,
+                         mhfd_result* d_result, hipStream_t s) {
+    mhfd::DetectWorkspace ws;
+    ws.stack = stack;
+    ws.blk_n = reinterpret_cast<int32_t*>(base + L.blk_n);
+    ws.blk_o = reinterpret_cast<int32_t*>(base + L.blk_o);
+    ws.blk_off = reinterpret_cast<int32_t*>(base + L.blk_off);
+    ws.pool = reinterpret_cast<mhfd::Cand*>(base + L.pool);
+    ws.cand = reinterpret_cast<mhfd::Cand*>(base + L.cand);
+    ws.keep = reinterpret_cast<int32_t*>(base + L.keep);
+    ws.keep_off = reinterpret_cast<int32_t*>(base + L.keep_off);
+    ws.ctr = reinterpret_cast<mhfd::DetectCounters*>(base + L.ctr);
+    ws.cap = p->max_cand;
+    ws.n_blk = L.n_blk;
+    ws.blk_per_row = L.bpr;
+    hipError_t e = mhfd::launch_detect_tail(ws, p->K, h, w, p->threshold, p->overlap, p->reach,
+                                            p->d_sigmas, d_blobs, capacity, d_result, s);
+    if (e != hipSuccess) return hip_fail(e, "detection launch");
+    return MHFD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mhfd_status mhfd_log_stack(mhfd_plan p, const void* d_img, int32_t h, int32_t w, int64_t pitch,
+                           float* d_stack, void* stream) {
+    g_last_error.clear();
+    mhfd_status st = check_image(p, d_img, h, w, pitch);
+    if (st != MHFD_OK) return st;
+    if (!d_stack) return fail(MHFD_ERR_INVALID_ARG, "null stack");
+    if ((st = check_device(p)) != MHFD_OK) return st;
+    return enqueue_log_stack(p, d_img, h, w, pitch, d_stack, static_cast<hipStream_t>(stream));
+}
+
+mhfd_status mhfd_detect_stack(mhfd_plan p, const float* d_stack, int32_t h, int32_t w,
+                              mhfd_blob* d_blobs, int32_t capacity, mhfd_result* d_result,
+                              void* d_ws, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    mhfd_status st = check_image(p, d_stack, h, w, w);
+    if (st != MHFD_OK) return st;
+    DetectLayout L;
+    if ((st = check_outputs(p, h, w, d_blobs, capacity, d_result, d_ws, ws_bytes, &L)) != MHFD_OK)
+        return st;
+    if ((st = check_device(p)) != MHFD_OK) return st;
+    return enqueue_tail(p, d_stack, h, w, L, static_cast<char*>(d_ws), d_blobs, capacity, d_result,
+                        static_cast<hipStream_t>(stream));
+}
+
+mhfd_status mhfd_detect(mhfd_plan p, const void* d_img, int32_t h, int32_t w, int64_t pitch,
+                        mhfd_blob* d_blobs, int32_t capacity, mhfd_result* d_result,
+                        float* d_stack, void* d_ws, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    mhfd_status st = check_image(p, d_img, h, w, pitch);
+    if (st != MHFD_OK) return st;
+    DetectLayout L;
+    if ((st = check_outputs(p, h, w, d_blobs, capacity, d_result, d_ws, ws_bytes, &L)) != MHFD_OK)
+        return st;
+    if ((st = check_device(p)) != MHFD_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* base = static_cast<char*>(d_ws);
+    float* stack = d_stack ? d_stack : reinterpret_cast<float*>(base + L.stack);
+    if ((st = enqueue_log_stack(p, d_img, h, w, pitch, stack, s)) != MHFD_OK) return st;
+    return enqueue_tail(p, stack, h, w, L, base, d_blobs, capacity, d_result, s);
+}
+
+size_t mhfd_focus_workspace_size(mhfd_plan p, int32_t b, int32_t h, int32_t w) {
+    (void)p;
+    (void)b;
+    (void)h;
+    (void)w;
+    return 0;
+}
+
+mhfd_status mhfd_focus_score(mhfd_plan p, const float* d_imgs, int32_t b, int32_t h, int32_t w,
+                             const float* d_sigmas, float beta, float tau, float* d_scores,
+                             void* d_ws, size_t ws_bytes, void* stream) {
+    (void)p; (void)d_imgs; (void)b; (void)h; (void)w; (void)d_sigmas; (void)beta; (void)tau;
+    (void)d_scores; (void)d_ws; (void)ws_bytes; (void)stream;
+    return fail(MHFD_ERR_UNSUPPORTED, "focus_score is not built yet");
+}
+
+mhfd_status mhfd_focus_score_backward(mhfd_plan p, const float* d_imgs, int32_t b, int32_t h,
+                                      int32_t w, const float* d_sigmas, float beta, float tau,
+                                      const float* d_grad_scores, float* d_grad_imgs,
+                                      float* d_grad_sigmas, void* d_ws, size_t ws_bytes,
+                                      void* stream) {
+    (void)p; (void)d_imgs; (void)b; (void)h; (void)w; (void)d_sigmas; (void)beta; (void)tau;
+    (void)d_grad_scores; (void)d_grad_imgs; (void)d_grad_sigmas; (void)d_ws; (void)ws_bytes;
+    (void)stream;
+    return fail(MHFD_ERR_UNSUPPORTED, "focus_score_backward is not built yet");
+}
+
+}  // extern "C"

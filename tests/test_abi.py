@@ -1,0 +1,64 @@
+"""The C ABI: libmhfd.so loads on a machine without a GPU and exports every
+function include/mhfd.h declares; host-side argument checks return status
+codes without touching a device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "mhfd.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mhfd_[a-z_]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree():
+    from paper_2108_12050_amd import _lib
+    assert declared_functions() == sorted(_lib.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2108_12050_amd import _lib
+    L = _lib.load()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_status_strings():
+    from paper_2108_12050_amd import _lib
+    L = _lib.load()
+    for code in range(6):
+        assert L.mhfd_status_string(code)
+    assert L.mhfd_status_string(99) == b"unknown status"
+
+
+@pytest.mark.parametrize("bad", [dict(n_scales=0), dict(n_scales=33), dict(truncate=0.0),
+                                 dict(overlap=-1.0), dict(polarity=5), dict(in_dtype=7),
+                                 dict(max_h=0), dict(sigma_min=-1.0)])
+def test_create_plan_rejects_bad_config_on_host(bad):
+    """Validation happens before any device call, so it runs without a GPU."""
+    from paper_2108_12050_amd import _lib
+    L = _lib.load()
+    cfg = _lib.Config(n_scales=10, sigma_min=1.0, sigma_max=10.0, truncate=4.0, threshold=0.1,
+                      overlap=0.5, polarity=0, in_dtype=0, max_h=64, max_w=64, max_candidates=0)
+    for k, v in bad.items():
+        setattr(cfg, k, v)
+    h = C.c_void_p()
+    assert L.mhfd_create_plan(C.byref(cfg), C.byref(h)) == 1
+    assert L.mhfd_last_error()
+    assert h.value is None
+
+
+def test_null_arguments():
+    from paper_2108_12050_amd import _lib
+    L = _lib.load()
+    assert L.mhfd_create_plan(None, None) == 1
+    assert L.mhfd_destroy_plan(None) == 0
+    assert L.mhfd_plan_scales(None, None, None) == -1
+    assert L.mhfd_detect_workspace_size(None, 10, 10) == 0
+    assert L.mhfd_detect(None, None, 1, 1, 1, None, 0, None, None, None, 0, None) == 1
+    assert L.mhfd_log_stack(None, None, 1, 1, 1, None, None) == 1

@@ -1,0 +1,259 @@
+"""GPU parity of the detector (mhfd_detect through the C ABI) against the
+FP64 oracle on the same seeded inputs.
+
+Tolerances: the LoG stack within 1e-5 of each plane's largest oracle value;
+candidate and blob decisions identical wherever the oracle's decision is not
+within 1e-4 of the threshold or of a window neighbour (ambiguous decisions
+must be consistent with the GPU's own stack); blob lists bit-exact in
+(y, x, k, sigma) whenever the candidate sets agree, with responses within the
+stack tolerance.  Threshold and overlap are handed to the oracle as the
+float32 values the plan holds.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2108_12050_amd import synth
+
+from parity import as_set, compare_candidates, gpu_detect, plane_rel_err
+
+pytestmark = pytest.mark.gpu
+
+SIG10 = oracle.linear_sigmas(10, 1.0, 10.0)
+TAU = float(np.float32(0.1))
+STACK_TOL = 1e-5
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def make_plan(**kw):
+    from paper_2108_12050_amd import Plan
+    args = dict(n_scales=10, sigma_min=1.0, sigma_max=10.0, threshold=0.1, overlap=0.5,
+                max_h=1024, max_w=1024)
+    args.update(kw)
+    return Plan(**args)
+
+
+@pytest.fixture(scope="module")
+def plans():
+    return dict(prune=make_plan(), cand=make_plan(overlap=1.0))
+
+
+def test_plan_scales_match_paper_grid(plans):
+    p = plans["prune"]
+    np.testing.assert_array_equal(np.float64(p.sigmas), SIG10)
+    assert p.radii == [oracle.radius(s, 4.0) for s in SIG10]
+    from paper_2108_12050_amd import Plan
+    q = Plan(n_scales=5, sigma_min=1.5, sigma_max=3.25, max_h=64, max_w=64)
+    np.testing.assert_array_equal(np.float64(q.sigmas), oracle.linear_sigmas(5, 1.5, 3.25))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_plain_512_stack_and_blobs(plans, seed):
+    print(f"plain 512x512 seed {seed}", flush=True)
+    img = synth.plain_tile(seed)
+    ora = oracle.detect(img, SIG10, 4.0, TAU, 0.5)
+    g_c = gpu_detect(plans["cand"], img)
+    err = plane_rel_err(g_c["stack"], ora["stack"])
+    assert err.max() <= STACK_TOL, err
+    n_amb, n_diff = compare_candidates(g_c["stack"], as_set(g_c["yxk"]), ora["stack"],
+                                       as_set(ora["cand"]), TAU)
+    assert g_c["n_cand"] == len(g_c["yxk"])
+    g_p = gpu_detect(plans["prune"], img, return_stack=False)
+    if n_diff == 0:
+        np.testing.assert_array_equal(g_p["yxk"], ora["blobs"])
+        np.testing.assert_array_equal(g_p["sigma"], np.float32(ora["blob_sigma"]))
+        np.testing.assert_allclose(g_p["resp"], ora["blob_resp"], rtol=0,
+                                   atol=STACK_TOL * np.abs(ora["stack"]).max())
+        assert g_p["count"] == ora["count"]
+    else:
+        assert abs(g_p["count"] - ora["count"]) <= n_diff
+
+
+def test_strict_seeds_bit_exact(plans):
+    """Seeds with no decision within 1e-4 of the threshold or of a neighbour:
+    the blob lists must be identical."""
+    seeds = json.load(open(os.path.join(GOLD, "strict_seeds.json")))["seeds"]
+    for s in seeds:
+        print(f"strict seed {s}", flush=True)
+        img = synth.blob_field(s, 256, 256)
+        ora = oracle.detect(img, SIG10, 4.0, TAU, 0.5)
+        g_c = gpu_detect(plans["cand"], img, return_stack=False)
+        np.testing.assert_array_equal(g_c["yxk"], ora["cand"])
+        g = gpu_detect(plans["prune"], img)
+        assert plane_rel_err(g["stack"], ora["stack"]).max() <= STACK_TOL
+        np.testing.assert_array_equal(g["yxk"], ora["blobs"])
+        np.testing.assert_array_equal(g["sigma"], np.float32(ora["blob_sigma"]))
+        np.testing.assert_allclose(g["resp"], ora["blob_resp"], rtol=0,
+                                   atol=STACK_TOL * np.abs(ora["stack"]).max())
+        assert g["count"] == ora["count"] > 20
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (3, 2), (5, 70), (70, 5), (33, 65), (97, 130),
+                                   (200, 129), (64, 64)])
+def test_ragged_and_tiny_shapes(shape):
+    """Kernel radius larger than the image, widths and heights that are not
+    multiples of the strip width (64) or chunk height (32)."""
+    print(f"shape {shape}", flush=True)
+    rng = np.random.default_rng(sum(shape))
+    img = synth.blob_field(5, *shape, n_blobs=max(1, shape[0] * shape[1] // 500)) \
+        + rng.uniform(0, 0.05, shape).astype(np.float32)
+    plan = make_plan(overlap=1.0, max_h=256, max_w=256)
+    g = gpu_detect(plan, img)
+    ora = oracle.log_stack(img, SIG10)
+    err = np.abs(g["stack"] - ora).max()
+    assert err <= STACK_TOL * max(np.abs(ora).max(), np.abs(img).max()), err
+    ykx, _ = oracle.candidates(ora, TAU)
+    compare_candidates(g["stack"], as_set(g["yxk"]), ora, as_set(ykx), TAU)
+
+
+def test_constant_image_has_no_response():
+    plan = make_plan(max_h=128, max_w=128)
+    img = np.full((100, 77), 0.6, np.float32)
+    g = gpu_detect(plan, img)
+    assert np.abs(g["stack"]).max() < 1e-6
+    assert g["count"] == 0 and g["n_cand"] == 0
+
+
+def test_u8_input_and_pitch():
+    """8-bit input read as u/255, from a row-padded buffer (pitch > width)."""
+    import torch
+    from paper_2108_12050_amd import Plan
+    img = synth.sem_tile(1, psf_sigma=1.0, H=300, W=260)
+    plan = Plan(n_scales=10, sigma_min=1, sigma_max=10, threshold=0.05, overlap=0.5,
+                dtype="u8", max_h=512, max_w=512)
+    big = np.zeros((300, 300), np.uint8)
+    big[:, :260] = img
+    t = torch.from_numpy(big).to(plan.device)[:, :260]
+    assert t.stride(0) == 300
+    d = plan.detect(t, return_stack=True)
+    ora = oracle.detect(img, SIG10, 4.0, float(np.float32(0.05)), 0.5)
+    assert plane_rel_err(d.stack.cpu().numpy(), ora["stack"]).max() <= STACK_TOL
+    yxk = d.yxk.cpu().numpy()
+    diff = as_set(yxk) ^ as_set(ora["blobs"])
+    assert len(diff) <= 4, sorted(diff)
+
+
+def test_dark_polarity_and_scale_grid():
+    plan = make_plan(n_scales=4, sigma_min=1.5, sigma_max=3.0, polarity="dark", overlap=1.0,
+                     max_h=128, max_w=128)
+    sig = oracle.linear_sigmas(4, 1.5, 3.0)
+    img = 1.0 - synth.blob_field(9, 128, 96, n_blobs=12)
+    g = gpu_detect(plan, img)
+    ora = oracle.log_stack(img, sig, polarity=1)
+    assert plane_rel_err(g["stack"], ora).max() <= STACK_TOL
+    ykx, _ = oracle.candidates(ora, TAU)
+    compare_candidates(g["stack"], as_set(g["yxk"]), ora, as_set(ykx), TAU)
+    assert len(ykx) > 3
+
+
+def test_single_scale():
+    plan = make_plan(n_scales=1, sigma_min=2.0, sigma_max=2.0, overlap=1.0, max_h=64, max_w=64)
+    img = synth.blob_field(3, 64, 64, n_blobs=6)
+    g = gpu_detect(plan, img)
+    ora = oracle.log_stack(img, [2.0])
+    assert plane_rel_err(g["stack"], ora).max() <= STACK_TOL
+    ykx, _ = oracle.candidates(ora, TAU)
+    compare_candidates(g["stack"], as_set(g["yxk"]), ora, as_set(ykx), TAU)
+
+
+def test_capacity_overflow_truncates_in_canonical_order(plans):
+    img = synth.plain_tile(0)
+    full = gpu_detect(plans["prune"], img, return_stack=False)
+    part = gpu_detect(plans["prune"], img, return_stack=False, capacity=7)
+    assert part["count"] == full["count"] > 7
+    assert part["flags"] & 1
+    np.testing.assert_array_equal(part["yxk"], full["yxk"][:7])
+
+
+def test_deterministic(plans):
+    img = synth.plain_tile(4)
+    a = gpu_detect(plans["prune"], img)
+    b = gpu_detect(plans["prune"], img)
+    np.testing.assert_array_equal(a["stack"], b["stack"])
+    np.testing.assert_array_equal(a["yxk"], b["yxk"])
+    np.testing.assert_array_equal(a["resp"], b["resp"])
+
+
+def test_errors_are_reported():
+    import torch
+    from paper_2108_12050_amd import MHFDError
+    plan = make_plan(max_h=64, max_w=64)
+    with pytest.raises(MHFDError):
+        plan.detect(torch.zeros((65, 10), device=plan.device))
+    with pytest.raises(MHFDError):
+        make_plan(sigmas=[2.0, 1.0])
+    with pytest.raises(MHFDError):
+        make_plan(n_scales=1, sigma_min=20.0, sigma_max=20.0)   # radius 80 > 64
+
+
+def test_split_entry_points_equal_detect(plans):
+    """mhfd_log_stack followed by mhfd_detect_stack gives what mhfd_detect gives."""
+    import torch
+    from paper_2108_12050_amd import _lib
+    p = plans["prune"]
+    L = _lib.load()
+    img = torch.from_numpy(synth.plain_tile(6)).to(p.device)
+    d = p.detect(img, return_stack=True)
+    st = torch.empty_like(d.stack)
+    s = int(torch.cuda.current_stream().cuda_stream)
+    _lib.check(L.mhfd_log_stack(p._handle, img.data_ptr(), 512, 512, 512, st.data_ptr(), s), "ls")
+    cap = 4096
+    raw = torch.empty((cap, 5), dtype=torch.int32, device=p.device)
+    res = torch.zeros(3, dtype=torch.int64, device=p.device)
+    nb = p.detect_workspace_bytes(512, 512)
+    ws = torch.empty(nb, dtype=torch.uint8, device=p.device)
+    _lib.check(L.mhfd_detect_stack(p._handle, st.data_ptr(), 512, 512, raw.data_ptr(), cap,
+                                   res.data_ptr(), ws.data_ptr(), nb, s), "ds")
+    torch.cuda.synchronize()
+    assert torch.equal(st, d.stack)
+    n = int(res[0])
+    assert n == d.count
+    assert torch.equal(raw[:n, :3], d.yxk)
+
+
+def test_full_size_sem_tile():
+    """4096 x 4096 8-bit tile, sigma 1..10, threshold 0.05, in the launch
+    configuration the benchmark times: sampled stack voxels against the 2-D
+    definition over the whole tile; stack and candidate decisions
+    (ambiguity-aware) against the oracle on three full-width row bands
+    (top border, middle, bottom border)."""
+    import torch
+    from paper_2108_12050_amd import Plan
+    print("full-size 4096x4096 u8", flush=True)
+    img = synth.sem_tile(0, psf_sigma=0.0)
+    tau = float(np.float32(0.05))
+    plan_c = Plan(n_scales=10, sigma_min=1, sigma_max=10, threshold=0.05, overlap=1.0,
+                  dtype="u8", max_h=4096, max_w=4096)
+    t = torch.from_numpy(img).to(plan_c.device)
+    d = plan_c.detect(t, return_stack=True)
+    st = d.stack.cpu().numpy()
+    gpu_c = as_set(d.yxk.cpu().numpy())
+    I = oracle.to_f64(img)
+    rng = np.random.default_rng(0)
+    pts = [(int(rng.integers(0, 10)), int(rng.integers(0, 4096)), int(rng.integers(0, 4096)))
+           for _ in range(300)]
+    pts += [(k, y, x) for k in (0, 9) for y in (0, 1, 4095) for x in (0, 63, 64, 4095)]
+    for (k, y, x) in pts:
+        ref = oracle.log_point(I, SIG10[k], y, x)
+        assert abs(st[k, y, x] - ref) <= STACK_TOL * 0.5, (k, y, x, st[k, y, x], ref)
+    H = 4096
+    m = 42   # > largest radius + 1: band rows [y0 - 1, y1 + 1) are exact
+    total = 0
+    for (y0, y1) in [(0, 256), (2000, 2256), (3840, 4096)]:
+        a, b = max(0, y0 - m), min(H, y1 + m)
+        ora = oracle.log_stack(I[a:b], SIG10)
+        lo, hi = max(0, y0 - 1) - a, min(H, y1 + 1) - a
+        err = plane_rel_err(st[:, a + lo:a + hi], ora[:, lo:hi])
+        assert err.max() <= STACK_TOL, err
+        ykx, _ = oracle.candidates(ora, tau)
+        ykx[:, 0] += a
+        n_amb, n_diff = compare_candidates(st[:, a:b], gpu_c, ora, as_set(ykx), tau,
+                                           rows=(y0, y1), row0=a)
+        n_band = sum(1 for c in gpu_c if y0 <= c[0] < y1)
+        print(f"band {y0}-{y1}: gpu candidates {n_band} ambiguous {n_amb} differing {n_diff}",
+              flush=True)
+        total += n_band
+    assert total > 1000
