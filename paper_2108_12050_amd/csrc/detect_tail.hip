@@ -22,6 +22,8 @@
 #include <float.h>
 #include <math.h>
 
+#include <utility>
+
 #include "mhfd_internal.h"
 
 namespace mhfd {
@@ -29,6 +31,7 @@ namespace mhfd {
 namespace {
 
 constexpr int NMS_T = 256;
+constexpr int SLOT = 16;  // pool records each NMS workgroup owns
 constexpr int SCAN_T = 1024;
 
 __device__ __forceinline__ float fmax3(float a, float b, float c) { return fmaxf(a, fmaxf(b, c)); }
@@ -58,13 +61,20 @@ __global__ void init_counters_kernel(DetectCounters* ctr) {
     }
 }
 
-__global__ __launch_bounds__(NMS_T) void nms_kernel(const float* __restrict__ st, int K, int H,
-                                                    int W, float tau, int bpr,
+// One workgroup per (row, 256-column chunk).  Every thread first issues the
+// loads of its column's three rows for all K planes: indices are clamped so
+// that every load is in bounds and unconditional (no branch, so all 3K loads
+// are in flight together), and values from outside the image are replaced by
+// -inf afterwards.  Vertical 3-maxima go through LDS once, then each thread
+// tests its K voxels.
+template <int K>
+__global__ __launch_bounds__(NMS_T) void nms_kernel(const float* __restrict__ st, int H, int W,
+                                                    float tau, int bpr,
                                                     int32_t* __restrict__ blk_n,
                                                     int32_t* __restrict__ blk_o,
                                                     Cand* __restrict__ pool, int64_t cap,
                                                     DetectCounters* __restrict__ ctr) {
-    __shared__ float vm[2][NMS_T + 2];
+    __shared__ float vm[K][NMS_T + 2];
     __shared__ int wave_tot[NMS_T / 64];
     __shared__ int run_base;
 
@@ -75,44 +85,64 @@ __global__ __launch_bounds__(NMS_T) void nms_kernel(const float* __restrict__ st
     const int x = x0 + tid;
     const bool valid = x < W;
     const size_t plane = static_cast<size_t>(H) * W;
+    const int yu = y > 0 ? y - 1 : 0;
+    const int yd = y + 1 < H ? y + 1 : H - 1;
+    const int xc = valid ? x : W - 1;
 
-    // Largest of rows y-1..y+1 of plane k at column xc, -inf outside.
-    auto vmax = [&](int k, int xc) -> float {
-        if (xc < 0 || xc >= W) return -INFINITY;
-        const float* p = st + k * plane + static_cast<size_t>(y) * W + xc;
-        float m = p[0];
-        if (y > 0) m = fmaxf(m, p[-W]);
-        if (y + 1 < H) m = fmaxf(m, p[W]);
-        return m;
-    };
+    float cv[K], vmx[K];
+    {
+        const float* pc = st + static_cast<size_t>(y) * W + xc;
+        const float* pu = st + static_cast<size_t>(yu) * W + xc;
+        const float* pd = st + static_cast<size_t>(yd) * W + xc;
+        float u[K], d[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            cv[k] = pc[k * plane];
+            u[k] = pu[k * plane];
+            d[k] = pd[k * plane];
+        }
+        // rows clamped onto the centre row contribute nothing new to the max
+#pragma unroll
+        for (int k = 0; k < K; ++k) vmx[k] = valid ? fmax3(u[k], cv[k], d[k]) : -INFINITY;
+    }
+    // halo columns x0 - 1 and x0 + 256 (clamped, then masked)
+    if (tid == 0 || tid == NMS_T - 1) {
+        const int xh = tid == 0 ? x0 - 1 : x0 + NMS_T;
+        const bool ok = xh >= 0 && xh < W;
+        const int xs = ok ? xh : 0;
+        const int slot = tid == 0 ? 0 : NMS_T + 1;
+        const float* pc = st + static_cast<size_t>(y) * W + xs;
+        const float* pu = st + static_cast<size_t>(yu) * W + xs;
+        const float* pd = st + static_cast<size_t>(yd) * W + xs;
+        float hv[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) hv[k] = fmax3(pu[k * plane], pc[k * plane], pd[k * plane]);
+#pragma unroll
+        for (int k = 0; k < K; ++k) vm[k][slot] = ok ? hv[k] : -INFINITY;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) vm[k][tid + 1] = vmx[k];
+    __syncthreads();
 
-    float m_prev2 = -INFINITY, m_prev = -INFINITY, v_prev = -INFINITY;
-    unsigned long long mask = 0ull;
-    for (int k = 0; k <= K; ++k) {
-        const int buf = k & 1;
-        if (k < K) {
-            vm[buf][tid + 1] = vmax(k, x);
-            if (tid == 0) vm[buf][0] = vmax(k, x0 - 1);
-            if (tid == NMS_T - 1) vm[buf][NMS_T + 1] = vmax(k, x0 + NMS_T);
+    unsigned mask = 0u;
+    {
+        float m_prev = -INFINITY;
+        float m_cur = fmax3(vm[0][tid], vm[0][tid + 1], vm[0][tid + 2]);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const float m_next =
+                k + 1 < K ? fmax3(vm[k + 1][tid], vm[k + 1][tid + 1], vm[k + 1][tid + 2]) : -INFINITY;
+            const float v = cv[k];
+            if (v > tau && v >= fmax3(m_prev, m_cur, m_next)) mask |= 1u << k;
+            m_prev = m_cur;
+            m_cur = m_next;
         }
-        __syncthreads();
-        float m_cur = -INFINITY, v_cur = -INFINITY;
-        if (k < K && valid) {
-            m_cur = fmax3(vm[buf][tid], vm[buf][tid + 1], vm[buf][tid + 2]);
-            v_cur = st[k * plane + static_cast<size_t>(y) * W + x];
-        }
-        if (k >= 1 && valid) {
-            const float mm = fmax3(m_prev2, m_prev, m_cur);
-            if (v_prev > tau && v_prev >= mm) mask |= 1ull << (k - 1);
-        }
-        m_prev2 = m_prev;
-        m_prev = m_cur;
-        v_prev = v_cur;
+        if (!valid) mask = 0u;
     }
 
-    const int c = __popcll(mask);
+    const int c = __popc(mask);
     int wtot;
-    const int pre = wave_exclusive_prefix<7>(c, &wtot);
+    const int pre = wave_exclusive_prefix<6>(c, &wtot);
     const int lane = tid & 63, wv = tid >> 6;
     if (lane == 0) wave_tot[wv] = wtot;
     __syncthreads();
@@ -122,11 +152,15 @@ __global__ __launch_bounds__(NMS_T) void nms_kernel(const float* __restrict__ st
         woff += i < wv ? wave_tot[i] : 0;
         n += wave_tot[i];
     }
+    // The first SLOT records of a workgroup go to its own pool slot; a
+    // workgroup with more reserves room for the rest in the shared overflow
+    // region (one atomic, only for such workgroups).
     if (tid == 0) {
         int o = 0;
-        if (n > 0) {
-            o = atomicAdd(&ctr->pool_used, n);
-            if (static_cast<int64_t>(o) + n > cap) atomicOr(&ctr->flags, MHFD_FLAG_CAND_OVERFLOW);
+        if (n > SLOT) {
+            o = atomicAdd(&ctr->pool_used, n - SLOT);
+            if (static_cast<int64_t>(o) + (n - SLOT) > cap)
+                atomicOr(&ctr->flags, MHFD_FLAG_CAND_OVERFLOW);
         }
         run_base = o;
         blk_n[blk] = n;
@@ -134,66 +168,157 @@ __global__ __launch_bounds__(NMS_T) void nms_kernel(const float* __restrict__ st
     }
     __syncthreads();
     if (c > 0) {
-        int64_t pos = static_cast<int64_t>(run_base) + woff + pre;
-        unsigned long long m = mask;
-        while (m) {
-            const int k = __ffsll(m) - 1;
-            m &= m - 1;
-            if (pos < cap) {
+        int j = woff + pre;  // rank of this thread's first record in the workgroup
+        Cand* own = pool + static_cast<int64_t>(blk) * SLOT;
+        Cand* over = pool + static_cast<int64_t>(gridDim.x) * SLOT + run_base - SLOT;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (mask & (1u << k)) {
                 Cand r;
                 r.y = y;
                 r.x = x;
                 r.k = k;
-                r.r = st[k * plane + static_cast<size_t>(y) * W + x];
-                pool[pos] = r;
+                r.r = cv[k];
+                if (j < SLOT)
+                    own[j] = r;
+                else if (run_base + (j - SLOT) < cap)
+                    over[j] = r;
+                ++j;
             }
-            ++pos;
         }
     }
 }
 
-// Exclusive scan of in[0, n) into out[0, n], out[n] = total, by one
-// workgroup.  n is min(n_host, *n_dev) when n_dev is given.  If total_out is
-// given it receives the total as well.
-__global__ __launch_bounds__(SCAN_T) void scan_kernel(const int32_t* __restrict__ in, int n_host,
-                                                      const int32_t* __restrict__ n_dev,
-                                                      int32_t* __restrict__ out,
-                                                      int32_t* __restrict__ total_out) {
-    __shared__ int part[SCAN_T];
-    int n = n_host;
-    if (n_dev) n = min(n, *n_dev);
-    const int tid = threadIdx.x;
-    const int per = (n + SCAN_T - 1) / SCAN_T;
-    const int lo = min(n, tid * per), hi = min(n, lo + per);
-    int s = 0;
-    for (int i = lo; i < hi; ++i) s += in[i];
-    part[tid] = s;
+template <int K>
+void launch_nms_k(const DetectWorkspace& ws, int h, int w, float tau, hipStream_t s) {
+    nms_kernel<K><<<ws.n_blk, NMS_T, 0, s>>>(ws.stack, h, w, tau, ws.blk_per_row, ws.blk_n,
+                                             ws.blk_o, ws.pool, ws.cap, ws.ctr);
+}
+
+template <int... Ks>
+void launch_nms(int K, const DetectWorkspace& ws, int h, int w, float tau, hipStream_t s,
+                std::integer_sequence<int, Ks...>) {
+    ((K == Ks + 1 ? launch_nms_k<Ks + 1>(ws, h, w, tau, s) : void()), ...);
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive scan over n = min(n_host, *n_dev) ints in three launches:
+// per-span sums, a scan of the span sums by one workgroup, per-span scans.
+constexpr int SCAN_BT = 256;              // threads per span workgroup
+constexpr int SCAN_ITEMS = 16;            // items per thread
+constexpr int SCAN_SPAN = SCAN_BT * SCAN_ITEMS;
+
+__device__ __forceinline__ int scan_n(int n_host, const int32_t* n_dev) {
+    return n_dev ? min(n_host, *n_dev) : n_host;
+}
+
+// Inclusive scan of one int per thread across a workgroup of SCAN_BT threads.
+__device__ __forceinline__ int block_inclusive_scan(int v, int* sh /* SCAN_BT/64 ints */) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int t = __shfl_up(v, d, 64);
+        if (lane >= d) v += t;
+    }
+    if (lane == 63) sh[wv] = v;
     __syncthreads();
-    // Hillis-Steele inclusive scan of the partial sums
-    for (int d = 1; d < SCAN_T; d <<= 1) {
-        const int v = tid >= d ? part[tid - d] : 0;
+    int add = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_BT / 64; ++i) add += i < wv ? sh[i] : 0;
+    return v + add;
+}
+
+__global__ __launch_bounds__(SCAN_BT) void scan_sums_kernel(const int32_t* __restrict__ in,
+                                                           int n_host,
+                                                           const int32_t* __restrict__ n_dev,
+                                                           int32_t* __restrict__ sums) {
+    __shared__ int sh[SCAN_BT / 64];
+    const int n = scan_n(n_host, n_dev);
+    const int base = blockIdx.x * SCAN_SPAN + threadIdx.x * SCAN_ITEMS;
+    int s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i)
+        if (base + i < n) s += in[base + i];
+    const int incl = block_inclusive_scan(s, sh);
+    if (threadIdx.x == SCAN_BT - 1) sums[blockIdx.x] = incl;
+}
+
+// Exclusive scan of the nb span sums in place; writes the total to out[n]
+// and to *total_out if given.
+__global__ __launch_bounds__(1024) void scan_top_kernel(int32_t* __restrict__ sums, int nb,
+                                                        int n_host,
+                                                        const int32_t* __restrict__ n_dev,
+                                                        int32_t* __restrict__ out,
+                                                        int32_t* __restrict__ total_out) {
+    __shared__ int sh[1024];
+    const int n = scan_n(n_host, n_dev);
+    const int nb_used = (n + SCAN_SPAN - 1) / SCAN_SPAN;
+    int carry = 0;
+    for (int b0 = 0; b0 < nb_used; b0 += 1024) {
+        const int i = b0 + threadIdx.x;
+        const int v = i < nb_used ? sums[i] : 0;
+        sh[threadIdx.x] = v;
         __syncthreads();
-        part[tid] += v;
+        for (int d = 1; d < 1024; d <<= 1) {
+            const int t = threadIdx.x >= d ? sh[threadIdx.x - d] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (i < nb_used) sums[i] = carry + sh[threadIdx.x] - v;
+        carry += sh[1023];
         __syncthreads();
     }
-    int run = part[tid] - s;
-    for (int i = lo; i < hi; ++i) {
-        out[i] = run;
-        run += in[i];
+    (void)nb;
+    if (threadIdx.x == 0) {
+        out[n] = carry;
+        if (total_out) *total_out = carry;
     }
-    if (tid == SCAN_T - 1) {
-        out[n] = part[SCAN_T - 1];
-        if (total_out) *total_out = part[SCAN_T - 1];
+}
+
+__global__ __launch_bounds__(SCAN_BT) void scan_apply_kernel(const int32_t* __restrict__ in,
+                                                            int n_host,
+                                                            const int32_t* __restrict__ n_dev,
+                                                            const int32_t* __restrict__ sums,
+                                                            int32_t* __restrict__ out) {
+    __shared__ int sh[SCAN_BT / 64];
+    const int n = scan_n(n_host, n_dev);
+    if (blockIdx.x * SCAN_SPAN >= n) return;
+    const int base = blockIdx.x * SCAN_SPAN + threadIdx.x * SCAN_ITEMS;
+    int v[SCAN_ITEMS];
+    int s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        v[i] = base + i < n ? in[base + i] : 0;
+        s += v[i];
     }
+    int run = block_inclusive_scan(s, sh) - s + sums[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        if (base + i < n) out[base + i] = run;
+        run += v[i];
+    }
+}
+
+void launch_scan(const int32_t* in, int n_host, const int32_t* n_dev, int32_t* sums,
+                 int32_t* out, int32_t* total_out, hipStream_t s) {
+    const int nb = (n_host + SCAN_SPAN - 1) / SCAN_SPAN;
+    const int grid = nb > 0 ? nb : 1;
+    scan_sums_kernel<<<grid, SCAN_BT, 0, s>>>(in, n_host, n_dev, sums);
+    scan_top_kernel<<<1, 1024, 0, s>>>(sums, grid, n_host, n_dev, out, total_out);
+    scan_apply_kernel<<<grid, SCAN_BT, 0, s>>>(in, n_host, n_dev, sums, out);
 }
 
 __global__ void order_kernel(const int32_t* __restrict__ blk_off, const int32_t* __restrict__ blk_o,
                              int n_blk, const Cand* __restrict__ pool, Cand* __restrict__ cand,
                              int64_t cap, const DetectCounters* __restrict__ ctr) {
     const int64_t n = min(static_cast<int64_t>(ctr->n_cand), cap);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && ctr->n_cand > cap)
+        atomicOr(const_cast<int32_t*>(&ctr->flags), MHFD_FLAG_CAND_OVERFLOW);
+    const Cand* over = pool + static_cast<int64_t>(n_blk) * SLOT;
     for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        // last block b with blk_off[b] <= i
+        // last workgroup b with blk_off[b] <= i
         int lo = 0, hi = n_blk;  // invariant: blk_off[lo] <= i < blk_off[hi]
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
@@ -202,47 +327,60 @@ __global__ void order_kernel(const int32_t* __restrict__ blk_off, const int32_t*
             else
                 hi = mid;
         }
-        const int64_t src = static_cast<int64_t>(blk_o[lo]) + (i - blk_off[lo]);
-        if (src < cap) cand[i] = pool[src];
+        const int j = static_cast<int>(i - blk_off[lo]);
+        if (j < SLOT) {
+            cand[i] = pool[static_cast<int64_t>(lo) * SLOT + j];
+        } else {
+            const int64_t src = static_cast<int64_t>(blk_o[lo]) + (j - SLOT);
+            if (src < cap) cand[i] = over[src];
+        }
     }
 }
 
-// Fraction of the smaller disc covered by the intersection of two discs.
-__device__ double disc_overlap(double dy, double dx, double ra, double rb) {
-    const double d = sqrt(dy * dy + dx * dx);
-    if (d >= ra + rb) return 0.0;
-    if (d <= fabs(ra - rb)) return 1.0;
-    const double rs = fmin(ra, rb);
-    const double ca = (d * d + ra * ra - rb * rb) / (2.0 * d * ra);
-    const double cb = (d * d + rb * rb - ra * ra) / (2.0 * d * rb);
-    const double lens = ra * ra * acos(ca) + rb * rb * acos(cb) -
-                        0.5 * sqrt((-d + ra + rb) * (d + ra - rb) * (d - ra + rb) * (d + ra + rb));
-    return lens / (M_PI * rs * rs);
-}
-
+// One thread per candidate b.  Candidates a that can remove b lie within
+// `reach` rows and, in row y_b + dy, within |dx| <= sqrt(reach^2 - dy^2);
+// rows come from the per-row offsets of the canonical list and the column
+// range from a binary search in the row (sorted by x).  The overlap test is
+// the plan's exact integer form: overlap(a, b) > theta iff
+// dy^2 + dx^2 <= d2max[k_a][k_b] (the lens fraction falls monotonically with
+// distance; the table is evaluated in double on the host).
 __global__ void prune_kernel(const Cand* __restrict__ cand, const int32_t* __restrict__ blk_off,
-                             int bpr, int H, const float* __restrict__ sigmas, int reach,
-                             double theta, int32_t* __restrict__ keep, int64_t cap,
+                             int bpr, int H, int K, const int32_t* __restrict__ d2max, int reach,
+                             int32_t* __restrict__ keep, int64_t cap,
                              const DetectCounters* __restrict__ ctr) {
     const int64_t n = min(static_cast<int64_t>(ctr->n_cand), cap);
-    const double kSqrt2 = 1.4142135623730951;
+    const long long r2 = static_cast<long long>(reach) * reach;
     for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const Cand b = cand[i];
-        const double rb = kSqrt2 * static_cast<double>(sigmas[b.k]);
-        const int ylo = max(0, b.y - reach), yhi = min(H - 1, b.y + reach);
-        const int64_t j0 = blk_off[ylo * bpr];
-        const int64_t j1 = min(static_cast<int64_t>(blk_off[(yhi + 1) * bpr]), n);
+        const int32_t* dcol = d2max + b.k;  // d2max[ka * K + kb]
         int kp = 1;
-        for (int64_t j = j0; j < j1 && kp; ++j) {
-            if (j == i) continue;
-            const Cand a = cand[j];
-            const bool dom = a.k > b.k || (a.k == b.k && (a.y < b.y || (a.y == b.y && a.x < b.x)));
-            if (!dom) continue;
-            const double ra = kSqrt2 * static_cast<double>(sigmas[a.k]);
-            const double dy = static_cast<double>(a.y - b.y), dx = static_cast<double>(a.x - b.x);
-            if (fabs(dx) >= ra + rb) continue;  // disjoint discs (overlap 0)
-            if (disc_overlap(dy, dx, ra, rb) > theta) kp = 0;
+        const int ylo = max(0, b.y - reach), yhi = min(H - 1, b.y + reach);
+        for (int yy = ylo; yy <= yhi && kp; ++yy) {
+            const long long dy = yy - b.y;
+            const int xr = static_cast<int>(sqrt(static_cast<double>(r2 - dy * dy)));
+            int lo = blk_off[yy * bpr];
+            const int hi = min(static_cast<int64_t>(blk_off[(yy + 1) * bpr]), n);
+            // first candidate of the row with x >= b.x - xr
+            int top = hi;
+            while (lo < top) {
+                const int mid = (lo + top) >> 1;
+                if (cand[mid].x < b.x - xr)
+                    lo = mid + 1;
+                else
+                    top = mid;
+            }
+            for (int j = lo; j < hi; ++j) {
+                const Cand a = cand[j];
+                if (a.x > b.x + xr) break;
+                const bool dom =
+                    a.k > b.k || (a.k == b.k && (a.y < b.y || (a.y == b.y && a.x < b.x)));
+                const long long dx = a.x - b.x;
+                if (dom && dy * dy + dx * dx <= dcol[a.k * K]) {
+                    kp = 0;
+                    break;
+                }
+            }
         }
         keep[i] = kp;
     }
@@ -291,25 +429,26 @@ __global__ void emit_kernel(const Cand* __restrict__ cand, const int32_t* __rest
 
 int nms_blocks_per_row(int w) { return (w + NMS_T - 1) / NMS_T; }
 
+size_t nms_pool_records(int n_blk, int64_t cap) { return static_cast<size_t>(n_blk) * SLOT + cap; }
+
+size_t scan_sums_ints(int64_t n) { return static_cast<size_t>((n + SCAN_SPAN - 1) / SCAN_SPAN + 1); }
+
 hipError_t launch_detect_tail(const DetectWorkspace& ws, int K, int h, int w, float tau,
-                              float overlap, int reach, const float* sigmas_dev, mhfd_blob* blobs,
-                              int capacity, mhfd_result* result, hipStream_t s) {
+                              const int32_t* d2max, int reach, const float* sigmas_dev,
+                              mhfd_blob* blobs, int capacity, mhfd_result* result, hipStream_t s) {
     init_counters_kernel<<<1, 64, 0, s>>>(ws.ctr);
-    nms_kernel<<<ws.n_blk, NMS_T, 0, s>>>(ws.stack, K, h, w, tau, ws.blk_per_row, ws.blk_n,
-                                          ws.blk_o, ws.pool, ws.cap, ws.ctr);
-    scan_kernel<<<1, SCAN_T, 0, s>>>(ws.blk_n, ws.n_blk, nullptr, ws.blk_off, &ws.ctr->n_cand);
+    launch_nms(K, ws, h, w, tau, s, std::make_integer_sequence<int, MHFD_MAX_SCALES>{});
+    launch_scan(ws.blk_n, ws.n_blk, nullptr, ws.scan_sums, ws.blk_off, &ws.ctr->n_cand, s);
     const int grid = 1024;
     order_kernel<<<grid, 256, 0, s>>>(ws.blk_off, ws.blk_o, ws.n_blk, ws.pool, ws.cand, ws.cap,
                                       ws.ctr);
-    if (overlap < 1.0f) {
-        prune_kernel<<<grid, 256, 0, s>>>(ws.cand, ws.blk_off, ws.blk_per_row, h, sigmas_dev,
-                                          reach, static_cast<double>(overlap), ws.keep, ws.cap,
-                                          ws.ctr);
-    } else {
+    if (d2max)
+        prune_kernel<<<grid, 256, 0, s>>>(ws.cand, ws.blk_off, ws.blk_per_row, h, K, d2max, reach,
+                                          ws.keep, ws.cap, ws.ctr);
+    else
         keep_all_kernel<<<grid, 256, 0, s>>>(ws.keep, ws.cap, ws.ctr);
-    }
-    scan_kernel<<<1, SCAN_T, 0, s>>>(ws.keep, static_cast<int>(ws.cap), &ws.ctr->n_cand,
-                                     ws.keep_off, &ws.ctr->n_blobs);
+    launch_scan(ws.keep, static_cast<int>(ws.cap), &ws.ctr->n_cand, ws.scan_sums, ws.keep_off,
+                &ws.ctr->n_blobs, s);
     emit_kernel<<<grid, 256, 0, s>>>(ws.cand, ws.keep, ws.keep_off, sigmas_dev, blobs, capacity,
                                      ws.cap, ws.ctr, result);
     return hipGetLastError();

@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -22,8 +23,9 @@ struct mhfd_plan_s {
     int polarity = MHFD_BRIGHT, dtype = MHFD_F32;
     int max_h = 0, max_w = 0;
     int64_t max_cand = 0;
-    int reach = 0;               // floor(2 sqrt(2) sigma_max): prune row reach
+    int reach = 0;               // prune row reach, floor(sqrt(max d2max))
     float* d_taps = nullptr;     // device tap table
+    int32_t* d_d2max = nullptr;  // K x K prune table (null: pruning off)
     float* d_sigmas = nullptr;   // device copy of sigmas (float)
     size_t tap_floats = 0;
 };
@@ -87,8 +89,38 @@ void synth_taps(double sigma, int R, int P, int polarity, float* dst) {
     }
 }
 
+// Fraction of the smaller disc covered by the intersection of two discs whose
+// centres are d apart (lens area over pi min(ra, rb)^2).
+double disc_overlap(double d, double ra, double rb) {
+    if (d >= ra + rb) return 0.0;
+    if (d <= fabs(ra - rb)) return 1.0;
+    const double rs = ra < rb ? ra : rb;
+    const double ca = (d * d + ra * ra - rb * rb) / (2.0 * d * ra);
+    const double cb = (d * d + rb * rb - ra * ra) / (2.0 * d * rb);
+    const double lens = ra * ra * acos(ca) + rb * rb * acos(cb) -
+                        0.5 * sqrt((-d + ra + rb) * (d + ra - rb) * (d - ra + rb) * (d + ra + rb));
+    return lens / (M_PI * rs * rs);
+}
+
+// Largest integer D with overlap(sqrt(D)) > theta for blob radii ra, rb, or -1.
+// The overlap falls monotonically as the centres move apart, so the decision
+// for integer coordinates is exactly dy^2 + dx^2 <= D.
+int max_overlapping_d2(double ra, double rb, double theta) {
+    if (!(disc_overlap(0.0, ra, rb) > theta)) return -1;
+    long lo = 0;                                             // overlap > theta
+    long hi = static_cast<long>(ceil((ra + rb) * (ra + rb))) + 1;  // overlap == 0
+    while (hi - lo > 1) {
+        const long mid = (lo + hi) / 2;
+        if (disc_overlap(sqrt(static_cast<double>(mid)), ra, rb) > theta)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return static_cast<int>(lo);
+}
+
 struct DetectLayout {
-    size_t stack, blk_n, blk_o, blk_off, pool, cand, keep, keep_off, ctr, total;
+    size_t stack, blk_n, blk_o, blk_off, pool, cand, keep, keep_off, scan_sums, ctr, total;
     int n_blk, bpr;
 };
 
@@ -107,10 +139,12 @@ DetectLayout detect_layout(const mhfd_plan_s* p, int h, int w) {
     L.blk_n = take(sizeof(int32_t) * L.n_blk);
     L.blk_o = take(sizeof(int32_t) * L.n_blk);
     L.blk_off = take(sizeof(int32_t) * (L.n_blk + 1));
-    L.pool = take(sizeof(mhfd::Cand) * cap);
+    L.pool = take(sizeof(mhfd::Cand) * mhfd::nms_pool_records(L.n_blk, p->max_cand));
     L.cand = take(sizeof(mhfd::Cand) * cap);
     L.keep = take(sizeof(int32_t) * cap);
     L.keep_off = take(sizeof(int32_t) * (cap + 1));
+    const int64_t longest = static_cast<int64_t>(cap) > L.n_blk ? static_cast<int64_t>(cap) : L.n_blk;
+    L.scan_sums = take(sizeof(int32_t) * mhfd::scan_sums_ints(longest));
     L.ctr = take(sizeof(mhfd::DetectCounters));
     L.total = off;
     return L;
@@ -216,7 +250,20 @@ mhfd_status mhfd_create_plan(const mhfd_config* cfg, mhfd_plan* out) {
         off += mhfd::tap_block_floats(P);
     }
     p->tap_floats = off;
-    p->reach = static_cast<int>(floor(2.0 * 1.4142135623730951 * sig[K - 1]));
+    // Blob radius sqrt(2) sigma; prune table in double.
+    std::vector<int32_t> d2(static_cast<size_t>(K) * K, -1);
+    int d2_top = 0;
+    const bool prune = p->overlap < 1.0f;
+    if (prune) {
+        const double sq2 = sqrt(2.0);
+        for (int a = 0; a < K; ++a)
+            for (int b = 0; b < K; ++b) {
+                d2[a * K + b] = max_overlapping_d2(sq2 * sig[a], sq2 * sig[b],
+                                                   static_cast<double>(p->overlap));
+                if (d2[a * K + b] > d2_top) d2_top = d2[a * K + b];
+            }
+    }
+    p->reach = static_cast<int>(floor(sqrt(static_cast<double>(d2_top))));
     std::vector<float> host(off, 0.0f);
     for (int k = 0; k < K; ++k)
         synth_taps(static_cast<double>(sig[k]), p->radii[k], p->padded[k], p->polarity,
@@ -229,17 +276,23 @@ mhfd_status mhfd_create_plan(const mhfd_config* cfg, mhfd_plan* out) {
     }
     e = hipMalloc(reinterpret_cast<void**>(&p->d_taps), sizeof(float) * off);
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->d_sigmas), sizeof(float) * K);
+    if (e == hipSuccess && prune)
+        e = hipMalloc(reinterpret_cast<void**>(&p->d_d2max), sizeof(int32_t) * K * K);
     if (e != hipSuccess) {
         hipFree(p->d_taps);
+        hipFree(p->d_sigmas);
         delete p;
         return fail(MHFD_ERR_OOM, "plan tables: %s", hipGetErrorString(e));
     }
     e = hipMemcpy(p->d_taps, host.data(), sizeof(float) * off, hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(p->d_sigmas, sig.data(), sizeof(float) * K, hipMemcpyHostToDevice);
+    if (e == hipSuccess && prune)
+        e = hipMemcpy(p->d_d2max, d2.data(), sizeof(int32_t) * K * K, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         hipFree(p->d_taps);
         hipFree(p->d_sigmas);
+        hipFree(p->d_d2max);
         delete p;
         return hip_fail(e, "copy of the plan tables");
     }
@@ -251,6 +304,7 @@ mhfd_status mhfd_destroy_plan(mhfd_plan p) {
     if (!p) return MHFD_OK;
     hipFree(p->d_taps);
     hipFree(p->d_sigmas);
+    hipFree(p->d_d2max);
     delete p;
     return MHFD_OK;
 }
@@ -303,13 +357,35 @@ mhfd_status check_outputs(const mhfd_plan_s* p, int32_t h, int32_t w, const mhfd
 
 mhfd_status enqueue_log_stack(const mhfd_plan_s* p, const void* d_img, int h, int w,
                               int64_t pitch, float* stack, hipStream_t s) {
+    const int tw = mhfd::log_strip_width();
     const int seg = strip_segment_rows(h, w);
-    const size_t plane = static_cast<size_t>(h) * w;
-    for (int k = 0; k < p->K; ++k) {
-        hipError_t e = mhfd::launch_log_scale(p->padded[k], p->dtype, d_img, h, w, pitch,
-                                              p->d_taps + p->tap_off[k], stack + k * plane, w, seg,
-                                              s);
-        if (e != hipSuccess) return hip_fail(e, "LoG strip launch");
+    const int strips = (w + tw - 1) / tw;
+    const int segs = (h + seg - 1) / seg;
+    for (int cls = 2; cls >= 0; --cls) {
+        mhfd::StackLaunch L{};
+        L.strips = strips;
+        L.seg_rows = seg;
+        // scales of this class, largest radius first
+        std::vector<int> ks;
+        for (int k = 0; k < p->K; ++k)
+            if (mhfd::log_radius_class(p->padded[k]) == cls) ks.push_back(k);
+        std::sort(ks.begin(), ks.end(), [&](int a, int b) {
+            return p->padded[a] != p->padded[b] ? p->padded[a] > p->padded[b] : a < b;
+        });
+        int begin = 0;
+        for (int k : ks) {
+            mhfd::StackScale& sc = L.sc[L.n++];
+            sc.radius = p->padded[k];
+            sc.tap_off = p->tap_off[k];
+            sc.plane = k;
+            sc.block_begin = begin;
+            sc.n_blocks = strips * segs;
+            begin += sc.n_blocks;
+        }
+        if (L.n == 0) continue;
+        hipError_t e = mhfd::launch_log_class(cls, p->dtype, d_img, h, w, pitch, p->d_taps, stack,
+                                              L, s);
+        if (e != hipSuccess) return hip_fail(e, "LoG stack launch");
     }
     return MHFD_OK;
 }
@@ -326,11 +402,12 @@ mhfd_status enqueue_tail(const mhfd_plan_s* p, const float* stack, int h, int w,
     ws.cand = reinterpret_cast<mhfd::Cand*>(base + L.cand);
     ws.keep = reinterpret_cast<int32_t*>(base + L.keep);
     ws.keep_off = reinterpret_cast<int32_t*>(base + L.keep_off);
+    ws.scan_sums = reinterpret_cast<int32_t*>(base + L.scan_sums);
     ws.ctr = reinterpret_cast<mhfd::DetectCounters*>(base + L.ctr);
     ws.cap = p->max_cand;
     ws.n_blk = L.n_blk;
     ws.blk_per_row = L.bpr;
-    hipError_t e = mhfd::launch_detect_tail(ws, p->K, h, w, p->threshold, p->overlap, p->reach,
+    hipError_t e = mhfd::launch_detect_tail(ws, p->K, h, w, p->threshold, p->d_d2max, p->reach,
                                             p->d_sigmas, d_blobs, capacity, d_result, s);
     if (e != hipSuccess) return hip_fail(e, "detection launch");
     return MHFD_OK;

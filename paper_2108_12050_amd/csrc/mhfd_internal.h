@@ -45,11 +45,33 @@ struct DetectCounters {
     int32_t n_blobs;     // total blobs after pruning
 };
 
-// Launch the LoG strip kernel for one scale: writes R_k (h x w, pitch
-// out_pitch) from the image.  `padded` selects the instantiation.
-hipError_t launch_log_scale(int padded, int in_dtype, const void* img, int h, int w, int64_t pitch,
-                            const float* taps, float* out, int64_t out_pitch, int seg_rows,
-                            hipStream_t s);
+// One scale inside a LoG stack launch.
+struct StackScale {
+    int radius;       // padded radius (multiple of 4)
+    int tap_off;      // float offset of the scale's tap block
+    int plane;        // output plane index k
+    int block_begin;  // first workgroup of the scale in the launch
+    int n_blocks;     // strips * segments
+};
+
+// All scales of one radius class, in launch order (largest radius first).
+struct StackLaunch {
+    int n;
+    int strips;       // strips of log_strip_width() columns
+    int seg_rows;     // rows per workgroup segment (multiple of log_chunk_rows())
+    int pad;
+    StackScale sc[MHFD_MAX_SCALES];
+};
+
+// Radius class of a padded radius: 0 (<= 16), 1 (<= 40), 2 (<= 64).
+int log_radius_class(int padded);
+int log_strip_width();
+int log_chunk_rows();
+
+// Enqueue the LoG stack of every scale in L (all of class `cls`) into
+// `stack` (K planes of h x w floats).
+hipError_t launch_log_class(int cls, int in_dtype, const void* img, int h, int w, int64_t pitch,
+                            const float* taps, float* stack, const StackLaunch& L, hipStream_t s);
 
 // Detection tail: stack -> candidates -> canonical order -> prune -> blobs.
 struct DetectWorkspace {
@@ -57,21 +79,30 @@ struct DetectWorkspace {
     int32_t* blk_n;          // per NMS block: candidate count
     int32_t* blk_o;          // per NMS block: offset in the pool
     int32_t* blk_off;        // per NMS block: exclusive scan of blk_n (n_blk + 1)
-    Cand* pool;              // unordered candidate records
+    Cand* pool;              // unordered records: per-workgroup slots, then overflow
     Cand* cand;              // candidates in canonical order
     int32_t* keep;           // keep flag per candidate
     int32_t* keep_off;       // exclusive scan of keep (cap + 1)
+    int32_t* scan_sums;      // span sums of the scans (scan_sums_ints of the longer input)
     DetectCounters* ctr;
     int64_t cap;             // candidate capacity
     int n_blk;               // number of NMS blocks
     int blk_per_row;         // NMS blocks per image row
 };
 
-// `reach`: rows farther apart than this cannot hold overlapping blobs
-// (floor(2 sqrt(2) sigma_max)).
+// d2max: K x K table, d2max[ka * K + kb] = largest squared integer distance at
+// which blobs of scales ka and kb overlap by more than the plan's threshold
+// (-1: never); null disables pruning.  `reach` = floor(sqrt(max d2max)).
 hipError_t launch_detect_tail(const DetectWorkspace& ws, int K, int h, int w, float tau,
-                              float overlap, int reach, const float* sigmas_dev, mhfd_blob* blobs,
-                              int capacity, mhfd_result* result, hipStream_t s);
+                              const int32_t* d2max, int reach, const float* sigmas_dev,
+                              mhfd_blob* blobs, int capacity, mhfd_result* result, hipStream_t s);
+
+// Records of the unordered candidate pool: a fixed slot per NMS workgroup
+// plus a shared overflow region of `cap` records.
+size_t nms_pool_records(int n_blk, int64_t cap);
+
+// Ints of span-sum scratch a scan over n items needs.
+size_t scan_sums_ints(int64_t n);
 
 int nms_blocks_per_row(int w);
 
