@@ -8,7 +8,7 @@ from ._lib import MHFDError, MHFDLibraryError  # noqa: F401
 
 
 def __getattr__(name):
-    if name in ("Plan", "Detection", "split_blobs"):
+    if name in ("Plan", "Detection", "split_blobs", "FocusScore", "focus_score"):
         from . import api
         return getattr(api, name)
     raise AttributeError(name)

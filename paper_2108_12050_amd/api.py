@@ -174,3 +174,81 @@ class Plan:
         d = Detection(yxk, sig, resp, n_blobs, n_cand, flags, stack)
         d._density = n_blobs * 1e6 / (h * w)
         return d
+
+    # ---------------------------------------------------------------- soft score
+    def focus_workspace_bytes(self, b: int, h: int, w: int) -> int:
+        n = int(self._L.mhfd_focus_workspace_size(self._handle, int(b), int(h), int(w)))
+        if n == 0:
+            raise _lib.MHFDError(1, "mhfd_focus_workspace_size",
+                                 f"batch {b} x {h} x {w} is empty or exceeds the plan's "
+                                 f"{self.max_h} x {self.max_w}")
+        return n
+
+    def _check_soft(self, imgs: torch.Tensor, sigmas: torch.Tensor):
+        if imgs.dim() == 2:
+            imgs = imgs.unsqueeze(0)
+        if imgs.dim() != 3 or imgs.dtype != torch.float32 or imgs.device != self.device:
+            raise ValueError(f"images must be float32 [B, H, W] on {self.device}")
+        if sigmas.dtype != torch.float32 or sigmas.numel() != self.K or sigmas.device != self.device:
+            raise ValueError(f"sigmas must be float32 [{self.K}] on {self.device}")
+        return imgs.contiguous(), sigmas.contiguous()
+
+    def focus_score(self, imgs: torch.Tensor, sigmas: torch.Tensor, beta: float = 50.0,
+                    tau: float = 0.05, stream=None) -> torch.Tensor:
+        """S_b (float32 [B]) for device images [B, H, W]; no synchronisation."""
+        imgs, sigmas = self._check_soft(imgs, sigmas)
+        B, h, w = imgs.shape
+        ws = self._workspace(("focus", B, h, w), self.focus_workspace_bytes(B, h, w))
+        out = torch.empty(B, dtype=torch.float32, device=self.device)
+        st = self._L.mhfd_focus_score(self._handle, _ptr(imgs), B, h, w, _ptr(sigmas),
+                                      float(beta), float(tau), _ptr(out), _ptr(ws), ws.numel(),
+                                      _stream_ptr(stream))
+        _lib.check(st, "mhfd_focus_score")
+        return out
+
+    def focus_score_backward(self, imgs: torch.Tensor, sigmas: torch.Tensor,
+                             grad_scores: torch.Tensor, beta: float = 50.0, tau: float = 0.05,
+                             stream=None):
+        """(dS/dI, dS/dsigma) contracted with grad_scores [B]; no synchronisation."""
+        imgs, sigmas = self._check_soft(imgs, sigmas)
+        B, h, w = imgs.shape
+        g = grad_scores.to(device=self.device, dtype=torch.float32).contiguous().reshape(B)
+        ws = self._workspace(("focus", B, h, w), self.focus_workspace_bytes(B, h, w))
+        dI = torch.empty_like(imgs)
+        ds = torch.empty(self.K, dtype=torch.float32, device=self.device)
+        st = self._L.mhfd_focus_score_backward(self._handle, _ptr(imgs), B, h, w, _ptr(sigmas),
+                                               float(beta), float(tau), _ptr(g), _ptr(dI),
+                                               _ptr(ds), _ptr(ws), ws.numel(),
+                                               _stream_ptr(stream))
+        _lib.check(st, "mhfd_focus_score_backward")
+        return dI, ds
+
+
+class FocusScore(torch.autograd.Function):
+    """Differentiable soft focus score.  Forward and backward are the HIP
+    kernels behind mhfd_focus_score / mhfd_focus_score_backward; the backward
+    recomputes the per-scale responses instead of keeping a stack."""
+
+    @staticmethod
+    def forward(ctx, imgs, sigmas, plan, beta, tau):
+        ctx.plan, ctx.beta, ctx.tau = plan, beta, tau
+        ctx.squeeze = imgs.dim() == 2
+        ctx.save_for_backward(imgs, sigmas)
+        return plan.focus_score(imgs.detach(), sigmas.detach(), beta, tau)
+
+    @staticmethod
+    def backward(ctx, grad):
+        imgs, sigmas = ctx.saved_tensors
+        dI, ds = ctx.plan.focus_score_backward(imgs.detach(), sigmas.detach(), grad, ctx.beta,
+                                               ctx.tau)
+        if ctx.squeeze:
+            dI = dI[0]
+        return (dI if ctx.needs_input_grad[0] else None,
+                ds if ctx.needs_input_grad[1] else None, None, None, None)
+
+
+def focus_score(imgs: torch.Tensor, sigmas: torch.Tensor, plan: Plan, beta: float = 50.0,
+                tau: float = 0.05) -> torch.Tensor:
+    """S_b = mean over scales and pixels of softplus(beta (|sigma^2 Lap(G_sigma * I)| - tau)),
+    differentiable in the images and the sigmas (radii frozen at the plan's)."""
+    return FocusScore.apply(imgs, sigmas, plan, float(beta), float(tau))

@@ -61,12 +61,28 @@ __device__ __forceinline__ const float* tap_block(const float* __restrict__ taps
 __device__ __forceinline__ float to_float(float v) { return v; }
 __device__ __forceinline__ float to_float(uint8_t v) { return static_cast<float>(v) / 255.0f; }
 
-template <int R, typename T>
+__device__ __forceinline__ float softplusf(float z) { return fmaxf(z, 0.0f) + log1pf(expf(-fabsf(z))); }
+
+// Block sum of one double per thread (fixed tree order); smem must hold NT doubles.
+__device__ __forceinline__ double block_sum(double v, double* smem) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_down(v, d, 64);
+    if ((threadIdx.x & 63) == 0) smem[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int i = 0; i < NT / 64; ++i) t += smem[i];
+    return t;  // valid in thread 0
+}
+
+template <int R, int EPI, typename T>
 __device__ __forceinline__ void log_strip_body(float* __restrict__ smem, const T* __restrict__ img,
                                                int H, int W, long long pitch,
                                                const float* __restrict__ taps,
                                                float* __restrict__ out, long long out_pitch,
-                                               int x0, int ys, int ye) {
+                                               int x0, int ys, int ye, float beta, float tau,
+                                               double* __restrict__ partial) {
     constexpr int NB = TW + 2 * R;            // staged input columns
     constexpr int S = CH + 2 * R;             // ring rows
     constexpr int P = (2 * R + CH - 1) / CH;  // prologue chunks (rows ys - R .. ys + R)
@@ -161,6 +177,8 @@ __device__ __forceinline__ void log_strip_body(float* __restrict__ smem, const T
         }
     };
 
+    float tsum = 0.0f;  // softplus sum of this thread's outputs (EPI_SOFTSUM)
+
     // Output rows [yc, yc + CH): wave w owns rows yc + 8w .. yc + 8w + 7, lane = column.
     // Two half passes, h (*)_y A then g (*)_y B, so only one 8 + 2R window of
     // ring values is live in registers at a time.
@@ -205,7 +223,12 @@ __device__ __forceinline__ void log_strip_body(float* __restrict__ smem, const T
 #pragma unroll
             for (int q = 0; q < QY; ++q) {
                 const int y = yc + q0 + q;
-                if (y < ye) out[static_cast<long long>(y) * out_pitch + x] = acc[q];
+                if (y < ye) {
+                    float* o = out + static_cast<long long>(y) * out_pitch + x;
+                    if constexpr (EPI == EPI_STORE) *o = acc[q];
+                    if constexpr (EPI == EPI_ACCUM) *o += acc[q];
+                    if constexpr (EPI == EPI_SOFTSUM) tsum += softplusf(beta * (fabsf(acc[q]) - tau));
+                }
             }
         }
     };
@@ -220,16 +243,20 @@ __device__ __forceinline__ void log_strip_body(float* __restrict__ smem, const T
         __syncthreads();
         if (m >= P) colpass(ys + (m - P) * CH);
     }
+    if constexpr (EPI == EPI_SOFTSUM) {
+        __syncthreads();  // smem is reused for the reduction
+        const double t = block_sum(static_cast<double>(tsum), reinterpret_cast<double*>(smem));
+        if (threadIdx.x == 0) *partial = t;
+    }
 }
 
 // Radius classes share a kernel: registers are allocated for the largest
-// radius of the class, so small radii do not pay for large ones.
-template <int RLO, int RHI, typename T>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void log_stack_kernel(const T* __restrict__ img, int H, int W,
-                                                       long long pitch,
-                                                       const float* __restrict__ taps,
-                                                       float* __restrict__ stack,
-                                                       StackLaunch L) {
+// radius of the class, so small radii do not pay for large ones.  blockIdx.y
+// is the image of a batch.
+template <int RLO, int RHI, int EPI, typename T>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void log_stack_kernel(const T* __restrict__ img, int H, int W, long long pitch,
+                      const float* __restrict__ taps, StackLaunch L, StackIO io) {
     extern __shared__ __attribute__((aligned(16))) float smem[];
     const int b = blockIdx.x;
     int i = 0;
@@ -241,13 +268,20 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     const int x0 = strip * TW;
     const int ys = seg * L.seg_rows;
     const int ye = min(ys + L.seg_rows, H);
-    float* out = stack + static_cast<long long>(sc.plane) * H * W;
+    const int bi = blockIdx.y;
+    const T* im = img + static_cast<long long>(bi) * io.img_batch;
+    float* out = io.out ? io.out + static_cast<long long>(bi) * io.out_batch +
+                              static_cast<long long>(sc.plane) * io.plane_stride
+                        : nullptr;
+    double* part = io.partial ? io.partial + static_cast<long long>(bi) * io.total_blocks + b
+                              : nullptr;
     const float* tp = taps + sc.tap_off;
     switch (sc.radius) {
-#define MHFD_BODY(R)                                                              \
-    case R:                                                                       \
-        if constexpr (R >= RLO && R <= RHI)                                       \
-            log_strip_body<R, T>(smem, img, H, W, pitch, tp, out, W, x0, ys, ye); \
+#define MHFD_BODY(R)                                                                       \
+    case R:                                                                                \
+        if constexpr (R >= RLO && R <= RHI)                                                \
+            log_strip_body<R, EPI, T>(smem, im, H, W, pitch, tp, out, W, x0, ys, ye,      \
+                                      io.beta, io.tau, part);                              \
         break;
         MHFD_BODY(4)
         MHFD_BODY(8)
@@ -271,28 +305,37 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     }
 }
 
-template <int RLO, int RHI, typename T>
-hipError_t launch_typed(const T* img, int h, int w, int64_t pitch, const float* taps,
-                        float* stack, const StackLaunch& L, int blocks, size_t lds,
+template <int RLO, int RHI, int EPI, typename T>
+hipError_t launch_typed(const T* img, int h, int w, int64_t pitch, int batch, const float* taps,
+                        const StackLaunch& L, const StackIO& io, int blocks, size_t lds,
                         hipStream_t s) {
-    auto k = log_stack_kernel<RLO, RHI, T>;
+    auto k = log_stack_kernel<RLO, RHI, EPI, T>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        static_cast<int>(lds));
     if (e != hipSuccess) return e;
-    k<<<blocks, NT, lds, s>>>(img, h, w, pitch, taps, stack, L);
+    k<<<dim3(blocks, batch), NT, lds, s>>>(img, h, w, pitch, taps, L, io);
     return hipGetLastError();
 }
 
 template <int RLO, int RHI>
-hipError_t launch_range(int in_dtype, const void* img, int h, int w, int64_t pitch,
-                        const float* taps, float* stack, const StackLaunch& L, int blocks,
-                        size_t lds, hipStream_t s) {
-    if (in_dtype == MHFD_U8)
-        return launch_typed<RLO, RHI, uint8_t>(static_cast<const uint8_t*>(img), h, w, pitch,
-                                               taps, stack, L, blocks, lds, s);
-    return launch_typed<RLO, RHI, float>(static_cast<const float*>(img), h, w, pitch, taps,
-                                         stack, L, blocks, lds, s);
+hipError_t launch_range(int in_dtype, int epi, const void* img, int h, int w, int64_t pitch,
+                        int batch, const float* taps, const StackLaunch& L, const StackIO& io,
+                        int blocks, size_t lds, hipStream_t s) {
+    if (in_dtype == MHFD_U8) {
+        if (epi != EPI_STORE) return hipErrorInvalidValue;
+        return launch_typed<RLO, RHI, EPI_STORE, uint8_t>(static_cast<const uint8_t*>(img), h, w,
+                                                          pitch, batch, taps, L, io, blocks, lds, s);
+    }
+    const float* f = static_cast<const float*>(img);
+    if (epi == EPI_STORE)
+        return launch_typed<RLO, RHI, EPI_STORE, float>(f, h, w, pitch, batch, taps, L, io, blocks,
+                                                        lds, s);
+    if (epi == EPI_ACCUM)
+        return launch_typed<RLO, RHI, EPI_ACCUM, float>(f, h, w, pitch, batch, taps, L, io, blocks,
+                                                        lds, s);
+    return launch_typed<RLO, RHI, EPI_SOFTSUM, float>(f, h, w, pitch, batch, taps, L, io, blocks,
+                                                      lds, s);
 }
 
 }  // namespace
@@ -303,18 +346,25 @@ int log_strip_width() { return TW; }
 
 int log_chunk_rows() { return CH; }
 
-hipError_t launch_log_class(int cls, int in_dtype, const void* img, int h, int w, int64_t pitch,
-                            const float* taps, float* stack, const StackLaunch& L, hipStream_t s) {
+hipError_t launch_log_class(int cls, int in_dtype, int epi, const void* img, int h, int w,
+                            int64_t pitch, int batch, const float* taps, const StackLaunch& L,
+                            const StackIO& io, hipStream_t s) {
     int blocks = 0, rmax = 0;
     for (int i = 0; i < L.n; ++i) {
         blocks += L.sc[i].n_blocks;
         rmax = L.sc[i].radius > rmax ? L.sc[i].radius : rmax;
     }
-    if (blocks == 0) return hipSuccess;
-    const size_t lds = sizeof(float) * static_cast<size_t>(lds_floats(rmax));
-    if (cls == 0) return launch_range<4, 16>(in_dtype, img, h, w, pitch, taps, stack, L, blocks, lds, s);
-    if (cls == 1) return launch_range<20, 40>(in_dtype, img, h, w, pitch, taps, stack, L, blocks, lds, s);
-    return launch_range<44, 64>(in_dtype, img, h, w, pitch, taps, stack, L, blocks, lds, s);
+    if (blocks == 0 || batch == 0) return hipSuccess;
+    size_t lds = sizeof(float) * static_cast<size_t>(lds_floats(rmax));
+    if (lds < sizeof(double) * NT) lds = sizeof(double) * NT;
+    if (cls == 0)
+        return launch_range<4, 16>(in_dtype, epi, img, h, w, pitch, batch, taps, L, io, blocks,
+                                   lds, s);
+    if (cls == 1)
+        return launch_range<20, 40>(in_dtype, epi, img, h, w, pitch, batch, taps, L, io, blocks,
+                                    lds, s);
+    return launch_range<44, 64>(in_dtype, epi, img, h, w, pitch, batch, taps, L, io, blocks, lds,
+                                s);
 }
 
 }  // namespace mhfd

@@ -355,19 +355,23 @@ mhfd_status check_outputs(const mhfd_plan_s* p, int32_t h, int32_t w, const mhfd
     return MHFD_OK;
 }
 
-mhfd_status enqueue_log_stack(const mhfd_plan_s* p, const void* d_img, int h, int w,
-                              int64_t pitch, float* stack, hipStream_t s) {
+// Per radius class, the launch covering `scales` (largest radius first):
+// tap_off(k) gives the tap block of scale k, plane(k) its output plane.
+template <typename TapOff, typename Plane>
+std::vector<std::pair<int, mhfd::StackLaunch>> make_launches(const mhfd_plan_s* p, int h, int w,
+                                                             const std::vector<int>& scales,
+                                                             TapOff tap_off, Plane plane) {
     const int tw = mhfd::log_strip_width();
     const int seg = strip_segment_rows(h, w);
     const int strips = (w + tw - 1) / tw;
     const int segs = (h + seg - 1) / seg;
+    std::vector<std::pair<int, mhfd::StackLaunch>> out;
     for (int cls = 2; cls >= 0; --cls) {
         mhfd::StackLaunch L{};
         L.strips = strips;
         L.seg_rows = seg;
-        // scales of this class, largest radius first
         std::vector<int> ks;
-        for (int k = 0; k < p->K; ++k)
+        for (int k : scales)
             if (mhfd::log_radius_class(p->padded[k]) == cls) ks.push_back(k);
         std::sort(ks.begin(), ks.end(), [&](int a, int b) {
             return p->padded[a] != p->padded[b] ? p->padded[a] > p->padded[b] : a < b;
@@ -376,15 +380,39 @@ mhfd_status enqueue_log_stack(const mhfd_plan_s* p, const void* d_img, int h, in
         for (int k : ks) {
             mhfd::StackScale& sc = L.sc[L.n++];
             sc.radius = p->padded[k];
-            sc.tap_off = p->tap_off[k];
-            sc.plane = k;
+            sc.tap_off = tap_off(k);
+            sc.plane = plane(k);
             sc.block_begin = begin;
             sc.n_blocks = strips * segs;
             begin += sc.n_blocks;
         }
-        if (L.n == 0) continue;
-        hipError_t e = mhfd::launch_log_class(cls, p->dtype, d_img, h, w, pitch, p->d_taps, stack,
-                                              L, s);
+        if (L.n) out.emplace_back(cls, L);
+    }
+    return out;
+}
+
+int launch_blocks(const mhfd::StackLaunch& L) {
+    int n = 0;
+    for (int i = 0; i < L.n; ++i) n += L.sc[i].n_blocks;
+    return n;
+}
+
+std::vector<int> all_scales(const mhfd_plan_s* p) {
+    std::vector<int> v(p->K);
+    for (int k = 0; k < p->K; ++k) v[k] = k;
+    return v;
+}
+
+mhfd_status enqueue_log_stack(const mhfd_plan_s* p, const void* d_img, int h, int w,
+                              int64_t pitch, float* stack, hipStream_t s) {
+    auto launches = make_launches(
+        p, h, w, all_scales(p), [&](int k) { return p->tap_off[k]; }, [](int k) { return k; });
+    mhfd::StackIO io{};
+    io.out = stack;
+    io.plane_stride = static_cast<long long>(h) * w;
+    for (auto& cl : launches) {
+        hipError_t e = mhfd::launch_log_class(cl.first, p->dtype, mhfd::EPI_STORE, d_img, h, w,
+                                              pitch, 1, p->d_taps, cl.second, io, s);
         if (e != hipSuccess) return hip_fail(e, "LoG stack launch");
     }
     return MHFD_OK;
@@ -410,6 +438,60 @@ mhfd_status enqueue_tail(const mhfd_plan_s* p, const float* stack, int h, int w,
     hipError_t e = mhfd::launch_detect_tail(ws, p->K, h, w, p->threshold, p->d_d2max, p->reach,
                                             p->d_sigmas, d_blobs, capacity, d_result, s);
     if (e != hipSuccess) return hip_fail(e, "detection launch");
+    return MHFD_OK;
+}
+
+struct FocusLayout {
+    size_t taps, partial, rplane, dplane, cot, total;
+    mhfd::SoftTapLayout lay;
+    int fwd_blocks;  // workgroups per image over every class launch
+};
+
+FocusLayout focus_layout(const mhfd_plan_s* p, int b, int h, int w) {
+    FocusLayout F{};
+    F.lay.K = p->K;
+    int off = 0;
+    for (int k = 0; k < p->K; ++k) {
+        F.lay.radius[k] = p->radii[k];
+        F.lay.padded[k] = p->padded[k];
+        F.lay.offset[k] = off;
+        off += mhfd::SOFT_SETS * 4 * (p->padded[k] + 1);
+    }
+    auto launches = make_launches(
+        p, h, w, all_scales(p), [](int) { return 0; }, [](int k) { return k; });
+    F.fwd_blocks = 0;
+    for (auto& cl : launches) F.fwd_blocks += launch_blocks(cl.second);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t r = o;
+        o = align_up(o + bytes);
+        return r;
+    };
+    F.taps = take(sizeof(float) * off);
+    F.partial = take(sizeof(double) * static_cast<size_t>(F.fwd_blocks) * b);
+    F.rplane = take(sizeof(float) * static_cast<size_t>(b) * h * w);
+    F.dplane = take(sizeof(float) * static_cast<size_t>(b) * h * w);
+    F.cot = take(sizeof(double) * static_cast<size_t>(p->K) * mhfd::soft_cotangent_blocks());
+    F.total = o;
+    return F;
+}
+
+mhfd_status check_focus(const mhfd_plan_s* p, const float* d_imgs, int b, int h, int w,
+                        const float* d_sigmas, float beta, float tau, const void* d_ws,
+                        size_t ws_bytes) {
+    if (!p) return fail(MHFD_ERR_INVALID_ARG, "null plan");
+    if (!d_imgs || !d_sigmas || !d_ws) return fail(MHFD_ERR_INVALID_ARG, "null pointer argument");
+    if (b < 1 || h < 1 || w < 1) return fail(MHFD_ERR_INVALID_ARG, "empty batch %d x %d x %d", b, h, w);
+    if (h > p->max_h || w > p->max_w)
+        return fail(MHFD_ERR_INVALID_ARG, "image %d x %d exceeds the plan's %d x %d", h, w,
+                    p->max_h, p->max_w);
+    if (!(beta > 0.0f) || !isfinite(beta) || !isfinite(tau))
+        return fail(MHFD_ERR_INVALID_ARG, "beta must be positive and finite, tau finite");
+    if (reinterpret_cast<uintptr_t>(d_imgs) % 4 || reinterpret_cast<uintptr_t>(d_ws) % kAlign)
+        return fail(MHFD_ERR_INVALID_ARG, "misaligned image or workspace");
+    const size_t need = focus_layout(p, b, h, w).total;
+    if (ws_bytes < need)
+        return fail(MHFD_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
     return MHFD_OK;
 }
 
@@ -459,19 +541,49 @@ mhfd_status mhfd_detect(mhfd_plan p, const void* d_img, int32_t h, int32_t w, in
 }
 
 size_t mhfd_focus_workspace_size(mhfd_plan p, int32_t b, int32_t h, int32_t w) {
-    (void)p;
-    (void)b;
-    (void)h;
-    (void)w;
-    return 0;
+    if (!p || b < 1 || h < 1 || w < 1 || h > p->max_h || w > p->max_w) return 0;
+    return focus_layout(p, b, h, w).total;
 }
 
 mhfd_status mhfd_focus_score(mhfd_plan p, const float* d_imgs, int32_t b, int32_t h, int32_t w,
                              const float* d_sigmas, float beta, float tau, float* d_scores,
                              void* d_ws, size_t ws_bytes, void* stream) {
-    (void)p; (void)d_imgs; (void)b; (void)h; (void)w; (void)d_sigmas; (void)beta; (void)tau;
-    (void)d_scores; (void)d_ws; (void)ws_bytes; (void)stream;
-    return fail(MHFD_ERR_UNSUPPORTED, "focus_score is not built yet");
+    g_last_error.clear();
+    mhfd_status st = check_focus(p, d_imgs, b, h, w, d_sigmas, beta, tau, d_ws, ws_bytes);
+    if (st != MHFD_OK) return st;
+    if (!d_scores) return fail(MHFD_ERR_INVALID_ARG, "null score buffer");
+    if ((st = check_device(p)) != MHFD_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const FocusLayout F = focus_layout(p, b, h, w);
+    char* base = static_cast<char*>(d_ws);
+    float* taps = reinterpret_cast<float*>(base + F.taps);
+    double* partial = reinterpret_cast<double*>(base + F.partial);
+    hipError_t e = mhfd::launch_soft_taps(d_sigmas, F.lay, taps, s);
+    if (e != hipSuccess) return hip_fail(e, "soft tap synthesis");
+    auto launches = make_launches(
+        p, h, w, all_scales(p), [&](int k) { return F.lay.offset[k] + mhfd::SOFT_FWD * 4 * (p->padded[k] + 1); },
+        [](int k) { return k; });
+    mhfd::SoftPartials sp{};
+    long long done = 0;
+    for (auto& cl : launches) {
+        mhfd::StackIO io{};
+        io.img_batch = static_cast<long long>(h) * w;
+        io.partial = partial + done;
+        io.total_blocks = launch_blocks(cl.second);
+        io.beta = beta;
+        io.tau = tau;
+        e = mhfd::launch_log_class(cl.first, MHFD_F32, mhfd::EPI_SOFTSUM, d_imgs, h, w, w, b, taps,
+                                   cl.second, io, s);
+        if (e != hipSuccess) return hip_fail(e, "soft score launch");
+        sp.base[sp.n] = done;
+        sp.blocks[sp.n] = io.total_blocks;
+        ++sp.n;
+        done += static_cast<long long>(io.total_blocks) * b;
+    }
+    e = mhfd::launch_soft_finish(partial, sp, b, 1.0 / (static_cast<double>(p->K) * h * w),
+                                 d_scores, s);
+    if (e != hipSuccess) return hip_fail(e, "soft score finish");
+    return MHFD_OK;
 }
 
 mhfd_status mhfd_focus_score_backward(mhfd_plan p, const float* d_imgs, int32_t b, int32_t h,
@@ -479,10 +591,58 @@ mhfd_status mhfd_focus_score_backward(mhfd_plan p, const float* d_imgs, int32_t 
                                       const float* d_grad_scores, float* d_grad_imgs,
                                       float* d_grad_sigmas, void* d_ws, size_t ws_bytes,
                                       void* stream) {
-    (void)p; (void)d_imgs; (void)b; (void)h; (void)w; (void)d_sigmas; (void)beta; (void)tau;
-    (void)d_grad_scores; (void)d_grad_imgs; (void)d_grad_sigmas; (void)d_ws; (void)ws_bytes;
-    (void)stream;
-    return fail(MHFD_ERR_UNSUPPORTED, "focus_score_backward is not built yet");
+    g_last_error.clear();
+    mhfd_status st = check_focus(p, d_imgs, b, h, w, d_sigmas, beta, tau, d_ws, ws_bytes);
+    if (st != MHFD_OK) return st;
+    if (!d_grad_scores || !d_grad_imgs || !d_grad_sigmas)
+        return fail(MHFD_ERR_INVALID_ARG, "null gradient buffer");
+    if ((st = check_device(p)) != MHFD_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const FocusLayout F = focus_layout(p, b, h, w);
+    char* base = static_cast<char*>(d_ws);
+    float* taps = reinterpret_cast<float*>(base + F.taps);
+    float* rpl = reinterpret_cast<float*>(base + F.rplane);
+    float* dpl = reinterpret_cast<float*>(base + F.dplane);
+    double* cot = reinterpret_cast<double*>(base + F.cot);
+    hipError_t e = mhfd::launch_soft_taps(d_sigmas, F.lay, taps, s);
+    if (e != hipSuccess) return hip_fail(e, "soft tap synthesis");
+    const long long npix = static_cast<long long>(h) * w;
+    const double inv_khw = 1.0 / (static_cast<double>(p->K) * h * w);
+    const int ncb = mhfd::soft_cotangent_blocks();
+    for (int k = 0; k < p->K; ++k) {
+        const std::vector<int> one{k};
+        auto run = [&](int set, int epi, const float* src, float* dst) -> hipError_t {
+            auto launches = make_launches(
+                p, h, w, one, [&](int kk) { return F.lay.offset[kk] + set * 4 * (p->padded[kk] + 1); },
+                [](int) { return 0; });
+            mhfd::StackIO io{};
+            io.img_batch = npix;
+            io.out = dst;
+            io.out_batch = npix;
+            io.plane_stride = 0;
+            for (auto& cl : launches) {
+                hipError_t err = mhfd::launch_log_class(cl.first, MHFD_F32, epi, src, h, w, w, b,
+                                                        taps, cl.second, io, s);
+                if (err != hipSuccess) return err;
+            }
+            return hipSuccess;
+        };
+        // r = sigma^2 Lap I, d = D1 I + D2 I (the sigma-derivative of Lap I)
+        if ((e = run(mhfd::SOFT_FWD, mhfd::EPI_STORE, d_imgs, rpl)) != hipSuccess ||
+            (e = run(mhfd::SOFT_D1, mhfd::EPI_STORE, d_imgs, dpl)) != hipSuccess ||
+            (e = run(mhfd::SOFT_D2, mhfd::EPI_ACCUM, d_imgs, dpl)) != hipSuccess)
+            return hip_fail(e, "soft score backward recompute");
+        e = mhfd::launch_soft_cotangent(rpl, dpl, npix, b, d_sigmas, k, d_grad_scores, inv_khw,
+                                        beta, tau, cot + static_cast<long long>(k) * ncb, s);
+        if (e != hipSuccess) return hip_fail(e, "soft score cotangent");
+        // dI (+)= Lap^T c = Lap c
+        if ((e = run(mhfd::SOFT_ADJ, k == 0 ? mhfd::EPI_STORE : mhfd::EPI_ACCUM, rpl,
+                     d_grad_imgs)) != hipSuccess)
+            return hip_fail(e, "soft score adjoint");
+    }
+    e = mhfd::launch_sigma_grad_finish(cot, ncb, p->K, d_grad_sigmas, s);
+    if (e != hipSuccess) return hip_fail(e, "sigma gradient finish");
+    return MHFD_OK;
 }
 
 }  // extern "C"

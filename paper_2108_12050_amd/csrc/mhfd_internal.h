@@ -68,10 +68,30 @@ int log_radius_class(int padded);
 int log_strip_width();
 int log_chunk_rows();
 
-// Enqueue the LoG stack of every scale in L (all of class `cls`) into
-// `stack` (K planes of h x w floats).
-hipError_t launch_log_class(int cls, int in_dtype, const void* img, int h, int w, int64_t pitch,
-                            const float* taps, float* stack, const StackLaunch& L, hipStream_t s);
+// Where a stack launch writes.  Plane k of image b is at
+// out + b * out_batch + k * plane_stride (row pitch = image width).
+enum { EPI_STORE = 0, EPI_ACCUM = 1, EPI_SOFTSUM = 2 };
+struct StackIO {
+    long long img_batch;     // elements between consecutive images of a batch
+    float* out;              // EPI_STORE: out = R; EPI_ACCUM: out += R
+    long long out_batch;     // elements between the outputs of consecutive images
+    long long plane_stride;  // elements between output planes
+    double* partial;         // EPI_SOFTSUM: partial[b * total_blocks + block] =
+                             //   sum of softplus(beta (|R| - tau)) over the block
+    int total_blocks;        // workgroups per image in the launch
+    float beta, tau;
+};
+
+// Enqueue the scale-space operator of every scale in L (all of radius class
+// `cls`) for `batch` images: R = hcol (*)_y (grow (*)_x I) + gcol (*)_y (hrow
+// (*)_x I) with the four tap runs at taps + sc.tap_off, and the epilogue
+// `epi` (EPI_*).  u8 images support EPI_STORE only.
+hipError_t launch_log_class(int cls, int in_dtype, int epi, const void* img, int h, int w,
+                            int64_t pitch, int batch, const float* taps, const StackLaunch& L,
+                            const StackIO& io, hipStream_t s);
+
+// Workgroups of one scale (strips x segments) for an h x w image.
+int log_blocks_per_scale(int h, int w, int seg_rows);
 
 // Detection tail: stack -> candidates -> canonical order -> prune -> blobs.
 struct DetectWorkspace {
@@ -105,5 +125,33 @@ size_t nms_pool_records(int n_blk, int64_t cap);
 size_t scan_sums_ints(int64_t n);
 
 int nms_blocks_per_row(int w);
+
+// Device-synthesised taps of the soft focus score: for scale k, four tap sets
+// (FWD, D1, D2, ADJ) of four runs of padded[k] + 1 floats start at offset[k].
+enum { SOFT_FWD = 0, SOFT_D1 = 1, SOFT_D2 = 2, SOFT_ADJ = 3, SOFT_SETS = 4 };
+struct SoftTapLayout {
+    int K;
+    int radius[MHFD_MAX_SCALES];
+    int padded[MHFD_MAX_SCALES];
+    int offset[MHFD_MAX_SCALES];
+};
+
+hipError_t launch_soft_taps(const float* sigmas, const SoftTapLayout& lay, float* taps,
+                            hipStream_t s);
+// Softplus partials of the forward launches: launch c wrote [image][block]
+// (blocks[c] per image) starting at partial + base[c].
+struct SoftPartials {
+    int n;
+    long long base[3];
+    int blocks[3];
+};
+hipError_t launch_soft_finish(const double* partial, const SoftPartials& sp, int batch,
+                              double inv_khw, float* scores, hipStream_t s);
+int soft_cotangent_blocks();
+hipError_t launch_soft_cotangent(float* r, const float* d, long long n_per_image, int batch,
+                                 const float* sigmas, int k, const float* gbar, double inv_khw,
+                                 float beta, float tau, double* partial, hipStream_t s);
+hipError_t launch_sigma_grad_finish(const double* partial, int nb, int K, float* dsig,
+                                    hipStream_t s);
 
 }  // namespace mhfd

@@ -76,3 +76,29 @@ def compare_candidates(gpu_stack: np.ndarray, gpu_cand: set, ora_stack: np.ndarr
 
 def as_set(yxk) -> set:
     return set(map(tuple, np.asarray(yxk).reshape(-1, 3).tolist()))
+
+
+def kink_bound(img: np.ndarray, sig, beta: float, tau: float, gbar: float, eps: float = 1e-5):
+    """Per-pixel bound on how much the image gradient of the soft score may
+    legitimately differ between two evaluations whose responses agree to
+    within eps.  Only voxels with |r| <= eps can take the other sign of r;
+    there the cotangent c = w sigma^2 changes by at most
+    2 beta sigmoid(beta (eps - tau)) |gbar| sigma^2 / (K H W), and the change
+    reaches dI through the Laplacian operator, bounded by the same operator
+    with absolute taps."""
+    from scipy.ndimage import correlate1d
+    I = np.asarray(img, dtype=np.float64)
+    H, W = I.shape
+    K = len(sig)
+    r = oracle.log_stack(I, sig, polarity=1)
+    dw = 2.0 * beta / (1.0 + np.exp(-beta * (eps - tau))) * abs(gbar) / (K * H * W)
+    out = np.zeros((H, W))
+    for k, s in enumerate(sig):
+        m = (np.abs(r[k]) <= eps).astype(np.float64) * dw * s * s
+        if not m.any():
+            continue
+        g, h = oracle.taps(s, oracle.radius(s))
+        ag, ah = np.abs(g), np.abs(h)
+        out += correlate1d(correlate1d(m, ag, axis=1, mode="reflect"), ah, axis=0, mode="reflect")
+        out += correlate1d(correlate1d(m, ah, axis=1, mode="reflect"), ag, axis=0, mode="reflect")
+    return out
