@@ -64,6 +64,7 @@ extern "C" {
 
 #define MHFD_MAX_SCALES 32   /* largest K */
 #define MHFD_MAX_RADIUS 64   /* largest kernel radius floor(truncate*sigma + 0.5) */
+#define MHFD_MAX_BATCH 4096  /* largest number of tiles in one batched call */
 
 typedef enum mhfd_status {
     MHFD_OK = 0,
@@ -169,6 +170,43 @@ mhfd_status mhfd_log_stack(mhfd_plan plan, const void *d_img, int32_t h, int32_t
 mhfd_status mhfd_detect_stack(mhfd_plan plan, const float *d_stack, int32_t h, int32_t w,
                               mhfd_blob *d_blobs, int32_t capacity, mhfd_result *d_result,
                               void *d_ws, size_t ws_bytes, void *stream);
+
+/* One image of a batch (device-resident descriptor, 48 bytes). */
+typedef struct mhfd_tile {
+    const void *img;       /* device image of the plan's dtype                  */
+    int32_t h, w;          /* 1 <= h <= max_h, 1 <= w <= max_w                  */
+    int64_t pitch;         /* row pitch in elements, >= w                       */
+    mhfd_blob *blobs;      /* device: room for `capacity` blobs                 */
+    mhfd_result *result;   /* device: one result, always written               */
+    int32_t capacity;      /* >= 0                                              */
+    int32_t seg_rows;      /* rows per LoG workgroup for this tile: 0 = library
+                              default, else a multiple of 32 in [32, 4096]      */
+} mhfd_tile;
+
+/* A descriptor failed the device-side checks (or the batch exceeded the
+ * workspace bounds); nothing was computed for the batch. */
+#define MHFD_FLAG_INVALID_TILE 4
+
+/* Workspace bytes mhfd_detect_batched needs for up to max_tiles tiles with at
+ * most max_pixels pixels in total (0 on bad input). */
+size_t mhfd_batch_workspace_size(mhfd_plan plan, int32_t max_tiles, int64_t max_pixels);
+
+/*
+ * Detect blobs in n tiles of different sizes at once: the same results per
+ * tile as mhfd_detect (bit for bit), from one fixed sequence of launches.
+ *   d_tiles   n device descriptors.  The host never reads them: a setup kernel
+ *             checks them on the device, so the call can be captured in a HIP
+ *             graph once and replayed with new descriptors of any sizes within
+ *             the bounds.  If any descriptor is invalid, or the tiles hold more
+ *             than max_pixels pixels, every tile's result gets
+ *             MHFD_FLAG_INVALID_TILE with zero counts and no tile is processed.
+ *   max_pixels, d_ws, ws_bytes  bounds the workspace was sized for
+ *             (mhfd_batch_workspace_size(plan, n_max, max_pixels), n <= n_max).
+ * Scales of a radius class run as persistent workgroups that pull
+ * (scale, tile, strip, segment) items, largest radius first.
+ */
+mhfd_status mhfd_detect_batched(mhfd_plan plan, int32_t n, const mhfd_tile *d_tiles,
+                                int64_t max_pixels, void *d_ws, size_t ws_bytes, void *stream);
 
 /* Workspace bytes mhfd_focus_score and mhfd_focus_score_backward need for a
  * batch of b images of h x w (0 on bad input). */

@@ -11,4 +11,7 @@ def __getattr__(name):
     if name in ("Plan", "Detection", "split_blobs", "FocusScore", "focus_score"):
         from . import api
         return getattr(api, name)
+    if name in ("BatchRunner", "detect_batched"):
+        from . import batch
+        return getattr(batch, name)
     raise AttributeError(name)

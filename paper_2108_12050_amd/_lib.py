@@ -18,6 +18,8 @@ MHFD_F32, MHFD_U8 = 0, 1
 MHFD_BRIGHT, MHFD_DARK = 0, 1
 MHFD_FLAG_BLOB_OVERFLOW = 1
 MHFD_FLAG_CAND_OVERFLOW = 2
+MHFD_FLAG_INVALID_TILE = 4
+MHFD_MAX_BATCH = 4096
 
 STATUS = {0: "MHFD_OK", 1: "MHFD_ERR_INVALID_ARG", 2: "MHFD_ERR_UNSUPPORTED",
           3: "MHFD_ERR_WORKSPACE", 4: "MHFD_ERR_HIP", 5: "MHFD_ERR_OOM"}
@@ -25,7 +27,7 @@ STATUS = {0: "MHFD_OK", 1: "MHFD_ERR_INVALID_ARG", 2: "MHFD_ERR_UNSUPPORTED",
 # Every symbol include/mhfd.h declares.
 EXPORTS = ("mhfd_create_plan", "mhfd_destroy_plan", "mhfd_plan_scales",
            "mhfd_detect_workspace_size", "mhfd_detect", "mhfd_log_stack", "mhfd_detect_stack",
-           "mhfd_focus_workspace_size",
+           "mhfd_batch_workspace_size", "mhfd_detect_batched", "mhfd_focus_workspace_size",
            "mhfd_focus_score", "mhfd_focus_score_backward", "mhfd_status_string",
            "mhfd_last_error")
 
@@ -55,12 +57,18 @@ class Blob(C.Structure):
                 ("response", C.c_float)]
 
 
+class Tile(C.Structure):
+    _fields_ = [("img", C.c_void_p), ("h", C.c_int32), ("w", C.c_int32), ("pitch", C.c_int64),
+                ("blobs", C.c_void_p), ("result", C.c_void_p), ("capacity", C.c_int32),
+                ("seg_rows", C.c_int32)]
+
+
 class Result(C.Structure):
     _fields_ = [("n_blobs", C.c_int64), ("n_candidates", C.c_int64), ("flags", C.c_int32),
                 ("reserved", C.c_int32)]
 
 
-assert C.sizeof(Blob) == 20 and C.sizeof(Result) == 24
+assert C.sizeof(Blob) == 20 and C.sizeof(Result) == 24 and C.sizeof(Tile) == 48
 
 _lib = None
 
@@ -93,6 +101,10 @@ def load(path: str | None = None):
     L.mhfd_log_stack.restype = C.c_int
     L.mhfd_detect_stack.argtypes = [vp, vp, i32, i32, vp, i32, vp, vp, sz, vp]
     L.mhfd_detect_stack.restype = C.c_int
+    L.mhfd_batch_workspace_size.argtypes = [vp, i32, i64]
+    L.mhfd_batch_workspace_size.restype = sz
+    L.mhfd_detect_batched.argtypes = [vp, i32, vp, i64, vp, sz, vp]
+    L.mhfd_detect_batched.restype = C.c_int
     L.mhfd_focus_workspace_size.argtypes = [vp, i32, i32, i32]
     L.mhfd_focus_workspace_size.restype = sz
     L.mhfd_focus_score.argtypes = [vp, vp, i32, i32, i32, vp, f32, f32, vp, vp, sz, vp]

@@ -1,0 +1,446 @@
+// Batched detection of tiles of different sizes from one fixed launch
+// sequence.  The host never reads the tile descriptors: the setup kernel
+// checks them and builds the per-tile table, so the sequence can be captured
+// in a HIP graph and replayed with new descriptors.
+//
+//   setup      validate, per-tile LoG items / NMS workgroups / stack offsets
+//              and their prefix sums (one workgroup);
+//   LoG        persistent per radius class (log_strip.hip);
+//   nms        persistent over every tile's (row, 256-column chunk) pieces; the
+//              same maxima test, slots and overflow pool as the single-tile
+//              path; the tile index rides in the upper bits of k;
+//   scan       over all pieces, tile-major: the canonical list of every tile
+//              is one contiguous run of the global list;
+//   order, prune (rows of the candidate's own tile), keep scan, emit into the
+//              tile's buffer, per-tile results.
+#include <math.h>
+
+#include <utility>
+
+#include "mhfd_internal.h"
+
+namespace mhfd {
+
+namespace {
+
+constexpr int NMS_T = 256;
+constexpr int SLOT = 16;
+constexpr int SETUP_T = 1024;
+constexpr int TILE_SHIFT = 5;  // k in the low bits (K <= 32), tile above
+
+__device__ __forceinline__ float fmax3(float a, float b, float c) { return fmaxf(a, fmaxf(b, c)); }
+
+__device__ int default_seg_rows(int h, int w) {
+    const int strips = (w + 63) / 64;
+    long long seg = (static_cast<long long>(h) * strips + 1023) / 1024;
+    seg = (seg + 31) / 32 * 32;
+    if (seg < 32) seg = 32;
+    if (seg > 1024) seg = 1024;
+    return static_cast<int>(seg);
+}
+
+// Exclusive block scan of per-thread values (SETUP_T threads).
+template <typename V>
+__device__ V block_exclusive_scan(V v, V* sh, V* total) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int d = 1; d < SETUP_T; d <<= 1) {
+        const V t = threadIdx.x >= d ? sh[threadIdx.x - d] : V(0);
+        __syncthreads();
+        sh[threadIdx.x] += t;
+        __syncthreads();
+    }
+    const V incl = sh[threadIdx.x];
+    *total = sh[SETUP_T - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ __launch_bounds__(SETUP_T) void batch_setup_kernel(
+    const mhfd_tile* __restrict__ in, int n, long long max_pixels, int K, int max_h, int max_w,
+    int dtype, BatchTile* __restrict__ tiles, BatchCounters* __restrict__ ctr) {
+    __shared__ long long shl[SETUP_T];
+    __shared__ int bad_s;
+    if (threadIdx.x == 0) bad_s = 0;
+    __syncthreads();
+    const int per = (n + SETUP_T - 1) / SETUP_T;
+    const int t0 = min(n, static_cast<int>(threadIdx.x) * per), t1 = min(n, t0 + per);
+    long long items = 0, nms = 0, pix = 0;
+    for (int t = t0; t < t1; ++t) {
+        const mhfd_tile d = in[t];
+        bool ok = d.img && d.result && d.h >= 1 && d.w >= 1 && d.h <= max_h && d.w <= max_w &&
+                  d.pitch >= d.w && d.capacity >= 0 && (d.capacity == 0 || d.blobs) &&
+                  (d.seg_rows == 0 || (d.seg_rows % 32 == 0 && d.seg_rows >= 32 && d.seg_rows <= 4096)) &&
+                  (dtype == MHFD_U8 || (reinterpret_cast<uintptr_t>(d.img) & 3) == 0);
+        if (!ok) atomicOr(&bad_s, 1);
+        BatchTile bt{};
+        bt.img = d.img;
+        bt.pitch = d.pitch;
+        bt.blobs = d.blobs;
+        bt.result = d.result;
+        bt.h = ok ? d.h : 1;
+        bt.w = ok ? d.w : 1;
+        bt.capacity = ok ? d.capacity : 0;
+        bt.seg_rows = ok ? (d.seg_rows ? d.seg_rows : default_seg_rows(d.h, d.w)) : 32;
+        bt.strips = (bt.w + 63) / 64;
+        bt.segs = (bt.h + bt.seg_rows - 1) / bt.seg_rows;
+        bt.bpr = (bt.w + NMS_T - 1) / NMS_T;
+        tiles[t] = bt;
+        items += static_cast<long long>(bt.strips) * bt.segs;
+        nms += static_cast<long long>(bt.h) * bt.bpr;
+        pix += static_cast<long long>(bt.h) * bt.w;
+    }
+    long long tot_items, tot_nms, tot_pix;
+    const long long b_items = block_exclusive_scan(items, shl, &tot_items);
+    const long long b_nms = block_exclusive_scan(nms, shl, &tot_nms);
+    const long long b_pix = block_exclusive_scan(pix, shl, &tot_pix);
+    long long ri = b_items, rn = b_nms, rp = b_pix;
+    for (int t = t0; t < t1; ++t) {
+        BatchTile& bt = tiles[t];
+        bt.item_base = static_cast<int>(ri);
+        bt.nms_base = static_cast<int>(rn);
+        bt.stack_off = rp * K;
+        ri += static_cast<long long>(bt.strips) * bt.segs;
+        rn += static_cast<long long>(bt.h) * bt.bpr;
+        rp += static_cast<long long>(bt.h) * bt.w;
+    }
+    __syncthreads();
+    const bool valid = !bad_s && tot_pix <= max_pixels && tot_items * K < (1LL << 30) &&
+                       tot_nms < (1LL << 30);
+    if (threadIdx.x == 0) {
+        ctr->items_per_scale = valid ? static_cast<int>(tot_items) : 0;
+        ctr->nms_blocks = valid ? static_cast<int>(tot_nms) : 0;
+        ctr->valid = valid ? 1 : 0;
+        ctr->pool_used = 0;
+        ctr->flags = 0;
+        ctr->n_cand = 0;
+        ctr->n_blobs = 0;
+        ctr->work[0] = ctr->work[1] = ctr->work[2] = 0;
+    }
+    if (!valid) {
+        for (int t = t0; t < t1; ++t) {
+            mhfd_result* r = in[t].result;
+            if (r) {
+                r->n_blobs = 0;
+                r->n_candidates = 0;
+                r->flags = MHFD_FLAG_INVALID_TILE;
+                r->reserved = 0;
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ int tile_of(const BatchTile* __restrict__ tiles, int n_tiles, int blk) {
+    int lo = 0, hi = n_tiles;  // last t with nms_base <= blk
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (tiles[mid].nms_base <= blk)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Exclusive prefix within the wave of a per-lane count c in [0, 2^BITS).
+template <int BITS>
+__device__ __forceinline__ int wave_exclusive_prefix(int c, int* wave_total) {
+    int pre = 0, tot = 0;
+#pragma unroll
+    for (int b = 0; b < BITS; ++b) {
+        const unsigned long long bal = __ballot((c >> b) & 1);
+        const unsigned lo = static_cast<unsigned>(bal);
+        const unsigned hi = static_cast<unsigned>(bal >> 32);
+        pre += static_cast<int>(__builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u))) << b;
+        tot += __popcll(bal) << b;
+    }
+    *wave_total = tot;
+    return pre;
+}
+
+template <int K>
+__global__ __launch_bounds__(NMS_T) void nms_batch_kernel(
+    const float* __restrict__ stack, const BatchTile* __restrict__ tiles, int n_tiles, float tau,
+    int n_blk_bound, int32_t* __restrict__ blk_n, int32_t* __restrict__ blk_o,
+    Cand* __restrict__ pool, int64_t cap, BatchCounters* __restrict__ ctr) {
+    __shared__ float vm[K][NMS_T + 2];
+    __shared__ int wave_tot[NMS_T / 64];
+    __shared__ int run_base;
+    const int total = ctr->nms_blocks;
+    const int tid = threadIdx.x;
+    for (int blk = blockIdx.x; blk < total; blk += gridDim.x) {
+        const int ti = tile_of(tiles, n_tiles, blk);
+        const BatchTile& T = tiles[ti];
+        const int H = T.h, W = T.w;
+        const float* st = stack + T.stack_off;
+        const int local = blk - T.nms_base;
+        const int y = local / T.bpr;
+        const int x0 = (local - y * T.bpr) * NMS_T;
+        const int x = x0 + tid;
+        const bool valid = x < W;
+        const size_t plane = static_cast<size_t>(H) * W;
+        const int yu = y > 0 ? y - 1 : 0;
+        const int yd = y + 1 < H ? y + 1 : H - 1;
+        const int xc = valid ? x : W - 1;
+        float cv[K], vmx[K];
+        {
+            const float* pc = st + static_cast<size_t>(y) * W + xc;
+            const float* pu = st + static_cast<size_t>(yu) * W + xc;
+            const float* pd = st + static_cast<size_t>(yd) * W + xc;
+            float u[K], d[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                cv[k] = pc[k * plane];
+                u[k] = pu[k * plane];
+                d[k] = pd[k * plane];
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k) vmx[k] = valid ? fmax3(u[k], cv[k], d[k]) : -INFINITY;
+        }
+        if (tid == 0 || tid == NMS_T - 1) {
+            const int xh = tid == 0 ? x0 - 1 : x0 + NMS_T;
+            const bool ok = xh >= 0 && xh < W;
+            const int xs = ok ? xh : 0;
+            const int slot = tid == 0 ? 0 : NMS_T + 1;
+            const float* pc = st + static_cast<size_t>(y) * W + xs;
+            const float* pu = st + static_cast<size_t>(yu) * W + xs;
+            const float* pd = st + static_cast<size_t>(yd) * W + xs;
+            float hv[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) hv[k] = fmax3(pu[k * plane], pc[k * plane], pd[k * plane]);
+#pragma unroll
+            for (int k = 0; k < K; ++k) vm[k][slot] = ok ? hv[k] : -INFINITY;
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) vm[k][tid + 1] = vmx[k];
+        __syncthreads();
+        unsigned mask = 0u;
+        {
+            float m_prev = -INFINITY;
+            float m_cur = fmax3(vm[0][tid], vm[0][tid + 1], vm[0][tid + 2]);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const float m_next = k + 1 < K ? fmax3(vm[k + 1][tid], vm[k + 1][tid + 1],
+                                                       vm[k + 1][tid + 2])
+                                               : -INFINITY;
+                const float v = cv[k];
+                if (v > tau && v >= fmax3(m_prev, m_cur, m_next)) mask |= 1u << k;
+                m_prev = m_cur;
+                m_cur = m_next;
+            }
+            if (!valid) mask = 0u;
+        }
+        const int c = __popc(mask);
+        int wtot;
+        const int pre = wave_exclusive_prefix<6>(c, &wtot);
+        const int lane = tid & 63, wv = tid >> 6;
+        if (lane == 0) wave_tot[wv] = wtot;
+        __syncthreads();
+        int woff = 0, n = 0;
+#pragma unroll
+        for (int i = 0; i < NMS_T / 64; ++i) {
+            woff += i < wv ? wave_tot[i] : 0;
+            n += wave_tot[i];
+        }
+        if (tid == 0) {
+            int o = 0;
+            if (n > SLOT) {
+                o = atomicAdd(&ctr->pool_used, n - SLOT);
+                if (static_cast<int64_t>(o) + (n - SLOT) > cap)
+                    atomicOr(&ctr->flags, MHFD_FLAG_CAND_OVERFLOW);
+            }
+            run_base = o;
+            blk_n[blk] = n;
+            blk_o[blk] = o;
+        }
+        __syncthreads();
+        if (c > 0) {
+            int j = woff + pre;
+            Cand* own = pool + static_cast<int64_t>(blk) * SLOT;
+            Cand* over = pool + static_cast<int64_t>(n_blk_bound) * SLOT + run_base - SLOT;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                if (mask & (1u << k)) {
+                    Cand r;
+                    r.y = y;
+                    r.x = x;
+                    r.k = k | (ti << TILE_SHIFT);
+                    r.r = cv[k];
+                    if (j < SLOT)
+                        own[j] = r;
+                    else if (run_base + (j - SLOT) < cap)
+                        over[j] = r;
+                    ++j;
+                }
+            }
+        }
+        __syncthreads();  // vm and run_base are reused by the next piece
+    }
+}
+
+__global__ void order_batch_kernel(const int32_t* __restrict__ blk_off,
+                                   const int32_t* __restrict__ blk_o, int n_blk_bound,
+                                   const Cand* __restrict__ pool, Cand* __restrict__ cand,
+                                   int64_t cap, BatchCounters* __restrict__ ctr) {
+    const int n_blk = ctr->nms_blocks;
+    const int64_t n = min(static_cast<int64_t>(ctr->n_cand), cap);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && ctr->n_cand > cap)
+        atomicOr(&ctr->flags, MHFD_FLAG_CAND_OVERFLOW);
+    const Cand* over = pool + static_cast<int64_t>(n_blk_bound) * SLOT;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        int lo = 0, hi = n_blk;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (blk_off[mid] <= i)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const int j = static_cast<int>(i - blk_off[lo]);
+        if (j < SLOT) {
+            cand[i] = pool[static_cast<int64_t>(lo) * SLOT + j];
+        } else {
+            const int64_t src = static_cast<int64_t>(blk_o[lo]) + (j - SLOT);
+            if (src < cap) cand[i] = over[src];
+        }
+    }
+}
+
+__global__ void prune_batch_kernel(const Cand* __restrict__ cand,
+                                   const int32_t* __restrict__ blk_off,
+                                   const BatchTile* __restrict__ tiles, int K,
+                                   const int32_t* __restrict__ d2max, int reach,
+                                   int32_t* __restrict__ keep, int64_t cap,
+                                   const BatchCounters* __restrict__ ctr) {
+    const int64_t n = min(static_cast<int64_t>(ctr->n_cand), cap);
+    const long long r2 = static_cast<long long>(reach) * reach;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const Cand b = cand[i];
+        const int ti = b.k >> TILE_SHIFT, kb = b.k & ((1 << TILE_SHIFT) - 1);
+        const BatchTile& T = tiles[ti];
+        int kp = 1;
+        if (d2max) {
+            const int32_t* dcol = d2max + kb;
+            const int ylo = max(0, b.y - reach), yhi = min(T.h - 1, b.y + reach);
+            for (int yy = ylo; yy <= yhi && kp; ++yy) {
+                const long long dy = yy - b.y;
+                const int xr = static_cast<int>(sqrt(static_cast<double>(r2 - dy * dy)));
+                int lo = blk_off[T.nms_base + yy * T.bpr];
+                const int hi = min(static_cast<int64_t>(blk_off[T.nms_base + (yy + 1) * T.bpr]), n);
+                int top = hi;
+                while (lo < top) {
+                    const int mid = (lo + top) >> 1;
+                    if (cand[mid].x < b.x - xr)
+                        lo = mid + 1;
+                    else
+                        top = mid;
+                }
+                for (int j = lo; j < hi; ++j) {
+                    const Cand a = cand[j];
+                    if (a.x > b.x + xr) break;
+                    const int ka = a.k & ((1 << TILE_SHIFT) - 1);
+                    const bool dom =
+                        ka > kb || (ka == kb && (a.y < b.y || (a.y == b.y && a.x < b.x)));
+                    const long long dx = a.x - b.x;
+                    if (dom && dy * dy + dx * dx <= dcol[ka * K]) {
+                        kp = 0;
+                        break;
+                    }
+                }
+            }
+        }
+        keep[i] = kp;
+    }
+}
+
+__global__ void emit_batch_kernel(const Cand* __restrict__ cand, const int32_t* __restrict__ keep,
+                                  const int32_t* __restrict__ keep_off,
+                                  const int32_t* __restrict__ blk_off,
+                                  const BatchTile* __restrict__ tiles,
+                                  const float* __restrict__ sigmas, int64_t cap,
+                                  const BatchCounters* __restrict__ ctr) {
+    const int64_t n = min(static_cast<int64_t>(ctr->n_cand), cap);
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        if (!keep[i]) continue;
+        const Cand c = cand[i];
+        const int ti = c.k >> TILE_SHIFT, k = c.k & ((1 << TILE_SHIFT) - 1);
+        const BatchTile& T = tiles[ti];
+        const int64_t first = blk_off[T.nms_base];  // first candidate of the tile
+        const int pos = keep_off[i] - keep_off[first];
+        if (pos < T.capacity) {
+            mhfd_blob b;
+            b.y = c.y;
+            b.x = c.x;
+            b.k = k;
+            b.sigma = sigmas[k];
+            b.response = c.r;
+            T.blobs[pos] = b;
+        }
+    }
+}
+
+__global__ void results_batch_kernel(const int32_t* __restrict__ blk_off,
+                                     const int32_t* __restrict__ keep_off,
+                                     const BatchTile* __restrict__ tiles, int n_tiles, int64_t cap,
+                                     const BatchCounters* __restrict__ ctr) {
+    if (!ctr->valid) return;
+    const int64_t n = min(static_cast<int64_t>(ctr->n_cand), cap);
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n_tiles; t += gridDim.x * blockDim.x) {
+        const BatchTile& T = tiles[t];
+        const int64_t cb = blk_off[T.nms_base];
+        const int64_t ce = blk_off[T.nms_base + T.h * T.bpr];
+        const int64_t kb = keep_off[min(cb, n)], ke = keep_off[min(ce, n)];
+        int32_t flags = ctr->flags & MHFD_FLAG_CAND_OVERFLOW;
+        const int64_t nb = ke - kb;
+        if (nb > T.capacity) flags |= MHFD_FLAG_BLOB_OVERFLOW;
+        T.result->n_blobs = nb;
+        T.result->n_candidates = ce - cb;
+        T.result->flags = flags;
+        T.result->reserved = 0;
+    }
+}
+
+template <int K>
+void launch_nms_batch_k(const BatchLaunchArgs& a, hipStream_t s) {
+    nms_batch_kernel<K><<<a.nms_grid, NMS_T, 0, s>>>(a.stack, a.tiles, a.n_tiles, a.tau,
+                                                     a.n_blk_bound, a.blk_n, a.blk_o, a.pool,
+                                                     a.cap, a.ctr);
+}
+
+template <int... Ks>
+void launch_nms_batch(int K, const BatchLaunchArgs& a, hipStream_t s,
+                      std::integer_sequence<int, Ks...>) {
+    ((K == Ks + 1 ? launch_nms_batch_k<Ks + 1>(a, s) : void()), ...);
+}
+
+}  // namespace
+
+hipError_t launch_batch_setup(const mhfd_tile* in, int n, long long max_pixels, int K, int max_h,
+                              int max_w, int dtype, BatchTile* tiles, BatchCounters* ctr,
+                              hipStream_t s) {
+    batch_setup_kernel<<<1, SETUP_T, 0, s>>>(in, n, max_pixels, K, max_h, max_w, dtype, tiles, ctr);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_tail(const BatchLaunchArgs& a, hipStream_t s) {
+    launch_nms_batch(a.K, a, s, std::make_integer_sequence<int, MHFD_MAX_SCALES>{});
+    launch_batch_scan(a.blk_n, a.n_blk_bound, &a.ctr->nms_blocks, a.scan_sums, a.blk_off,
+                      &a.ctr->n_cand, s);
+    const int grid = 1024;
+    order_batch_kernel<<<grid, 256, 0, s>>>(a.blk_off, a.blk_o, a.n_blk_bound, a.pool, a.cand,
+                                            a.cap, a.ctr);
+    prune_batch_kernel<<<grid, 256, 0, s>>>(a.cand, a.blk_off, a.tiles, a.K, a.d2max, a.reach,
+                                            a.keep, a.cap, a.ctr);
+    launch_batch_scan(a.keep, static_cast<int>(a.cap), &a.ctr->n_cand, a.scan_sums, a.keep_off,
+                      &a.ctr->n_blobs, s);
+    emit_batch_kernel<<<grid, 256, 0, s>>>(a.cand, a.keep, a.keep_off, a.blk_off, a.tiles,
+                                           a.sigmas, a.cap, a.ctr);
+    results_batch_kernel<<<(a.n_tiles + 255) / 256, 256, 0, s>>>(a.blk_off, a.keep_off, a.tiles,
+                                                                 a.n_tiles, a.cap, a.ctr);
+    return hipGetLastError();
+}
+
+}  // namespace mhfd

@@ -429,6 +429,11 @@ __global__ void emit_kernel(const Cand* __restrict__ cand, const int32_t* __rest
 
 int nms_blocks_per_row(int w) { return (w + NMS_T - 1) / NMS_T; }
 
+void launch_batch_scan(const int32_t* in, int n_host, const int32_t* n_dev, int32_t* sums,
+                       int32_t* out, int32_t* total_out, hipStream_t s) {
+    launch_scan(in, n_host, n_dev, sums, out, total_out, s);
+}
+
 size_t nms_pool_records(int n_blk, int64_t cap) { return static_cast<size_t>(n_blk) * SLOT + cap; }
 
 size_t scan_sums_ints(int64_t n) { return static_cast<size_t>((n + SCAN_SPAN - 1) / SCAN_SPAN + 1); }

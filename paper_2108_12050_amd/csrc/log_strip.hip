@@ -368,3 +368,124 @@ hipError_t launch_log_class(int cls, int in_dtype, int epi, const void* img, int
 }
 
 }  // namespace mhfd
+
+// ---------------------------------------------------------------------------
+// Persistent form for a batch of tiles of different sizes.  Workgroups pull
+// items (scale j of the class, tile, strip, segment) from a counter; items
+// are numbered scale-major, so every tile's largest radius goes first.
+namespace mhfd {
+
+namespace {
+
+template <int RLO, int RHI, typename T>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void log_batch_kernel(int n_tiles, const BatchTile* __restrict__ tiles, int K,
+                      float* __restrict__ stack, const float* __restrict__ taps, BatchScales sc,
+                      BatchCounters* __restrict__ ctr, int cls) {
+    extern __shared__ __attribute__((aligned(16))) float smem[];
+    __shared__ int item_s;
+    const int per_scale = ctr->items_per_scale;
+    const int total = ctr->valid ? per_scale * sc.n : 0;
+    for (;;) {
+        if (threadIdx.x == 0) item_s = atomicAdd(&ctr->work[cls], 1);
+        __syncthreads();
+        const int item = item_s;
+        __syncthreads();
+        if (item >= total) break;
+        const int j = item / per_scale;
+        const int rem = item - j * per_scale;
+        // tile: last t with item_base <= rem
+        int lo = 0, hi = n_tiles;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (tiles[mid].item_base <= rem)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const BatchTile& t = tiles[lo];
+        const int local = rem - t.item_base;
+        const int strip = local % t.strips;
+        const int seg = local / t.strips;
+        const int x0 = strip * TW;
+        const int ys = seg * t.seg_rows;
+        const int ye = min(ys + t.seg_rows, t.h);
+        float* out = stack + t.stack_off + static_cast<long long>(sc.plane[j]) * t.h * t.w;
+        const T* img = static_cast<const T*>(t.img);
+        const float* tp = taps + sc.tap_off[j];
+        switch (sc.radius[j]) {
+#define MHFD_BODY(R)                                                                        \
+    case R:                                                                                 \
+        if constexpr (R >= RLO && R <= RHI)                                                 \
+            log_strip_body<R, EPI_STORE, T>(smem, img, t.h, t.w, t.pitch, tp, out, t.w, x0, \
+                                            ys, ye, 0.0f, 0.0f, nullptr);                   \
+        break;
+            MHFD_BODY(4)
+            MHFD_BODY(8)
+            MHFD_BODY(12)
+            MHFD_BODY(16)
+            MHFD_BODY(20)
+            MHFD_BODY(24)
+            MHFD_BODY(28)
+            MHFD_BODY(32)
+            MHFD_BODY(36)
+            MHFD_BODY(40)
+            MHFD_BODY(44)
+            MHFD_BODY(48)
+            MHFD_BODY(52)
+            MHFD_BODY(56)
+            MHFD_BODY(60)
+            MHFD_BODY(64)
+#undef MHFD_BODY
+            default:
+                break;
+        }
+        __syncthreads();  // LDS is reused by the next item
+    }
+    (void)K;
+}
+
+template <int RLO, int RHI, typename T>
+hipError_t launch_batch_typed(int n_tiles, const BatchTile* tiles, int K, float* stack,
+                              const float* taps, const BatchScales& sc, BatchCounters* ctr,
+                              int cls, int grid, size_t lds, hipStream_t s) {
+    auto k = log_batch_kernel<RLO, RHI, T>;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+    k<<<grid, NT, lds, s>>>(n_tiles, tiles, K, stack, taps, sc, ctr, cls);
+    return hipGetLastError();
+}
+
+template <int RLO, int RHI>
+hipError_t launch_batch_range(int in_dtype, int n_tiles, const BatchTile* tiles, int K,
+                              float* stack, const float* taps, const BatchScales& sc,
+                              BatchCounters* ctr, int cls, int grid, size_t lds, hipStream_t s) {
+    if (in_dtype == MHFD_U8)
+        return launch_batch_typed<RLO, RHI, uint8_t>(n_tiles, tiles, K, stack, taps, sc, ctr, cls,
+                                                     grid, lds, s);
+    return launch_batch_typed<RLO, RHI, float>(n_tiles, tiles, K, stack, taps, sc, ctr, cls, grid,
+                                               lds, s);
+}
+
+}  // namespace
+
+hipError_t launch_log_batch(int cls, int in_dtype, int n_tiles, const BatchTile* tiles, int K,
+                            float* stack, const float* taps, const BatchScales& sc,
+                            BatchCounters* ctr, int grid, hipStream_t s) {
+    if (sc.n == 0) return hipSuccess;
+    int rmax = 0;
+    for (int i = 0; i < sc.n; ++i) rmax = sc.radius[i] > rmax ? sc.radius[i] : rmax;
+    const size_t lds = sizeof(float) * static_cast<size_t>(lds_floats(rmax));
+    if (cls == 0)
+        return launch_batch_range<4, 16>(in_dtype, n_tiles, tiles, K, stack, taps, sc, ctr, cls,
+                                         grid, lds, s);
+    if (cls == 1)
+        return launch_batch_range<20, 40>(in_dtype, n_tiles, tiles, K, stack, taps, sc, ctr, cls,
+                                          grid, lds, s);
+    return launch_batch_range<44, 64>(in_dtype, n_tiles, tiles, K, stack, taps, sc, ctr, cls,
+                                      grid, lds, s);
+}
+
+}  // namespace mhfd

@@ -24,6 +24,7 @@ struct mhfd_plan_s {
     int max_h = 0, max_w = 0;
     int64_t max_cand = 0;
     int reach = 0;               // prune row reach, floor(sqrt(max d2max))
+    int n_cu = 0;                // compute units of the plan's device
     float* d_taps = nullptr;     // device tap table
     int32_t* d_d2max = nullptr;  // K x K prune table (null: pruning off)
     float* d_sigmas = nullptr;   // device copy of sigmas (float)
@@ -270,9 +271,11 @@ mhfd_status mhfd_create_plan(const mhfd_config* cfg, mhfd_plan* out) {
                    host.data() + p->tap_off[k]);
 
     hipError_t e = hipGetDevice(&p->device);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device);
     if (e != hipSuccess) {
         delete p;
-        return hip_fail(e, "hipGetDevice");
+        return hip_fail(e, "device query");
     }
     e = hipMalloc(reinterpret_cast<void**>(&p->d_taps), sizeof(float) * off);
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->d_sigmas), sizeof(float) * K);
@@ -495,6 +498,42 @@ mhfd_status check_focus(const mhfd_plan_s* p, const float* d_imgs, int b, int h,
     return MHFD_OK;
 }
 
+struct BatchLayout {
+    size_t stack, tiles, ctr, blk_n, blk_o, blk_off, pool, cand, keep, keep_off, scan_sums, total;
+    int n_blk_bound;
+    int64_t cap;
+};
+
+bool batch_layout(const mhfd_plan_s* p, int n, int64_t max_pixels, BatchLayout* L) {
+    if (n < 1 || n > MHFD_MAX_BATCH || max_pixels < 1 || max_pixels > (int64_t(1) << 31) - 1)
+        return false;
+    const int64_t nbb = max_pixels / 256 + static_cast<int64_t>(n) * (p->max_h + 1);
+    if (nbb > (int64_t(1) << 30)) return false;
+    L->n_blk_bound = static_cast<int>(nbb);
+    int64_t cap = p->max_cand * n;
+    if (cap > (int64_t(1) << 30)) cap = int64_t(1) << 30;
+    L->cap = cap;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    L->stack = take(sizeof(float) * static_cast<size_t>(p->K) * max_pixels);
+    L->tiles = take(sizeof(mhfd::BatchTile) * n);
+    L->ctr = take(sizeof(mhfd::BatchCounters));
+    L->blk_n = take(sizeof(int32_t) * nbb);
+    L->blk_o = take(sizeof(int32_t) * nbb);
+    L->blk_off = take(sizeof(int32_t) * (nbb + 1));
+    L->pool = take(sizeof(mhfd::Cand) * mhfd::nms_pool_records(static_cast<int>(nbb), cap));
+    L->cand = take(sizeof(mhfd::Cand) * cap);
+    L->keep = take(sizeof(int32_t) * cap);
+    L->keep_off = take(sizeof(int32_t) * (cap + 1));
+    L->scan_sums = take(sizeof(int32_t) * mhfd::scan_sums_ints(nbb > cap ? nbb : cap));
+    L->total = off;
+    return true;
+}
+
 }  // namespace
 
 extern "C" {
@@ -538,6 +577,80 @@ mhfd_status mhfd_detect(mhfd_plan p, const void* d_img, int32_t h, int32_t w, in
     float* stack = d_stack ? d_stack : reinterpret_cast<float*>(base + L.stack);
     if ((st = enqueue_log_stack(p, d_img, h, w, pitch, stack, s)) != MHFD_OK) return st;
     return enqueue_tail(p, stack, h, w, L, base, d_blobs, capacity, d_result, s);
+}
+
+size_t mhfd_batch_workspace_size(mhfd_plan p, int32_t max_tiles, int64_t max_pixels) {
+    BatchLayout L;
+    if (!p || !batch_layout(p, max_tiles, max_pixels, &L)) return 0;
+    return L.total;
+}
+
+mhfd_status mhfd_detect_batched(mhfd_plan p, int32_t n, const mhfd_tile* d_tiles,
+                                int64_t max_pixels, void* d_ws, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    if (!p) return fail(MHFD_ERR_INVALID_ARG, "null plan");
+    if (!d_tiles || !d_ws) return fail(MHFD_ERR_INVALID_ARG, "null tiles or workspace");
+    BatchLayout L;
+    if (!batch_layout(p, n, max_pixels, &L))
+        return fail(MHFD_ERR_INVALID_ARG, "batch of %d tiles / %lld pixels outside [1, %d] / [1, 2^31)",
+                    n, (long long)max_pixels, MHFD_MAX_BATCH);
+    if (reinterpret_cast<uintptr_t>(d_ws) % kAlign)
+        return fail(MHFD_ERR_INVALID_ARG, "workspace not %zu-byte aligned", kAlign);
+    if (ws_bytes < L.total)
+        return fail(MHFD_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, L.total);
+    mhfd_status st = check_device(p);
+    if (st != MHFD_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* base = static_cast<char*>(d_ws);
+    float* stack = reinterpret_cast<float*>(base + L.stack);
+    auto* tiles = reinterpret_cast<mhfd::BatchTile*>(base + L.tiles);
+    auto* ctr = reinterpret_cast<mhfd::BatchCounters*>(base + L.ctr);
+    hipError_t e = mhfd::launch_batch_setup(d_tiles, n, max_pixels, p->K, p->max_h, p->max_w,
+                                            p->dtype, tiles, ctr, s);
+    if (e != hipSuccess) return hip_fail(e, "batch setup");
+    for (int cls = 2; cls >= 0; --cls) {
+        mhfd::BatchScales sc{};
+        std::vector<int> ks;
+        for (int k = 0; k < p->K; ++k)
+            if (mhfd::log_radius_class(p->padded[k]) == cls) ks.push_back(k);
+        std::sort(ks.begin(), ks.end(), [&](int a, int b) {
+            return p->padded[a] != p->padded[b] ? p->padded[a] > p->padded[b] : a < b;
+        });
+        for (int k : ks) {
+            sc.radius[sc.n] = p->padded[k];
+            sc.tap_off[sc.n] = p->tap_off[k];
+            sc.plane[sc.n] = k;
+            ++sc.n;
+        }
+        if (!sc.n) continue;
+        e = mhfd::launch_log_batch(cls, p->dtype, n, tiles, p->K, stack, p->d_taps, sc, ctr,
+                                   2 * p->n_cu, s);
+        if (e != hipSuccess) return hip_fail(e, "batched LoG launch");
+    }
+    mhfd::BatchLaunchArgs a{};
+    a.K = p->K;
+    a.n_tiles = n;
+    a.n_blk_bound = L.n_blk_bound;
+    a.nms_grid = 8 * p->n_cu;
+    a.reach = p->reach;
+    a.tau = p->threshold;
+    a.cap = L.cap;
+    a.stack = stack;
+    a.tiles = tiles;
+    a.blk_n = reinterpret_cast<int32_t*>(base + L.blk_n);
+    a.blk_o = reinterpret_cast<int32_t*>(base + L.blk_o);
+    a.blk_off = reinterpret_cast<int32_t*>(base + L.blk_off);
+    a.keep = reinterpret_cast<int32_t*>(base + L.keep);
+    a.keep_off = reinterpret_cast<int32_t*>(base + L.keep_off);
+    a.scan_sums = reinterpret_cast<int32_t*>(base + L.scan_sums);
+    a.pool = reinterpret_cast<mhfd::Cand*>(base + L.pool);
+    a.cand = reinterpret_cast<mhfd::Cand*>(base + L.cand);
+    a.d2max = p->d_d2max;
+    a.sigmas = p->d_sigmas;
+    a.ctr = ctr;
+    e = mhfd::launch_batch_tail(a, s);
+    if (e != hipSuccess) return hip_fail(e, "batched detection launch");
+    return MHFD_OK;
 }
 
 size_t mhfd_focus_workspace_size(mhfd_plan p, int32_t b, int32_t h, int32_t w) {

@@ -126,6 +126,72 @@ size_t scan_sums_ints(int64_t n);
 
 int nms_blocks_per_row(int w);
 
+// ---------------------------------------------------------------------------
+// Batched detection.  The setup kernel turns the caller's device descriptors
+// into this per-tile table and the work prefixes below.
+struct BatchTile {
+    const void* img;
+    long long pitch;
+    long long stack_off;    // first float of the tile's K planes in the stack
+    mhfd_blob* blobs;
+    mhfd_result* result;
+    int h, w;
+    int capacity;
+    int seg_rows;
+    int strips, segs;       // LoG workgroups per scale: strips * segs
+    int bpr;                // NMS workgroups per row
+    int item_base;          // prefix of strips * segs over earlier tiles
+    int nms_base;           // prefix of h * bpr over earlier tiles
+    int pad;
+};
+
+struct BatchCounters {
+    int32_t items_per_scale;  // sum over tiles of strips * segs
+    int32_t nms_blocks;       // sum over tiles of h * bpr
+    int32_t valid;            // 1 when every descriptor passed the checks
+    int32_t pool_used;
+    int32_t flags;
+    int32_t n_cand;
+    int32_t n_blobs;
+    int32_t work[3];          // persistent LoG work counters, one per radius class
+};
+
+// Scales of one radius class for the persistent LoG launch.
+struct BatchScales {
+    int n;
+    int radius[MHFD_MAX_SCALES];
+    int tap_off[MHFD_MAX_SCALES];
+    int plane[MHFD_MAX_SCALES];
+};
+
+hipError_t launch_log_batch(int cls, int in_dtype, int n_tiles, const BatchTile* tiles,
+                            int K, float* stack, const float* taps, const BatchScales& sc,
+                            BatchCounters* ctr, int grid, hipStream_t s);
+
+struct BatchLaunchArgs {
+    int K, n_tiles, n_blk_bound, nms_grid, reach;
+    float tau;
+    int64_t cap;
+    const float* stack;
+    const BatchTile* tiles;
+    int32_t *blk_n, *blk_o, *blk_off, *keep, *keep_off, *scan_sums;
+    Cand *pool, *cand;
+    const int32_t* d2max;   // null: no pruning
+    const float* sigmas;
+    BatchCounters* ctr;
+};
+
+hipError_t launch_batch_setup(const mhfd_tile* in, int n, long long max_pixels, int K, int max_h,
+                              int max_w, int dtype, BatchTile* tiles, BatchCounters* ctr,
+                              hipStream_t s);
+hipError_t launch_batch_tail(const BatchLaunchArgs& a, hipStream_t s);
+
+// Exclusive scan of n = min(n_host, *n_dev) ints (n_dev may be null):
+// out[0..n], total also to *total_out when given.  `sums` needs
+// scan_sums_ints(n_host) ints.
+void launch_batch_scan(const int32_t* in, int n_host, const int32_t* n_dev, int32_t* sums,
+                       int32_t* out, int32_t* total_out, hipStream_t s);
+
 // Device-synthesised taps of the soft focus score: for scale k, four tap sets
 // (FWD, D1, D2, ADJ) of four runs of padded[k] + 1 floats start at offset[k].
 enum { SOFT_FWD = 0, SOFT_D1 = 1, SOFT_D2 = 2, SOFT_ADJ = 3, SOFT_SETS = 4 };

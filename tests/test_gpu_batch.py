@@ -1,0 +1,158 @@
+"""Batched detection (mhfd_detect_batched) against the single-tile path and
+the oracle: identical per-tile results whatever the batch composition or
+order, HIP-graph replay equal to eager execution, replay with new
+descriptors without re-capture, and device-side rejection of bad
+descriptors."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2108_12050_amd import synth
+
+from parity import as_set, compare_candidates
+
+pytestmark = pytest.mark.gpu
+
+SIG10 = oracle.linear_sigmas(10, 1.0, 10.0)
+
+
+def plan_f32(max_hw=1024, **kw):
+    from paper_2108_12050_amd import Plan
+    args = dict(n_scales=10, sigma_min=1.0, sigma_max=10.0, threshold=0.1, overlap=0.5,
+                max_h=max_hw, max_w=max_hw)
+    args.update(kw)
+    return Plan(**args)
+
+
+def small_mixed(seed, n, scale=0.125):
+    tiles = synth.mixed_batch(seed, n, scale=scale)
+    return [torch.from_numpy(t).cuda() for t in tiles]
+
+
+def same(a, b):
+    assert a.count == b.count and a.n_candidates == b.n_candidates, (a.count, b.count)
+    assert torch.equal(a.yxk, b.yxk)
+    assert torch.equal(a.sigma, b.sigma) and torch.equal(a.response, b.response)
+
+
+def test_batched_equals_single_tile_path():
+    from paper_2108_12050_amd import detect_batched
+    plan = plan_f32()
+    imgs = small_mixed(1, 12)
+    got = detect_batched(plan, imgs)
+    for im, g in zip(imgs, got):
+        same(g, plan.detect(im))
+
+
+def test_batched_against_oracle():
+    from paper_2108_12050_amd import detect_batched
+    plan_c = plan_f32(overlap=1.0)
+    imgs = small_mixed(2, 6)
+    got = detect_batched(plan_c, imgs)
+    tau = float(np.float32(0.1))
+    for im, g in zip(imgs, got):
+        st = oracle.log_stack(im.cpu().numpy(), SIG10)
+        ykx, _ = oracle.candidates(st, tau)
+        d = plan_c.detect(im, return_stack=True)
+        compare_candidates(d.stack.cpu().numpy(), as_set(g.yxk.cpu().numpy()), st, as_set(ykx), tau)
+
+
+def test_order_and_composition_do_not_matter():
+    from paper_2108_12050_amd import detect_batched
+    plan = plan_f32()
+    imgs = small_mixed(3, 9)
+    ref = detect_batched(plan, imgs)
+    perm = [4, 0, 8, 2, 7, 1, 6, 3, 5]
+    got = detect_batched(plan, [imgs[i] for i in perm])
+    for j, i in enumerate(perm):
+        same(got[j], ref[i])
+    sub = detect_batched(plan, [imgs[2], imgs[2], imgs[5]])   # repeated tile
+    same(sub[0], ref[2])
+    same(sub[1], ref[2])
+    same(sub[2], ref[5])
+
+
+def test_u8_batch_and_segment_override():
+    from paper_2108_12050_amd import Plan, detect_batched
+    plan = Plan(n_scales=10, sigma_min=1, sigma_max=10, threshold=0.05, overlap=0.5, dtype="u8",
+                max_h=700, max_w=700)
+    imgs = [torch.from_numpy(synth.sem_tile(s, psf_sigma=p, H=h, W=w)).cuda()
+            for s, p, h, w in [(1, 0.0, 300, 260), (2, 2.0, 700, 512), (3, 1.0, 64, 700)]]
+    ref = [plan.detect(im) for im in imgs]
+    for seg in ([0, 0, 0], [32, 64, 96], [512, 4096, 128]):
+        got = detect_batched(plan, imgs, seg_rows=seg)
+        for g, r in zip(got, ref):
+            same(g, r)
+
+
+def test_graph_replay_and_new_descriptors():
+    from paper_2108_12050_amd import BatchRunner
+    plan = plan_f32()
+    a = small_mixed(4, 8)
+    b = small_mixed(5, 8)
+    px = max(sum(t.numel() for t in a), sum(t.numel() for t in b))
+    r = BatchRunner(plan, 8, px, 1 << 14)
+    r.set_tiles(a)
+    g = r.capture()
+    ref_a = [plan.detect(t) for t in a]
+    ref_b = [plan.detect(t) for t in b]
+    for rep in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        for d, ref in zip(r.detections(), ref_a):
+            same(d, ref)
+        _ = plan.detect(a[rep])       # eager work between replays
+    r.set_tiles(b)                    # new images and sizes, same graph
+    g.replay()
+    torch.cuda.synchronize()
+    for d, ref in zip(r.detections(), ref_b):
+        same(d, ref)
+
+
+def test_invalid_descriptor_is_rejected_on_device():
+    from paper_2108_12050_amd import BatchRunner, MHFDError
+    plan = plan_f32(max_hw=256)
+    imgs = [torch.rand(100, 90, device="cuda"), torch.rand(300, 50, device="cuda")]  # 300 > 256
+    r = BatchRunner(plan, 2, 100 * 90 + 300 * 50, 1024)
+    r.set_tiles(imgs)
+    r.run()
+    torch.cuda.synchronize()
+    flags = r.results[:2, 2].cpu().numpy() & 0xFFFFFFFF
+    assert np.all(flags & 4)
+    with pytest.raises(MHFDError):
+        r.detections()
+    # exceeding the pixel bound is rejected the same way
+    r2 = BatchRunner(plan, 2, 1000, 1024)
+    r2.set_tiles([imgs[0]])
+    r2.run()
+    torch.cuda.synchronize()
+    assert int(r2.results[0, 2]) & 4
+
+
+def test_full_size_mixed_batch():
+    """64 tiles with sizes drawn from {1024^2, 2048x1536, 3072x2048, 4096^2},
+    the batched workload's shapes (8 distinct rendered images, one per size
+    class and defocus pair, reused across the 64 descriptors): every tile equals
+    the single-tile path."""
+    from paper_2108_12050_amd import BatchRunner
+    print("full-size mixed batch", flush=True)
+    shapes = synth.mixed_batch_shapes(0, 64)
+    pool = {}
+    for i, (h, w, p) in enumerate(shapes):
+        key = (h, w, i % 2)
+        if key not in pool:
+            pool[key] = torch.from_numpy(synth.blob_field(1000 + len(pool), h, w, psf_sigma=p)).cuda()
+    imgs = [pool[(h, w, i % 2)] for i, (h, w, p) in enumerate(shapes)]
+    plan = plan_f32(max_hw=4096)
+    px = sum(t.numel() for t in imgs)
+    r = BatchRunner(plan, 64, px, 1 << 17)
+    r.set_tiles(imgs)
+    r.run()
+    got = r.detections()
+    ref = {}
+    for im, g in zip(imgs, got):
+        k = im.data_ptr()
+        if k not in ref:
+            ref[k] = plan.detect(im)
+        same(g, ref[k])
