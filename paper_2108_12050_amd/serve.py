@@ -1,0 +1,260 @@
+"""Continuous-batching focus-detection server on one GPU.
+
+Requests (one tile each) arrive at any time.  Each scheduler iteration:
+
+  1. completes finished batches (results copied out, the tiles' device
+     memory released); a batch whose execution raised completes its
+     requests with the error instead, and the loop goes on;
+  2. admits waiting requests in arrival order while the HBM budget allows:
+     the budget is charged the executor's fixed workspaces once and every
+     admitted tile while it is resident; an admitted tile's host-to-device
+     copy starts at once;
+  3. launches a batch on every idle slot with the admitted tiles that fit its
+     tile and pixel bounds -- so a batch formed from late arrivals runs while
+     an earlier one is still on the device.
+
+The scheduler only talks to an executor: `GpuExecutor` runs batches with
+mhfd_detect_batched on per-slot streams (plans, workspaces, descriptor
+tables and outputs stay on the device for the server's lifetime); tests use
+a host executor to exercise admission, ordering and failures without a GPU.
+Latency is arrival to result on the host, host-to-device copy included.
+"""
+from __future__ import annotations
+
+import collections
+import time
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass
+class Request:
+    rid: int
+    image: object                # host image (a pinned torch tensor for the GPU executor)
+    arrival: float               # time.perf_counter() seconds
+    h: int = 0
+    w: int = 0
+    staged: object = None        # executor's handle of the resident copy
+    admitted: float = 0.0
+    started: float = 0.0
+    done: float = 0.0
+    count: int = -1
+    n_candidates: int = -1
+    flags: int = 0
+    blobs: np.ndarray | None = None
+    error: str | None = None
+
+    def __post_init__(self):
+        if not self.h:
+            self.h, self.w = int(self.image.shape[0]), int(self.image.shape[1])
+
+    @property
+    def pixels(self) -> int:
+        return self.h * self.w
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+class Server:
+    """Admission by HBM budget and continuous batching over an executor's
+    slots (each slot runs one batch of up to `tiles` tiles / `pixels`
+    pixels at a time)."""
+
+    def __init__(self, executor, hbm_budget: int):
+        self.ex = executor
+        if executor.fixed_bytes > hbm_budget:
+            raise ValueError(f"executor workspaces need {executor.fixed_bytes} bytes, budget "
+                             f"{hbm_budget}")
+        self.budget = hbm_budget
+        self.resident = 0
+        self.waiting: collections.deque[Request] = collections.deque()
+        self.admitted: collections.deque[Request] = collections.deque()
+        self.running: dict[int, list[Request]] = {}
+        self.finished: list[Request] = []
+        self.rejected: list[Request] = []
+        self.peak_resident = 0
+        self.max_inflight = 0
+
+    def tile_bytes(self, r: Request) -> int:
+        return r.pixels * self.ex.bytes_per_pixel
+
+    def submit(self, req: Request) -> bool:
+        """Queue a request; one that can never fit a slot or the budget is
+        rejected at once (returns False, req.error set)."""
+        if req.pixels > self.ex.slot_pixels:
+            req.error = f"{req.pixels} pixels exceed a slot's {self.ex.slot_pixels}"
+        elif self.ex.fixed_bytes + self.tile_bytes(req) > self.budget:
+            req.error = "the tile can never fit the HBM budget"
+        if req.error:
+            req.done = time.perf_counter()
+            self.rejected.append(req)
+            return False
+        self.waiting.append(req)
+        return True
+
+    def busy(self) -> bool:
+        return bool(self.waiting or self.admitted or self.running)
+
+    def _complete(self) -> None:
+        for slot, batch in list(self.running.items()):
+            out = self.ex.poll(slot)
+            if out is None:
+                continue
+            now = time.perf_counter()
+            for r, res in zip(batch, out):
+                if isinstance(res, Exception):
+                    r.error = str(res)
+                else:
+                    r.count, r.n_candidates, r.flags, r.blobs = res
+                r.done = now
+                r.staged = None
+                self.resident -= self.tile_bytes(r)
+                self.finished.append(r)
+            del self.running[slot]
+
+    def _admit(self) -> None:
+        while self.waiting:
+            r = self.waiting[0]
+            need = self.tile_bytes(r)
+            if self.ex.fixed_bytes + self.resident + need > self.budget:
+                break
+            self.waiting.popleft()
+            r.staged = self.ex.stage(r)
+            r.admitted = time.perf_counter()
+            self.resident += need
+            self.peak_resident = max(self.peak_resident, self.resident)
+            self.admitted.append(r)
+
+    def _launch(self) -> None:
+        for slot in self.ex.idle_slots():
+            if slot in self.running or not self.admitted:
+                continue
+            batch, px = [], 0
+            while (self.admitted and len(batch) < self.ex.slot_tiles
+                   and px + self.admitted[0].pixels <= self.ex.slot_pixels):
+                r = self.admitted.popleft()
+                batch.append(r)
+                px += r.pixels
+            if not batch:
+                continue
+            try:
+                self.ex.launch(slot, batch)
+            except Exception as e:  # the batch fails, the server goes on
+                now = time.perf_counter()
+                for r in batch:
+                    r.error, r.done, r.staged = f"launch failed: {e}", now, None
+                    self.resident -= self.tile_bytes(r)
+                    self.finished.append(r)
+                continue
+            now = time.perf_counter()
+            for r in batch:
+                r.started = now
+            self.running[slot] = batch
+        self.max_inflight = max(self.max_inflight, len(self.running))
+
+    def step(self) -> None:
+        self._complete()
+        self._admit()
+        self._launch()
+
+    def drain(self, idle_sleep: float = 0.0002) -> None:
+        while self.busy():
+            self.step()
+            time.sleep(idle_sleep)
+
+    def run_trace(self, arrivals, images, idle_sleep: float = 0.0002) -> list:
+        """Submit images[i] at arrivals[i] seconds after the start, in real
+        time, and serve until every request has finished."""
+        t0 = time.perf_counter()
+        i, n = 0, len(arrivals)
+        while i < n or self.busy():
+            now = time.perf_counter() - t0
+            while i < n and arrivals[i] <= now:
+                self.submit(Request(i, images[i], t0 + arrivals[i]))
+                i += 1
+            self.step()
+            time.sleep(idle_sleep)
+        return sorted(self.finished + self.rejected, key=lambda r: r.rid)
+
+
+class GpuExecutor:
+    """Slots = BatchRunners, each with its own stream; tile copies on a
+    separate copy stream."""
+
+    def __init__(self, plan, n_slots: int = 2, slot_tiles: int = 32, slot_pixels: int = 1 << 27,
+                 capacity: int = 1 << 16, autotuner=None, keep_blobs: bool = False):
+        import torch
+
+        from .batch import BatchRunner
+        self.torch = torch
+        self.plan = plan
+        self.bytes_per_pixel = 1 if plan.dtype == "u8" else 4
+        self.slot_tiles, self.slot_pixels = slot_tiles, slot_pixels
+        self.autotuner, self.keep_blobs = autotuner, keep_blobs
+        self.copy_stream = torch.cuda.Stream()
+        self.runners = [BatchRunner(plan, slot_tiles, slot_pixels, capacity) for _ in range(n_slots)]
+        self.streams = [torch.cuda.Stream() for _ in range(n_slots)]
+        self.events = [None] * n_slots
+        self.batches = [None] * n_slots
+        self.fixed_bytes = sum(r.ws_bytes + r.blobs.numel() * 4 + r.results.numel() * 8
+                               for r in self.runners)
+
+    def stage(self, r: Request):
+        torch = self.torch
+        with torch.cuda.stream(self.copy_stream):
+            dev = torch.empty(r.image.shape, dtype=r.image.dtype, device=self.plan.device)
+            dev.copy_(r.image, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(self.copy_stream)
+        return dev, ev
+
+    def idle_slots(self):
+        return [i for i, b in enumerate(self.batches) if b is None]
+
+    def launch(self, slot: int, batch) -> None:
+        s = self.streams[slot]
+        for r in batch:
+            dev, ev = r.staged
+            s.wait_event(ev)
+            dev.record_stream(s)
+        imgs = [r.staged[0] for r in batch]
+        segs = ([self.autotuner.seg_rows_for(r.h, r.w) for r in batch]
+                if self.autotuner else None)
+        runner = self.runners[slot]
+        runner.set_tiles(imgs, segs, stream=s)
+        runner.run(s)
+        ev = self.torch.cuda.Event()
+        ev.record(s)
+        self.events[slot] = ev
+        self.batches[slot] = batch
+
+    def poll(self, slot: int):
+        ev = self.events[slot]
+        if ev is None or not ev.query():
+            return None
+        runner, n = self.runners[slot], len(self.batches[slot])
+        with self.torch.cuda.stream(self.streams[slot]):
+            res = runner.results[:n].cpu().numpy()
+            blobs = runner.blobs[:n].cpu().numpy() if self.keep_blobs else None
+        out = []
+        for i in range(n):
+            cnt = int(res[i, 0])
+            b = blobs[i, : min(cnt, blobs.shape[1])].copy() if blobs is not None else None
+            out.append((cnt, int(res[i, 1]), int(res[i, 2]) & 0xFFFFFFFF, b))
+        self.events[slot] = None
+        self.batches[slot] = None
+        return out
+
+
+def summarize(reqs, wall: float) -> dict:
+    ok = [r for r in reqs if r.error is None]
+    lat = np.array([r.latency for r in ok]) * 1e3
+    mpix = sum(r.pixels for r in ok) / 1e6
+    return {"requests": len(reqs), "served": len(ok),
+            "p50_ms": float(np.percentile(lat, 50)) if len(lat) else None,
+            "p99_ms": float(np.percentile(lat, 99)) if len(lat) else None,
+            "mean_ms": float(lat.mean()) if len(lat) else None,
+            "mpix": mpix, "mpix_per_s": mpix / wall}

@@ -1,0 +1,81 @@
+"""The continuous-batching server on the GPU: every result served in a mix
+of concurrent requests equals the single-tile detector's result for that tile
+alone, bit for bit; a small HBM budget queues requests but serves them all;
+a short trace of the serving workload's arrival and size mix completes."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2108_12050_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def make_plan(m):
+    from paper_2108_12050_amd import Plan
+    return Plan(n_scales=10, sigma_min=1.0, sigma_max=10.0, threshold=0.1, overlap=0.5,
+                max_h=m, max_w=m)
+
+
+def pinned(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).pin_memory()
+
+
+def alone(plan, host):
+    d = plan.detect(host.cuda())
+    raw = torch.cat([d.yxk, d.sigma.view(torch.int32)[:, None], d.response.view(torch.int32)[:, None]], 1)
+    return d.count, d.n_candidates, raw.cpu().numpy()
+
+
+def test_results_in_the_mix_equal_results_alone():
+    from paper_2108_12050_amd.serve import GpuExecutor, Server
+    plan = make_plan(2048)
+    sizes = [256, 512, 1024, 2048, 384, 640]
+    imgs = [pinned(synth.blob_field(50 + i, s, s + 32 * (i % 3))) for i, s in enumerate(sizes)]
+    ex = GpuExecutor(plan, n_slots=2, slot_tiles=4, slot_pixels=1 << 23, capacity=1 << 15,
+                     keep_blobs=True)
+    srv = Server(ex, ex.fixed_bytes + (1 << 30))
+    order = [0, 3, 1, 2, 5, 4, 3, 3, 0, 2, 1, 5, 4, 2, 3, 0]
+    arrivals = [0.002 * i for i in range(len(order))]
+    out = srv.run_trace(arrivals, [imgs[j] for j in order])
+    assert len(out) == len(order) and all(r.error is None for r in out)
+    assert srv.max_inflight == 2            # batches overlapped on the device
+    ref = {j: alone(plan, imgs[j]) for j in set(order)}
+    for r, j in zip(out, order):
+        cnt, nc, blobs = ref[j]
+        assert r.count == cnt and r.n_candidates == nc and r.flags == 0
+        np.testing.assert_array_equal(r.blobs, blobs)
+
+
+def test_small_budget_queues_and_serves_everything():
+    from paper_2108_12050_amd.serve import GpuExecutor, Server
+    plan = make_plan(1024)
+    imgs = [pinned(synth.blob_field(70 + i, 1024, 1024)) for i in range(3)]
+    ex = GpuExecutor(plan, n_slots=2, slot_tiles=4, slot_pixels=1 << 21, capacity=1 << 14)
+    budget = ex.fixed_bytes + 2 * 1024 * 1024 * 4          # two resident tiles at most
+    srv = Server(ex, budget)
+    out = srv.run_trace([0.0] * 9, [imgs[i % 3] for i in range(9)])
+    assert all(r.error is None for r in out) and len(out) == 9
+    assert srv.peak_resident + ex.fixed_bytes <= budget
+    ref = [alone(plan, im)[0] for im in imgs]
+    assert [r.count for r in out] == [ref[i % 3] for i in range(9)]
+
+
+def test_short_serving_trace():
+    """2 s of the serving workload: Poisson arrivals at 50 requests/s, square
+    sizes {512, 1024, 2048, 4096, 8192} with probabilities {.1, .2, .3, .3, .1},
+    content as the plain workload (a pool of rendered tiles per size)."""
+    from paper_2108_12050_amd.serve import GpuExecutor, Server, summarize
+    plan = make_plan(8192)
+    times, sizes = synth.arrivals(0, 50.0, 2.0)
+    pool = {s: pinned(synth.blob_field(900 + s, s, s)) for s in sorted(set(sizes))}
+    ex = GpuExecutor(plan, n_slots=2, slot_tiles=16, slot_pixels=1 << 27)
+    srv = Server(ex, 64 << 30)
+    import time
+    t0 = time.perf_counter()
+    out = srv.run_trace(times, [pool[s] for s in sizes])
+    stats = summarize(out, time.perf_counter() - t0)
+    print(stats, flush=True)
+    assert stats["served"] == len(sizes) > 50
+    small = next(r for r in out if r.h == 512)
+    assert small.count == alone(plan, pool[512])[0]
