@@ -9,15 +9,21 @@ the four tiles stay resident in HBM and step i runs the whole detector
 i mod 4.  `value` is MPix/s over the timed steps.
 
 Besides the headline line the JSON carries:
-  roofline       the LoG strip kernel (the dominant one), algorithmic FLOP per
-                 tile over its measured duration (HIP events on the library's
-                 stream), against the FP32 vector peak;
+  roofline       the LoG stack kernels (the dominant ones), algorithmic FLOP
+                 per tile over their measured duration (HIP events on the
+                 library's stream), against the FP32 vector peak;
   latency_ms     p50 / p99 of the device time per 4096^2 tile;
   focus          blob count per PSF sigma (the focus criterion);
-  cpu_baseline   the FP64 oracle on a bounded band of the same tile, on this
-                 host's cores.
+  forms.batched  64 fp32 tiles of sizes {1024^2, 2048x1536, 3072x2048, 4096^2}
+                 (8 rendered images reused across the 64 descriptors):
+                 autotuned segment heights, one captured HIP graph replayed,
+                 against a loop of single-tile calls on the same tiles;
+  forms.soft_score  8 x 2048^2 fp32, K = 10: forward and backward times;
+  forms.serving  a slice of the serving workload (Poisson arrivals at 50/s,
+                 sizes 512..8192), p50 / p99 latency and throughput;
+  cpu_baseline   the FP64 oracle on the same 4096^2 tile, on this host's cores.
 
-    python bench.py [--gpus 1] [--steps 200] [--warmup 10]
+    python bench.py [--gpus 1] [--steps 200] [--warmup 10] [--serve-seconds 10]
 """
 from __future__ import annotations
 
@@ -72,6 +78,133 @@ def cpu_baseline(img, rows: int) -> dict:
                       f"full detector (stack, maxima, prune) in FP64, one run, {dt:.1f} s"}
 
 
+def _timed(fn, reps):
+    import torch
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(reps)]
+    for e0, e1 in evs:
+        e0.record()
+        fn()
+        e1.record()
+    torch.cuda.synchronize()
+    return [e0.elapsed_time(e1) for e0, e1 in evs]
+
+
+def bench_batched(warmup: int) -> dict:
+    """64 mixed fp32 tiles: batched (autotuned, graph replay) vs single-tile calls."""
+    import numpy as np
+    import torch
+
+    from paper_2108_12050_amd import Plan, _lib, synth
+    from paper_2108_12050_amd.autotune import Autotuner
+    from paper_2108_12050_amd.batch import BatchRunner
+    shapes = synth.mixed_batch_shapes(0, 64)
+    pool = {}
+    for i, (h, w, p) in enumerate(shapes):
+        key = (h, w, i % 2)
+        if key not in pool:
+            pool[key] = torch.from_numpy(synth.blob_field(1000 + len(pool), h, w,
+                                                          psf_sigma=p)).cuda()
+    imgs = [pool[(h, w, i % 2)] for i, (h, w, p) in enumerate(shapes)]
+    px = sum(t.numel() for t in imgs)
+    plan = Plan(n_scales=K, sigma_min=1.0, sigma_max=10.0, threshold=0.1, overlap=OVERLAP,
+                max_h=4096, max_w=4096)
+    tuner = Autotuner(plan)
+    classes = sorted(set((h, w) for h, w, _ in shapes))
+    report = tuner.tune(classes, reps=3)
+    segs = [tuner.seg_rows_for(*t.shape) for t in imgs]
+    r = BatchRunner(plan, 64, px, 1 << 17)
+    r.set_tiles(imgs, segs)
+    g = r.capture()
+    for _ in range(max(1, warmup // 5)):
+        g.replay()
+    graph_ms = _timed(g.replay, 5)
+    eager_ms = _timed(r.run, 3)
+    counts_b = [d.count for d in r.detections()]
+    # single-tile calls on the same 64 tiles, default segment heights
+    L = _lib.load()
+    cap = 1 << 17
+    raws = torch.empty((cap, 5), dtype=torch.int32, device="cuda")
+    ress = torch.zeros((64, 3), dtype=torch.int64, device="cuda")
+    ws = torch.empty(plan.detect_workspace_bytes(4096, 4096), dtype=torch.uint8, device="cuda")
+    sptr = int(torch.cuda.current_stream().cuda_stream)
+
+    def plain_all():
+        for i, t in enumerate(imgs):
+            _lib.check(L.mhfd_detect(plan._handle, t.data_ptr(), t.shape[0], t.shape[1],
+                                     t.stride(0), raws.data_ptr(), cap, ress[i].data_ptr(), None,
+                                     ws.data_ptr(), ws.numel(), sptr), "mhfd_detect")
+    plain_all()
+    plain_ms = _timed(plain_all, 3)
+    counts_p = ress[:, 0].cpu().tolist()
+    mp = px / 1e6
+    return {"workload": "64 fp32 tiles, sizes {1024^2, 2048x1536, 3072x2048, 4096^2}, "
+                        "sigma 1..10, threshold 0.1, overlap 0.5",
+            "mpix": round(mp, 2),
+            "batched_graph_mpix_s": round(mp / (np.median(graph_ms) * 1e-3), 1),
+            "batched_eager_mpix_s": round(mp / (np.median(eager_ms) * 1e-3), 1),
+            "plain_per_tile_mpix_s": round(mp / (np.median(plain_ms) * 1e-3), 1),
+            "batched_graph_ms": round(float(np.median(graph_ms)), 3),
+            "plain_per_tile_ms": round(float(np.median(plain_ms)), 3),
+            "identical_counts": counts_b == counts_p,
+            "seg_rows": {f"{h}x{w}": report[(h, w)][0] for (h, w) in classes}}
+
+
+def bench_soft() -> dict:
+    """Soft focus score on 8 x 2048^2 fp32, K = 10: forward and backward."""
+    import numpy as np
+    import torch
+
+    from paper_2108_12050_amd import Plan, synth
+    B, Hs, Ws = 8, 2048, 2048
+    imgs = torch.from_numpy(synth.grad_batch(0, B, Hs, Ws)).cuda()
+    plan = Plan(n_scales=K, sigma_min=1.0, sigma_max=10.0, max_h=Hs, max_w=Ws)
+    sig = torch.arange(1, K + 1, dtype=torch.float32, device="cuda")
+    gb = torch.ones(B, device="cuda")
+    plan.focus_score(imgs, sig)
+    plan.focus_score_backward(imgs, sig, gb)
+    fwd = _timed(lambda: plan.focus_score(imgs, sig), 5)
+    bwd = _timed(lambda: plan.focus_score_backward(imgs, sig, gb), 3)
+    mp = B * Hs * Ws / 1e6
+    return {"workload": "8 x 2048^2 fp32, sigma 1..10 trainable, beta 50, tau 0.05",
+            "forward_ms": round(float(np.median(fwd)), 3),
+            "backward_ms": round(float(np.median(bwd)), 3),
+            "forward_mpix_s": round(mp / (np.median(fwd) * 1e-3), 1),
+            "backward_mpix_s": round(mp / (np.median(bwd) * 1e-3), 1)}
+
+
+def bench_serving(seconds: float) -> dict:
+    """Serving workload slice: Poisson arrivals at 50/s, square sizes
+    {512, 1024, 2048, 4096, 8192} with probabilities {.1, .2, .3, .3, .1},
+    plain-workload content from a pool of 2 rendered tiles per size in pinned
+    host memory, 64 GB HBM budget, two batch slots."""
+    import time
+
+    import torch
+
+    from paper_2108_12050_amd import Plan, synth
+    from paper_2108_12050_amd.serve import GpuExecutor, Server, summarize
+    times, sizes = synth.arrivals(0, 50.0, seconds)
+    pool = {}
+    for sz in sorted(set(sizes)):
+        for j in range(2):
+            pool[(sz, j)] = torch.from_numpy(synth.blob_field(2000 + 10 * sz + j, sz, sz)).pin_memory()
+    plan = Plan(n_scales=K, sigma_min=1.0, sigma_max=10.0, threshold=0.1, overlap=OVERLAP,
+                max_h=8192, max_w=8192)
+    ex = GpuExecutor(plan, n_slots=2, slot_tiles=16, slot_pixels=1 << 27)
+    srv = Server(ex, 64 << 30)
+    t0 = time.perf_counter()
+    out = srv.run_trace(times, [pool[(s, i % 2)] for i, s in enumerate(sizes)])
+    wall = time.perf_counter() - t0
+    st = summarize(out, wall)
+    return {"workload": f"{seconds:g} s of Poisson arrivals at 50/s, sizes 512..8192",
+            "requests": st["requests"], "served": st["served"],
+            "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+            "mpix_per_s": round(st["mpix_per_s"], 1),
+            "offered_mpix_per_s": round(st["mpix"] / seconds, 1),
+            "max_batches_in_flight": srv.max_inflight}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,6 +212,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-rows", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}); the multi-GPU "
@@ -170,11 +305,17 @@ def main() -> int:
         "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 3),
                      "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP32_VECTOR, 4), "traffic": traffic,
-                     "kernel": "log_strip_kernel (10 launches per tile, one per scale)",
+                     "kernel": "log_stack_kernel (2 launches per tile: radius classes 4..16 and 20..40)",
                      "flop_per_tile": FLOP_PER_PX * H * W,
                      "frac_of_unpacked_fp32_peak": round(achieved / PEAK_FP32_VECTOR_UNPACKED, 4)},
         "focus": {"psf_sigma": list(PSF), "blobs": counts, "candidates": cands},
     }
+    if not a.no_forms:
+        del stack, ws, raw
+        torch.cuda.empty_cache()
+        out["forms"] = {"batched": bench_batched(a.warmup),
+                        "soft_score": bench_soft(),
+                        "serving": bench_serving(a.serve_seconds)}
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(imgs_np[0], a.cpu_rows)
     print(json.dumps(out), flush=True)
