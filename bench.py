@@ -205,7 +205,88 @@ def bench_serving(seconds: float) -> dict:
             "max_batches_in_flight": srv.max_inflight}
 
 
+def traffic_run() -> int:
+    """Workload for the HBM-traffic counter runs (rocprofv3 --pmc FETCH_SIZE,
+    then --pmc WRITE_SIZE): first a plain elementwise copy of exactly 256 MiB
+    (the calibration of the counters), then three 4096^2 u8 tiles through
+    mhfd_log_stack and mhfd_detect_stack."""
+    import torch
+
+    from paper_2108_12050_amd import Plan, _lib, synth
+    torch.cuda.set_device(0)
+    src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    img = torch.from_numpy(synth.sem_tile(0, psf_sigma=0.0)).cuda()
+    plan = Plan(n_scales=K, sigma_min=1.0, sigma_max=10.0, threshold=TAU, overlap=OVERLAP,
+                dtype="u8", max_h=H, max_w=W)
+    L = _lib.load()
+    stack = torch.empty((K, H, W), dtype=torch.float32, device="cuda")
+    cap = H * W // 64
+    raw = torch.empty((cap, 5), dtype=torch.int32, device="cuda")
+    res = torch.zeros(3, dtype=torch.int64, device="cuda")
+    nb = plan.detect_workspace_bytes(H, W)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    sp = int(torch.cuda.current_stream().cuda_stream)
+    for _ in range(3):
+        _lib.check(L.mhfd_log_stack(plan._handle, img.data_ptr(), H, W, W, stack.data_ptr(), sp), "ls")
+        _lib.check(L.mhfd_detect_stack(plan._handle, stack.data_ptr(), H, W, raw.data_ptr(), cap,
+                                       res.data_ptr(), ws.data_ptr(), nb, sp), "ds")
+    torch.cuda.synchronize()
+    print("traffic run done", flush=True)
+    return 0
+
+
+def _pmc_per_kernel(path: str) -> dict:
+    """Mean counter value per dispatch of each kernel in a rocprofv3 --pmc CSV."""
+    import csv
+    import glob
+    import os
+    files = glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True)
+    acc = {}
+    for fn in files:
+        with open(fn) as f:
+            for row in csv.DictReader(f):
+                name = row["Kernel_Name"]
+                acc.setdefault(name, []).append(float(row["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
+def traffic_summarize(fetch_dir: str, write_dir: str) -> int:
+    """Write profiles/log_strip_4096_u8_traffic.{json,md} from the two counter runs."""
+    fetch, write = _pmc_per_kernel(fetch_dir), _pmc_per_kernel(write_dir)
+    cal = [k for k in fetch if "elementwise" in k and "neg" in k.lower()] or \
+          [k for k in fetch if "elementwise" in k]
+    expect_kib = (256 << 20) / 1024.0
+    f_scale = expect_kib / fetch[cal[0]]
+    w_scale = expect_kib / write[cal[0]]
+    lg = [k for k in fetch if "log_stack_kernel" in k]
+    tail = [k for k in fetch if "log_stack_kernel" not in k and k not in cal
+            and "mhfd" in k]
+    kib_f = sum(fetch[k] for k in lg)
+    kib_w = sum(write[k] for k in lg)
+    bytes_tile = (kib_f * f_scale + kib_w * w_scale) * 1024.0
+    algo = H * W * 1 + K * H * W * 4
+    out = {"kernel_source_sha256_16": kernel_source_hash(),
+           "workload": "4096x4096 u8, sigma 1..10, the two log_stack_kernel launches of one tile",
+           "bytes_per_launch": round(bytes_tile),
+           "fetch_kib_raw": round(kib_f, 1), "write_kib_raw": round(kib_w, 1),
+           "calibration_kernel": cal[0][:80], "fetch_scale": round(f_scale, 4),
+           "write_scale": round(w_scale, 4), "algorithmic_bytes": algo,
+           "tail_kernels_fetch_kib": {k.split("(")[0][-40:]: round(fetch[k], 1) for k in tail},
+           "tail_kernels_write_kib": {k.split("(")[0][-40:]: round(write.get(k, 0.0), 1) for k in tail}}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out, indent=1))
+    return 0
+
+
 def main() -> int:
+    if len(sys.argv) > 1 and sys.argv[1] == "--traffic-run":
+        return traffic_run()
+    if len(sys.argv) > 1 and sys.argv[1] == "--traffic-summarize":
+        return traffic_summarize(sys.argv[2], sys.argv[3])
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
