@@ -1,17 +1,15 @@
 // Detection after the LoG stack: 3x3x3 maxima, threshold, compaction into
 // canonical (y, x, k) order, one-shot overlap pruning, blob list.
 //
-//   nms        one workgroup per (row, 256-column chunk).  A thread owns one
-//              pixel and walks the scales keeping the 3x3 spatial maxima of
-//              planes k-1, k, k+1; vertical maxima are shared through LDS.
-//              A voxel is a candidate when it equals the maximum of its
-//              3x3x3 window (the maxpool-equality test of section 3, taken
-//              local in scale too) and is above the threshold.  Counts per
-//              thread become in-wave offsets with ballot + mbcnt over the
-//              bits of the count; each workgroup reserves one run in an
-//              unordered pool with a single atomic.
-//   scan       exclusive scan of the per-workgroup counts in workgroup order,
-//              i.e. in (y, x) order: the canonical position of every run.
+//   nms        one wave per (62-column strip, run of rows); a lane owns a
+//              column and walks down the rows.  A voxel is a candidate when
+//              it equals the maximum of its 3x3x3 window (the maxpool-equality
+//              test of section 3, taken local in scale too) and is above the
+//              threshold.  Counts per lane become in-wave offsets with ballot
+//              + mbcnt over the bits of the count; every (row, strip) cell
+//              owns a pool slot.
+//   scan       exclusive scan of the per-cell counts in cell order, i.e. in
+//              (y, x) order: the canonical position of every cell's run.
 //   order      copies each run from the pool to its canonical place.
 //   prune      one thread per candidate scans the candidates of the rows
 //              that can reach it (row ranges come from the scan) and applies
@@ -30,8 +28,10 @@ namespace mhfd {
 
 namespace {
 
-constexpr int NMS_T = 256;
-constexpr int SLOT = 16;  // pool records each NMS workgroup owns
+constexpr int NMS_W = 62;      // output columns per NMS wave (64 lanes with a 1-column halo)
+constexpr int NMS_ROWS = 32;   // rows per NMS wave
+constexpr int NMS_WAVES = 4;   // independent waves per NMS workgroup
+constexpr int SLOT = 16;       // pool records each (row, strip) cell owns
 constexpr int SCAN_T = 1024;
 
 __device__ __forceinline__ float fmax3(float a, float b, float c) { return fmaxf(a, fmaxf(b, c)); }
@@ -61,138 +61,117 @@ __global__ void init_counters_kernel(DetectCounters* ctr) {
     }
 }
 
-// One workgroup per (row, 256-column chunk).  Every thread first issues the
-// loads of its column's three rows for all K planes: indices are clamped so
-// that every load is in bounds and unconditional (no branch, so all 3K loads
-// are in flight together), and values from outside the image are replaced by
-// -inf afterwards.  Vertical 3-maxima go through LDS once, then each thread
-// tests its K voxels.
+// One wave per (strip of NMS_W = 62 output columns, run of NMS_ROWS rows); a
+// workgroup holds NMS_WAVES independent waves.  Lane l holds column
+// x0 - 1 + l, so lanes 0 and 63 are the strip's horizontal halo.  The wave
+// keeps rows y-1, y, y+1 of every plane in registers, rolling down the run
+// with row y+2 already in flight; horizontal neighbours come from lane
+// shuffles, so there is no LDS and no barrier.  Every (row, strip) cell
+// compacts its candidates with ballot/mbcnt offsets into its own pool slot
+// (SLOT records) and reserves the shared overflow region with one atomic only
+// when it has more.
 template <int K>
-__global__ __launch_bounds__(NMS_T) void nms_kernel(const float* __restrict__ st, int H, int W,
-                                                    float tau, int bpr,
-                                                    int32_t* __restrict__ blk_n,
-                                                    int32_t* __restrict__ blk_o,
-                                                    Cand* __restrict__ pool, int64_t cap,
-                                                    DetectCounters* __restrict__ ctr) {
-    __shared__ float vm[K][NMS_T + 2];
-    __shared__ int wave_tot[NMS_T / 64];
-    __shared__ int run_base;
-
-    const int tid = threadIdx.x;
-    const int blk = blockIdx.x;
-    const int y = blk / bpr;
-    const int x0 = (blk - y * bpr) * NMS_T;
-    const int x = x0 + tid;
-    const bool valid = x < W;
+__global__ __launch_bounds__(64 * NMS_WAVES) void nms_kernel(
+    const float* __restrict__ st, int H, int W, float tau, int bpr, int n_runs,
+    int32_t* __restrict__ blk_n, int32_t* __restrict__ blk_o, Cand* __restrict__ pool,
+    int64_t n_cells, int64_t cap, DetectCounters* __restrict__ ctr) {
+    const int lane = threadIdx.x & 63;
+    const int wid = blockIdx.x * NMS_WAVES + (threadIdx.x >> 6);  // (run, strip), strip fastest
+    if (wid >= n_runs * bpr) return;
+    const int strip = wid % bpr;
+    const int run = wid / bpr;
+    const int x0 = strip * NMS_W;
+    const int x = x0 - 1 + lane;
+    const bool col_ok = x >= 0 && x < W;
+    const bool is_out = lane >= 1 && lane <= NMS_W && col_ok;
+    const int xc = x < 0 ? 0 : (x >= W ? W - 1 : x);
     const size_t plane = static_cast<size_t>(H) * W;
-    const int yu = y > 0 ? y - 1 : 0;
-    const int yd = y + 1 < H ? y + 1 : H - 1;
-    const int xc = valid ? x : W - 1;
+    const int y0 = run * NMS_ROWS;
+    const int y1 = min(y0 + NMS_ROWS, H);
 
-    float cv[K], vmx[K];
-    {
-        const float* pc = st + static_cast<size_t>(y) * W + xc;
-        const float* pu = st + static_cast<size_t>(yu) * W + xc;
-        const float* pd = st + static_cast<size_t>(yd) * W + xc;
-        float u[K], d[K];
+    auto load_row = [&](int y, float* v) {
+        const bool ok = col_ok && y >= 0 && y < H;
+        const int yy = y < 0 ? 0 : (y >= H ? H - 1 : y);
+        const float* p = st + static_cast<size_t>(yy) * W + xc;
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = p[k * plane];
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = ok ? v[k] : -INFINITY;
+    };
+    float up[K], cur[K], dn[K], nx[K];
+    load_row(y0 - 1, up);
+    load_row(y0, cur);
+    load_row(y0 + 1, dn);
+    for (int y = y0; y < y1; ++y) {
+        load_row(y + 2, nx);  // in flight while row y is tested
+        float m3[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            cv[k] = pc[k * plane];
-            u[k] = pu[k * plane];
-            d[k] = pd[k * plane];
+            const float vm = fmax3(up[k], cur[k], dn[k]);
+            const float l = __shfl_up(vm, 1, 64);
+            const float r = __shfl_down(vm, 1, 64);
+            m3[k] = fmax3(vm, l, r);
         }
-        // rows clamped onto the centre row contribute nothing new to the max
-#pragma unroll
-        for (int k = 0; k < K; ++k) vmx[k] = valid ? fmax3(u[k], cv[k], d[k]) : -INFINITY;
-    }
-    // halo columns x0 - 1 and x0 + 256 (clamped, then masked)
-    if (tid == 0 || tid == NMS_T - 1) {
-        const int xh = tid == 0 ? x0 - 1 : x0 + NMS_T;
-        const bool ok = xh >= 0 && xh < W;
-        const int xs = ok ? xh : 0;
-        const int slot = tid == 0 ? 0 : NMS_T + 1;
-        const float* pc = st + static_cast<size_t>(y) * W + xs;
-        const float* pu = st + static_cast<size_t>(yu) * W + xs;
-        const float* pd = st + static_cast<size_t>(yd) * W + xs;
-        float hv[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) hv[k] = fmax3(pu[k * plane], pc[k * plane], pd[k * plane]);
-#pragma unroll
-        for (int k = 0; k < K; ++k) vm[k][slot] = ok ? hv[k] : -INFINITY;
-    }
-#pragma unroll
-    for (int k = 0; k < K; ++k) vm[k][tid + 1] = vmx[k];
-    __syncthreads();
-
-    unsigned mask = 0u;
-    {
-        float m_prev = -INFINITY;
-        float m_cur = fmax3(vm[0][tid], vm[0][tid + 1], vm[0][tid + 2]);
+        unsigned mask = 0u;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const float m_next =
-                k + 1 < K ? fmax3(vm[k + 1][tid], vm[k + 1][tid + 1], vm[k + 1][tid + 2]) : -INFINITY;
-            const float v = cv[k];
-            if (v > tau && v >= fmax3(m_prev, m_cur, m_next)) mask |= 1u << k;
-            m_prev = m_cur;
-            m_cur = m_next;
+            const float mp = k > 0 ? m3[k - 1] : -INFINITY;
+            const float mn = k + 1 < K ? m3[k + 1] : -INFINITY;
+            const float v = cur[k];
+            if (v > tau && v >= fmax3(mp, m3[k], mn)) mask |= 1u << k;
         }
-        if (!valid) mask = 0u;
-    }
-
-    const int c = __popc(mask);
-    int wtot;
-    const int pre = wave_exclusive_prefix<6>(c, &wtot);
-    const int lane = tid & 63, wv = tid >> 6;
-    if (lane == 0) wave_tot[wv] = wtot;
-    __syncthreads();
-    int woff = 0, n = 0;
-#pragma unroll
-    for (int i = 0; i < NMS_T / 64; ++i) {
-        woff += i < wv ? wave_tot[i] : 0;
-        n += wave_tot[i];
-    }
-    // The first SLOT records of a workgroup go to its own pool slot; a
-    // workgroup with more reserves room for the rest in the shared overflow
-    // region (one atomic, only for such workgroups).
-    if (tid == 0) {
+        if (!is_out) mask = 0u;
+        const int c = __popc(mask);
+        int n;
+        const int pre = wave_exclusive_prefix<6>(c, &n);
+        const int64_t cell = static_cast<int64_t>(y) * bpr + strip;
         int o = 0;
-        if (n > SLOT) {
-            o = atomicAdd(&ctr->pool_used, n - SLOT);
-            if (static_cast<int64_t>(o) + (n - SLOT) > cap)
-                atomicOr(&ctr->flags, MHFD_FLAG_CAND_OVERFLOW);
+        if (lane == 0) {
+            if (n > SLOT) {
+                o = atomicAdd(&ctr->pool_used, n - SLOT);
+                if (static_cast<int64_t>(o) + (n - SLOT) > cap)
+                    atomicOr(&ctr->flags, MHFD_FLAG_CAND_OVERFLOW);
+            }
+            blk_n[cell] = n;
+            blk_o[cell] = o;
         }
-        run_base = o;
-        blk_n[blk] = n;
-        blk_o[blk] = o;
-    }
-    __syncthreads();
-    if (c > 0) {
-        int j = woff + pre;  // rank of this thread's first record in the workgroup
-        Cand* own = pool + static_cast<int64_t>(blk) * SLOT;
-        Cand* over = pool + static_cast<int64_t>(gridDim.x) * SLOT + run_base - SLOT;
+        o = __shfl(o, 0, 64);
+        if (c > 0) {
+            int j = pre;
+            Cand* own = pool + cell * SLOT;
+            Cand* over = pool + n_cells * SLOT + o - SLOT;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                if (mask & (1u << k)) {
+                    Cand rec;
+                    rec.y = y;
+                    rec.x = x;
+                    rec.k = k;
+                    rec.r = cur[k];
+                    if (j < SLOT)
+                        own[j] = rec;
+                    else if (o + (j - SLOT) < cap)
+                        over[j] = rec;
+                    ++j;
+                }
+            }
+        }
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            if (mask & (1u << k)) {
-                Cand r;
-                r.y = y;
-                r.x = x;
-                r.k = k;
-                r.r = cv[k];
-                if (j < SLOT)
-                    own[j] = r;
-                else if (run_base + (j - SLOT) < cap)
-                    over[j] = r;
-                ++j;
-            }
+            up[k] = cur[k];
+            cur[k] = dn[k];
+            dn[k] = nx[k];
         }
     }
 }
 
 template <int K>
 void launch_nms_k(const DetectWorkspace& ws, int h, int w, float tau, hipStream_t s) {
-    nms_kernel<K><<<ws.n_blk, NMS_T, 0, s>>>(ws.stack, h, w, tau, ws.blk_per_row, ws.blk_n,
-                                             ws.blk_o, ws.pool, ws.cap, ws.ctr);
+    const int runs = (h + NMS_ROWS - 1) / NMS_ROWS;
+    const int waves = runs * ws.blk_per_row;
+    nms_kernel<K><<<(waves + NMS_WAVES - 1) / NMS_WAVES, 64 * NMS_WAVES, 0, s>>>(
+        ws.stack, h, w, tau, ws.blk_per_row, runs, ws.blk_n, ws.blk_o, ws.pool, ws.n_blk, ws.cap,
+        ws.ctr);
 }
 
 template <int... Ks>
@@ -427,7 +406,7 @@ __global__ void emit_kernel(const Cand* __restrict__ cand, const int32_t* __rest
 
 }  // namespace
 
-int nms_blocks_per_row(int w) { return (w + NMS_T - 1) / NMS_T; }
+int nms_blocks_per_row(int w) { return (w + NMS_W - 1) / NMS_W; }
 
 void launch_batch_scan(const int32_t* in, int n_host, const int32_t* n_dev, int32_t* sums,
                        int32_t* out, int32_t* total_out, hipStream_t s) {

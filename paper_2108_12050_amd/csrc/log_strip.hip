@@ -266,8 +266,8 @@ void log_stack_kernel(const T* __restrict__ img, int H, int W, long long pitch,
     const int strip = local % L.strips;
     const int seg = local / L.strips;
     const int x0 = strip * TW;
-    const int ys = seg * L.seg_rows;
-    const int ye = min(ys + L.seg_rows, H);
+    const int ys = seg * sc.seg_rows;
+    const int ye = min(ys + sc.seg_rows, H);
     const int bi = blockIdx.y;
     const T* im = img + static_cast<long long>(bi) * io.img_batch;
     float* out = io.out ? io.out + static_cast<long long>(bi) * io.out_batch +

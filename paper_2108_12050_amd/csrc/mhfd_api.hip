@@ -53,17 +53,6 @@ mhfd_status hip_fail(hipError_t e, const char* what) {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-// Segment height (rows per workgroup) of the strip kernel: a multiple of the
-// 32-row chunk aiming at about 1024 workgroups per scale.
-int strip_segment_rows(int h, int w) {
-    const int strips = (w + 63) / 64;
-    long long seg = (static_cast<long long>(h) * strips + 1023) / 1024;
-    seg = (seg + 31) / 32 * 32;
-    if (seg < 32) seg = 32;
-    if (seg > 1024) seg = 1024;
-    return static_cast<int>(seg);
-}
-
 // Taps of one scale in double, then rounded to float into `dst`
 // (layout documented with tap_block_floats).
 void synth_taps(double sigma, int R, int P, int polarity, float* dst) {
@@ -360,36 +349,64 @@ mhfd_status check_outputs(const mhfd_plan_s* p, int32_t h, int32_t w, const mhfd
 
 // Per radius class, the launch covering `scales` (largest radius first):
 // tap_off(k) gives the tap block of scale k, plane(k) its output plane.
+// Segment heights: every segment recomputes a 2R-row halo of row-pass
+// results, so a scale gets about 16R rows per workgroup (halo overhead near
+// 10%), halved while the launch would have fewer than ~3 workgroups per
+// resident slot.
 template <typename TapOff, typename Plane>
 std::vector<std::pair<int, mhfd::StackLaunch>> make_launches(const mhfd_plan_s* p, int h, int w,
                                                              const std::vector<int>& scales,
                                                              TapOff tap_off, Plane plane) {
     const int tw = mhfd::log_strip_width();
-    const int seg = strip_segment_rows(h, w);
+    const int ch = mhfd::log_chunk_rows();
     const int strips = (w + tw - 1) / tw;
-    const int segs = (h + seg - 1) / seg;
+    const int target = 6 * (p->n_cu > 0 ? p->n_cu : 256);
     std::vector<std::pair<int, mhfd::StackLaunch>> out;
     for (int cls = 2; cls >= 0; --cls) {
-        mhfd::StackLaunch L{};
-        L.strips = strips;
-        L.seg_rows = seg;
         std::vector<int> ks;
         for (int k : scales)
             if (mhfd::log_radius_class(p->padded[k]) == cls) ks.push_back(k);
+        if (ks.empty()) continue;
         std::sort(ks.begin(), ks.end(), [&](int a, int b) {
             return p->padded[a] != p->padded[b] ? p->padded[a] > p->padded[b] : a < b;
         });
+        const int hr = (h + ch - 1) / ch * ch;
+        std::vector<int> seg(ks.size());
+        for (size_t i = 0; i < ks.size(); ++i) {
+            int sgr = 16 * p->padded[ks[i]];
+            sgr = sgr < 2 * ch ? 2 * ch : (sgr > 1024 ? 1024 : sgr);
+            sgr = (sgr + ch - 1) / ch * ch;
+            seg[i] = sgr < hr ? sgr : hr;
+        }
+        auto blocks = [&]() {
+            long long n = 0;
+            for (size_t i = 0; i < ks.size(); ++i) n += static_cast<long long>(strips) * ((h + seg[i] - 1) / seg[i]);
+            return n;
+        };
+        while (blocks() < target) {
+            bool shrunk = false;
+            for (auto& sgr : seg)
+                if (sgr > ch) {
+                    sgr = ((sgr / 2 + ch - 1) / ch) * ch;
+                    shrunk = true;
+                }
+            if (!shrunk) break;
+        }
+        mhfd::StackLaunch L{};
+        L.strips = strips;
         int begin = 0;
-        for (int k : ks) {
+        for (size_t i = 0; i < ks.size(); ++i) {
+            const int k = ks[i];
             mhfd::StackScale& sc = L.sc[L.n++];
             sc.radius = p->padded[k];
             sc.tap_off = tap_off(k);
             sc.plane = plane(k);
+            sc.seg_rows = seg[i];
             sc.block_begin = begin;
-            sc.n_blocks = strips * segs;
+            sc.n_blocks = strips * ((h + seg[i] - 1) / seg[i]);
             begin += sc.n_blocks;
         }
-        if (L.n) out.emplace_back(cls, L);
+        out.emplace_back(cls, L);
     }
     return out;
 }

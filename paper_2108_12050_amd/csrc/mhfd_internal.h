@@ -52,14 +52,14 @@ struct StackScale {
     int plane;        // output plane index k
     int block_begin;  // first workgroup of the scale in the launch
     int n_blocks;     // strips * segments
+    int seg_rows;     // rows per workgroup segment (multiple of log_chunk_rows())
 };
 
 // All scales of one radius class, in launch order (largest radius first).
 struct StackLaunch {
     int n;
     int strips;       // strips of log_strip_width() columns
-    int seg_rows;     // rows per workgroup segment (multiple of log_chunk_rows())
-    int pad;
+    int pad0, pad1;
     StackScale sc[MHFD_MAX_SCALES];
 };
 
@@ -89,9 +89,6 @@ struct StackIO {
 hipError_t launch_log_class(int cls, int in_dtype, int epi, const void* img, int h, int w,
                             int64_t pitch, int batch, const float* taps, const StackLaunch& L,
                             const StackIO& io, hipStream_t s);
-
-// Workgroups of one scale (strips x segments) for an h x w image.
-int log_blocks_per_scale(int h, int w, int seg_rows);
 
 // Detection tail: stack -> candidates -> canonical order -> prune -> blobs.
 struct DetectWorkspace {
