@@ -9,9 +9,12 @@ the four tiles stay resident in HBM and step i runs the whole detector
 i mod 4.  `value` is MPix/s over the timed steps.
 
 Besides the headline line the JSON carries:
-  roofline       the LoG stack kernels (the dominant ones), algorithmic FLOP
-                 per tile over their measured duration (HIP events on the
-                 library's stream), against the FP32 vector peak;
+  roofline       the LoG stack (the dominant operation: the matrix-core
+                 launches of one tile), algorithmic FLOP per tile over its
+                 measured duration (HIP events on the library's stream),
+                 against the dense FP16 MFMA peak the kernels run on, with
+                 the FP32 vector view and, from the committed rocprofv3
+                 counter summary, HBM traffic and executed MFMA FLOP;
   latency_ms     p50 / p99 of the device time per 4096^2 tile;
   focus          blob count per PSF sigma (the focus criterion);
   forms.batched  64 fp32 tiles of sizes {1024^2, 2048x1536, 3072x2048, 4096^2}
@@ -49,11 +52,13 @@ RADII = [4 * s for s in range(1, K + 1)]
 FLOP_PER_PX = sum(11 * r + 6 for r in RADII)
 PEAK_FP32_VECTOR = 157.3e12   # MI355X FP32 vector, packed FMA
 PEAK_FP32_VECTOR_UNPACKED = 78.6e12
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "log_strip_4096_u8_traffic.json")
+PEAK_FP16_MFMA = 2.5e15       # MI355X dense FP16 matrix
+COUNTER_FILE = os.path.join(ROOT, "profiles", "log_mfma_4096_u8_counters.json")
+LOG_KERNEL = "log_mfma_u8_kernel"
 
 
 def kernel_source_hash() -> str:
-    p = os.path.join(ROOT, "paper_2108_12050_amd", "csrc", "log_strip.hip")
+    p = os.path.join(ROOT, "paper_2108_12050_amd", "csrc", "log_mfma.hip")
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
@@ -253,30 +258,35 @@ def _pmc_per_kernel(path: str) -> dict:
     return {k: sum(v) / len(v) for k, v in acc.items()}
 
 
-def traffic_summarize(fetch_dir: str, write_dir: str) -> int:
-    """Write profiles/log_strip_4096_u8_traffic.{json,md} from the two counter runs."""
+def traffic_summarize(fetch_dir: str, write_dir: str, mfma_dir: str) -> int:
+    """Write profiles/log_mfma_4096_u8_counters.json from three counter runs
+    of --traffic-run: FETCH_SIZE, WRITE_SIZE (KiB per dispatch, scaled by
+    what they read for the 256 MiB copy) and SQ_INSTS_VALU_MFMA_MOPS_F16
+    (512 FLOP per count)."""
     fetch, write = _pmc_per_kernel(fetch_dir), _pmc_per_kernel(write_dir)
+    mops = _pmc_per_kernel(mfma_dir)
     cal = [k for k in fetch if "elementwise" in k and "neg" in k.lower()] or \
           [k for k in fetch if "elementwise" in k]
     expect_kib = (256 << 20) / 1024.0
     f_scale = expect_kib / fetch[cal[0]]
     w_scale = expect_kib / write[cal[0]]
-    lg = [k for k in fetch if "log_stack_kernel" in k]
-    tail = [k for k in fetch if "log_stack_kernel" not in k and k not in cal
-            and "mhfd" in k]
+    lg = [k for k in fetch if LOG_KERNEL in k]
+    tail = [k for k in fetch if LOG_KERNEL not in k and k not in cal and "mhfd" in k]
     kib_f = sum(fetch[k] for k in lg)
     kib_w = sum(write[k] for k in lg)
     bytes_tile = (kib_f * f_scale + kib_w * w_scale) * 1024.0
+    mfma_flop = sum(v for k, v in mops.items() if LOG_KERNEL in k) * 512
     algo = H * W * 1 + K * H * W * 4
     out = {"kernel_source_sha256_16": kernel_source_hash(),
-           "workload": "4096x4096 u8, sigma 1..10, the two log_stack_kernel launches of one tile",
-           "bytes_per_launch": round(bytes_tile),
+           "workload": "4096x4096 u8, sigma 1..10, the log_mfma_u8_kernel launches of one tile",
+           "bytes_per_tile": round(bytes_tile),
            "fetch_kib_raw": round(kib_f, 1), "write_kib_raw": round(kib_w, 1),
            "calibration_kernel": cal[0][:80], "fetch_scale": round(f_scale, 4),
            "write_scale": round(w_scale, 4), "algorithmic_bytes": algo,
+           "mfma_flop_per_tile": round(mfma_flop),
            "tail_kernels_fetch_kib": {k.split("(")[0][-40:]: round(fetch[k], 1) for k in tail},
            "tail_kernels_write_kib": {k.split("(")[0][-40:]: round(write.get(k, 0.0), 1) for k in tail}}
-    with open(TRAFFIC_FILE, "w") as f:
+    with open(COUNTER_FILE, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out, indent=1))
     return 0
@@ -286,7 +296,7 @@ def main() -> int:
     if len(sys.argv) > 1 and sys.argv[1] == "--traffic-run":
         return traffic_run()
     if len(sys.argv) > 1 and sys.argv[1] == "--traffic-summarize":
-        return traffic_summarize(sys.argv[2], sys.argv[3])
+        return traffic_summarize(sys.argv[2], sys.argv[3], sys.argv[4])
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
@@ -359,11 +369,13 @@ def main() -> int:
     mpix = H * W / 1e6
     value = a.steps * mpix / elapsed
     achieved = FLOP_PER_PX * H * W / (log_ms.mean() * 1e-3)
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        tr = json.load(open(TRAFFIC_FILE))
+    traffic = mfma_flop = None
+    if os.path.exists(COUNTER_FILE):
+        tr = json.load(open(COUNTER_FILE))
         if tr.get("kernel_source_sha256_16") == kernel_source_hash():
-            traffic = tr.get("bytes_per_launch")
+            traffic = tr.get("bytes_per_tile")
+            mfma_flop = tr.get("mfma_flop_per_tile")
+    log_s = log_ms.mean() * 1e-3
     out = {
         "metric": "MPix/s, 10-scale LoG detect+NMS (plain vs batched); p99 latency/4096² tile",
         "value": round(value, 2),
@@ -383,12 +395,19 @@ def main() -> int:
         "latency_ms": {"p50": round(float(np.percentile(tile_ms, 50)), 4),
                        "p99": round(float(np.percentile(tile_ms, 99)), 4),
                        "log_stack_mean": round(float(log_ms.mean()), 4)},
-        "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 3),
-                     "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_FP32_VECTOR, 4), "traffic": traffic,
-                     "kernel": "log_stack_kernel (2 launches per tile: radius classes 4..16 and 20..40)",
+        "roofline": {"bound": "mfma", "achieved": round(achieved / 1e12, 3),
+                     "peak": PEAK_FP16_MFMA / 1e12, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_FP16_MFMA, 4), "traffic": traffic,
+                     "kernel": "log_mfma_u8_kernel (one launch per K-block shape, 5 per tile; "
+                               "split-FP16 MFMA, FP32 accumulate)",
                      "flop_per_tile": FLOP_PER_PX * H * W,
-                     "frac_of_unpacked_fp32_peak": round(achieved / PEAK_FP32_VECTOR_UNPACKED, 4)},
+                     "fp32_vector_view": {"peak": PEAK_FP32_VECTOR / 1e12,
+                                          "frac": round(achieved / PEAK_FP32_VECTOR, 4),
+                                          "frac_unpacked": round(achieved / PEAK_FP32_VECTOR_UNPACKED, 4)},
+                     "executed_mfma": None if mfma_flop is None else {
+                         "flop_per_tile": mfma_flop,
+                         "tflops": round(mfma_flop / log_s / 1e12, 2),
+                         "frac": round(mfma_flop / log_s / PEAK_FP16_MFMA, 4)}},
         "focus": {"psf_sigma": list(PSF), "blobs": counts, "candidates": cands},
     }
     if not a.no_forms:

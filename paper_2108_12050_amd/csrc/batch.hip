@@ -56,16 +56,23 @@ __device__ V block_exclusive_scan(V v, V* sh, V* total) {
     return incl - v;
 }
 
+// Rows per matrix-core work item: a wave recomputes 2 nkc - 1 intermediate
+// blocks of 16 rows per item, so items are tall unless the tile is short.
+__device__ int default_mfma_seg_rows(int h) {
+    const int hr = (h + 15) / 16 * 16;
+    return hr < 1024 ? hr : 1024;
+}
+
 __global__ __launch_bounds__(SETUP_T) void batch_setup_kernel(
     const mhfd_tile* __restrict__ in, int n, long long max_pixels, int K, int max_h, int max_w,
-    int dtype, BatchTile* __restrict__ tiles, BatchCounters* __restrict__ ctr) {
+    int dtype, int mfma, BatchTile* __restrict__ tiles, BatchCounters* __restrict__ ctr) {
     __shared__ long long shl[SETUP_T];
     __shared__ int bad_s;
     if (threadIdx.x == 0) bad_s = 0;
     __syncthreads();
     const int per = (n + SETUP_T - 1) / SETUP_T;
     const int t0 = min(n, static_cast<int>(threadIdx.x) * per), t1 = min(n, t0 + per);
-    long long items = 0, nms = 0, pix = 0;
+    long long items = 0, nms = 0, pix = 0, mitems = 0;
     for (int t = t0; t < t1; ++t) {
         const mhfd_tile d = in[t];
         bool ok = d.img && d.result && d.h >= 1 && d.w >= 1 && d.h <= max_h && d.w <= max_w &&
@@ -85,28 +92,35 @@ __global__ __launch_bounds__(SETUP_T) void batch_setup_kernel(
         bt.strips = (bt.w + 63) / 64;
         bt.segs = (bt.h + bt.seg_rows - 1) / bt.seg_rows;
         bt.bpr = (bt.w + NMS_T - 1) / NMS_T;
+        bt.mseg_rows = d.seg_rows && ok ? d.seg_rows : default_mfma_seg_rows(bt.h);
+        bt.mtiles_x = mfma ? (bt.w + 15) / 16 : 0;
+        bt.msegs = (bt.h + bt.mseg_rows - 1) / bt.mseg_rows;
         tiles[t] = bt;
+        mitems += static_cast<long long>(bt.mtiles_x) * bt.msegs;
         items += static_cast<long long>(bt.strips) * bt.segs;
         nms += static_cast<long long>(bt.h) * bt.bpr;
         pix += static_cast<long long>(bt.h) * bt.w;
     }
-    long long tot_items, tot_nms, tot_pix;
+    long long tot_items, tot_nms, tot_pix, tot_mitems;
     const long long b_items = block_exclusive_scan(items, shl, &tot_items);
     const long long b_nms = block_exclusive_scan(nms, shl, &tot_nms);
     const long long b_pix = block_exclusive_scan(pix, shl, &tot_pix);
-    long long ri = b_items, rn = b_nms, rp = b_pix;
+    const long long b_mitems = block_exclusive_scan(mitems, shl, &tot_mitems);
+    long long ri = b_items, rn = b_nms, rp = b_pix, rm = b_mitems;
     for (int t = t0; t < t1; ++t) {
         BatchTile& bt = tiles[t];
         bt.item_base = static_cast<int>(ri);
         bt.nms_base = static_cast<int>(rn);
+        bt.mitem_base = static_cast<int>(rm);
         bt.stack_off = rp * K;
         ri += static_cast<long long>(bt.strips) * bt.segs;
         rn += static_cast<long long>(bt.h) * bt.bpr;
         rp += static_cast<long long>(bt.h) * bt.w;
+        rm += static_cast<long long>(bt.mtiles_x) * bt.msegs;
     }
     __syncthreads();
     const bool valid = !bad_s && tot_pix <= max_pixels && tot_items * K < (1LL << 30) &&
-                       tot_nms < (1LL << 30);
+                       tot_nms < (1LL << 30) && tot_mitems * K < (1LL << 30);
     if (threadIdx.x == 0) {
         ctr->items_per_scale = valid ? static_cast<int>(tot_items) : 0;
         ctr->nms_blocks = valid ? static_cast<int>(tot_nms) : 0;
@@ -116,6 +130,8 @@ __global__ __launch_bounds__(SETUP_T) void batch_setup_kernel(
         ctr->n_cand = 0;
         ctr->n_blobs = 0;
         ctr->work[0] = ctr->work[1] = ctr->work[2] = 0;
+        ctr->mitems_per_scale = valid ? static_cast<int>(tot_mitems) : 0;
+        for (int i = 0; i < MFMA_SHAPES; ++i) ctr->mwork[i] = 0;
     }
     if (!valid) {
         for (int t = t0; t < t1; ++t) {
@@ -419,9 +435,10 @@ void launch_nms_batch(int K, const BatchLaunchArgs& a, hipStream_t s,
 }  // namespace
 
 hipError_t launch_batch_setup(const mhfd_tile* in, int n, long long max_pixels, int K, int max_h,
-                              int max_w, int dtype, BatchTile* tiles, BatchCounters* ctr,
-                              hipStream_t s) {
-    batch_setup_kernel<<<1, SETUP_T, 0, s>>>(in, n, max_pixels, K, max_h, max_w, dtype, tiles, ctr);
+                              int max_w, int dtype, int mfma, BatchTile* tiles,
+                              BatchCounters* ctr, hipStream_t s) {
+    batch_setup_kernel<<<1, SETUP_T, 0, s>>>(in, n, max_pixels, K, max_h, max_w, dtype, mfma,
+                                             tiles, ctr);
     return hipGetLastError();
 }
 

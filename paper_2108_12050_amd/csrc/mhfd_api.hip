@@ -29,6 +29,11 @@ struct mhfd_plan_s {
     int32_t* d_d2max = nullptr;  // K x K prune table (null: pruning off)
     float* d_sigmas = nullptr;   // device copy of sigmas (float)
     size_t tap_floats = 0;
+    // u8 plans: split-FP16 MFMA fragment tables of the scales whose radius
+    // the matrix-core kernel supports (mfma_off[k] < 0: strip kernel).
+    std::vector<int> mfma_off;   // first 8-half fragment of scale k
+    std::vector<float> mfma_out_scale;
+    uint16_t* d_frags = nullptr;
 };
 
 namespace {
@@ -53,10 +58,11 @@ mhfd_status hip_fail(hipError_t e, const char* what) {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-// Taps of one scale in double, then rounded to float into `dst`
-// (layout documented with tap_block_floats).
-void synth_taps(double sigma, int R, int P, int polarity, float* dst) {
-    std::vector<double> g(R + 1), h(R + 1);
+// One-sided taps of one scale in double: g[0..R] the unit-sum sampled
+// Gaussian, h[0..R] = (j^2 - V) g_j / sigma^4 with V its discrete variance.
+void gauss_taps(double sigma, int R, std::vector<double>& g, std::vector<double>& h) {
+    g.assign(R + 1, 0.0);
+    h.assign(R + 1, 0.0);
     double z = 0.0;
     for (int j = 0; j <= R; ++j) {
         g[j] = exp(-static_cast<double>(j) * j / (2.0 * sigma * sigma));
@@ -69,7 +75,18 @@ void synth_taps(double sigma, int R, int P, int polarity, float* dst) {
     }
     const double s4 = sigma * sigma * sigma * sigma;
     for (int j = 0; j <= R; ++j) h[j] = (static_cast<double>(j) * j - var) * g[j] / s4;
-    const double norm = (polarity == MHFD_BRIGHT ? -1.0 : 1.0) * sigma * sigma;
+}
+
+double polarity_norm(double sigma, int polarity) {
+    return (polarity == MHFD_BRIGHT ? -1.0 : 1.0) * sigma * sigma;
+}
+
+// Taps of one scale in double, then rounded to float into `dst`
+// (layout documented with tap_block_floats).
+void synth_taps(double sigma, int R, int P, int polarity, float* dst) {
+    std::vector<double> g, h;
+    gauss_taps(sigma, R, g, h);
+    const double norm = polarity_norm(sigma, polarity);
     for (int j = 0; j <= P; ++j) {
         const bool in = j <= R;
         dst[j] = in ? static_cast<float>(g[j]) : 0.0f;
@@ -258,6 +275,24 @@ mhfd_status mhfd_create_plan(const mhfd_config* cfg, mhfd_plan* out) {
     for (int k = 0; k < K; ++k)
         synth_taps(static_cast<double>(sig[k]), p->radii[k], p->padded[k], p->polarity,
                    host.data() + p->tap_off[k]);
+    // u8 plans: matrix-core fragment tables (codes 0..255, intensity code / 255).
+    std::vector<uint16_t> frags;
+    p->mfma_off.assign(K, -1);
+    p->mfma_out_scale.assign(K, 0.0f);
+    if (p->dtype == MHFD_U8) {
+        for (int k = 0; k < K; ++k) {
+            const int R = p->radii[k];
+            if (!mhfd::mfma_radius_ok(R)) continue;
+            std::vector<double> g, h;
+            gauss_taps(static_cast<double>(sig[k]), R, g, h);
+            const size_t at = frags.size();
+            frags.resize(at + mhfd::mfma_frag_halves(R));
+            p->mfma_off[k] = static_cast<int>(at / 8);
+            p->mfma_out_scale[k] = mhfd::mfma_build_frags(
+                g.data(), h.data(), R, polarity_norm(static_cast<double>(sig[k]), p->polarity),
+                255.0, 255.0, frags.data() + at);
+        }
+    }
 
     hipError_t e = hipGetDevice(&p->device);
     if (e == hipSuccess)
@@ -270,9 +305,13 @@ mhfd_status mhfd_create_plan(const mhfd_config* cfg, mhfd_plan* out) {
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->d_sigmas), sizeof(float) * K);
     if (e == hipSuccess && prune)
         e = hipMalloc(reinterpret_cast<void**>(&p->d_d2max), sizeof(int32_t) * K * K);
+    if (e == hipSuccess && !frags.empty())
+        e = hipMalloc(reinterpret_cast<void**>(&p->d_frags), sizeof(uint16_t) * frags.size());
     if (e != hipSuccess) {
         hipFree(p->d_taps);
         hipFree(p->d_sigmas);
+        hipFree(p->d_d2max);
+        hipFree(p->d_frags);
         delete p;
         return fail(MHFD_ERR_OOM, "plan tables: %s", hipGetErrorString(e));
     }
@@ -281,10 +320,14 @@ mhfd_status mhfd_create_plan(const mhfd_config* cfg, mhfd_plan* out) {
         e = hipMemcpy(p->d_sigmas, sig.data(), sizeof(float) * K, hipMemcpyHostToDevice);
     if (e == hipSuccess && prune)
         e = hipMemcpy(p->d_d2max, d2.data(), sizeof(int32_t) * K * K, hipMemcpyHostToDevice);
+    if (e == hipSuccess && !frags.empty())
+        e = hipMemcpy(p->d_frags, frags.data(), sizeof(uint16_t) * frags.size(),
+                      hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         hipFree(p->d_taps);
         hipFree(p->d_sigmas);
         hipFree(p->d_d2max);
+        hipFree(p->d_frags);
         delete p;
         return hip_fail(e, "copy of the plan tables");
     }
@@ -297,6 +340,7 @@ mhfd_status mhfd_destroy_plan(mhfd_plan p) {
     hipFree(p->d_taps);
     hipFree(p->d_sigmas);
     hipFree(p->d_d2max);
+    hipFree(p->d_frags);
     delete p;
     return MHFD_OK;
 }
@@ -423,10 +467,93 @@ std::vector<int> all_scales(const mhfd_plan_s* p) {
     return v;
 }
 
+// (nkr, nkc) shapes of the plan's matrix-core scales, costliest first.
+std::vector<std::pair<int, int>> mfma_shapes(const mhfd_plan_s* p) {
+    std::vector<std::pair<int, int>> shapes;
+    if (!p->d_frags) return shapes;
+    for (int k = 0; k < p->K; ++k) {
+        if (p->mfma_off[k] < 0) continue;
+        const mhfd::MfmaShape m = mhfd::mfma_shape(p->radii[k]);
+        const std::pair<int, int> key(m.nkr, m.nkc);
+        if (std::find(shapes.begin(), shapes.end(), key) == shapes.end()) shapes.push_back(key);
+    }
+    std::sort(shapes.begin(), shapes.end(), [](const std::pair<int, int>& a,
+                                               const std::pair<int, int>& b) {
+        return a.second != b.second ? a.second > b.second : a.first > b.first;
+    });
+    return shapes;
+}
+
+// Work counter of a shape in the batched launch (nkr in 1..4, nkc in 2..4).
+int mfma_slot(const std::pair<int, int>& key) {
+    static const int table[4][3] = {{0, -1, -1}, {1, 2, -1}, {-1, 3, 4}, {-1, -1, 5}};
+    if (key.first < 1 || key.first > 4 || key.second < 2 || key.second > 4) return -1;
+    return table[key.first - 1][key.second - 2];
+}
+
+// Matrix-core launches of the u8 scales that have fragment tables, one per
+// (nkr, nkc) instantiation, largest first.  A wave computes one 16-column
+// tile over a segment of rows and first recomputes 2 nkc - 1 intermediate
+// blocks of 16 rows; segments are about 8x that prologue, halved while a
+// launch has fewer than ~16 waves per compute unit.
+std::vector<std::pair<std::pair<int, int>, mhfd::MfmaLaunch>> mfma_launches(const mhfd_plan_s* p,
+                                                                             int h, int w) {
+    std::vector<std::pair<std::pair<int, int>, mhfd::MfmaLaunch>> out;
+    if (!p->d_frags) return out;
+    const int tiles_x = mhfd::mfma_wave_tiles(w);
+    const int mw = mhfd::mfma_waves_per_block();
+    const int groups_x = (tiles_x + mw - 1) / mw;
+    const long long target = 16LL * (p->n_cu > 0 ? p->n_cu : 256);
+    const int hr = (h + 15) / 16 * 16;
+    for (const auto& key : mfma_shapes(p)) {
+        std::vector<int> ks;
+        for (int k = 0; k < p->K; ++k) {
+            if (p->mfma_off[k] < 0) continue;
+            const mhfd::MfmaShape m = mhfd::mfma_shape(p->radii[k]);
+            if (m.nkr == key.first && m.nkc == key.second) ks.push_back(k);
+        }
+        int seg = 8 * 16 * (2 * key.second - 1);
+        seg = seg < hr ? seg : hr;
+        auto waves = [&]() {
+            return static_cast<long long>(ks.size()) * tiles_x * ((h + seg - 1) / seg);
+        };
+        while (waves() < target && seg > 16) seg = (seg / 2 + 15) / 16 * 16;
+        mhfd::MfmaLaunch L{};
+        L.tiles_x = tiles_x;
+        L.groups_x = groups_x;
+        int begin = 0;
+        for (int k : ks) {
+            const mhfd::MfmaShape m = mhfd::mfma_shape(p->radii[k]);
+            mhfd::MfmaScale& sc = L.sc[L.n++];
+            sc.rw8 = m.rw8;
+            sc.rw16 = m.rw16;
+            sc.frag_off = p->mfma_off[k];
+            sc.plane = k;
+            sc.seg_rows = seg;
+            sc.block_begin = begin;
+            sc.n_blocks = groups_x * ((h + seg - 1) / seg);
+            sc.out_scale = p->mfma_out_scale[k];
+            begin += sc.n_blocks;
+        }
+        out.emplace_back(key, L);
+    }
+    return out;
+}
+
 mhfd_status enqueue_log_stack(const mhfd_plan_s* p, const void* d_img, int h, int w,
                               int64_t pitch, float* stack, hipStream_t s) {
+    std::vector<int> strip_scales;
+    for (int k = 0; k < p->K; ++k)
+        if (p->mfma_off.empty() || p->mfma_off[k] < 0) strip_scales.push_back(k);
+    for (const auto& ml : mfma_launches(p, h, w)) {
+        hipError_t e = mhfd::launch_log_mfma(ml.first.first, ml.first.second,
+                                             static_cast<const uint8_t*>(d_img), h, w, pitch,
+                                             p->d_frags, ml.second, stack,
+                                             static_cast<long long>(h) * w, s);
+        if (e != hipSuccess) return hip_fail(e, "LoG stack (matrix cores) launch");
+    }
     auto launches = make_launches(
-        p, h, w, all_scales(p), [&](int k) { return p->tap_off[k]; }, [](int k) { return k; });
+        p, h, w, strip_scales, [&](int k) { return p->tap_off[k]; }, [](int k) { return k; });
     mhfd::StackIO io{};
     io.out = stack;
     io.plane_stride = static_cast<long long>(h) * w;
@@ -623,13 +750,39 @@ mhfd_status mhfd_detect_batched(mhfd_plan p, int32_t n, const mhfd_tile* d_tiles
     auto* tiles = reinterpret_cast<mhfd::BatchTile*>(base + L.tiles);
     auto* ctr = reinterpret_cast<mhfd::BatchCounters*>(base + L.ctr);
     hipError_t e = mhfd::launch_batch_setup(d_tiles, n, max_pixels, p->K, p->max_h, p->max_w,
-                                            p->dtype, tiles, ctr, s);
+                                            p->dtype, p->d_frags ? 1 : 0, tiles, ctr, s);
     if (e != hipSuccess) return hip_fail(e, "batch setup");
+    // Matrix-core scales (u8 plans), one persistent launch per shape, the
+    // costliest shape first; the same per-wave arithmetic as the single-tile
+    // path, so every tile's stack equals its single-tile stack.
+    for (const auto& key : mfma_shapes(p)) {
+        mhfd::MfmaBatchScales sc{};
+        for (int k = 0; k < p->K; ++k) {
+            if (p->mfma_off[k] < 0) continue;
+            const mhfd::MfmaShape m = mhfd::mfma_shape(p->radii[k]);
+            if (m.nkr != key.first || m.nkc != key.second) continue;
+            sc.rw8[sc.n] = m.rw8;
+            sc.rw16[sc.n] = m.rw16;
+            sc.frag_off[sc.n] = p->mfma_off[k];
+            sc.plane[sc.n] = k;
+            sc.out_scale[sc.n] = p->mfma_out_scale[k];
+            ++sc.n;
+        }
+        const int slot = mfma_slot(key);
+        if (slot < 0 || slot >= mhfd::MFMA_SHAPES)
+            return fail(MHFD_ERR_UNSUPPORTED, "no matrix-core counter for shape %d x %d",
+                        key.first, key.second);
+        e = mhfd::launch_log_mfma_batch(key.first, key.second, n, tiles, stack, p->d_frags, sc,
+                                        ctr, slot, 2 * p->n_cu, s);
+        if (e != hipSuccess) return hip_fail(e, "batched LoG (matrix cores) launch");
+    }
     for (int cls = 2; cls >= 0; --cls) {
         mhfd::BatchScales sc{};
         std::vector<int> ks;
         for (int k = 0; k < p->K; ++k)
-            if (mhfd::log_radius_class(p->padded[k]) == cls) ks.push_back(k);
+            if (mhfd::log_radius_class(p->padded[k]) == cls &&
+                (p->mfma_off.empty() || p->mfma_off[k] < 0))
+                ks.push_back(k);
         std::sort(ks.begin(), ks.end(), [&](int a, int b) {
             return p->padded[a] != p->padded[b] ? p->padded[a] > p->padded[b] : a < b;
         });

@@ -90,6 +90,49 @@ hipError_t launch_log_class(int cls, int in_dtype, int epi, const void* img, int
                             int64_t pitch, int batch, const float* taps, const StackLaunch& L,
                             const StackIO& io, hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// Scale-space operator of u8 tiles on the matrix cores (split-FP16 MFMA).
+// Window geometry of one radius: the row pass reads columns x0 - rw8 ...
+// (nkr K-blocks of 32), the column pass rows y0 - rw16 ... (nkc K-blocks).
+struct MfmaShape {
+    int rw8, rw16, nkr, nkc;
+};
+constexpr int MFMA_SHAPES = 7;  // (nkr, nkc) instantiations, plus one spare counter
+bool mfma_radius_ok(int radius);
+MfmaShape mfma_shape(int radius);
+// FP16 fragment table of one scale: (nkr + nkc) * 4 * 64 lanes * 8 halves.
+size_t mfma_frag_halves(int radius);
+// Builds the table from the one-sided taps g[0..R], h[0..R] (double), the
+// normalisation norm = s sigma^2, the input code scale (intensity = code /
+// in_scale) and the largest code; returns the exact power-of-two output scale.
+float mfma_build_frags(const double* g, const double* h, int R, double norm, double in_scale,
+                       double in_max, uint16_t* dst);
+int mfma_wave_tiles(int w);        // 16-column tiles of a row
+int mfma_waves_per_block();
+
+struct MfmaScale {
+    int rw8, rw16;
+    int frag_off;     // first 8-half fragment of the scale in the table
+    int plane;        // output plane index
+    int block_begin;  // first workgroup of the scale in the launch
+    int n_blocks;     // groups_x * segments
+    int seg_rows;     // rows per wave segment (multiple of 16)
+    float out_scale;  // exact power of two
+};
+
+// Scales sharing one (nkr, nkc) instantiation.
+struct MfmaLaunch {
+    int n;
+    int tiles_x;      // 16-column tiles
+    int groups_x;     // workgroups across a row: ceil(tiles_x / waves per block)
+    int pad;
+    MfmaScale sc[MHFD_MAX_SCALES];
+};
+
+hipError_t launch_log_mfma(int nkr, int nkc, const uint8_t* img, int h, int w, int64_t pitch,
+                           const uint16_t* frags, const MfmaLaunch& L, float* out,
+                           long long plane_stride, hipStream_t s);
+
 // Detection tail: stack -> candidates -> canonical order -> prune -> blobs.
 struct DetectWorkspace {
     const float* stack;      // K x h x w
@@ -140,6 +183,9 @@ struct BatchTile {
     int item_base;          // prefix of strips * segs over earlier tiles
     int nms_base;           // prefix of h * bpr over earlier tiles
     int pad;
+    // matrix-core items (u8 plans): 16-column tiles x row segments
+    int mtiles_x, msegs, mseg_rows;
+    int mitem_base;         // prefix of mtiles_x * msegs over earlier tiles
 };
 
 struct BatchCounters {
@@ -151,7 +197,21 @@ struct BatchCounters {
     int32_t n_cand;
     int32_t n_blobs;
     int32_t work[3];          // persistent LoG work counters, one per radius class
+    int32_t mitems_per_scale; // sum over tiles of mtiles_x * msegs (u8 plans)
+    int32_t mwork[MFMA_SHAPES];  // persistent matrix-core work counters, one per shape
 };
+
+// Scales of one (nkr, nkc) shape for the persistent matrix-core launch.
+struct MfmaBatchScales {
+    int n;
+    int rw8[MHFD_MAX_SCALES], rw16[MHFD_MAX_SCALES];
+    int frag_off[MHFD_MAX_SCALES], plane[MHFD_MAX_SCALES];
+    float out_scale[MHFD_MAX_SCALES];
+};
+
+hipError_t launch_log_mfma_batch(int nkr, int nkc, int n_tiles, const BatchTile* tiles,
+                                 float* stack, const uint16_t* frags, const MfmaBatchScales& sc,
+                                 BatchCounters* ctr, int slot, int grid, hipStream_t s);
 
 // Scales of one radius class for the persistent LoG launch.
 struct BatchScales {
@@ -178,9 +238,11 @@ struct BatchLaunchArgs {
     BatchCounters* ctr;
 };
 
+// mfma: the plan computes some scales on the matrix cores (u8 plans), so the
+// setup also numbers the matrix-core items.
 hipError_t launch_batch_setup(const mhfd_tile* in, int n, long long max_pixels, int K, int max_h,
-                              int max_w, int dtype, BatchTile* tiles, BatchCounters* ctr,
-                              hipStream_t s);
+                              int max_w, int dtype, int mfma, BatchTile* tiles,
+                              BatchCounters* ctr, hipStream_t s);
 hipError_t launch_batch_tail(const BatchLaunchArgs& a, hipStream_t s);
 
 // Exclusive scan of n = min(n_host, *n_dev) ints (n_dev may be null):
