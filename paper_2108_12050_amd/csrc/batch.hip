@@ -93,7 +93,7 @@ __global__ __launch_bounds__(SETUP_T) void batch_setup_kernel(
         bt.segs = (bt.h + bt.seg_rows - 1) / bt.seg_rows;
         bt.bpr = (bt.w + NMS_T - 1) / NMS_T;
         bt.mseg_rows = d.seg_rows && ok ? d.seg_rows : default_mfma_seg_rows(bt.h);
-        bt.mtiles_x = mfma ? (bt.w + 15) / 16 : 0;
+        bt.mtiles_x = mfma ? (bt.w + MFMA_WAVE_COLS - 1) / MFMA_WAVE_COLS : 0;
         bt.msegs = (bt.h + bt.mseg_rows - 1) / bt.mseg_rows;
         tiles[t] = bt;
         mitems += static_cast<long long>(bt.mtiles_x) * bt.msegs;

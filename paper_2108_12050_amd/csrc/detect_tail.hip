@@ -28,7 +28,6 @@ namespace mhfd {
 
 namespace {
 
-constexpr int NMS_W = 62;      // output columns per NMS wave (64 lanes with a 1-column halo)
 constexpr int NMS_ROWS = 32;   // rows per NMS wave
 constexpr int NMS_WAVES = 4;   // independent waves per NMS workgroup
 constexpr int SLOT = 16;       // pool records each (row, strip) cell owns
@@ -61,69 +60,105 @@ __global__ void init_counters_kernel(DetectCounters* ctr) {
     }
 }
 
-// One wave per (strip of NMS_W = 62 output columns, run of NMS_ROWS rows); a
-// workgroup holds NMS_WAVES independent waves.  Lane l holds column
-// x0 - 1 + l, so lanes 0 and 63 are the strip's horizontal halo.  The wave
-// keeps rows y-1, y, y+1 of every plane in registers, rolling down the run
-// with row y+2 already in flight; horizontal neighbours come from lane
-// shuffles, so there is no LDS and no barrier.  Every (row, strip) cell
-// compacts its candidates with ballot/mbcnt offsets into its own pool slot
-// (SLOT records) and reserves the shared overflow region with one atomic only
-// when it has more.
-template <int K>
+// Neighbour exchange across the whole wave (DPP wave shifts, no LDS): lane l
+// receives lane l - 1's value (shr) or lane l + 1's (shl); the lane without
+// a source receives `edge`.
+__device__ __forceinline__ float wave_shr1(float v, float edge) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+        __builtin_bit_cast(int, edge), __builtin_bit_cast(int, v), 0x138, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float lane_value(float v, int lane) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+}
+__device__ __forceinline__ float wave_shl1(float v, float edge) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+        __builtin_bit_cast(int, edge), __builtin_bit_cast(int, v), 0x130, 0xF, 0xF, false));
+}
+
+// One wave per (strip of 64 CW columns, run of NMS_ROWS rows); a workgroup
+// holds NMS_WAVES independent waves.  Lane l owns columns x0 + CW l ...
+// x0 + CW l + CW - 1, read as one aligned CW-float load per plane and row.
+// The wave keeps rows y-1, y, y+1 of every plane in registers, rolling down
+// the run with row y+2 already in flight.  Horizontal neighbours come from
+// DPP wave shifts; the two columns beyond the strip (x0 - 1 and x0 + 64 CW)
+// of every plane come from one more load per row (lanes k and 32 + k hold
+// plane k's left and right halo), reduced vertically in those lanes and
+// read out per plane.  Every (row, strip) cell compacts its candidates in
+// (x, k) order with ballot/mbcnt offsets into its own pool slot (SLOT
+// records) and reserves the shared overflow region with one atomic only when
+// it has more.
+template <int K, int CW>
 __global__ __launch_bounds__(64 * NMS_WAVES) void nms_kernel(
     const float* __restrict__ st, int H, int W, float tau, int bpr, int n_runs,
     int32_t* __restrict__ blk_n, int32_t* __restrict__ blk_o, Cand* __restrict__ pool,
     int64_t n_cells, int64_t cap, DetectCounters* __restrict__ ctr) {
+    static_assert(CW * K <= 32, "candidate mask is 32 bits");
+    typedef float Vec __attribute__((ext_vector_type(CW)));
     const int lane = threadIdx.x & 63;
     const int wid = blockIdx.x * NMS_WAVES + (threadIdx.x >> 6);  // (run, strip), strip fastest
     if (wid >= n_runs * bpr) return;
     const int strip = wid % bpr;
     const int run = wid / bpr;
-    const int x0 = strip * NMS_W;
-    const int x = x0 - 1 + lane;
-    const bool col_ok = x >= 0 && x < W;
-    const bool is_out = lane >= 1 && lane <= NMS_W && col_ok;
-    const int xc = x < 0 ? 0 : (x >= W ? W - 1 : x);
+    const int x0 = strip * 64 * CW;
+    const int xl = x0 + CW * lane;            // first column of the lane
+    const bool col_ok = xl < W;               // W % CW == 0: all CW columns or none
+    const int xc = col_ok ? xl : W - CW;
     const size_t plane = static_cast<size_t>(H) * W;
     const int y0 = run * NMS_ROWS;
     const int y1 = min(y0 + NMS_ROWS, H);
+    // halo lane: plane hk, column hx
+    const int hk = lane & 31;
+    const int hx = lane < 32 ? x0 - 1 : x0 + 64 * CW;
+    const bool h_ok = hk < K && hx >= 0 && hx < W;
+    const size_t h_off = static_cast<size_t>(h_ok ? hk : 0) * plane + (h_ok ? hx : 0);
 
-    auto load_row = [&](int y, float* v) {
-        const bool ok = col_ok && y >= 0 && y < H;
+    auto load_row = [&](int y, Vec* v, float& hv) {
+        const bool ok = y >= 0 && y < H;
         const int yy = y < 0 ? 0 : (y >= H ? H - 1 : y);
         const float* p = st + static_cast<size_t>(yy) * W + xc;
 #pragma unroll
-        for (int k = 0; k < K; ++k) v[k] = p[k * plane];
+        for (int k = 0; k < K; ++k) v[k] = *reinterpret_cast<const Vec*>(p + k * plane);
+        hv = st[h_off + static_cast<size_t>(yy) * W];
 #pragma unroll
-        for (int k = 0; k < K; ++k) v[k] = ok ? v[k] : -INFINITY;
+        for (int k = 0; k < K; ++k) v[k] = (ok && col_ok) ? v[k] : static_cast<Vec>(-INFINITY);
+        hv = (ok && h_ok) ? hv : -INFINITY;
     };
-    float up[K], cur[K], dn[K], nx[K];
-    load_row(y0 - 1, up);
-    load_row(y0, cur);
-    load_row(y0 + 1, dn);
+    Vec up[K], cur[K], dn[K], nx[K];
+    float hup, hcur, hdn, hnx;
+    load_row(y0 - 1, up, hup);
+    load_row(y0, cur, hcur);
+    load_row(y0 + 1, dn, hdn);
     for (int y = y0; y < y1; ++y) {
-        load_row(y + 2, nx);  // in flight while row y is tested
-        float m3[K];
+        load_row(y + 2, nx, hnx);  // in flight while row y is tested
+        const float hm = fmax3(hup, hcur, hdn);
+        Vec m3[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const float vm = fmax3(up[k], cur[k], dn[k]);
-            const float l = __shfl_up(vm, 1, 64);
-            const float r = __shfl_down(vm, 1, 64);
-            m3[k] = fmax3(vm, l, r);
+            Vec vm;
+#pragma unroll
+            for (int c = 0; c < CW; ++c) vm[c] = fmax3(up[k][c], cur[k][c], dn[k][c]);
+            const float left = wave_shr1(vm[CW - 1], lane_value(hm, k));
+            const float right = wave_shl1(vm[0], lane_value(hm, 32 + k));
+#pragma unroll
+            for (int c = 0; c < CW; ++c) {
+                const float l = c > 0 ? vm[c - 1] : left;
+                const float r = c + 1 < CW ? vm[c + 1] : right;
+                m3[k][c] = fmax3(l, vm[c], r);
+            }
         }
         unsigned mask = 0u;
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const float mp = k > 0 ? m3[k - 1] : -INFINITY;
-            const float mn = k + 1 < K ? m3[k + 1] : -INFINITY;
-            const float v = cur[k];
-            if (v > tau && v >= fmax3(mp, m3[k], mn)) mask |= 1u << k;
-        }
-        if (!is_out) mask = 0u;
-        const int c = __popc(mask);
+        for (int c = 0; c < CW; ++c)
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const float mp = k > 0 ? m3[k - 1][c] : -INFINITY;
+                const float mn = k + 1 < K ? m3[k + 1][c] : -INFINITY;
+                const float v = cur[k][c];
+                if (v > tau && v >= fmax3(mp, m3[k][c], mn)) mask |= 1u << (c * K + k);
+            }
+        const int cnt = __popc(mask);
         int n;
-        const int pre = wave_exclusive_prefix<6>(c, &n);
+        const int pre = wave_exclusive_prefix<6>(cnt, &n);
         const int64_t cell = static_cast<int64_t>(y) * bpr + strip;
         int o = 0;
         if (lane == 0) {
@@ -136,25 +171,27 @@ __global__ __launch_bounds__(64 * NMS_WAVES) void nms_kernel(
             blk_o[cell] = o;
         }
         o = __shfl(o, 0, 64);
-        if (c > 0) {
+        if (cnt > 0) {
             int j = pre;
             Cand* own = pool + cell * SLOT;
             Cand* over = pool + n_cells * SLOT + o - SLOT;
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                if (mask & (1u << k)) {
-                    Cand rec;
-                    rec.y = y;
-                    rec.x = x;
-                    rec.k = k;
-                    rec.r = cur[k];
-                    if (j < SLOT)
-                        own[j] = rec;
-                    else if (o + (j - SLOT) < cap)
-                        over[j] = rec;
-                    ++j;
+            for (int c = 0; c < CW; ++c)
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    if (mask & (1u << (c * K + k))) {
+                        Cand rec;
+                        rec.y = y;
+                        rec.x = xl + c;
+                        rec.k = k;
+                        rec.r = cur[k][c];
+                        if (j < SLOT)
+                            own[j] = rec;
+                        else if (o + (j - SLOT) < cap)
+                            over[j] = rec;
+                        ++j;
+                    }
                 }
-            }
         }
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -162,22 +199,30 @@ __global__ __launch_bounds__(64 * NMS_WAVES) void nms_kernel(
             cur[k] = dn[k];
             dn[k] = nx[k];
         }
+        hup = hcur;
+        hcur = hdn;
+        hdn = hnx;
     }
 }
 
-template <int K>
+template <int K, int CW>
 void launch_nms_k(const DetectWorkspace& ws, int h, int w, float tau, hipStream_t s) {
     const int runs = (h + NMS_ROWS - 1) / NMS_ROWS;
     const int waves = runs * ws.blk_per_row;
-    nms_kernel<K><<<(waves + NMS_WAVES - 1) / NMS_WAVES, 64 * NMS_WAVES, 0, s>>>(
+    nms_kernel<K, CW><<<(waves + NMS_WAVES - 1) / NMS_WAVES, 64 * NMS_WAVES, 0, s>>>(
         ws.stack, h, w, tau, ws.blk_per_row, runs, ws.blk_n, ws.blk_o, ws.pool, ws.n_blk, ws.cap,
         ws.ctr);
 }
 
 template <int... Ks>
-void launch_nms(int K, const DetectWorkspace& ws, int h, int w, float tau, hipStream_t s,
+void launch_nms(int K, int cw, const DetectWorkspace& ws, int h, int w, float tau, hipStream_t s,
                 std::integer_sequence<int, Ks...>) {
-    ((K == Ks + 1 ? launch_nms_k<Ks + 1>(ws, h, w, tau, s) : void()), ...);
+    if (cw == 2) {
+        ((K == Ks + 1 && Ks + 1 <= 16 ? launch_nms_k<Ks + 1, (Ks + 1 <= 16 ? 2 : 1)>(ws, h, w, tau, s)
+                                      : void()), ...);
+    } else {
+        ((K == Ks + 1 ? launch_nms_k<Ks + 1, 1>(ws, h, w, tau, s) : void()), ...);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -406,7 +451,7 @@ __global__ void emit_kernel(const Cand* __restrict__ cand, const int32_t* __rest
 
 }  // namespace
 
-int nms_blocks_per_row(int w) { return (w + NMS_W - 1) / NMS_W; }
+int nms_blocks_per_row(int w) { return (w + 63) / 64; }  // one column per lane: the most cells
 
 void launch_batch_scan(const int32_t* in, int n_host, const int32_t* n_dev, int32_t* sums,
                        int32_t* out, int32_t* total_out, hipStream_t s) {
@@ -421,13 +466,18 @@ hipError_t launch_detect_tail(const DetectWorkspace& ws, int K, int h, int w, fl
                               const int32_t* d2max, int reach, const float* sigmas_dev,
                               mhfd_blob* blobs, int capacity, mhfd_result* result, hipStream_t s) {
     init_counters_kernel<<<1, 64, 0, s>>>(ws.ctr);
-    launch_nms(K, ws, h, w, tau, s, std::make_integer_sequence<int, MHFD_MAX_SCALES>{});
-    launch_scan(ws.blk_n, ws.n_blk, nullptr, ws.scan_sums, ws.blk_off, &ws.ctr->n_cand, s);
+    // Two columns per lane when the planes allow aligned float2 loads.
+    DetectWorkspace wk = ws;
+    const int cw = (K <= 16 && w % 2 == 0 && reinterpret_cast<uintptr_t>(ws.stack) % 8 == 0) ? 2 : 1;
+    wk.blk_per_row = (w + 64 * cw - 1) / (64 * cw);
+    wk.n_blk = h * wk.blk_per_row;
+    launch_nms(K, cw, wk, h, w, tau, s, std::make_integer_sequence<int, MHFD_MAX_SCALES>{});
+    launch_scan(wk.blk_n, wk.n_blk, nullptr, ws.scan_sums, ws.blk_off, &ws.ctr->n_cand, s);
     const int grid = 1024;
-    order_kernel<<<grid, 256, 0, s>>>(ws.blk_off, ws.blk_o, ws.n_blk, ws.pool, ws.cand, ws.cap,
+    order_kernel<<<grid, 256, 0, s>>>(wk.blk_off, wk.blk_o, wk.n_blk, ws.pool, ws.cand, ws.cap,
                                       ws.ctr);
     if (d2max)
-        prune_kernel<<<grid, 256, 0, s>>>(ws.cand, ws.blk_off, ws.blk_per_row, h, K, d2max, reach,
+        prune_kernel<<<grid, 256, 0, s>>>(wk.cand, wk.blk_off, wk.blk_per_row, h, K, d2max, reach,
                                           ws.keep, ws.cap, ws.ctr);
     else
         keep_all_kernel<<<grid, 256, 0, s>>>(ws.keep, ws.cap, ws.ctr);

@@ -80,7 +80,13 @@ __device__ __forceinline__ half8_t codes_to_half(uint32_t d0, uint32_t d1) {
     return v - static_cast<half8_t>(static_cast<_Float16>(1024.0f));
 }
 
-// One wave's work item: a 16-column tile (x0) over rows [y0, y1).
+// One wave's work item: WT adjacent 16-column tiles from x0 over rows
+// [y0, y1).  Several tiles per wave would share the tap fragments and give
+// more independent MFMA chains, but their rings push the large shapes past
+// 256 VGPRs; measured on the 4096^2 workload one tile per wave is fastest.
+constexpr int WT = 1;
+static_assert(16 * WT == MFMA_WAVE_COLS, "wave width");
+
 struct WaveJob {
     const uint8_t* img;
     long long pitch;
@@ -100,20 +106,21 @@ struct WaveJob {
 // the window, partial 16-row or 16-column tiles) reflects every index as
 // often as needed and guards every store.  Keeping the regular body free of
 // the general code keeps its loop small and its memory waits exact.
-template <int NKR, int NKC>
+template <int NKR, int NKC, int NT>
 __device__ __forceinline__ bool regular_job(const WaveJob& J) {
     constexpr int NS = 2 * NKC;
     const int xw = J.x0 - J.rw8;
     // rows touched: y0 - rw16 ... y1 + 16 (NS + 2) (prefetch overrun)
-    return J.aligned && J.out_vec && (J.w & 7) == 0 && J.x0 + 16 <= J.w && xw >= -J.w &&
-           xw + 32 * NKR <= 2 * J.w && J.h >= J.rw16 + 16 * (NS + 3) &&
+    return J.aligned && J.out_vec && (J.w & 7) == 0 && J.x0 + 16 * NT <= J.w && xw >= -J.w &&
+           xw + 16 * (NT - 1) + 32 * NKR <= 2 * J.w && J.h >= J.rw16 + 16 * (NS + 3) &&
            ((J.y1 - J.y0) & 15) == 0;
 }
 
-template <int NKR, int NKC, bool EDGE>
+template <int NKR, int NKC, int NT, bool EDGE>
 __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __restrict__ fr,
                                          int lane) {
-    constexpr int NS = 2 * NKC;
+    constexpr int NS = 2 * NKC;        // ring of intermediate blocks
+    constexpr int D = 2;  // input prefetch depth (divides NS)
     const int g = lane >> 4;
     const int c = lane & 15;
     const int h = J.h, w = J.w, x0 = J.x0, y0 = J.y0, y1 = J.y1;
@@ -132,19 +139,21 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
         for (int t = 0; t < 4; ++t) ct[kb][t] = fr[((NKR + kb) * 4 + t) * 64 + lane];
 
     // Regular items: source column and byte order of each 8-byte group.
-    int src[NKR];
-    bool rev[NKR];
+    int src[NT][NKR];
+    bool rev[NT][NKR];
     if (!EDGE) {
 #pragma unroll
-        for (int kb = 0; kb < NKR; ++kb) {
-            const int gs = xw + 32 * kb + 8 * g;
-            rev[kb] = gs < 0 || gs >= w;
-            src[kb] = gs < 0 ? -gs - 8 : (gs >= w ? 2 * w - 8 - gs : gs);
-        }
+        for (int s = 0; s < NT; ++s)
+#pragma unroll
+            for (int kb = 0; kb < NKR; ++kb) {
+                const int gs = xw + 16 * s + 32 * kb + 8 * g;
+                rev[s][kb] = gs < 0 || gs >= w;
+                src[s][kb] = gs < 0 ? -gs - 8 : (gs >= w ? 2 * w - 8 - gs : gs);
+            }
     }
     // Raw codes of intermediate block hb (image rows y0 - rw16 + 16 hb ...):
-    // NKR pairs of dwords per lane, loaded two blocks ahead of their use.
-    typedef uint2 Raw[NKR];
+    // NKR pairs of dwords per lane and tile, loaded D blocks ahead of use.
+    typedef uint2 Raw[NT][NKR];
     auto fetch = [&](int hb, Raw& raw) {
         const int yr = y0 - J.rw16 + 16 * hb + c;
         int r;
@@ -155,56 +164,73 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
             r = min(r0, 2 * h - 1 - r0);
         }
         const uint8_t* row = J.img + static_cast<long long>(r) * J.pitch;
-        if (!EDGE) {
 #pragma unroll
-            for (int kb = 0; kb < NKR; ++kb) {
-                const uint2 v = *reinterpret_cast<const uint2*>(row + src[kb]);
-                const uint32_t lo = __builtin_amdgcn_perm(0u, v.y, 0x00010203u);  // bswap
-                const uint32_t hi = __builtin_amdgcn_perm(0u, v.x, 0x00010203u);
-                raw[kb] = rev[kb] ? make_uint2(lo, hi) : v;
-            }
-        } else if (fast) {
+        for (int s = 0; s < NT; ++s) {
+            if (!EDGE) {
 #pragma unroll
-            for (int kb = 0; kb < NKR; ++kb)
-                raw[kb] = *reinterpret_cast<const uint2*>(row + xw + 32 * kb + 8 * g);
-        } else {
-#pragma unroll
-            for (int kb = 0; kb < NKR; ++kb) {
-                uint32_t d[2] = {0u, 0u};
-#pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    const int col = reflect_index(xw + 32 * kb + 8 * g + i, w);
-                    d[i >> 2] |= static_cast<uint32_t>(row[col]) << (8 * (i & 3));
+                for (int kb = 0; kb < NKR; ++kb) {
+                    const uint2 v = *reinterpret_cast<const uint2*>(row + src[s][kb]);
+                    const uint32_t lo = __builtin_amdgcn_perm(0u, v.y, 0x00010203u);  // bswap
+                    const uint32_t hi = __builtin_amdgcn_perm(0u, v.x, 0x00010203u);
+                    raw[s][kb] = rev[s][kb] ? make_uint2(lo, hi) : v;
                 }
-                raw[kb] = make_uint2(d[0], d[1]);
+            } else if (fast) {
+#pragma unroll
+                for (int kb = 0; kb < NKR; ++kb)
+                    raw[s][kb] = *reinterpret_cast<const uint2*>(row + xw + 32 * kb + 8 * g);
+            } else {
+#pragma unroll
+                for (int kb = 0; kb < NKR; ++kb) {
+                    uint32_t d[2] = {0u, 0u};
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        const int col = reflect_index(xw + 32 * kb + 8 * g + i, w);
+                        d[i >> 2] |= static_cast<uint32_t>(row[col]) << (8 * (i & 3));
+                    }
+                    raw[s][kb] = make_uint2(d[0], d[1]);
+                }
             }
         }
     };
-    // Row pass of block hb from raw (then refilled with block hb + 2).
-    Raw raw[2];
-    auto rowpass = [&](int hb, Raw& rw, Slot& s) {
-        half8_t in[NKR];
+    // Row pass of block hb from raw (then refilled with block hb + D).
+    Raw raw[D];
+    auto rowpass = [&](int hb, Raw& rw, Slot (&out)[NT]) {
+        half8_t in[NT][NKR];
 #pragma unroll
-        for (int kb = 0; kb < NKR; ++kb) in[kb] = codes_to_half(rw[kb].x, rw[kb].y);
-        fetch(hb + 2, rw);
-        float4_t a = {0.f, 0.f, 0.f, 0.f}, b = {0.f, 0.f, 0.f, 0.f};
+        for (int s = 0; s < NT; ++s)
 #pragma unroll
-        for (int kb = 0; kb < NKR; ++kb) {
-            a = mfma16(in[kb], rt[kb][0], a);
-            b = mfma16(in[kb], rt[kb][2], b);
-            a = mfma16(in[kb], rt[kb][1], a);
-            b = mfma16(in[kb], rt[kb][3], b);
+            for (int kb = 0; kb < NKR; ++kb) in[s][kb] = codes_to_half(rw[s][kb].x, rw[s][kb].y);
+        fetch(hb + D, rw);
+        float4_t a[NT], b[NT];
+#pragma unroll
+        for (int s = 0; s < NT; ++s) a[s] = b[s] = (float4_t){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < NKR; ++kb)
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int s = 0; s < NT; ++s) {
+                    a[s] = mfma16(in[s][kb], rt[kb][q], a[s]);
+                    b[s] = mfma16(in[s][kb], rt[kb][2 + q], b[s]);
+                }
+#pragma unroll
+        for (int s = 0; s < NT; ++s) {
+            split(a[s], out[s].ah, out[s].al);
+            split(b[s], out[s].bh, out[s].bl);
         }
-        split(a, s.ah, s.al);
-        split(b, s.bh, s.bl);
     };
 
     const bool vec = !EDGE || (J.out_vec && x0 + 16 <= w);
-    auto store = [&](int t, float4_t v) {
+    auto store = [&](int t, int s, float4_t v) {
         const int y = y0 + 16 * t + c;
         if (EDGE && y >= y1) return;
-        float* o = J.plane + static_cast<long long>(y) * w + x0 + 4 * g;
-        if (!EDGE || vec) {
+        float* o = J.plane + static_cast<long long>(y) * w + x0 + 16 * s + 4 * g;
+        if (!EDGE) {
+            // Streaming store: the stack is read once, by the maxima pass, and
+            // measured end to end it is faster when the stores do not stay
+            // dirty in the caches that pass reads through.
+            __builtin_nontemporal_store(v, reinterpret_cast<float4_t*>(o));
+        } else if (vec) {
             *reinterpret_cast<float4_t*>(o) = v;
         } else {
 #pragma unroll
@@ -213,33 +239,54 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
         }
     };
 
-    Slot ring[NS];
-    fetch(0, raw[0]);
-    fetch(1, raw[1]);
+    Slot ring[NS][NT];
 #pragma unroll
-    for (int p = 0; p < NS - 1; ++p) rowpass(p, raw[p & 1], ring[p]);
+    for (int q = 0; q < D; ++q) fetch(q, raw[q]);
+#pragma unroll
+    for (int p = 0; p < NS - 1; ++p) rowpass(p, raw[p % D], ring[p]);
     for (int t0 = 0; t0 < ntiles; t0 += NS) {
 #pragma unroll
         for (int p = 0; p < NS; ++p) {
             const int t = t0 + p;
             if (t >= ntiles) break;
-            rowpass(t + NS - 1, raw[(p + NS - 1) & 1], ring[(p + NS - 1) % NS]);
-            float4_t ra = {0.f, 0.f, 0.f, 0.f}, rb = {0.f, 0.f, 0.f, 0.f};
+            rowpass(t + NS - 1, raw[(p + NS - 1) % D], ring[(p + NS - 1) % NS]);
+            float4_t ra[NT], rb[NT];
 #pragma unroll
-            for (int kb = 0; kb < NKC; ++kb) {
-                const Slot& sa = ring[(p + 2 * kb) % NS];
-                const Slot& sb = ring[(p + 2 * kb + 1) % NS];
-                const half8_t xh = cat(sa.ah, sb.ah), xl = cat(sa.al, sb.al);
-                const half8_t yh = cat(sa.bh, sb.bh), yl = cat(sa.bl, sb.bl);
-                ra = mfma16(xh, ct[kb][0], ra);
-                rb = mfma16(yh, ct[kb][2], rb);
-                ra = mfma16(xh, ct[kb][1], ra);
-                rb = mfma16(yh, ct[kb][3], rb);
-                ra = mfma16(xl, ct[kb][0], ra);
-                rb = mfma16(yl, ct[kb][2], rb);
-            }
-            store(t, (ra + rb) * J.out_scale);
+            for (int s = 0; s < NT; ++s) ra[s] = rb[s] = (float4_t){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kb = 0; kb < NKC; ++kb)
+#pragma unroll
+                for (int s = 0; s < NT; ++s) {
+                    const Slot& sa = ring[(p + 2 * kb) % NS][s];
+                    const Slot& sb = ring[(p + 2 * kb + 1) % NS][s];
+                    const half8_t xh = cat(sa.ah, sb.ah), xl = cat(sa.al, sb.al);
+                    const half8_t yh = cat(sa.bh, sb.bh), yl = cat(sa.bl, sb.bl);
+                    ra[s] = mfma16(xh, ct[kb][0], ra[s]);
+                    rb[s] = mfma16(yh, ct[kb][2], rb[s]);
+                    ra[s] = mfma16(xh, ct[kb][1], ra[s]);
+                    rb[s] = mfma16(yh, ct[kb][3], rb[s]);
+                    ra[s] = mfma16(xl, ct[kb][0], ra[s]);
+                    rb[s] = mfma16(yl, ct[kb][2], rb[s]);
+                }
+#pragma unroll
+            for (int s = 0; s < NT; ++s) store(t, s, (ra[s] + rb[s]) * J.out_scale);
         }
+    }
+}
+
+// A wave's job: both tiles through the regular body, or each existing tile
+// through the general one.
+template <int NKR, int NKC>
+__device__ __forceinline__ void run_job(WaveJob J, const half8_t* __restrict__ fr, int lane) {
+    if (regular_job<NKR, NKC, WT>(J)) {
+        wave_job<NKR, NKC, WT, false>(J, fr, lane);
+        return;
+    }
+    const int x0 = J.x0;
+    for (int s = 0; s < WT; ++s) {
+        J.x0 = x0 + 16 * s;
+        if (J.x0 >= J.w) break;
+        wave_job<NKR, NKC, 1, true>(J, fr, lane);
     }
 }
 
@@ -248,20 +295,21 @@ __global__ __launch_bounds__(64 * MW) void log_mfma_u8_kernel(
     const uint8_t* __restrict__ img, int h, int w, long long pitch, int aligned, int out_vec,
     const half8_t* __restrict__ frags, MfmaLaunch L, float* __restrict__ out,
     long long plane_stride) {
+    const int bid = blockIdx.x;
     int si = 0;
-    while (si + 1 < L.n && static_cast<int>(blockIdx.x) >= L.sc[si + 1].block_begin) ++si;
+    while (si + 1 < L.n && bid >= L.sc[si + 1].block_begin) ++si;
     const MfmaScale& sc = L.sc[si];
-    const int local = blockIdx.x - sc.block_begin;
+    const int local = bid - sc.block_begin;
     const int seg = local / L.groups_x;
-    const int tile = (local - seg * L.groups_x) * MW + (threadIdx.x >> 6);
-    if (tile >= L.tiles_x) return;
+    const int wcol = (local - seg * L.groups_x) * MW + (threadIdx.x >> 6);
+    if (wcol >= L.tiles_x) return;
     WaveJob J;
     J.img = img;
     J.pitch = pitch;
     J.plane = out + static_cast<long long>(sc.plane) * plane_stride;
     J.h = h;
     J.w = w;
-    J.x0 = tile * 16;
+    J.x0 = wcol * 16 * WT;
     J.y0 = seg * sc.seg_rows;
     J.y1 = min(J.y0 + sc.seg_rows, h);
     J.rw8 = sc.rw8;
@@ -269,14 +317,11 @@ __global__ __launch_bounds__(64 * MW) void log_mfma_u8_kernel(
     J.aligned = aligned;
     J.out_vec = out_vec;
     J.out_scale = sc.out_scale;
-    if (regular_job<NKR, NKC>(J))
-        wave_job<NKR, NKC, false>(J, frags + sc.frag_off, threadIdx.x & 63);
-    else
-        wave_job<NKR, NKC, true>(J, frags + sc.frag_off, threadIdx.x & 63);
+    run_job<NKR, NKC>(J, frags + sc.frag_off, threadIdx.x & 63);
 }
 
 // Persistent form over a batch of tiles: every wave pulls items (scale j of
-// the launch, tile, row segment, 16-column tile) from a counter.  Items are
+// the launch, tile, row segment, wave column) from a counter.  Items are
 // numbered scale-major, so a launch finishes its scales in order.
 template <int NKR, int NKC>
 __global__ __launch_bounds__(64 * MW) void log_mfma_u8_batch_kernel(
@@ -304,14 +349,14 @@ __global__ __launch_bounds__(64 * MW) void log_mfma_u8_batch_kernel(
         const BatchTile& t = tiles[lo];
         const int local = rem - t.mitem_base;
         const int seg = local / t.mtiles_x;
-        const int tile = local - seg * t.mtiles_x;
+        const int wcol = local - seg * t.mtiles_x;
         WaveJob J;
         J.img = static_cast<const uint8_t*>(t.img);
         J.pitch = t.pitch;
         J.h = t.h;
         J.w = t.w;
         J.plane = stack + t.stack_off + static_cast<long long>(sc.plane[j]) * t.h * t.w;
-        J.x0 = tile * 16;
+        J.x0 = wcol * 16 * WT;
         J.y0 = seg * t.mseg_rows;
         J.y1 = min(J.y0 + t.mseg_rows, t.h);
         J.rw8 = sc.rw8[j];
@@ -320,10 +365,7 @@ __global__ __launch_bounds__(64 * MW) void log_mfma_u8_batch_kernel(
         J.out_vec = (t.w % 4 == 0) && (t.stack_off % 4 == 0) &&
                     (reinterpret_cast<uintptr_t>(stack) % 16 == 0);
         J.out_scale = sc.out_scale[j];
-        if (regular_job<NKR, NKC>(J))
-            wave_job<NKR, NKC, false>(J, frags + sc.frag_off[j], lane);
-        else
-            wave_job<NKR, NKC, true>(J, frags + sc.frag_off[j], lane);
+        run_job<NKR, NKC>(J, frags + sc.frag_off[j], lane);
     }
 }
 
@@ -456,7 +498,7 @@ float mfma_build_frags(const double* g, const double* h, int R, double norm, dou
     return static_cast<float>(ldexp(1.0, -Sc));
 }
 
-int mfma_wave_tiles(int w) { return (w + 15) / 16; }
+int mfma_wave_tiles(int w) { return (w + MFMA_WAVE_COLS - 1) / MFMA_WAVE_COLS; }
 
 hipError_t launch_log_mfma_batch(int nkr, int nkc, int n_tiles, const BatchTile* tiles,
                                  float* stack, const uint16_t* frags, const MfmaBatchScales& sc,

@@ -98,6 +98,7 @@ struct MfmaShape {
     int rw8, rw16, nkr, nkc;
 };
 constexpr int MFMA_SHAPES = 7;  // (nkr, nkc) instantiations, plus one spare counter
+constexpr int MFMA_WAVE_COLS = 16;  // image columns per matrix-core wave
 bool mfma_radius_ok(int radius);
 MfmaShape mfma_shape(int radius);
 // FP16 fragment table of one scale: (nkr + nkc) * 4 * 64 lanes * 8 halves.
@@ -107,7 +108,7 @@ size_t mfma_frag_halves(int radius);
 // in_scale) and the largest code; returns the exact power-of-two output scale.
 float mfma_build_frags(const double* g, const double* h, int R, double norm, double in_scale,
                        double in_max, uint16_t* dst);
-int mfma_wave_tiles(int w);        // 16-column tiles of a row
+int mfma_wave_tiles(int w);        // matrix-core waves across a row (MFMA_WAVE_COLS each)
 int mfma_waves_per_block();
 
 struct MfmaScale {
@@ -123,7 +124,7 @@ struct MfmaScale {
 // Scales sharing one (nkr, nkc) instantiation.
 struct MfmaLaunch {
     int n;
-    int tiles_x;      // 16-column tiles
+    int tiles_x;      // waves across a row (mfma_wave_tiles)
     int groups_x;     // workgroups across a row: ceil(tiles_x / waves per block)
     int pad;
     MfmaScale sc[MHFD_MAX_SCALES];
@@ -183,7 +184,7 @@ struct BatchTile {
     int item_base;          // prefix of strips * segs over earlier tiles
     int nms_base;           // prefix of h * bpr over earlier tiles
     int pad;
-    // matrix-core items (u8 plans): 16-column tiles x row segments
+    // matrix-core items (u8 plans): wave columns x row segments
     int mtiles_x, msegs, mseg_rows;
     int mitem_base;         // prefix of mtiles_x * msegs over earlier tiles
 };

@@ -36,7 +36,9 @@ def test_results_in_the_mix_equal_results_alone():
                      keep_blobs=True)
     srv = Server(ex, ex.fixed_bytes + (1 << 30))
     order = [0, 3, 1, 2, 5, 4, 3, 3, 0, 2, 1, 5, 4, 2, 3, 0]
-    arrivals = [0.002 * i for i in range(len(order))]
+    # everything arrives at once: both slots receive a batch in the first
+    # scheduler step, so the overlap does not depend on device speed
+    arrivals = [0.0] * len(order)
     out = srv.run_trace(arrivals, [imgs[j] for j in order])
     assert len(out) == len(order) and all(r.error is None for r in out)
     assert srv.max_inflight == 2            # batches overlapped on the device
