@@ -5,7 +5,10 @@
 //
 //   setup      validate, per-tile LoG items / NMS workgroups / stack offsets
 //              and their prefix sums (one workgroup);
-//   LoG        persistent per radius class (log_strip.hip);
+//   LoG        u8 plans: persistent matrix-core waves per K-block shape
+//              (log_mfma.hip), the same per-wave arithmetic as the single-
+//              tile path; other scales: persistent strip workgroups per
+//              radius class (log_strip.hip);
 //   nms        persistent over every tile's (row, 256-column chunk) pieces; the
 //              same maxima test, slots and overflow pool as the single-tile
 //              path; the tile index rides in the upper bits of k;
