@@ -6,7 +6,10 @@ sigma = 1..10 (radius 4 sigma), threshold 0.05, overlap prune 0.5, rendered
 in focus and defocused by a Gaussian PSF of sigma 0, 1, 2 and 4 px (seed 0);
 the four tiles stay resident in HBM and step i runs the whole detector
 (LoG stack, 3x3x3 maxima, threshold, canonical list, prune, count) on tile
-i mod 4.  `value` is MPix/s over the timed steps.
+i mod 4, on stream i mod S (S = --streams, default 3: independent tiles
+overlap, as a caller issuing per-tile calls on several streams gets).
+`value` is MPix/s over the timed steps.  A single-stream pass of the same
+steps gives the per-tile latency and the LoG kernels' own duration.
 
 Besides the headline line the JSON carries:
   roofline       the LoG stack (the dominant operation: the matrix-core
@@ -305,6 +308,8 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--streams", type=int, default=3,
+                    help="streams the plain per-tile calls alternate over (independent tiles)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}); the multi-GPU "
@@ -324,47 +329,62 @@ def main() -> int:
                 dtype="u8", max_h=H, max_w=W)
     L = _lib.load()
     cap = H * W // 64
-    raw = torch.empty((cap, 5), dtype=torch.int32, device=dev)
-    res = [torch.zeros(3, dtype=torch.int64, device=dev) for _ in PSF]
-    stack = torch.empty((K, H, W), dtype=torch.float32, device=dev)
     nbytes = plan.detect_workspace_bytes(H, W)
-    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
-    stream = torch.cuda.current_stream()
-    sptr = int(stream.cuda_stream)
+    S = max(1, a.streams)
+    streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(S - 1)]
+    # per stream: stack, workspace, raw blob buffer, one result per image
+    bufs = [dict(stack=torch.empty((K, H, W), dtype=torch.float32, device=dev),
+                 ws=torch.empty(nbytes, dtype=torch.uint8, device=dev),
+                 raw=torch.empty((cap, 5), dtype=torch.int32, device=dev),
+                 res=[torch.full((3,), -1, dtype=torch.int64, device=dev) for _ in PSF])
+            for _ in range(S)]
 
-    def step(i, ev=None):
+    def step(i, n_streams, ev=None):
         j = i % len(PSF)
+        st = streams[i % n_streams]
+        b = bufs[i % n_streams]
+        sptr = int(st.cuda_stream)
         if ev is not None:
-            ev[0].record(stream)
-        _lib.check(L.mhfd_log_stack(plan._handle, imgs[j].data_ptr(), H, W, W, stack.data_ptr(),
-                                    sptr), "mhfd_log_stack")
+            ev[0].record(st)
+        _lib.check(L.mhfd_log_stack(plan._handle, imgs[j].data_ptr(), H, W, W,
+                                    b["stack"].data_ptr(), sptr), "mhfd_log_stack")
         if ev is not None:
-            ev[1].record(stream)
-        _lib.check(L.mhfd_detect_stack(plan._handle, stack.data_ptr(), H, W, raw.data_ptr(), cap,
-                                       res[j].data_ptr(), ws.data_ptr(), nbytes, sptr),
-                   "mhfd_detect_stack")
+            ev[1].record(st)
+        _lib.check(L.mhfd_detect_stack(plan._handle, b["stack"].data_ptr(), H, W,
+                                       b["raw"].data_ptr(), cap, b["res"][j].data_ptr(),
+                                       b["ws"].data_ptr(), nbytes, sptr), "mhfd_detect_stack")
         if ev is not None:
-            ev[2].record(stream)
+            ev[2].record(st)
 
-    for i in range(a.warmup):
-        step(i)
-    torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(a.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(a.steps):
-        step(i, evs[i])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
-    log_ms = np.array([e[0].elapsed_time(e[1]) for e in evs])
-    tile_ms = np.array([e[0].elapsed_time(e[2]) for e in evs])
+    def timed(n_streams):
+        for i in range(a.warmup):
+            step(i, n_streams)
+        torch.cuda.synchronize()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(a.steps)]
+        t0 = time.perf_counter()
+        for i in range(a.steps):
+            step(i, n_streams, evs[i])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        return (el, np.array([e[0].elapsed_time(e[1]) for e in evs]),
+                np.array([e[0].elapsed_time(e[2]) for e in evs]))
+
+    # One stream: per-tile latency and the LoG kernels' own duration (roofline).
+    el1, log_ms, tile_ms = timed(1)
+    res = bufs[0]["res"]
     counts = [int(r[0].item()) for r in res]
     cands = [int(r[1].item()) for r in res]
     flags = [int(r[2].item()) & 0xFFFFFFFF for r in res]
     if any(f & _lib.MHFD_FLAG_CAND_OVERFLOW for f in flags):
         print("candidate capacity overflow", file=sys.stderr)
         return 1
+    # S streams: independent tiles overlap (throughput, latency under load).
+    elapsed, _, tile_ms_s = timed(S) if S > 1 else (el1, log_ms, tile_ms)
+    for b in bufs[1:]:
+        got = [int(r[0].item()) for r in b["res"]]
+        if any(g != c for g, c in zip(got, counts) if g != -1):
+            print("stream results differ from the single-stream run", file=sys.stderr)
+            return 1
 
     mpix = H * W / 1e6
     value = a.steps * mpix / elapsed
@@ -391,10 +411,16 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": "SEM-tile 4096x4096 u8, sigma 1..10 (K=10, radius 4 sigma), "
                                "threshold 0.05, overlap 0.5, psf sigma {0,1,2,4}, plain per-tile",
-                   "tile": [H, W], "scales": K, "form": "plain"},
+                   "tile": [H, W], "scales": K, "form": "plain", "streams": S},
         "latency_ms": {"p50": round(float(np.percentile(tile_ms, 50)), 4),
                        "p99": round(float(np.percentile(tile_ms, 99)), 4),
-                       "log_stack_mean": round(float(log_ms.mean()), 4)},
+                       "log_stack_mean": round(float(log_ms.mean()), 4),
+                       "note": "one stream, tiles back to back"},
+        "single_stream": {"value": round(a.steps * mpix / el1, 2),
+                          "ms_per_step": round(el1 / a.steps * 1e3, 4)},
+        "under_load_latency_ms": {"p50": round(float(np.percentile(tile_ms_s, 50)), 4),
+                                  "p99": round(float(np.percentile(tile_ms_s, 99)), 4),
+                                  "note": f"{S} streams, per stream from the previous tile's end"},
         "roofline": {"bound": "mfma", "achieved": round(achieved / 1e12, 3),
                      "peak": PEAK_FP16_MFMA / 1e12, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP16_MFMA, 4), "traffic": traffic,
@@ -411,7 +437,7 @@ def main() -> int:
         "focus": {"psf_sigma": list(PSF), "blobs": counts, "candidates": cands},
     }
     if not a.no_forms:
-        del stack, ws, raw
+        del bufs
         torch.cuda.empty_cache()
         out["forms"] = {"batched": bench_batched(a.warmup),
                         "soft_score": bench_soft(),
