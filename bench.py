@@ -424,8 +424,8 @@ def main() -> int:
         "roofline": {"bound": "mfma", "achieved": round(achieved / 1e12, 3),
                      "peak": PEAK_FP16_MFMA / 1e12, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP16_MFMA, 4), "traffic": traffic,
-                     "kernel": "log_mfma_u8_kernel (one launch per K-block shape, 5 per tile; "
-                               "split-FP16 MFMA, FP32 accumulate)",
+                     "kernel": "log_mfma_u8_kernel (one launch per K-block shape, 3 per tile "
+                               "for sigma 1..10; split-FP16 MFMA, FP32 accumulate)",
                      "flop_per_tile": FLOP_PER_PX * H * W,
                      "fp32_vector_view": {"peak": PEAK_FP32_VECTOR / 1e12,
                                           "frac": round(achieved / PEAK_FP32_VECTOR, 4),

@@ -6,9 +6,11 @@
 //
 //   row pass     A = I * Tg, B = I * Th: M = 16 image rows, N = 16 output
 //                columns, K = 32 input columns per instruction; the band of
-//                2R + 1 taps spans ceil((16 + R + rw8) / 32) K-blocks.
+//                2R + 1 taps spans ceil((16 + R + rw8) / 32) K-blocks, the
+//                window starting rw8 = ceil8(R) columns left of the tile.
 //   column pass  R = [A | B] * [Thc ; Tgc]: M = 16 columns, N = 16 output
-//                rows, K = 32 intermediate rows per instruction.
+//                rows, K = 32 intermediate rows per instruction; the window
+//                starts R rows above the tile, ceil((16 + 2R) / 32) K-blocks.
 //
 // Precision.  u8 codes are exact in FP16.  Every tap and every intermediate is
 // split into an FP16 pair hi + lo (hi = nearest FP16, lo = nearest FP16 of the
@@ -44,7 +46,7 @@ typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
 constexpr int MW = 4;          // waves per workgroup, one 16-column tile each
-constexpr int MAX_RADIUS = 48;  // largest radius with NKC <= 4
+constexpr int MAX_RADIUS = 56;  // largest radius with nkr, nkc <= 4
 
 __device__ __forceinline__ float4_t mfma16(half8_t a, half8_t b, float4_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
@@ -91,7 +93,7 @@ struct WaveJob {
     const uint8_t* img;
     long long pitch;
     float* plane;     // output plane, row pitch w
-    int h, w, x0, y0, y1, rw8, rw16;
+    int h, w, x0, y0, y1, rw8, rwc;
     int aligned;      // 8-byte aligned rows: vector loads allowed in the interior
     int out_vec;      // 16-byte aligned output rows and w % 4 == 0
     float out_scale;
@@ -110,9 +112,9 @@ template <int NKR, int NKC, int NT>
 __device__ __forceinline__ bool regular_job(const WaveJob& J) {
     constexpr int NS = 2 * NKC;
     const int xw = J.x0 - J.rw8;
-    // rows touched: y0 - rw16 ... y1 + 16 (NS + 2) (prefetch overrun)
+    // rows touched: y0 - rwc ... y1 + 16 (NS + 2) (prefetch overrun)
     return J.aligned && J.out_vec && (J.w & 7) == 0 && J.x0 + 16 * NT <= J.w && xw >= -J.w &&
-           xw + 16 * (NT - 1) + 32 * NKR <= 2 * J.w && J.h >= J.rw16 + 16 * (NS + 3) &&
+           xw + 16 * (NT - 1) + 32 * NKR <= 2 * J.w && J.h >= J.rwc + 16 * (NS + 3) &&
            ((J.y1 - J.y0) & 15) == 0;
 }
 
@@ -151,11 +153,11 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
                 src[s][kb] = gs < 0 ? -gs - 8 : (gs >= w ? 2 * w - 8 - gs : gs);
             }
     }
-    // Raw codes of intermediate block hb (image rows y0 - rw16 + 16 hb ...):
+    // Raw codes of intermediate block hb (image rows y0 - rwc + 16 hb ...):
     // NKR pairs of dwords per lane and tile, loaded D blocks ahead of use.
     typedef uint2 Raw[NT][NKR];
     auto fetch = [&](int hb, Raw& raw) {
-        const int yr = y0 - J.rw16 + 16 * hb + c;
+        const int yr = y0 - J.rwc + 16 * hb + c;
         int r;
         if (EDGE) {
             r = reflect_index(yr, h);
@@ -290,8 +292,17 @@ __device__ __forceinline__ void run_job(WaveJob J, const half8_t* __restrict__ f
     }
 }
 
+// Two waves per SIMD where the live state fits 256 registers (no spills up
+// to nkc = 3 in the single-tile kernel, nkc = 2 in the persistent one, whose
+// item loop keeps more state); otherwise one wave per SIMD.
+template <int NKC>
+constexpr int mfma_waves() { return NKC <= 3 ? 2 : 1; }
+template <int NKC>
+constexpr int mfma_batch_waves() { return NKC <= 2 ? 2 : 1; }
+
 template <int NKR, int NKC>
-__global__ __launch_bounds__(64 * MW) void log_mfma_u8_kernel(
+__global__ __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(mfma_waves<NKC>(), 2)))
+void log_mfma_u8_kernel(
     const uint8_t* __restrict__ img, int h, int w, long long pitch, int aligned, int out_vec,
     const half8_t* __restrict__ frags, MfmaLaunch L, float* __restrict__ out,
     long long plane_stride) {
@@ -313,7 +324,7 @@ __global__ __launch_bounds__(64 * MW) void log_mfma_u8_kernel(
     J.y0 = seg * sc.seg_rows;
     J.y1 = min(J.y0 + sc.seg_rows, h);
     J.rw8 = sc.rw8;
-    J.rw16 = sc.rw16;
+    J.rwc = sc.rwc;
     J.aligned = aligned;
     J.out_vec = out_vec;
     J.out_scale = sc.out_scale;
@@ -324,7 +335,8 @@ __global__ __launch_bounds__(64 * MW) void log_mfma_u8_kernel(
 // the launch, tile, row segment, wave column) from a counter.  Items are
 // numbered scale-major, so a launch finishes its scales in order.
 template <int NKR, int NKC>
-__global__ __launch_bounds__(64 * MW) void log_mfma_u8_batch_kernel(
+__global__ __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(mfma_batch_waves<NKC>(), 2)))
+void log_mfma_u8_batch_kernel(
     int n_tiles, const BatchTile* __restrict__ tiles, float* __restrict__ stack,
     const half8_t* __restrict__ frags, MfmaBatchScales sc, BatchCounters* __restrict__ ctr,
     int slot) {
@@ -360,7 +372,7 @@ __global__ __launch_bounds__(64 * MW) void log_mfma_u8_batch_kernel(
         J.y0 = seg * t.mseg_rows;
         J.y1 = min(J.y0 + t.mseg_rows, t.h);
         J.rw8 = sc.rw8[j];
-        J.rw16 = sc.rw16[j];
+        J.rwc = sc.rwc[j];
         J.aligned = (t.pitch % 8 == 0) && (reinterpret_cast<uintptr_t>(t.img) % 8 == 0);
         J.out_vec = (t.w % 4 == 0) && (t.stack_off % 4 == 0) &&
                     (reinterpret_cast<uintptr_t>(stack) % 16 == 0);
@@ -432,10 +444,11 @@ MfmaShape mfma_shape(int radius) {
     MfmaShape s;
     s.rw8 = (radius + 7) / 8 * 8;
     if (s.rw8 < 8) s.rw8 = 8;
-    s.rw16 = (radius + 15) / 16 * 16;
-    if (s.rw16 < 16) s.rw16 = 16;
+    // The ring's 16-row grid may start anywhere, so the column window starts
+    // exactly R rows above the tile and spans 16 + 2R rows.
+    s.rwc = radius;
     s.nkr = (16 + radius + s.rw8 + 31) / 32;
-    s.nkc = s.rw16 / 16 + 1;
+    s.nkc = (16 + 2 * radius + 31) / 32;
     return s;
 }
 
@@ -489,7 +502,7 @@ float mfma_build_frags(const double* g, const double* h, int R, double norm, dou
                 for (int i = 0; i < 8; ++i) {
                     const int n = lane & 15, gq = lane >> 4;
                     const int r = 32 * kb + (i < 4 ? 4 * gq + i : 16 + 4 * gq + (i - 4));
-                    const int j = r - s.rw16 - n;
+                    const int j = r - s.rwc - n;
                     const int a = j < 0 ? -j : j;
                     double v = 0.0;
                     if (a <= R) v = ldexp(t < 2 ? ca[a] : cb[a], Sc);
@@ -511,11 +524,9 @@ hipError_t launch_log_mfma_batch(int nkr, int nkc, int n_tiles, const BatchTile*
                                                                 ctr, slot);               \
         return hipGetLastError();                                                         \
     }
-    MHFD_MFMA_BATCH_CASE(1, 2)
+    MHFD_MFMA_BATCH_CASE(1, 1)
     MHFD_MFMA_BATCH_CASE(2, 2)
-    MHFD_MFMA_BATCH_CASE(2, 3)
     MHFD_MFMA_BATCH_CASE(3, 3)
-    MHFD_MFMA_BATCH_CASE(3, 4)
     MHFD_MFMA_BATCH_CASE(4, 4)
 #undef MHFD_MFMA_BATCH_CASE
     return hipErrorInvalidValue;
@@ -527,11 +538,9 @@ hipError_t launch_log_mfma(int nkr, int nkc, const uint8_t* img, int h, int w, i
                            long long plane_stride, hipStream_t s) {
 #define MHFD_MFMA_CASE(A, B) \
     if (nkr == A && nkc == B) return launch_one<A, B>(img, h, w, pitch, frags, L, out, plane_stride, s);
-    MHFD_MFMA_CASE(1, 2)
+    MHFD_MFMA_CASE(1, 1)
     MHFD_MFMA_CASE(2, 2)
-    MHFD_MFMA_CASE(2, 3)
     MHFD_MFMA_CASE(3, 3)
-    MHFD_MFMA_CASE(3, 4)
     MHFD_MFMA_CASE(4, 4)
 #undef MHFD_MFMA_CASE
     return hipErrorInvalidValue;

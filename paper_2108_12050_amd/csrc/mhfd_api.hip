@@ -484,11 +484,11 @@ std::vector<std::pair<int, int>> mfma_shapes(const mhfd_plan_s* p) {
     return shapes;
 }
 
-// Work counter of a shape in the batched launch (nkr in 1..4, nkc in 2..4).
+// Work counter of a shape in the batched launch: the shapes are (n, n),
+// n = 1..4.
 int mfma_slot(const std::pair<int, int>& key) {
-    static const int table[4][3] = {{0, -1, -1}, {1, 2, -1}, {-1, 3, 4}, {-1, -1, 5}};
-    if (key.first < 1 || key.first > 4 || key.second < 2 || key.second > 4) return -1;
-    return table[key.first - 1][key.second - 2];
+    if (key.first != key.second || key.first < 1 || key.first > 4) return -1;
+    return key.first - 1;
 }
 
 // Matrix-core launches of the u8 scales that have fragment tables, one per
@@ -526,7 +526,7 @@ std::vector<std::pair<std::pair<int, int>, mhfd::MfmaLaunch>> mfma_launches(cons
             const mhfd::MfmaShape m = mhfd::mfma_shape(p->radii[k]);
             mhfd::MfmaScale& sc = L.sc[L.n++];
             sc.rw8 = m.rw8;
-            sc.rw16 = m.rw16;
+            sc.rwc = m.rwc;
             sc.frag_off = p->mfma_off[k];
             sc.plane = k;
             sc.seg_rows = seg;
@@ -762,7 +762,7 @@ mhfd_status mhfd_detect_batched(mhfd_plan p, int32_t n, const mhfd_tile* d_tiles
             const mhfd::MfmaShape m = mhfd::mfma_shape(p->radii[k]);
             if (m.nkr != key.first || m.nkc != key.second) continue;
             sc.rw8[sc.n] = m.rw8;
-            sc.rw16[sc.n] = m.rw16;
+            sc.rwc[sc.n] = m.rwc;
             sc.frag_off[sc.n] = p->mfma_off[k];
             sc.plane[sc.n] = k;
             sc.out_scale[sc.n] = p->mfma_out_scale[k];

@@ -93,11 +93,12 @@ hipError_t launch_log_class(int cls, int in_dtype, int epi, const void* img, int
 // ---------------------------------------------------------------------------
 // Scale-space operator of u8 tiles on the matrix cores (split-FP16 MFMA).
 // Window geometry of one radius: the row pass reads columns x0 - rw8 ...
-// (nkr K-blocks of 32), the column pass rows y0 - rw16 ... (nkc K-blocks).
+// (nkr K-blocks of 32), the column pass rows y0 - rwc ... (nkc K-blocks).
+// Shapes are (n, n), n = 1..4, for radii 0..56.
 struct MfmaShape {
-    int rw8, rw16, nkr, nkc;
+    int rw8, rwc, nkr, nkc;
 };
-constexpr int MFMA_SHAPES = 7;  // (nkr, nkc) instantiations, plus one spare counter
+constexpr int MFMA_SHAPES = 4;  // (nkr, nkc) instantiations: (1,1) ... (4,4)
 constexpr int MFMA_WAVE_COLS = 16;  // image columns per matrix-core wave
 bool mfma_radius_ok(int radius);
 MfmaShape mfma_shape(int radius);
@@ -112,7 +113,7 @@ int mfma_wave_tiles(int w);        // matrix-core waves across a row (MFMA_WAVE_
 int mfma_waves_per_block();
 
 struct MfmaScale {
-    int rw8, rw16;
+    int rw8, rwc;
     int frag_off;     // first 8-half fragment of the scale in the table
     int plane;        // output plane index
     int block_begin;  // first workgroup of the scale in the launch
@@ -205,7 +206,7 @@ struct BatchCounters {
 // Scales of one (nkr, nkc) shape for the persistent matrix-core launch.
 struct MfmaBatchScales {
     int n;
-    int rw8[MHFD_MAX_SCALES], rw16[MHFD_MAX_SCALES];
+    int rw8[MHFD_MAX_SCALES], rwc[MHFD_MAX_SCALES];
     int frag_off[MHFD_MAX_SCALES], plane[MHFD_MAX_SCALES];
     float out_scale[MHFD_MAX_SCALES];
 };

@@ -1,10 +1,10 @@
 """Matrix-core (split-FP16 MFMA) LoG stack of 8-bit tiles against the FP64
 oracle.
 
-The scale list reaches every kernel instantiation: radius 0 and 4 (one
-row-pass K-block, two column-pass K-blocks), 9 (2, 2), 18 (2, 3), 28 (3, 3),
-36 (3, 4), 46 (4, 4), and 50, above the matrix-core limit of 48, which the
-strip kernel computes in the same call.  Shapes cover tiles narrower than
+The scale list reaches every kernel instantiation (row-pass, column-pass
+K-blocks): radius 0 and 4 (1, 1), 9 and 18 (2, 2), 28 and 36 (3, 3), 46 and
+54 (4, 4), and 60, above the matrix-core limit of 56, which the strip kernel
+computes in the same call.  Shapes cover tiles narrower than
 the taps (repeated reflection), widths that are not multiples of 16 or 4,
 row pitches that are not multiples of 8 (the per-element load path) and the
 aligned fast path.  Tolerance: each plane within 1e-5 of its largest oracle
@@ -21,8 +21,8 @@ from parity import as_set, compare_candidates, plane_rel_err
 pytestmark = pytest.mark.gpu
 
 STACK_TOL = 1e-5
-SIGMAS = [0.1, 1.0, 2.2, 4.5, 7.0, 9.0, 11.5, 12.5]
-RADII = [0, 4, 9, 18, 28, 36, 46, 50]
+SIGMAS = [0.1, 1.0, 2.2, 4.5, 7.0, 9.0, 11.5, 13.5, 15.0]
+RADII = [0, 4, 9, 18, 28, 36, 46, 54, 60]
 
 
 def run_stack(plan, img: np.ndarray, pitch: int | None = None) -> np.ndarray:
