@@ -156,3 +156,41 @@ def test_full_size_mixed_batch():
         if k not in ref:
             ref[k] = plan.detect(im)
         same(g, ref[k])
+
+
+def test_u8_graph_replay_and_full_size_batch():
+    """8-bit tiles through the persistent matrix-core LoG: a captured graph
+    replayed with new descriptors equals the single-tile path, and 16 tiles
+    of the 4096^2 SEM workload (4 rendered images reused) equal it too."""
+    from paper_2108_12050_amd import BatchRunner, Plan
+    print("u8 batch graph + full size", flush=True)
+    plan = Plan(n_scales=10, sigma_min=1, sigma_max=10, threshold=0.05, overlap=0.5, dtype="u8",
+                max_h=4096, max_w=4096)
+    small_a = [torch.from_numpy(synth.sem_tile(s, psf_sigma=1.0, H=h, W=w)).cuda()
+               for s, h, w in [(11, 512, 384), (12, 300, 640), (13, 96, 96)]]
+    small_b = [torch.from_numpy(synth.sem_tile(s, psf_sigma=2.0, H=h, W=w)).cuda()
+               for s, h, w in [(14, 640, 200), (15, 257, 333)]]
+    px = max(sum(t.numel() for t in small_a), sum(t.numel() for t in small_b))
+    r = BatchRunner(plan, 4, px, 1 << 15)
+    r.set_tiles(small_a)
+    g = r.capture()
+    ref_a = [plan.detect(t) for t in small_a]
+    for rep in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        for d, ref in zip(r.detections(), ref_a):
+            same(d, ref)
+    r.set_tiles(small_b)
+    g.replay()
+    torch.cuda.synchronize()
+    for d, t in zip(r.detections(), small_b):
+        same(d, plan.detect(t))
+    big = [torch.from_numpy(synth.sem_tile(0, psf_sigma=p)).cuda() for p in (0.0, 1.0, 2.0, 4.0)]
+    imgs = [big[i % 4] for i in range(16)]
+    rb = BatchRunner(plan, 16, 16 * 4096 * 4096, 1 << 17)
+    rb.set_tiles(imgs)
+    rb.run()
+    got = rb.detections()
+    ref = [plan.detect(t) for t in big]
+    for i, d in enumerate(got):
+        same(d, ref[i % 4])
