@@ -238,7 +238,8 @@ def traffic_run() -> int:
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
     sp = int(torch.cuda.current_stream().cuda_stream)
     for _ in range(3):
-        _lib.check(L.mhfd_log_stack(plan._handle, img.data_ptr(), H, W, W, stack.data_ptr(), sp), "ls")
+        _lib.check(L.mhfd_log_stack(plan._handle, img.data_ptr(), H, W, W, stack.data_ptr(),
+                                    None, 0, sp), "ls")
         _lib.check(L.mhfd_detect_stack(plan._handle, stack.data_ptr(), H, W, raw.data_ptr(), cap,
                                        res.data_ptr(), ws.data_ptr(), nb, sp), "ds")
     torch.cuda.synchronize()
@@ -347,7 +348,7 @@ def main() -> int:
         if ev is not None:
             ev[0].record(st)
         _lib.check(L.mhfd_log_stack(plan._handle, imgs[j].data_ptr(), H, W, W,
-                                    b["stack"].data_ptr(), sptr), "mhfd_log_stack")
+                                    b["stack"].data_ptr(), None, 0, sptr), "mhfd_log_stack")
         if ev is not None:
             ev[1].record(st)
         _lib.check(L.mhfd_detect_stack(plan._handle, b["stack"].data_ptr(), H, W,

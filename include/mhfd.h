@@ -154,12 +154,24 @@ mhfd_status mhfd_detect(mhfd_plan plan, const void *d_img, int32_t h, int32_t w,
                         float *d_stack, void *d_ws, size_t ws_bytes, void *stream);
 
 /*
+ * Bytes of device scratch mhfd_log_stack needs for an h x w image (0 on bad
+ * input, and for 8-bit plans, which need none).  fp32 plans keep one word:
+ * the image's max |I|, from which the matrix-core kernels take an exact
+ * power-of-two input scale.
+ */
+size_t mhfd_log_stack_workspace_size(mhfd_plan plan, int32_t h, int32_t w);
+
+/*
  * The LoG stack alone -- the first step of mhfd_detect: writes
  * R_k(y, x) for k < K into d_stack (K x h x w floats, plane k at k*h*w).
- * Needs no workspace.  Same image requirements as mhfd_detect.
+ * Same image requirements as mhfd_detect.  d_ws: at least
+ * mhfd_log_stack_workspace_size bytes of caller-owned device memory, 4-byte
+ * aligned (may be null when that size is 0); the call overwrites it, so calls
+ * in flight at once need separate workspaces.  fp32 images with non-finite
+ * values give unspecified stacks.
  */
 mhfd_status mhfd_log_stack(mhfd_plan plan, const void *d_img, int32_t h, int32_t w, int64_t pitch,
-                           float *d_stack, void *stream);
+                           float *d_stack, void *d_ws, size_t ws_bytes, void *stream);
 
 /*
  * The rest of mhfd_detect on a stack the caller already holds (as written by

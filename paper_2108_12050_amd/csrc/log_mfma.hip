@@ -1,4 +1,4 @@
-// Scale-space operator of u8 tiles on the matrix cores.
+// Scale-space operator on the matrix cores (u8 codes or fp32 values).
 //
 // The operator of one scale (the sigma^2-normalised Laplacian of the Gaussian
 // of section 3, computed separably as in the strip kernel) is a pair of banded
@@ -12,11 +12,13 @@
 //                rows, K = 32 intermediate rows per instruction; the window
 //                starts R rows above the tile, ceil((16 + 2R) / 32) K-blocks.
 //
-// Precision.  u8 codes are exact in FP16.  Every tap and every intermediate is
-// split into an FP16 pair hi + lo (hi = nearest FP16, lo = nearest FP16 of the
-// exact FP32 remainder, error <= 2^-22 of the value), and each product is
-// formed as hi*hi + hi*lo + lo*hi with FP32 accumulation; the dropped lo*lo
-// term is below 2^-22 of the product.  Powers of two scale the row taps so
+// Precision.  u8 codes are exact in FP16; fp32 values are first scaled by an
+// exact power of two that brings the tile's max |I| (a pre-pass) just below
+// 2^14.  Every tap, fp32 input and intermediate is split into an FP16 pair
+// hi + lo (hi = nearest FP16, lo = nearest FP16 of the exact FP32 remainder,
+// error <= 2^-22 of the value), and each product is formed as hi*hi + hi*lo
+// + lo*hi with FP32 accumulation (hi*hi + hi*lo for exact codes); the
+// dropped lo*lo term is below 2^-22 of the product.  Powers of two scale the row taps so
 // that intermediates stay below 2^15 and the column taps so that their largest
 // entry is 2^14; values far below those maxima fall into FP16's subnormal
 // range, where the absolute error (2^-25) is negligible against the maxima.
@@ -82,47 +84,137 @@ __device__ __forceinline__ half8_t codes_to_half(uint32_t d0, uint32_t d1) {
     return v - static_cast<half8_t>(static_cast<_Float16>(1024.0f));
 }
 
-// One wave's work item: WT adjacent 16-column tiles from x0 over rows
-// [y0, y1).  Several tiles per wave would share the tap fragments and give
-// more independent MFMA chains, but their rings push the large shapes past
-// 256 VGPRs; measured on the 4096^2 workload one tile per wave is fastest.
-constexpr int WT = 1;
-static_assert(16 * WT == MFMA_WAVE_COLS, "wave width");
-
+// One wave's work item: a 16-column tile from x0 over rows [y0, y1).  (Two
+// tiles per wave would share the tap fragments and give more independent
+// MFMA chains, but their rings push the large shapes past 256 VGPRs;
+// measured on the 4096^2 workload one tile per wave is fastest.)
 struct WaveJob {
-    const uint8_t* img;
-    long long pitch;
+    const void* img;  // u8 codes or fp32 values
+    long long pitch;  // elements
     float* plane;     // output plane, row pitch w
     int h, w, x0, y0, y1, rw8, rwc;
-    int aligned;      // 8-byte aligned rows: vector loads allowed in the interior
+    int aligned;      // rows aligned for whole 8-element group loads
     int out_vec;      // 16-byte aligned output rows and w % 4 == 0
-    float out_scale;
+    float in_scale;   // fp32 input: exact power of two applied before the split
+    float out_scale;  // exact power of two
 };
 
-// Regular items (EDGE = false) read whole 8-byte groups, store float4 rows
+// fp32 input: the scale that brings max |I| just below 2^14, from the bit
+// pattern of max |I| (an exact power of two; 1 for zero or non-finite data,
+// whose results are then unspecified).
+__device__ __forceinline__ float input_scale(uint32_t maxbits) {
+    const float m = __uint_as_float(maxbits);
+    if (!(m > 0.0f) || !isfinite(m)) return 1.0f;
+    int e;
+    frexpf(m, &e);  // m = f 2^e, f in [0.5, 1)
+    const int s = min(100, max(-120, 14 - e));
+    return ldexpf(1.0f, s);
+}
+
+// Regular items (EDGE = false) read whole 8-element groups, store float4 rows
 // and reflect rows and columns at most once.  Windows start on multiples of
-// 8 columns, so when the width is a multiple of 8 every 8-byte group lies
-// wholly inside the image or wholly beyond one border; a group beyond a
-// border is the mirrored group, loaded aligned and byte-reversed.  The
-// general form (EDGE = true: widths not a multiple of 8, tiles narrower than
-// the window, partial 16-row or 16-column tiles) reflects every index as
-// often as needed and guards every store.  Keeping the regular body free of
-// the general code keeps its loop small and its memory waits exact.
-template <int NKR, int NKC, int NT>
+// 8 columns, so when the width is a multiple of 8 every group lies wholly
+// inside the image or wholly beyond one border; a group beyond a border is
+// the mirrored group, loaded aligned and reversed.  The general form (EDGE =
+// true: widths not a multiple of 8, tiles narrower than the window, partial
+// 16-row or 16-column tiles) reflects every index as often as needed and
+// guards every store.  Keeping the regular body free of the general code
+// keeps its loop small and its memory waits exact.
+template <int NKR, int NKC>
 __device__ __forceinline__ bool regular_job(const WaveJob& J) {
     constexpr int NS = 2 * NKC;
     const int xw = J.x0 - J.rw8;
     // rows touched: y0 - rwc ... y1 + 16 (NS + 2) (prefetch overrun)
-    return J.aligned && J.out_vec && (J.w & 7) == 0 && J.x0 + 16 * NT <= J.w && xw >= -J.w &&
-           xw + 16 * (NT - 1) + 32 * NKR <= 2 * J.w && J.h >= J.rwc + 16 * (NS + 3) &&
+    return J.aligned && J.out_vec && (J.w & 7) == 0 && J.x0 + 16 <= J.w && xw >= -J.w &&
+           xw + 32 * NKR <= 2 * J.w && J.h >= J.rwc + 16 * (NS + 3) &&
            ((J.y1 - J.y0) & 15) == 0;
 }
 
-template <int NKR, int NKC, int NT, bool EDGE>
+// Input group of 8 elements per lane and K-block: the raw registers and
+// their conversion to the MFMA operand(s).
+template <typename T>
+struct Input;
+
+template <>
+struct Input<uint8_t> {
+    typedef uint2 Raw;  // 8 codes
+    static constexpr int PRODUCTS = 2;  // code x (tap hi, tap lo): the code is exact
+    __device__ static Raw load(const uint8_t* p) { return *reinterpret_cast<const uint2*>(p); }
+    __device__ static Raw reverse(Raw v) {
+        return make_uint2(__builtin_amdgcn_perm(0u, v.y, 0x00010203u),   // bswap
+                          __builtin_amdgcn_perm(0u, v.x, 0x00010203u));
+    }
+    __device__ static Raw gather(const uint8_t* row, const int* col) {
+        uint32_t d[2] = {0u, 0u};
+#pragma unroll
+        for (int i = 0; i < 8; ++i) d[i >> 2] |= static_cast<uint32_t>(row[col[i]]) << (8 * (i & 3));
+        return make_uint2(d[0], d[1]);
+    }
+    __device__ static void convert(Raw v, float, half8_t& hi, half8_t&) {
+        hi = codes_to_half(v.x, v.y);
+    }
+};
+
+template <>
+struct Input<float> {
+    struct Raw {
+        float4_t a, b;
+    };
+    static constexpr int PRODUCTS = 3;  // hi x tap hi, hi x tap lo, lo x tap hi
+    __device__ static Raw load(const float* p) {
+        Raw r;
+        r.a = *reinterpret_cast<const float4_t*>(p);
+        r.b = *reinterpret_cast<const float4_t*>(p + 4);
+        return r;
+    }
+    __device__ static Raw reverse(Raw v) {
+        Raw r;
+        r.a = __builtin_shufflevector(v.b, v.b, 3, 2, 1, 0);
+        r.b = __builtin_shufflevector(v.a, v.a, 3, 2, 1, 0);
+        return r;
+    }
+    __device__ static Raw gather(const float* row, const int* col) {
+        Raw r;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            r.a[i] = row[col[i]];
+            r.b[i] = row[col[4 + i]];
+        }
+        return r;
+    }
+    __device__ static void convert(Raw v, float scale, half8_t& hi, half8_t& lo) {
+        half4_t h0, l0, h1, l1;
+        split(v.a * scale, h0, l0);
+        split(v.b * scale, h1, l1);
+        hi = cat(h0, h1);
+        lo = cat(l0, l1);
+    }
+};
+
+template <typename T>
+__device__ __forceinline__ typename Input<T>::Raw select_raw(bool c, typename Input<T>::Raw a,
+                                                             typename Input<T>::Raw b);
+template <>
+__device__ __forceinline__ uint2 select_raw<uint8_t>(bool c, uint2 a, uint2 b) {
+    return c ? a : b;
+}
+template <>
+__device__ __forceinline__ Input<float>::Raw select_raw<float>(bool c, Input<float>::Raw a,
+                                                               Input<float>::Raw b) {
+    Input<float>::Raw r;
+    r.a = c ? a.a : b.a;
+    r.b = c ? a.b : b.b;
+    return r;
+}
+
+template <typename T, int NKR, int NKC, bool EDGE>
 __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __restrict__ fr,
                                          int lane) {
-    constexpr int NS = 2 * NKC;        // ring of intermediate blocks
-    constexpr int D = 2;  // input prefetch depth (divides NS)
+    typedef Input<T> In;
+    typedef typename In::Raw RawGroup;
+    constexpr int NS = 2 * NKC;  // ring of intermediate blocks
+    constexpr int D = 2;         // input prefetch depth (divides NS)
+    const T* img = static_cast<const T*>(J.img);
     const int g = lane >> 4;
     const int c = lane & 15;
     const int h = J.h, w = J.w, x0 = J.x0, y0 = J.y0, y1 = J.y1;
@@ -140,22 +232,20 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
 #pragma unroll
         for (int t = 0; t < 4; ++t) ct[kb][t] = fr[((NKR + kb) * 4 + t) * 64 + lane];
 
-    // Regular items: source column and byte order of each 8-byte group.
-    int src[NT][NKR];
-    bool rev[NT][NKR];
+    // Regular items: source column and order of each 8-element group.
+    int src[NKR];
+    bool rev[NKR];
     if (!EDGE) {
 #pragma unroll
-        for (int s = 0; s < NT; ++s)
-#pragma unroll
-            for (int kb = 0; kb < NKR; ++kb) {
-                const int gs = xw + 16 * s + 32 * kb + 8 * g;
-                rev[s][kb] = gs < 0 || gs >= w;
-                src[s][kb] = gs < 0 ? -gs - 8 : (gs >= w ? 2 * w - 8 - gs : gs);
-            }
+        for (int kb = 0; kb < NKR; ++kb) {
+            const int gs = xw + 32 * kb + 8 * g;
+            rev[kb] = gs < 0 || gs >= w;
+            src[kb] = gs < 0 ? -gs - 8 : (gs >= w ? 2 * w - 8 - gs : gs);
+        }
     }
-    // Raw codes of intermediate block hb (image rows y0 - rwc + 16 hb ...):
-    // NKR pairs of dwords per lane and tile, loaded D blocks ahead of use.
-    typedef uint2 Raw[NT][NKR];
+    // Raw input of intermediate block hb (image rows y0 - rwc + 16 hb ...):
+    // one group per K-block and lane, loaded D blocks ahead of use.
+    typedef RawGroup Raw[NKR];
     auto fetch = [&](int hb, Raw& raw) {
         const int yr = y0 - J.rwc + 16 * hb + c;
         int r;
@@ -165,68 +255,54 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
             const int r0 = yr ^ (yr >> 31);
             r = min(r0, 2 * h - 1 - r0);
         }
-        const uint8_t* row = J.img + static_cast<long long>(r) * J.pitch;
+        const T* row = img + static_cast<long long>(r) * J.pitch;
+        if (!EDGE) {
 #pragma unroll
-        for (int s = 0; s < NT; ++s) {
-            if (!EDGE) {
+            for (int kb = 0; kb < NKR; ++kb) {
+                const RawGroup v = In::load(row + src[kb]);
+                raw[kb] = select_raw<T>(rev[kb], In::reverse(v), v);
+            }
+        } else if (fast) {
 #pragma unroll
-                for (int kb = 0; kb < NKR; ++kb) {
-                    const uint2 v = *reinterpret_cast<const uint2*>(row + src[s][kb]);
-                    const uint32_t lo = __builtin_amdgcn_perm(0u, v.y, 0x00010203u);  // bswap
-                    const uint32_t hi = __builtin_amdgcn_perm(0u, v.x, 0x00010203u);
-                    raw[s][kb] = rev[s][kb] ? make_uint2(lo, hi) : v;
-                }
-            } else if (fast) {
+            for (int kb = 0; kb < NKR; ++kb) raw[kb] = In::load(row + xw + 32 * kb + 8 * g);
+        } else {
 #pragma unroll
-                for (int kb = 0; kb < NKR; ++kb)
-                    raw[s][kb] = *reinterpret_cast<const uint2*>(row + xw + 32 * kb + 8 * g);
-            } else {
+            for (int kb = 0; kb < NKR; ++kb) {
+                int col[8];
 #pragma unroll
-                for (int kb = 0; kb < NKR; ++kb) {
-                    uint32_t d[2] = {0u, 0u};
-#pragma unroll
-                    for (int i = 0; i < 8; ++i) {
-                        const int col = reflect_index(xw + 32 * kb + 8 * g + i, w);
-                        d[i >> 2] |= static_cast<uint32_t>(row[col]) << (8 * (i & 3));
-                    }
-                    raw[s][kb] = make_uint2(d[0], d[1]);
-                }
+                for (int i = 0; i < 8; ++i) col[i] = reflect_index(xw + 32 * kb + 8 * g + i, w);
+                raw[kb] = In::gather(row, col);
             }
         }
     };
     // Row pass of block hb from raw (then refilled with block hb + D).
     Raw raw[D];
-    auto rowpass = [&](int hb, Raw& rw, Slot (&out)[NT]) {
-        half8_t in[NT][NKR];
+    auto rowpass = [&](int hb, Raw& rw, Slot& out) {
+        half8_t in_hi[NKR], in_lo[NKR];
 #pragma unroll
-        for (int s = 0; s < NT; ++s)
-#pragma unroll
-            for (int kb = 0; kb < NKR; ++kb) in[s][kb] = codes_to_half(rw[s][kb].x, rw[s][kb].y);
+        for (int kb = 0; kb < NKR; ++kb) In::convert(rw[kb], J.in_scale, in_hi[kb], in_lo[kb]);
         fetch(hb + D, rw);
-        float4_t a[NT], b[NT];
+        float4_t a = {0.f, 0.f, 0.f, 0.f}, b = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int s = 0; s < NT; ++s) a[s] = b[s] = (float4_t){0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int kb = 0; kb < NKR; ++kb)
-#pragma unroll
-            for (int q = 0; q < 2; ++q)
-#pragma unroll
-                for (int s = 0; s < NT; ++s) {
-                    a[s] = mfma16(in[s][kb], rt[kb][q], a[s]);
-                    b[s] = mfma16(in[s][kb], rt[kb][2 + q], b[s]);
-                }
-#pragma unroll
-        for (int s = 0; s < NT; ++s) {
-            split(a[s], out[s].ah, out[s].al);
-            split(b[s], out[s].bh, out[s].bl);
+        for (int kb = 0; kb < NKR; ++kb) {
+            a = mfma16(in_hi[kb], rt[kb][0], a);
+            b = mfma16(in_hi[kb], rt[kb][2], b);
+            a = mfma16(in_hi[kb], rt[kb][1], a);
+            b = mfma16(in_hi[kb], rt[kb][3], b);
+            if (In::PRODUCTS == 3) {
+                a = mfma16(in_lo[kb], rt[kb][0], a);
+                b = mfma16(in_lo[kb], rt[kb][2], b);
+            }
         }
+        split(a, out.ah, out.al);
+        split(b, out.bh, out.bl);
     };
 
     const bool vec = !EDGE || (J.out_vec && x0 + 16 <= w);
-    auto store = [&](int t, int s, float4_t v) {
+    auto store = [&](int t, float4_t v) {
         const int y = y0 + 16 * t + c;
         if (EDGE && y >= y1) return;
-        float* o = J.plane + static_cast<long long>(y) * w + x0 + 16 * s + 4 * g;
+        float* o = J.plane + static_cast<long long>(y) * w + x0 + 4 * g;
         if (!EDGE) {
             // Streaming store: the stack is read once, by the maxima pass, and
             // measured end to end it is faster when the stores do not stay
@@ -241,7 +317,7 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
         }
     };
 
-    Slot ring[NS][NT];
+    Slot ring[NS];
 #pragma unroll
     for (int q = 0; q < D; ++q) fetch(q, raw[q]);
 #pragma unroll
@@ -252,60 +328,49 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
             const int t = t0 + p;
             if (t >= ntiles) break;
             rowpass(t + NS - 1, raw[(p + NS - 1) % D], ring[(p + NS - 1) % NS]);
-            float4_t ra[NT], rb[NT];
+            float4_t ra = {0.f, 0.f, 0.f, 0.f}, rb = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int s = 0; s < NT; ++s) ra[s] = rb[s] = (float4_t){0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int kb = 0; kb < NKC; ++kb)
-#pragma unroll
-                for (int s = 0; s < NT; ++s) {
-                    const Slot& sa = ring[(p + 2 * kb) % NS][s];
-                    const Slot& sb = ring[(p + 2 * kb + 1) % NS][s];
-                    const half8_t xh = cat(sa.ah, sb.ah), xl = cat(sa.al, sb.al);
-                    const half8_t yh = cat(sa.bh, sb.bh), yl = cat(sa.bl, sb.bl);
-                    ra[s] = mfma16(xh, ct[kb][0], ra[s]);
-                    rb[s] = mfma16(yh, ct[kb][2], rb[s]);
-                    ra[s] = mfma16(xh, ct[kb][1], ra[s]);
-                    rb[s] = mfma16(yh, ct[kb][3], rb[s]);
-                    ra[s] = mfma16(xl, ct[kb][0], ra[s]);
-                    rb[s] = mfma16(yl, ct[kb][2], rb[s]);
-                }
-#pragma unroll
-            for (int s = 0; s < NT; ++s) store(t, s, (ra[s] + rb[s]) * J.out_scale);
+            for (int kb = 0; kb < NKC; ++kb) {
+                const Slot& sa = ring[(p + 2 * kb) % NS];
+                const Slot& sb = ring[(p + 2 * kb + 1) % NS];
+                const half8_t xh = cat(sa.ah, sb.ah), xl = cat(sa.al, sb.al);
+                const half8_t yh = cat(sa.bh, sb.bh), yl = cat(sa.bl, sb.bl);
+                ra = mfma16(xh, ct[kb][0], ra);
+                rb = mfma16(yh, ct[kb][2], rb);
+                ra = mfma16(xh, ct[kb][1], ra);
+                rb = mfma16(yh, ct[kb][3], rb);
+                ra = mfma16(xl, ct[kb][0], ra);
+                rb = mfma16(yl, ct[kb][2], rb);
+            }
+            store(t, (ra + rb) * J.out_scale);
         }
     }
 }
 
-// A wave's job: both tiles through the regular body, or each existing tile
-// through the general one.
-template <int NKR, int NKC>
-__device__ __forceinline__ void run_job(WaveJob J, const half8_t* __restrict__ fr, int lane) {
-    if (regular_job<NKR, NKC, WT>(J)) {
-        wave_job<NKR, NKC, WT, false>(J, fr, lane);
-        return;
-    }
-    const int x0 = J.x0;
-    for (int s = 0; s < WT; ++s) {
-        J.x0 = x0 + 16 * s;
-        if (J.x0 >= J.w) break;
-        wave_job<NKR, NKC, 1, true>(J, fr, lane);
-    }
+template <typename T, int NKR, int NKC>
+__device__ __forceinline__ void run_job(const WaveJob& J, const half8_t* __restrict__ fr,
+                                        int lane) {
+    if (regular_job<NKR, NKC>(J))
+        wave_job<T, NKR, NKC, false>(J, fr, lane);
+    else
+        wave_job<T, NKR, NKC, true>(J, fr, lane);
 }
 
-// Two waves per SIMD where the live state fits 256 registers (no spills up
-// to nkc = 3 in the single-tile kernel, nkc = 2 in the persistent one, whose
-// item loop keeps more state); otherwise one wave per SIMD.
-template <int NKC>
-constexpr int mfma_waves() { return NKC <= 3 ? 2 : 1; }
-template <int NKC>
+// Two waves per SIMD where the live state fits 256 registers (u8: no spills
+// up to nkc = 3 in the single-tile kernel, nkc = 2 in the persistent one,
+// whose item loop keeps more state; fp32 inputs carry twice the operands);
+// otherwise one wave per SIMD.
+template <typename T, int NKC>
+constexpr int mfma_waves() { return NKC <= (sizeof(T) == 1 ? 3 : 2) ? 2 : 1; }
+template <typename T, int NKC>
 constexpr int mfma_batch_waves() { return NKC <= 2 ? 2 : 1; }
 
-template <int NKR, int NKC>
-__global__ __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(mfma_waves<NKC>(), 2)))
-void log_mfma_u8_kernel(
-    const uint8_t* __restrict__ img, int h, int w, long long pitch, int aligned, int out_vec,
-    const half8_t* __restrict__ frags, MfmaLaunch L, float* __restrict__ out,
-    long long plane_stride) {
+template <typename T, int NKR, int NKC>
+__global__ __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(mfma_waves<T, NKC>(), 2)))
+void log_mfma_kernel(const T* __restrict__ img, int h, int w, long long pitch, int aligned,
+                     int out_vec, const uint32_t* __restrict__ maxbits,
+                     const half8_t* __restrict__ frags, MfmaLaunch L, float* __restrict__ out,
+                     long long plane_stride) {
     const int bid = blockIdx.x;
     int si = 0;
     while (si + 1 < L.n && bid >= L.sc[si + 1].block_begin) ++si;
@@ -314,32 +379,34 @@ void log_mfma_u8_kernel(
     const int seg = local / L.groups_x;
     const int wcol = (local - seg * L.groups_x) * MW + (threadIdx.x >> 6);
     if (wcol >= L.tiles_x) return;
+    const float in_s = maxbits ? input_scale(*maxbits) : 1.0f;
     WaveJob J;
     J.img = img;
     J.pitch = pitch;
     J.plane = out + static_cast<long long>(sc.plane) * plane_stride;
     J.h = h;
     J.w = w;
-    J.x0 = wcol * 16 * WT;
+    J.x0 = wcol * 16;
     J.y0 = seg * sc.seg_rows;
     J.y1 = min(J.y0 + sc.seg_rows, h);
     J.rw8 = sc.rw8;
     J.rwc = sc.rwc;
     J.aligned = aligned;
     J.out_vec = out_vec;
-    J.out_scale = sc.out_scale;
-    run_job<NKR, NKC>(J, frags + sc.frag_off, threadIdx.x & 63);
+    J.in_scale = in_s;
+    J.out_scale = sc.out_scale / in_s;
+    run_job<T, NKR, NKC>(J, frags + sc.frag_off, threadIdx.x & 63);
 }
 
 // Persistent form over a batch of tiles: every wave pulls items (scale j of
 // the launch, tile, row segment, wave column) from a counter.  Items are
 // numbered scale-major, so a launch finishes its scales in order.
-template <int NKR, int NKC>
-__global__ __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(mfma_batch_waves<NKC>(), 2)))
-void log_mfma_u8_batch_kernel(
-    int n_tiles, const BatchTile* __restrict__ tiles, float* __restrict__ stack,
-    const half8_t* __restrict__ frags, MfmaBatchScales sc, BatchCounters* __restrict__ ctr,
-    int slot) {
+template <typename T, int NKR, int NKC>
+__global__ __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(mfma_batch_waves<T, NKC>(), 2)))
+void log_mfma_batch_kernel(int n_tiles, const BatchTile* __restrict__ tiles,
+                           const uint32_t* __restrict__ maxbits, float* __restrict__ stack,
+                           const half8_t* __restrict__ frags, MfmaBatchScales sc,
+                           BatchCounters* __restrict__ ctr, int slot) {
     const int lane = threadIdx.x & 63;
     const int per_scale = ctr->mitems_per_scale;
     const int total = ctr->valid ? per_scale * sc.n : 0;
@@ -362,37 +429,85 @@ void log_mfma_u8_batch_kernel(
         const int local = rem - t.mitem_base;
         const int seg = local / t.mtiles_x;
         const int wcol = local - seg * t.mtiles_x;
+        const float in_s = maxbits ? input_scale(maxbits[lo]) : 1.0f;
         WaveJob J;
-        J.img = static_cast<const uint8_t*>(t.img);
+        J.img = t.img;
         J.pitch = t.pitch;
         J.h = t.h;
         J.w = t.w;
         J.plane = stack + t.stack_off + static_cast<long long>(sc.plane[j]) * t.h * t.w;
-        J.x0 = wcol * 16 * WT;
+        J.x0 = wcol * 16;
         J.y0 = seg * t.mseg_rows;
         J.y1 = min(J.y0 + t.mseg_rows, t.h);
         J.rw8 = sc.rw8[j];
         J.rwc = sc.rwc[j];
-        J.aligned = (t.pitch % 8 == 0) && (reinterpret_cast<uintptr_t>(t.img) % 8 == 0);
+        J.aligned = (t.pitch % 8 == 0) &&
+                    (reinterpret_cast<uintptr_t>(t.img) % (8 * sizeof(T)) == 0);
         J.out_vec = (t.w % 4 == 0) && (t.stack_off % 4 == 0) &&
                     (reinterpret_cast<uintptr_t>(stack) % 16 == 0);
-        J.out_scale = sc.out_scale[j];
-        run_job<NKR, NKC>(J, frags + sc.frag_off[j], lane);
+        J.in_scale = in_s;
+        J.out_scale = sc.out_scale[j] / in_s;
+        run_job<T, NKR, NKC>(J, frags + sc.frag_off[j], lane);
     }
 }
 
-template <int NKR, int NKC>
-hipError_t launch_one(const uint8_t* img, int h, int w, int64_t pitch, const uint16_t* frags,
-                      const MfmaLaunch& L, float* out, long long plane_stride, hipStream_t s) {
+// max |I| of an fp32 image as float bits (non-negative floats order as their
+// bit patterns), for the input scale.  `bits` must be zero on entry.
+__global__ void absmax_kernel(const float* __restrict__ img, int h, int w, long long pitch,
+                              uint32_t* __restrict__ bits) {
+    float m = 0.0f;
+    const long long n = static_cast<long long>(h) * w;
+    for (long long i = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<long long>(gridDim.x) * blockDim.x) {
+        const long long y = i / w, x = i - y * w;
+        m = fmaxf(m, fabsf(img[y * pitch + x]));
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) m = fmaxf(m, __shfl_xor(m, d, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(bits, __float_as_uint(m));
+}
+
+// Per-tile max |I| of a batch (bits[t] zero on entry): every workgroup
+// strides over every tile.
+__global__ void absmax_batch_kernel(int n_tiles, const BatchTile* __restrict__ tiles,
+                                    const BatchCounters* __restrict__ ctr,
+                                    uint32_t* __restrict__ bits) {
+    if (!ctr->valid) return;
+    for (int t = 0; t < n_tiles; ++t) {
+        const BatchTile& d = tiles[t];
+        const float* img = static_cast<const float*>(d.img);
+        const long long n = static_cast<long long>(d.h) * d.w;
+        float m = 0.0f;
+        for (long long i = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; i < n;
+             i += static_cast<long long>(gridDim.x) * blockDim.x) {
+            const long long y = i / d.w, x = i - y * d.w;
+            m = fmaxf(m, fabsf(img[y * d.pitch + x]));
+        }
+#pragma unroll
+        for (int dd = 32; dd > 0; dd >>= 1) m = fmaxf(m, __shfl_xor(m, dd, 64));
+        if ((threadIdx.x & 63) == 0 && m > 0.0f) atomicMax(bits + t, __float_as_uint(m));
+    }
+}
+
+__global__ void zero_words_kernel(uint32_t* __restrict__ p, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+template <typename T, int NKR, int NKC>
+hipError_t launch_one(const T* img, int h, int w, int64_t pitch, const uint32_t* maxbits,
+                      const uint16_t* frags, const MfmaLaunch& L, float* out,
+                      long long plane_stride, hipStream_t s) {
     int blocks = 0;
     for (int i = 0; i < L.n; ++i) blocks += L.sc[i].n_blocks;
     if (blocks == 0) return hipSuccess;
-    const int aligned = (pitch % 8 == 0) && (reinterpret_cast<uintptr_t>(img) % 8 == 0);
+    const int aligned =
+        (pitch % 8 == 0) && (reinterpret_cast<uintptr_t>(img) % (8 * sizeof(T)) == 0);
     // float4 stores need 16-byte aligned rows and planes
     const int out_vec = (w % 4 == 0) && (plane_stride % 4 == 0) &&
                         (reinterpret_cast<uintptr_t>(out) % 16 == 0);
-    log_mfma_u8_kernel<NKR, NKC><<<blocks, 64 * MW, 0, s>>>(
-        img, h, w, static_cast<long long>(pitch), aligned, out_vec,
+    log_mfma_kernel<T, NKR, NKC><<<blocks, 64 * MW, 0, s>>>(
+        img, h, w, static_cast<long long>(pitch), aligned, out_vec, maxbits,
         reinterpret_cast<const half8_t*>(frags), L, out, plane_stride);
     return hipGetLastError();
 }
@@ -512,38 +627,75 @@ float mfma_build_frags(const double* g, const double* h, int R, double norm, dou
 }
 
 int mfma_wave_tiles(int w) { return (w + MFMA_WAVE_COLS - 1) / MFMA_WAVE_COLS; }
+int mfma_waves_per_block() { return MW; }
 
-hipError_t launch_log_mfma_batch(int nkr, int nkc, int n_tiles, const BatchTile* tiles,
-                                 float* stack, const uint16_t* frags, const MfmaBatchScales& sc,
+hipError_t launch_log_mfma_batch(int in_dtype, int nkr, int nkc, int n_tiles,
+                                 const BatchTile* tiles, const uint32_t* maxbits, float* stack,
+                                 const uint16_t* frags, const MfmaBatchScales& sc,
                                  BatchCounters* ctr, int slot, int grid, hipStream_t s) {
     if (sc.n == 0) return hipSuccess;
     const half8_t* f = reinterpret_cast<const half8_t*>(frags);
-#define MHFD_MFMA_BATCH_CASE(A, B)                                                        \
-    if (nkr == A && nkc == B) {                                                           \
-        log_mfma_u8_batch_kernel<A, B><<<grid, 64 * MW, 0, s>>>(n_tiles, tiles, stack, f, sc, \
-                                                                ctr, slot);               \
-        return hipGetLastError();                                                         \
+#define MHFD_MFMA_BATCH_CASE(T, A)                                                            \
+    if (nkr == A && nkc == A) {                                                               \
+        log_mfma_batch_kernel<T, A, A><<<grid, 64 * MW, 0, s>>>(n_tiles, tiles, maxbits, stack, \
+                                                                f, sc, ctr, slot);            \
+        return hipGetLastError();                                                             \
     }
-    MHFD_MFMA_BATCH_CASE(1, 1)
-    MHFD_MFMA_BATCH_CASE(2, 2)
-    MHFD_MFMA_BATCH_CASE(3, 3)
-    MHFD_MFMA_BATCH_CASE(4, 4)
+    if (in_dtype == MHFD_U8) {
+        MHFD_MFMA_BATCH_CASE(uint8_t, 1)
+        MHFD_MFMA_BATCH_CASE(uint8_t, 2)
+        MHFD_MFMA_BATCH_CASE(uint8_t, 3)
+        MHFD_MFMA_BATCH_CASE(uint8_t, 4)
+    } else {
+        MHFD_MFMA_BATCH_CASE(float, 1)
+        MHFD_MFMA_BATCH_CASE(float, 2)
+        MHFD_MFMA_BATCH_CASE(float, 3)
+        MHFD_MFMA_BATCH_CASE(float, 4)
+    }
 #undef MHFD_MFMA_BATCH_CASE
     return hipErrorInvalidValue;
 }
-int mfma_waves_per_block() { return MW; }
 
-hipError_t launch_log_mfma(int nkr, int nkc, const uint8_t* img, int h, int w, int64_t pitch,
-                           const uint16_t* frags, const MfmaLaunch& L, float* out,
-                           long long plane_stride, hipStream_t s) {
-#define MHFD_MFMA_CASE(A, B) \
-    if (nkr == A && nkc == B) return launch_one<A, B>(img, h, w, pitch, frags, L, out, plane_stride, s);
-    MHFD_MFMA_CASE(1, 1)
-    MHFD_MFMA_CASE(2, 2)
-    MHFD_MFMA_CASE(3, 3)
-    MHFD_MFMA_CASE(4, 4)
+hipError_t launch_log_mfma(int in_dtype, int nkr, int nkc, const void* img, int h, int w,
+                           int64_t pitch, const uint32_t* maxbits, const uint16_t* frags,
+                           const MfmaLaunch& L, float* out, long long plane_stride,
+                           hipStream_t s) {
+#define MHFD_MFMA_CASE(T, A)                                                                   \
+    if (nkr == A && nkc == A)                                                                  \
+        return launch_one<T, A, A>(static_cast<const T*>(img), h, w, pitch, maxbits, frags, L, \
+                                   out, plane_stride, s);
+    if (in_dtype == MHFD_U8) {
+        MHFD_MFMA_CASE(uint8_t, 1)
+        MHFD_MFMA_CASE(uint8_t, 2)
+        MHFD_MFMA_CASE(uint8_t, 3)
+        MHFD_MFMA_CASE(uint8_t, 4)
+    } else {
+        MHFD_MFMA_CASE(float, 1)
+        MHFD_MFMA_CASE(float, 2)
+        MHFD_MFMA_CASE(float, 3)
+        MHFD_MFMA_CASE(float, 4)
+    }
 #undef MHFD_MFMA_CASE
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_absmax(const float* img, int h, int w, int64_t pitch, uint32_t* bits,
+                         hipStream_t s) {
+    zero_words_kernel<<<1, 64, 0, s>>>(bits, 1);
+    const long long n = static_cast<long long>(h) * w;
+    long long blocks = (n + 256 * 16 - 1) / (256 * 16);
+    if (blocks > 2048) blocks = 2048;
+    if (blocks < 1) blocks = 1;
+    absmax_kernel<<<static_cast<int>(blocks), 256, 0, s>>>(img, h, w,
+                                                           static_cast<long long>(pitch), bits);
+    return hipGetLastError();
+}
+
+hipError_t launch_absmax_batch(int n_tiles, const BatchTile* tiles, const BatchCounters* ctr,
+                               uint32_t* bits, int grid, hipStream_t s) {
+    zero_words_kernel<<<(n_tiles + 255) / 256, 256, 0, s>>>(bits, n_tiles);
+    absmax_batch_kernel<<<grid, 256, 0, s>>>(n_tiles, tiles, ctr, bits);
+    return hipGetLastError();
 }
 
 }  // namespace mhfd

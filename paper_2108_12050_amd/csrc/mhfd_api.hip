@@ -29,8 +29,8 @@ struct mhfd_plan_s {
     int32_t* d_d2max = nullptr;  // K x K prune table (null: pruning off)
     float* d_sigmas = nullptr;   // device copy of sigmas (float)
     size_t tap_floats = 0;
-    // u8 plans: split-FP16 MFMA fragment tables of the scales whose radius
-    // the matrix-core kernel supports (mfma_off[k] < 0: strip kernel).
+    // Split-FP16 MFMA fragment tables of the scales whose radius the
+    // matrix-core kernel supports (mfma_off[k] < 0: strip kernel).
     std::vector<int> mfma_off;   // first 8-half fragment of scale k
     std::vector<float> mfma_out_scale;
     uint16_t* d_frags = nullptr;
@@ -127,7 +127,7 @@ int max_overlapping_d2(double ra, double rb, double theta) {
 }
 
 struct DetectLayout {
-    size_t stack, blk_n, blk_o, blk_off, pool, cand, keep, keep_off, scan_sums, ctr, total;
+    size_t stack, blk_n, blk_o, blk_off, pool, cand, keep, keep_off, scan_sums, ctr, maxbits, total;
     int n_blk, bpr;
 };
 
@@ -153,6 +153,7 @@ DetectLayout detect_layout(const mhfd_plan_s* p, int h, int w) {
     const int64_t longest = static_cast<int64_t>(cap) > L.n_blk ? static_cast<int64_t>(cap) : L.n_blk;
     L.scan_sums = take(sizeof(int32_t) * mhfd::scan_sums_ints(longest));
     L.ctr = take(sizeof(mhfd::DetectCounters));
+    L.maxbits = take(sizeof(uint32_t));
     L.total = off;
     return L;
 }
@@ -275,11 +276,13 @@ mhfd_status mhfd_create_plan(const mhfd_config* cfg, mhfd_plan* out) {
     for (int k = 0; k < K; ++k)
         synth_taps(static_cast<double>(sig[k]), p->radii[k], p->padded[k], p->polarity,
                    host.data() + p->tap_off[k]);
-    // u8 plans: matrix-core fragment tables (codes 0..255, intensity code / 255).
+    // Matrix-core fragment tables: u8 codes 0..255 (intensity code / 255), or
+    // fp32 values scaled on the device so that max |I| < 2^14.
     std::vector<uint16_t> frags;
     p->mfma_off.assign(K, -1);
     p->mfma_out_scale.assign(K, 0.0f);
-    if (p->dtype == MHFD_U8) {
+    const bool u8 = p->dtype == MHFD_U8;
+    {
         for (int k = 0; k < K; ++k) {
             const int R = p->radii[k];
             if (!mhfd::mfma_radius_ok(R)) continue;
@@ -290,7 +293,7 @@ mhfd_status mhfd_create_plan(const mhfd_config* cfg, mhfd_plan* out) {
             p->mfma_off[k] = static_cast<int>(at / 8);
             p->mfma_out_scale[k] = mhfd::mfma_build_frags(
                 g.data(), h.data(), R, polarity_norm(static_cast<double>(sig[k]), p->polarity),
-                255.0, 255.0, frags.data() + at);
+                u8 ? 255.0 : 1.0, u8 ? 255.0 : 16384.0, frags.data() + at);
         }
     }
 
@@ -540,14 +543,25 @@ std::vector<std::pair<std::pair<int, int>, mhfd::MfmaLaunch>> mfma_launches(cons
     return out;
 }
 
+// Bytes of scratch the stack needs: the max |I| word of fp32 plans with
+// matrix-core scales.
+size_t log_stack_scratch(const mhfd_plan_s* p) {
+    return (p->d_frags && p->dtype == MHFD_F32) ? kAlign : 0;
+}
+
 mhfd_status enqueue_log_stack(const mhfd_plan_s* p, const void* d_img, int h, int w,
-                              int64_t pitch, float* stack, hipStream_t s) {
+                              int64_t pitch, float* stack, uint32_t* maxbits, hipStream_t s) {
     std::vector<int> strip_scales;
     for (int k = 0; k < p->K; ++k)
         if (p->mfma_off.empty() || p->mfma_off[k] < 0) strip_scales.push_back(k);
-    for (const auto& ml : mfma_launches(p, h, w)) {
-        hipError_t e = mhfd::launch_log_mfma(ml.first.first, ml.first.second,
-                                             static_cast<const uint8_t*>(d_img), h, w, pitch,
+    const auto mls = mfma_launches(p, h, w);
+    if (!mls.empty() && p->dtype == MHFD_F32) {
+        hipError_t e = mhfd::launch_absmax(static_cast<const float*>(d_img), h, w, pitch, maxbits, s);
+        if (e != hipSuccess) return hip_fail(e, "input range pass");
+    }
+    for (const auto& ml : mls) {
+        hipError_t e = mhfd::launch_log_mfma(p->dtype, ml.first.first, ml.first.second, d_img, h,
+                                             w, pitch, p->dtype == MHFD_F32 ? maxbits : nullptr,
                                              p->d_frags, ml.second, stack,
                                              static_cast<long long>(h) * w, s);
         if (e != hipSuccess) return hip_fail(e, "LoG stack (matrix cores) launch");
@@ -643,7 +657,8 @@ mhfd_status check_focus(const mhfd_plan_s* p, const float* d_imgs, int b, int h,
 }
 
 struct BatchLayout {
-    size_t stack, tiles, ctr, blk_n, blk_o, blk_off, pool, cand, keep, keep_off, scan_sums, total;
+    size_t stack, tiles, ctr, blk_n, blk_o, blk_off, pool, cand, keep, keep_off, scan_sums, maxbits,
+        total;
     int n_blk_bound;
     int64_t cap;
 };
@@ -674,6 +689,7 @@ bool batch_layout(const mhfd_plan_s* p, int n, int64_t max_pixels, BatchLayout* 
     L->keep = take(sizeof(int32_t) * cap);
     L->keep_off = take(sizeof(int32_t) * (cap + 1));
     L->scan_sums = take(sizeof(int32_t) * mhfd::scan_sums_ints(nbb > cap ? nbb : cap));
+    L->maxbits = take(sizeof(uint32_t) * n);
     L->total = off;
     return true;
 }
@@ -682,14 +698,28 @@ bool batch_layout(const mhfd_plan_s* p, int n, int64_t max_pixels, BatchLayout* 
 
 extern "C" {
 
+size_t mhfd_log_stack_workspace_size(mhfd_plan p, int32_t h, int32_t w) {
+    if (!p || h < 1 || w < 1 || h > p->max_h || w > p->max_w) return 0;
+    return log_stack_scratch(p);
+}
+
 mhfd_status mhfd_log_stack(mhfd_plan p, const void* d_img, int32_t h, int32_t w, int64_t pitch,
-                           float* d_stack, void* stream) {
+                           float* d_stack, void* d_ws, size_t ws_bytes, void* stream) {
     g_last_error.clear();
     mhfd_status st = check_image(p, d_img, h, w, pitch);
     if (st != MHFD_OK) return st;
     if (!d_stack) return fail(MHFD_ERR_INVALID_ARG, "null stack");
+    const size_t need = log_stack_scratch(p);
+    if (need) {
+        if (!d_ws) return fail(MHFD_ERR_INVALID_ARG, "null workspace (fp32 plans need %zu bytes)", need);
+        if (reinterpret_cast<uintptr_t>(d_ws) % 4)
+            return fail(MHFD_ERR_INVALID_ARG, "workspace not 4-byte aligned");
+        if (ws_bytes < need)
+            return fail(MHFD_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
+    }
     if ((st = check_device(p)) != MHFD_OK) return st;
-    return enqueue_log_stack(p, d_img, h, w, pitch, d_stack, static_cast<hipStream_t>(stream));
+    return enqueue_log_stack(p, d_img, h, w, pitch, d_stack, static_cast<uint32_t*>(d_ws),
+                             static_cast<hipStream_t>(stream));
 }
 
 mhfd_status mhfd_detect_stack(mhfd_plan p, const float* d_stack, int32_t h, int32_t w,
@@ -719,7 +749,9 @@ mhfd_status mhfd_detect(mhfd_plan p, const void* d_img, int32_t h, int32_t w, in
     hipStream_t s = static_cast<hipStream_t>(stream);
     char* base = static_cast<char*>(d_ws);
     float* stack = d_stack ? d_stack : reinterpret_cast<float*>(base + L.stack);
-    if ((st = enqueue_log_stack(p, d_img, h, w, pitch, stack, s)) != MHFD_OK) return st;
+    if ((st = enqueue_log_stack(p, d_img, h, w, pitch, stack,
+                                reinterpret_cast<uint32_t*>(base + L.maxbits), s)) != MHFD_OK)
+        return st;
     return enqueue_tail(p, stack, h, w, L, base, d_blobs, capacity, d_result, s);
 }
 
@@ -755,7 +787,13 @@ mhfd_status mhfd_detect_batched(mhfd_plan p, int32_t n, const mhfd_tile* d_tiles
     // Matrix-core scales (u8 plans), one persistent launch per shape, the
     // costliest shape first; the same per-wave arithmetic as the single-tile
     // path, so every tile's stack equals its single-tile stack.
-    for (const auto& key : mfma_shapes(p)) {
+    uint32_t* maxbits = reinterpret_cast<uint32_t*>(base + L.maxbits);
+    const auto shapes = mfma_shapes(p);
+    if (!shapes.empty() && p->dtype == MHFD_F32) {
+        e = mhfd::launch_absmax_batch(n, tiles, ctr, maxbits, 2 * p->n_cu, s);
+        if (e != hipSuccess) return hip_fail(e, "batched input range pass");
+    }
+    for (const auto& key : shapes) {
         mhfd::MfmaBatchScales sc{};
         for (int k = 0; k < p->K; ++k) {
             if (p->mfma_off[k] < 0) continue;
@@ -772,8 +810,9 @@ mhfd_status mhfd_detect_batched(mhfd_plan p, int32_t n, const mhfd_tile* d_tiles
         if (slot < 0 || slot >= mhfd::MFMA_SHAPES)
             return fail(MHFD_ERR_UNSUPPORTED, "no matrix-core counter for shape %d x %d",
                         key.first, key.second);
-        e = mhfd::launch_log_mfma_batch(key.first, key.second, n, tiles, stack, p->d_frags, sc,
-                                        ctr, slot, 2 * p->n_cu, s);
+        e = mhfd::launch_log_mfma_batch(p->dtype, key.first, key.second, n, tiles,
+                                        p->dtype == MHFD_F32 ? maxbits : nullptr, stack,
+                                        p->d_frags, sc, ctr, slot, 2 * p->n_cu, s);
         if (e != hipSuccess) return hip_fail(e, "batched LoG (matrix cores) launch");
     }
     for (int cls = 2; cls >= 0; --cls) {

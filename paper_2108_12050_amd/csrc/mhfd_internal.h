@@ -91,7 +91,7 @@ hipError_t launch_log_class(int cls, int in_dtype, int epi, const void* img, int
                             const StackIO& io, hipStream_t s);
 
 // ---------------------------------------------------------------------------
-// Scale-space operator of u8 tiles on the matrix cores (split-FP16 MFMA).
+// Scale-space operator on the matrix cores (split-FP16 MFMA), u8 or fp32 tiles.
 // Window geometry of one radius: the row pass reads columns x0 - rw8 ...
 // (nkr K-blocks of 32), the column pass rows y0 - rwc ... (nkc K-blocks).
 // Shapes are (n, n), n = 1..4, for radii 0..56.
@@ -131,9 +131,15 @@ struct MfmaLaunch {
     MfmaScale sc[MHFD_MAX_SCALES];
 };
 
-hipError_t launch_log_mfma(int nkr, int nkc, const uint8_t* img, int h, int w, int64_t pitch,
-                           const uint16_t* frags, const MfmaLaunch& L, float* out,
-                           long long plane_stride, hipStream_t s);
+// in_dtype MHFD_U8 or MHFD_F32.  maxbits: fp32 inputs only, the float bits of
+// the tile's max |I| (launch_absmax), which picks the exact input scale.
+hipError_t launch_log_mfma(int in_dtype, int nkr, int nkc, const void* img, int h, int w,
+                           int64_t pitch, const uint32_t* maxbits, const uint16_t* frags,
+                           const MfmaLaunch& L, float* out, long long plane_stride,
+                           hipStream_t s);
+// *bits = float bits of max |I| over an fp32 image (zeroed first).
+hipError_t launch_absmax(const float* img, int h, int w, int64_t pitch, uint32_t* bits,
+                         hipStream_t s);
 
 // Detection tail: stack -> candidates -> canonical order -> prune -> blobs.
 struct DetectWorkspace {
@@ -211,9 +217,14 @@ struct MfmaBatchScales {
     float out_scale[MHFD_MAX_SCALES];
 };
 
-hipError_t launch_log_mfma_batch(int nkr, int nkc, int n_tiles, const BatchTile* tiles,
-                                 float* stack, const uint16_t* frags, const MfmaBatchScales& sc,
+hipError_t launch_log_mfma_batch(int in_dtype, int nkr, int nkc, int n_tiles,
+                                 const BatchTile* tiles, const uint32_t* maxbits, float* stack,
+                                 const uint16_t* frags, const MfmaBatchScales& sc,
                                  BatchCounters* ctr, int slot, int grid, hipStream_t s);
+// bits[t] = float bits of max |I| of fp32 tile t (zeroed first; nothing for an
+// invalid batch).
+hipError_t launch_absmax_batch(int n_tiles, const BatchTile* tiles, const BatchCounters* ctr,
+                               uint32_t* bits, int grid, hipStream_t s);
 
 // Scales of one radius class for the persistent LoG launch.
 struct BatchScales {

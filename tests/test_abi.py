@@ -61,4 +61,5 @@ def test_null_arguments():
     assert L.mhfd_plan_scales(None, None, None) == -1
     assert L.mhfd_detect_workspace_size(None, 10, 10) == 0
     assert L.mhfd_detect(None, None, 1, 1, 1, None, 0, None, None, None, 0, None) == 1
-    assert L.mhfd_log_stack(None, None, 1, 1, 1, None, None) == 1
+    assert L.mhfd_log_stack(None, None, 1, 1, 1, None, None, 0, None) == 1
+    assert L.mhfd_log_stack_workspace_size(None, 1, 1) == 0

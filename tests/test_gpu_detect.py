@@ -199,7 +199,10 @@ def test_split_entry_points_equal_detect(plans):
     d = p.detect(img, return_stack=True)
     st = torch.empty_like(d.stack)
     s = int(torch.cuda.current_stream().cuda_stream)
-    _lib.check(L.mhfd_log_stack(p._handle, img.data_ptr(), 512, 512, 512, st.data_ptr(), s), "ls")
+    nl = L.mhfd_log_stack_workspace_size(p._handle, 512, 512)
+    lws = torch.empty(max(nl, 1), dtype=torch.uint8, device=p.device)
+    _lib.check(L.mhfd_log_stack(p._handle, img.data_ptr(), 512, 512, 512, st.data_ptr(),
+                                lws.data_ptr(), nl, s), "ls")
     cap = 4096
     raw = torch.empty((cap, 5), dtype=torch.int32, device=p.device)
     res = torch.zeros(3, dtype=torch.int64, device=p.device)
