@@ -9,9 +9,9 @@
 //              (log_mfma.hip), the same per-wave arithmetic as the single-
 //              tile path; other scales: persistent strip workgroups per
 //              radius class (log_strip.hip);
-//   nms        persistent over every tile's (row, 256-column chunk) pieces; the
-//              same maxima test, slots and overflow pool as the single-tile
-//              path; the tile index rides in the upper bits of k;
+//   nms        persistent waves over every tile's (32-row run, strip) items,
+//              the per-wave body of the single-tile path (nms_wave.h); the
+//              tile index rides in the upper bits of k;
 //   scan       over all pieces, tile-major: the canonical list of every tile
 //              is one contiguous run of the global list;
 //   order, prune (rows of the candidate's own tile), keep scan, emit into the
@@ -21,17 +21,16 @@
 #include <utility>
 
 #include "mhfd_internal.h"
+#include "nms_wave.h"
 
 namespace mhfd {
 
 namespace {
 
-constexpr int NMS_T = 256;
+constexpr int NMS_WAVES = 4;   // maxima waves per workgroup
 constexpr int SLOT = 16;
 constexpr int SETUP_T = 1024;
 constexpr int TILE_SHIFT = 5;  // k in the low bits (K <= 32), tile above
-
-__device__ __forceinline__ float fmax3(float a, float b, float c) { return fmaxf(a, fmaxf(b, c)); }
 
 __device__ int default_seg_rows(int h, int w) {
     const int strips = (w + 63) / 64;
@@ -59,6 +58,14 @@ __device__ V block_exclusive_scan(V v, V* sh, V* total) {
     return incl - v;
 }
 
+__device__ __forceinline__ int nms_runs(int h) { return (h + nms::ROWS - 1) / nms::ROWS; }
+
+// Floats of a tile's K planes in the stack, rounded up to whole float4s so
+// every tile starts 16-byte aligned.
+__device__ __forceinline__ long long stack_floats(int h, int w, int K) {
+    return (static_cast<long long>(h) * w * K + 3) / 4 * 4;
+}
+
 // Rows per matrix-core work item: a wave recomputes 2 nkc - 1 intermediate
 // blocks of 16 rows per item, so items are tall unless the tile is short.
 __device__ int default_mfma_seg_rows(int h) {
@@ -75,7 +82,7 @@ __global__ __launch_bounds__(SETUP_T) void batch_setup_kernel(
     __syncthreads();
     const int per = (n + SETUP_T - 1) / SETUP_T;
     const int t0 = min(n, static_cast<int>(threadIdx.x) * per), t1 = min(n, t0 + per);
-    long long items = 0, nms = 0, pix = 0, mitems = 0;
+    long long items = 0, nms = 0, pix = 0, mitems = 0, nitems = 0, sfl = 0;
     for (int t = t0; t < t1; ++t) {
         const mhfd_tile d = in[t];
         bool ok = d.img && d.result && d.h >= 1 && d.w >= 1 && d.h <= max_h && d.w <= max_w &&
@@ -94,7 +101,11 @@ __global__ __launch_bounds__(SETUP_T) void batch_setup_kernel(
         bt.seg_rows = ok ? (d.seg_rows ? d.seg_rows : default_seg_rows(d.h, d.w)) : 32;
         bt.strips = (bt.w + 63) / 64;
         bt.segs = (bt.h + bt.seg_rows - 1) / bt.seg_rows;
-        bt.bpr = (bt.w + NMS_T - 1) / NMS_T;
+        // two columns per maxima lane when the K x 2 candidate bits fit the
+        // mask and every row of the tile starts 8-byte aligned; the stack
+        // offset is fixed below, so its parity is checked in the prefix pass
+        bt.nms_cw = (K <= 16 && bt.w % 2 == 0) ? 2 : 1;
+        bt.bpr = (bt.w + 64 * bt.nms_cw - 1) / (64 * bt.nms_cw);
         bt.mseg_rows = d.seg_rows && ok ? d.seg_rows : default_mfma_seg_rows(bt.h);
         bt.mtiles_x = mfma ? (bt.w + MFMA_WAVE_COLS - 1) / MFMA_WAVE_COLS : 0;
         bt.msegs = (bt.h + bt.mseg_rows - 1) / bt.mseg_rows;
@@ -102,31 +113,41 @@ __global__ __launch_bounds__(SETUP_T) void batch_setup_kernel(
         mitems += static_cast<long long>(bt.mtiles_x) * bt.msegs;
         items += static_cast<long long>(bt.strips) * bt.segs;
         nms += static_cast<long long>(bt.h) * bt.bpr;
+        nitems += static_cast<long long>(nms_runs(bt.h)) * bt.bpr;
         pix += static_cast<long long>(bt.h) * bt.w;
+        sfl += stack_floats(bt.h, bt.w, K);
     }
-    long long tot_items, tot_nms, tot_pix, tot_mitems;
+    long long tot_items, tot_nms, tot_pix, tot_mitems, tot_nitems, tot_sfl;
     const long long b_items = block_exclusive_scan(items, shl, &tot_items);
     const long long b_nms = block_exclusive_scan(nms, shl, &tot_nms);
     const long long b_pix = block_exclusive_scan(pix, shl, &tot_pix);
     const long long b_mitems = block_exclusive_scan(mitems, shl, &tot_mitems);
-    long long ri = b_items, rn = b_nms, rp = b_pix, rm = b_mitems;
+    const long long b_nitems = block_exclusive_scan(nitems, shl, &tot_nitems);
+    const long long b_sfl = block_exclusive_scan(sfl, shl, &tot_sfl);
+    (void)b_pix;
+    (void)tot_sfl;
+    long long ri = b_items, rn = b_nms, rm = b_mitems, rq = b_nitems, rs = b_sfl;
     for (int t = t0; t < t1; ++t) {
         BatchTile& bt = tiles[t];
         bt.item_base = static_cast<int>(ri);
         bt.nms_base = static_cast<int>(rn);
         bt.mitem_base = static_cast<int>(rm);
-        bt.stack_off = rp * K;
+        bt.nitem_base = static_cast<int>(rq);
+        bt.stack_off = rs;
         ri += static_cast<long long>(bt.strips) * bt.segs;
         rn += static_cast<long long>(bt.h) * bt.bpr;
-        rp += static_cast<long long>(bt.h) * bt.w;
         rm += static_cast<long long>(bt.mtiles_x) * bt.msegs;
+        rq += static_cast<long long>(nms_runs(bt.h)) * bt.bpr;
+        rs += stack_floats(bt.h, bt.w, K);
     }
     __syncthreads();
     const bool valid = !bad_s && tot_pix <= max_pixels && tot_items * K < (1LL << 30) &&
-                       tot_nms < (1LL << 30) && tot_mitems * K < (1LL << 30);
+                       tot_nms < (1LL << 30) && tot_mitems * K < (1LL << 30) &&
+                       tot_nitems < (1LL << 30);
     if (threadIdx.x == 0) {
         ctr->items_per_scale = valid ? static_cast<int>(tot_items) : 0;
         ctr->nms_blocks = valid ? static_cast<int>(tot_nms) : 0;
+        ctr->nms_items = valid ? static_cast<int>(tot_nitems) : 0;
         ctr->valid = valid ? 1 : 0;
         ctr->pool_used = 0;
         ctr->flags = 0;
@@ -149,151 +170,45 @@ __global__ __launch_bounds__(SETUP_T) void batch_setup_kernel(
     }
 }
 
-__device__ __forceinline__ int tile_of(const BatchTile* __restrict__ tiles, int n_tiles, int blk) {
-    int lo = 0, hi = n_tiles;  // last t with nms_base <= blk
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (tiles[mid].nms_base <= blk)
-            lo = mid;
-        else
-            hi = mid;
-    }
-    return lo;
-}
-
-// Exclusive prefix within the wave of a per-lane count c in [0, 2^BITS).
-template <int BITS>
-__device__ __forceinline__ int wave_exclusive_prefix(int c, int* wave_total) {
-    int pre = 0, tot = 0;
-#pragma unroll
-    for (int b = 0; b < BITS; ++b) {
-        const unsigned long long bal = __ballot((c >> b) & 1);
-        const unsigned lo = static_cast<unsigned>(bal);
-        const unsigned hi = static_cast<unsigned>(bal >> 32);
-        pre += static_cast<int>(__builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u))) << b;
-        tot += __popcll(bal) << b;
-    }
-    *wave_total = tot;
-    return pre;
-}
-
+// Persistent maxima waves over every tile's (run of nms::ROWS rows, strip of
+// 64 nms_cw columns) items, the per-wave body of the single-tile pass; the
+// tile index rides in the upper bits of every record's k.
 template <int K>
-__global__ __launch_bounds__(NMS_T) void nms_batch_kernel(
+__global__ __launch_bounds__(64 * NMS_WAVES) void nms_batch_kernel(
     const float* __restrict__ stack, const BatchTile* __restrict__ tiles, int n_tiles, float tau,
     int n_blk_bound, int32_t* __restrict__ blk_n, int32_t* __restrict__ blk_o,
     Cand* __restrict__ pool, int64_t cap, BatchCounters* __restrict__ ctr) {
-    __shared__ float vm[K][NMS_T + 2];
-    __shared__ int wave_tot[NMS_T / 64];
-    __shared__ int run_base;
-    const int total = ctr->nms_blocks;
-    const int tid = threadIdx.x;
-    for (int blk = blockIdx.x; blk < total; blk += gridDim.x) {
-        const int ti = tile_of(tiles, n_tiles, blk);
-        const BatchTile& T = tiles[ti];
-        const int H = T.h, W = T.w;
+    const int total = ctr->nms_items;
+    const int n_waves = gridDim.x * NMS_WAVES;
+    for (int item = blockIdx.x * NMS_WAVES + (threadIdx.x >> 6); item < total; item += n_waves) {
+        int lo = 0, hi = n_tiles;  // last t with nitem_base <= item
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (tiles[mid].nitem_base <= item)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const BatchTile& T = tiles[lo];
+        const int local = item - T.nitem_base;
+        const int run = local / T.bpr, strip = local - run * T.bpr;
+        nms::Sink out;
+        out.blk_n = blk_n + T.nms_base;
+        out.blk_o = blk_o + T.nms_base;
+        out.slots = pool + static_cast<int64_t>(T.nms_base) * SLOT;
+        out.over = pool + static_cast<int64_t>(n_blk_bound) * SLOT;
+        out.cap = cap;
+        out.pool_used = &ctr->pool_used;
+        out.flags = &ctr->flags;
+        out.k_tag = lo << TILE_SHIFT;
         const float* st = stack + T.stack_off;
-        const int local = blk - T.nms_base;
-        const int y = local / T.bpr;
-        const int x0 = (local - y * T.bpr) * NMS_T;
-        const int x = x0 + tid;
-        const bool valid = x < W;
-        const size_t plane = static_cast<size_t>(H) * W;
-        const int yu = y > 0 ? y - 1 : 0;
-        const int yd = y + 1 < H ? y + 1 : H - 1;
-        const int xc = valid ? x : W - 1;
-        float cv[K], vmx[K];
-        {
-            const float* pc = st + static_cast<size_t>(y) * W + xc;
-            const float* pu = st + static_cast<size_t>(yu) * W + xc;
-            const float* pd = st + static_cast<size_t>(yd) * W + xc;
-            float u[K], d[K];
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                cv[k] = pc[k * plane];
-                u[k] = pu[k * plane];
-                d[k] = pd[k * plane];
-            }
-#pragma unroll
-            for (int k = 0; k < K; ++k) vmx[k] = valid ? fmax3(u[k], cv[k], d[k]) : -INFINITY;
-        }
-        if (tid == 0 || tid == NMS_T - 1) {
-            const int xh = tid == 0 ? x0 - 1 : x0 + NMS_T;
-            const bool ok = xh >= 0 && xh < W;
-            const int xs = ok ? xh : 0;
-            const int slot = tid == 0 ? 0 : NMS_T + 1;
-            const float* pc = st + static_cast<size_t>(y) * W + xs;
-            const float* pu = st + static_cast<size_t>(yu) * W + xs;
-            const float* pd = st + static_cast<size_t>(yd) * W + xs;
-            float hv[K];
-#pragma unroll
-            for (int k = 0; k < K; ++k) hv[k] = fmax3(pu[k * plane], pc[k * plane], pd[k * plane]);
-#pragma unroll
-            for (int k = 0; k < K; ++k) vm[k][slot] = ok ? hv[k] : -INFINITY;
-        }
-#pragma unroll
-        for (int k = 0; k < K; ++k) vm[k][tid + 1] = vmx[k];
-        __syncthreads();
-        unsigned mask = 0u;
-        {
-            float m_prev = -INFINITY;
-            float m_cur = fmax3(vm[0][tid], vm[0][tid + 1], vm[0][tid + 2]);
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const float m_next = k + 1 < K ? fmax3(vm[k + 1][tid], vm[k + 1][tid + 1],
-                                                       vm[k + 1][tid + 2])
-                                               : -INFINITY;
-                const float v = cv[k];
-                if (v > tau && v >= fmax3(m_prev, m_cur, m_next)) mask |= 1u << k;
-                m_prev = m_cur;
-                m_cur = m_next;
-            }
-            if (!valid) mask = 0u;
-        }
-        const int c = __popc(mask);
-        int wtot;
-        const int pre = wave_exclusive_prefix<6>(c, &wtot);
-        const int lane = tid & 63, wv = tid >> 6;
-        if (lane == 0) wave_tot[wv] = wtot;
-        __syncthreads();
-        int woff = 0, n = 0;
-#pragma unroll
-        for (int i = 0; i < NMS_T / 64; ++i) {
-            woff += i < wv ? wave_tot[i] : 0;
-            n += wave_tot[i];
-        }
-        if (tid == 0) {
-            int o = 0;
-            if (n > SLOT) {
-                o = atomicAdd(&ctr->pool_used, n - SLOT);
-                if (static_cast<int64_t>(o) + (n - SLOT) > cap)
-                    atomicOr(&ctr->flags, MHFD_FLAG_CAND_OVERFLOW);
-            }
-            run_base = o;
-            blk_n[blk] = n;
-            blk_o[blk] = o;
-        }
-        __syncthreads();
-        if (c > 0) {
-            int j = woff + pre;
-            Cand* own = pool + static_cast<int64_t>(blk) * SLOT;
-            Cand* over = pool + static_cast<int64_t>(n_blk_bound) * SLOT + run_base - SLOT;
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                if (mask & (1u << k)) {
-                    Cand r;
-                    r.y = y;
-                    r.x = x;
-                    r.k = k | (ti << TILE_SHIFT);
-                    r.r = cv[k];
-                    if (j < SLOT)
-                        own[j] = r;
-                    else if (run_base + (j - SLOT) < cap)
-                        over[j] = r;
-                    ++j;
-                }
+        if constexpr (2 * K <= 32) {
+            if (T.nms_cw == 2) {
+                nms::wave<K, 2, SLOT>(st, T.h, T.w, tau, T.bpr, strip, run, out);
+                continue;
             }
         }
-        __syncthreads();  // vm and run_base are reused by the next piece
+        nms::wave<K, 1, SLOT>(st, T.h, T.w, tau, T.bpr, strip, run, out);
     }
 }
 
@@ -424,7 +339,7 @@ __global__ void results_batch_kernel(const int32_t* __restrict__ blk_off,
 
 template <int K>
 void launch_nms_batch_k(const BatchLaunchArgs& a, hipStream_t s) {
-    nms_batch_kernel<K><<<a.nms_grid, NMS_T, 0, s>>>(a.stack, a.tiles, a.n_tiles, a.tau,
+    nms_batch_kernel<K><<<a.nms_grid, 64 * NMS_WAVES, 0, s>>>(a.stack, a.tiles, a.n_tiles, a.tau,
                                                      a.n_blk_bound, a.blk_n, a.blk_o, a.pool,
                                                      a.cap, a.ctr);
 }

@@ -23,33 +23,18 @@
 #include <utility>
 
 #include "mhfd_internal.h"
+#include "nms_wave.h"
 
 namespace mhfd {
 
 namespace {
 
-constexpr int NMS_ROWS = 32;   // rows per NMS wave
 constexpr int NMS_WAVES = 4;   // independent waves per NMS workgroup
 constexpr int SLOT = 16;       // pool records each (row, strip) cell owns
 constexpr int SCAN_T = 1024;
 
-__device__ __forceinline__ float fmax3(float a, float b, float c) { return fmaxf(a, fmaxf(b, c)); }
-
-// Exclusive prefix within the wave of a per-lane count c in [0, 2^bits).
-template <int BITS>
-__device__ __forceinline__ int wave_exclusive_prefix(int c, int* wave_total) {
-    int pre = 0, tot = 0;
-#pragma unroll
-    for (int b = 0; b < BITS; ++b) {
-        const unsigned long long bal = __ballot((c >> b) & 1);
-        const unsigned lo = static_cast<unsigned>(bal);
-        const unsigned hi = static_cast<unsigned>(bal >> 32);
-        pre += static_cast<int>(__builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u))) << b;
-        tot += __popcll(bal) << b;
-    }
-    *wave_total = tot;
-    return pre;
-}
+using nms::fmax3;
+using nms::wave_exclusive_prefix;
 
 __global__ void init_counters_kernel(DetectCounters* ctr) {
     if (threadIdx.x == 0) {
@@ -60,154 +45,30 @@ __global__ void init_counters_kernel(DetectCounters* ctr) {
     }
 }
 
-// Neighbour exchange across the whole wave (DPP wave shifts, no LDS): lane l
-// receives lane l - 1's value (shr) or lane l + 1's (shl); the lane without
-// a source receives `edge`.
-__device__ __forceinline__ float wave_shr1(float v, float edge) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
-        __builtin_bit_cast(int, edge), __builtin_bit_cast(int, v), 0x138, 0xF, 0xF, false));
-}
-__device__ __forceinline__ float lane_value(float v, int lane) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
-}
-__device__ __forceinline__ float wave_shl1(float v, float edge) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
-        __builtin_bit_cast(int, edge), __builtin_bit_cast(int, v), 0x130, 0xF, 0xF, false));
-}
-
-// One wave per (strip of 64 CW columns, run of NMS_ROWS rows); a workgroup
-// holds NMS_WAVES independent waves.  Lane l owns columns x0 + CW l ...
-// x0 + CW l + CW - 1, read as one aligned CW-float load per plane and row.
-// The wave keeps rows y-1, y, y+1 of every plane in registers, rolling down
-// the run with row y+2 already in flight.  Horizontal neighbours come from
-// DPP wave shifts; the two columns beyond the strip (x0 - 1 and x0 + 64 CW)
-// of every plane come from one more load per row (lanes k and 32 + k hold
-// plane k's left and right halo), reduced vertically in those lanes and
-// read out per plane.  Every (row, strip) cell compacts its candidates in
-// (x, k) order with ballot/mbcnt offsets into its own pool slot (SLOT
-// records) and reserves the shared overflow region with one atomic only when
-// it has more.
+// One wave per (strip of 64 CW columns, run of nms::ROWS rows); a workgroup
+// holds NMS_WAVES independent waves.  The per-wave body is nms::wave.
 template <int K, int CW>
 __global__ __launch_bounds__(64 * NMS_WAVES) void nms_kernel(
     const float* __restrict__ st, int H, int W, float tau, int bpr, int n_runs,
     int32_t* __restrict__ blk_n, int32_t* __restrict__ blk_o, Cand* __restrict__ pool,
     int64_t n_cells, int64_t cap, DetectCounters* __restrict__ ctr) {
-    static_assert(CW * K <= 32, "candidate mask is 32 bits");
-    typedef float Vec __attribute__((ext_vector_type(CW)));
-    const int lane = threadIdx.x & 63;
     const int wid = blockIdx.x * NMS_WAVES + (threadIdx.x >> 6);  // (run, strip), strip fastest
     if (wid >= n_runs * bpr) return;
-    const int strip = wid % bpr;
-    const int run = wid / bpr;
-    const int x0 = strip * 64 * CW;
-    const int xl = x0 + CW * lane;            // first column of the lane
-    const bool col_ok = xl < W;               // W % CW == 0: all CW columns or none
-    const int xc = col_ok ? xl : W - CW;
-    const size_t plane = static_cast<size_t>(H) * W;
-    const int y0 = run * NMS_ROWS;
-    const int y1 = min(y0 + NMS_ROWS, H);
-    // halo lane: plane hk, column hx
-    const int hk = lane & 31;
-    const int hx = lane < 32 ? x0 - 1 : x0 + 64 * CW;
-    const bool h_ok = hk < K && hx >= 0 && hx < W;
-    const size_t h_off = static_cast<size_t>(h_ok ? hk : 0) * plane + (h_ok ? hx : 0);
-
-    auto load_row = [&](int y, Vec* v, float& hv) {
-        const bool ok = y >= 0 && y < H;
-        const int yy = y < 0 ? 0 : (y >= H ? H - 1 : y);
-        const float* p = st + static_cast<size_t>(yy) * W + xc;
-#pragma unroll
-        for (int k = 0; k < K; ++k) v[k] = *reinterpret_cast<const Vec*>(p + k * plane);
-        hv = st[h_off + static_cast<size_t>(yy) * W];
-#pragma unroll
-        for (int k = 0; k < K; ++k) v[k] = (ok && col_ok) ? v[k] : static_cast<Vec>(-INFINITY);
-        hv = (ok && h_ok) ? hv : -INFINITY;
-    };
-    Vec up[K], cur[K], dn[K], nx[K];
-    float hup, hcur, hdn, hnx;
-    load_row(y0 - 1, up, hup);
-    load_row(y0, cur, hcur);
-    load_row(y0 + 1, dn, hdn);
-    for (int y = y0; y < y1; ++y) {
-        load_row(y + 2, nx, hnx);  // in flight while row y is tested
-        const float hm = fmax3(hup, hcur, hdn);
-        Vec m3[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            Vec vm;
-#pragma unroll
-            for (int c = 0; c < CW; ++c) vm[c] = fmax3(up[k][c], cur[k][c], dn[k][c]);
-            const float left = wave_shr1(vm[CW - 1], lane_value(hm, k));
-            const float right = wave_shl1(vm[0], lane_value(hm, 32 + k));
-#pragma unroll
-            for (int c = 0; c < CW; ++c) {
-                const float l = c > 0 ? vm[c - 1] : left;
-                const float r = c + 1 < CW ? vm[c + 1] : right;
-                m3[k][c] = fmax3(l, vm[c], r);
-            }
-        }
-        unsigned mask = 0u;
-#pragma unroll
-        for (int c = 0; c < CW; ++c)
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const float mp = k > 0 ? m3[k - 1][c] : -INFINITY;
-                const float mn = k + 1 < K ? m3[k + 1][c] : -INFINITY;
-                const float v = cur[k][c];
-                if (v > tau && v >= fmax3(mp, m3[k][c], mn)) mask |= 1u << (c * K + k);
-            }
-        const int cnt = __popc(mask);
-        int n;
-        const int pre = wave_exclusive_prefix<6>(cnt, &n);
-        const int64_t cell = static_cast<int64_t>(y) * bpr + strip;
-        int o = 0;
-        if (lane == 0) {
-            if (n > SLOT) {
-                o = atomicAdd(&ctr->pool_used, n - SLOT);
-                if (static_cast<int64_t>(o) + (n - SLOT) > cap)
-                    atomicOr(&ctr->flags, MHFD_FLAG_CAND_OVERFLOW);
-            }
-            blk_n[cell] = n;
-            blk_o[cell] = o;
-        }
-        o = __shfl(o, 0, 64);
-        if (cnt > 0) {
-            int j = pre;
-            Cand* own = pool + cell * SLOT;
-            Cand* over = pool + n_cells * SLOT + o - SLOT;
-#pragma unroll
-            for (int c = 0; c < CW; ++c)
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    if (mask & (1u << (c * K + k))) {
-                        Cand rec;
-                        rec.y = y;
-                        rec.x = xl + c;
-                        rec.k = k;
-                        rec.r = cur[k][c];
-                        if (j < SLOT)
-                            own[j] = rec;
-                        else if (o + (j - SLOT) < cap)
-                            over[j] = rec;
-                        ++j;
-                    }
-                }
-        }
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            up[k] = cur[k];
-            cur[k] = dn[k];
-            dn[k] = nx[k];
-        }
-        hup = hcur;
-        hcur = hdn;
-        hdn = hnx;
-    }
+    nms::Sink out;
+    out.blk_n = blk_n;
+    out.blk_o = blk_o;
+    out.slots = pool;
+    out.over = pool + n_cells * SLOT;
+    out.cap = cap;
+    out.pool_used = &ctr->pool_used;
+    out.flags = &ctr->flags;
+    out.k_tag = 0;
+    nms::wave<K, CW, SLOT>(st, H, W, tau, bpr, wid % bpr, wid / bpr, out);
 }
 
 template <int K, int CW>
 void launch_nms_k(const DetectWorkspace& ws, int h, int w, float tau, hipStream_t s) {
-    const int runs = (h + NMS_ROWS - 1) / NMS_ROWS;
+    const int runs = (h + nms::ROWS - 1) / nms::ROWS;
     const int waves = runs * ws.blk_per_row;
     nms_kernel<K, CW><<<(waves + NMS_WAVES - 1) / NMS_WAVES, 64 * NMS_WAVES, 0, s>>>(
         ws.stack, h, w, tau, ws.blk_per_row, runs, ws.blk_n, ws.blk_o, ws.pool, ws.n_blk, ws.cap,

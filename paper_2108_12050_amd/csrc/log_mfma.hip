@@ -451,40 +451,45 @@ void log_mfma_batch_kernel(int n_tiles, const BatchTile* __restrict__ tiles,
     }
 }
 
+// max |I| over rows [y, y+1) ... of an fp32 image: workgroups stride over
+// rows, lanes over columns (float4 where rows are 16-byte aligned); no
+// per-element division.
+__device__ __forceinline__ float rows_absmax(const float* __restrict__ img, int h, int w,
+                                             long long pitch, int row0, int row_step) {
+    const bool v4 = (pitch % 4 == 0) && (reinterpret_cast<uintptr_t>(img) % 16 == 0);
+    const int w4 = v4 ? (w >> 2) : 0;
+    float m = 0.0f;
+    for (int y = row0; y < h; y += row_step) {
+        const float* row = img + static_cast<long long>(y) * pitch;
+        for (int i = threadIdx.x; i < w4; i += blockDim.x) {
+            const float4_t v = reinterpret_cast<const float4_t*>(row)[i];
+            m = fmaxf(m, fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3]))));
+        }
+        for (int x = 4 * w4 + threadIdx.x; x < w; x += blockDim.x) m = fmaxf(m, fabsf(row[x]));
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) m = fmaxf(m, __shfl_xor(m, d, 64));
+    return m;
+}
+
 // max |I| of an fp32 image as float bits (non-negative floats order as their
 // bit patterns), for the input scale.  `bits` must be zero on entry.
 __global__ void absmax_kernel(const float* __restrict__ img, int h, int w, long long pitch,
                               uint32_t* __restrict__ bits) {
-    float m = 0.0f;
-    const long long n = static_cast<long long>(h) * w;
-    for (long long i = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; i < n;
-         i += static_cast<long long>(gridDim.x) * blockDim.x) {
-        const long long y = i / w, x = i - y * w;
-        m = fmaxf(m, fabsf(img[y * pitch + x]));
-    }
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) m = fmaxf(m, __shfl_xor(m, d, 64));
-    if ((threadIdx.x & 63) == 0) atomicMax(bits, __float_as_uint(m));
+    const float m = rows_absmax(img, h, w, pitch, blockIdx.x, gridDim.x);
+    if ((threadIdx.x & 63) == 0 && m > 0.0f) atomicMax(bits, __float_as_uint(m));
 }
 
-// Per-tile max |I| of a batch (bits[t] zero on entry): every workgroup
-// strides over every tile.
+// Per-tile max |I| of a batch (bits[t] zero on entry): the workgroups split
+// the rows of every tile.
 __global__ void absmax_batch_kernel(int n_tiles, const BatchTile* __restrict__ tiles,
                                     const BatchCounters* __restrict__ ctr,
                                     uint32_t* __restrict__ bits) {
     if (!ctr->valid) return;
     for (int t = 0; t < n_tiles; ++t) {
         const BatchTile& d = tiles[t];
-        const float* img = static_cast<const float*>(d.img);
-        const long long n = static_cast<long long>(d.h) * d.w;
-        float m = 0.0f;
-        for (long long i = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; i < n;
-             i += static_cast<long long>(gridDim.x) * blockDim.x) {
-            const long long y = i / d.w, x = i - y * d.w;
-            m = fmaxf(m, fabsf(img[y * d.pitch + x]));
-        }
-#pragma unroll
-        for (int dd = 32; dd > 0; dd >>= 1) m = fmaxf(m, __shfl_xor(m, dd, 64));
+        const float m = rows_absmax(static_cast<const float*>(d.img), d.h, d.w, d.pitch,
+                                    blockIdx.x, gridDim.x);
         if ((threadIdx.x & 63) == 0 && m > 0.0f) atomicMax(bits + t, __float_as_uint(m));
     }
 }
@@ -682,12 +687,8 @@ hipError_t launch_log_mfma(int in_dtype, int nkr, int nkc, const void* img, int 
 hipError_t launch_absmax(const float* img, int h, int w, int64_t pitch, uint32_t* bits,
                          hipStream_t s) {
     zero_words_kernel<<<1, 64, 0, s>>>(bits, 1);
-    const long long n = static_cast<long long>(h) * w;
-    long long blocks = (n + 256 * 16 - 1) / (256 * 16);
-    if (blocks > 2048) blocks = 2048;
-    if (blocks < 1) blocks = 1;
-    absmax_kernel<<<static_cast<int>(blocks), 256, 0, s>>>(img, h, w,
-                                                           static_cast<long long>(pitch), bits);
+    const int blocks = h < 2048 ? h : 2048;  // a workgroup per row, up to 2048
+    absmax_kernel<<<blocks, 256, 0, s>>>(img, h, w, static_cast<long long>(pitch), bits);
     return hipGetLastError();
 }
 

@@ -666,7 +666,8 @@ struct BatchLayout {
 bool batch_layout(const mhfd_plan_s* p, int n, int64_t max_pixels, BatchLayout* L) {
     if (n < 1 || n > MHFD_MAX_BATCH || max_pixels < 1 || max_pixels > (int64_t(1) << 31) - 1)
         return false;
-    const int64_t nbb = max_pixels / 256 + static_cast<int64_t>(n) * (p->max_h + 1);
+    // maxima cells: h * ceil(w / 64) <= h w / 64 + h per tile
+    const int64_t nbb = max_pixels / 64 + static_cast<int64_t>(n) * (p->max_h + 1);
     if (nbb > (int64_t(1) << 30)) return false;
     L->n_blk_bound = static_cast<int>(nbb);
     int64_t cap = p->max_cand * n;
@@ -678,7 +679,8 @@ bool batch_layout(const mhfd_plan_s* p, int n, int64_t max_pixels, BatchLayout* 
         off = align_up(off + bytes);
         return o;
     };
-    L->stack = take(sizeof(float) * static_cast<size_t>(p->K) * max_pixels);
+    // every tile's planes start on a float4: up to 3 floats of padding each
+    L->stack = take(sizeof(float) * (static_cast<size_t>(p->K) * max_pixels + 4 * static_cast<size_t>(n)));
     L->tiles = take(sizeof(mhfd::BatchTile) * n);
     L->ctr = take(sizeof(mhfd::BatchCounters));
     L->blk_n = take(sizeof(int32_t) * nbb);

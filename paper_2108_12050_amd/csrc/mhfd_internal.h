@@ -187,10 +187,11 @@ struct BatchTile {
     int capacity;
     int seg_rows;
     int strips, segs;       // LoG workgroups per scale: strips * segs
-    int bpr;                // NMS workgroups per row
+    int bpr;                // maxima cells per row (strips of 64 nms_cw columns)
     int item_base;          // prefix of strips * segs over earlier tiles
     int nms_base;           // prefix of h * bpr over earlier tiles
-    int pad;
+    int nms_cw;             // columns per maxima lane (1 or 2)
+    int nitem_base;         // prefix of ceil(h / 32) * bpr (maxima wave items)
     // matrix-core items (u8 plans): wave columns x row segments
     int mtiles_x, msegs, mseg_rows;
     int mitem_base;         // prefix of mtiles_x * msegs over earlier tiles
@@ -198,7 +199,8 @@ struct BatchTile {
 
 struct BatchCounters {
     int32_t items_per_scale;  // sum over tiles of strips * segs
-    int32_t nms_blocks;       // sum over tiles of h * bpr
+    int32_t nms_blocks;       // sum over tiles of h * bpr (maxima cells)
+    int32_t nms_items;        // sum over tiles of ceil(h / 32) * bpr (maxima waves)
     int32_t valid;            // 1 when every descriptor passed the checks
     int32_t pool_used;
     int32_t flags;
