@@ -57,7 +57,7 @@ PEAK_FP32_VECTOR = 157.3e12   # MI355X FP32 vector, packed FMA
 PEAK_FP32_VECTOR_UNPACKED = 78.6e12
 PEAK_FP16_MFMA = 2.5e15       # MI355X dense FP16 matrix
 COUNTER_FILE = os.path.join(ROOT, "profiles", "log_mfma_4096_u8_counters.json")
-LOG_KERNEL = "log_mfma_u8_kernel"
+LOG_KERNEL = "log_mfma_kernel"  # log_mfma_kernel<T, nkr, nkc>; the batch kernel is named apart
 
 
 def kernel_source_hash() -> str:
@@ -262,6 +262,12 @@ def _pmc_per_kernel(path: str) -> dict:
     return {k: sum(v) / len(v) for k, v in acc.items()}
 
 
+def _short(name: str) -> str:
+    """Kernel name without namespace and argument list."""
+    n = name.replace("(anonymous namespace)::", "").replace("mhfd::", "").replace("void ", "")
+    return n.split("(")[0][:60]
+
+
 def traffic_summarize(fetch_dir: str, write_dir: str, mfma_dir: str) -> int:
     """Write profiles/log_mfma_4096_u8_counters.json from three counter runs
     of --traffic-run: FETCH_SIZE, WRITE_SIZE (KiB per dispatch, scaled by
@@ -282,14 +288,14 @@ def traffic_summarize(fetch_dir: str, write_dir: str, mfma_dir: str) -> int:
     mfma_flop = sum(v for k, v in mops.items() if LOG_KERNEL in k) * 512
     algo = H * W * 1 + K * H * W * 4
     out = {"kernel_source_sha256_16": kernel_source_hash(),
-           "workload": "4096x4096 u8, sigma 1..10, the log_mfma_u8_kernel launches of one tile",
+           "workload": "4096x4096 u8, sigma 1..10, the log_mfma_kernel<uint8_t, nkr, nkc> launches of one tile",
            "bytes_per_tile": round(bytes_tile),
            "fetch_kib_raw": round(kib_f, 1), "write_kib_raw": round(kib_w, 1),
            "calibration_kernel": cal[0][:80], "fetch_scale": round(f_scale, 4),
            "write_scale": round(w_scale, 4), "algorithmic_bytes": algo,
            "mfma_flop_per_tile": round(mfma_flop),
-           "tail_kernels_fetch_kib": {k.split("(")[0][-40:]: round(fetch[k], 1) for k in tail},
-           "tail_kernels_write_kib": {k.split("(")[0][-40:]: round(write.get(k, 0.0), 1) for k in tail}}
+           "tail_kernels_fetch_kib": {_short(k): round(fetch[k], 1) for k in tail},
+           "tail_kernels_write_kib": {_short(k): round(write.get(k, 0.0), 1) for k in tail}}
     with open(COUNTER_FILE, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out, indent=1))
@@ -425,7 +431,7 @@ def main() -> int:
         "roofline": {"bound": "mfma", "achieved": round(achieved / 1e12, 3),
                      "peak": PEAK_FP16_MFMA / 1e12, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP16_MFMA, 4), "traffic": traffic,
-                     "kernel": "log_mfma_u8_kernel (one launch per K-block shape, 3 per tile "
+                     "kernel": "log_mfma_kernel<uint8_t, nkr, nkc> (one launch per K-block shape, 3 per tile "
                                "for sigma 1..10; split-FP16 MFMA, FP32 accumulate)",
                      "flop_per_tile": FLOP_PER_PX * H * W,
                      "fp32_vector_view": {"peak": PEAK_FP32_VECTOR / 1e12,

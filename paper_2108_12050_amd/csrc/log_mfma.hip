@@ -120,13 +120,31 @@ __device__ __forceinline__ float input_scale(uint32_t maxbits) {
 // 16-row or 16-column tiles) reflects every index as often as needed and
 // guards every store.  Keeping the regular body free of the general code
 // keeps its loop small and its memory waits exact.
-template <int NKR, int NKC>
+// Input prefetch depth D (blocks of 16 rows loaded ahead of their row pass)
+// and ring length NS (intermediate blocks held: at least the 2 nkc the
+// column pass reads, rounded up to a multiple of D so that ring and prefetch
+// slots repeat together).
+// Measured on 4096^2 u8 tiles: depth 4 with the peeled loop below pays for
+// nkc = 1 (11% faster); for nkc = 2 it was 10% slower, and for nkc >= 3 the
+// extra registers spill.
+template <typename T, int NKC>
+constexpr int mfma_depth() { return NKC == 1 ? 4 : 2; }
+// Whether the first ring turn is peeled off the main loop.
+template <typename T, int NKC>
+constexpr bool mfma_peel() { return NKC == 1; }
+template <typename T, int NKC>
+constexpr int mfma_ring() {
+    return (2 * NKC + mfma_depth<T, NKC>() - 1) / mfma_depth<T, NKC>() * mfma_depth<T, NKC>();
+}
+
+template <typename T, int NKR, int NKC>
 __device__ __forceinline__ bool regular_job(const WaveJob& J) {
-    constexpr int NS = 2 * NKC;
+    constexpr int NS = mfma_ring<T, NKC>(), D = mfma_depth<T, NKC>();
     const int xw = J.x0 - J.rw8;
-    // rows touched: y0 - rwc ... y1 + 16 (NS + 2) (prefetch overrun)
+    // rows touched: y0 - rwc ... y1 - rwc + 16 (NS - 1 + D) (ring and
+    // prefetch overrun), reflected once at most
     return J.aligned && J.out_vec && (J.w & 7) == 0 && J.x0 + 16 <= J.w && xw >= -J.w &&
-           xw + 32 * NKR <= 2 * J.w && J.h >= J.rwc + 16 * (NS + 3) &&
+           xw + 32 * NKR <= 2 * J.w && J.h >= J.rwc + 16 * (NS + D + 1) &&
            ((J.y1 - J.y0) & 15) == 0;
 }
 
@@ -212,8 +230,12 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
                                          int lane) {
     typedef Input<T> In;
     typedef typename In::Raw RawGroup;
-    constexpr int NS = 2 * NKC;  // ring of intermediate blocks
-    constexpr int D = 2;         // input prefetch depth (divides NS)
+    constexpr int NS = mfma_ring<T, NKC>();   // ring of intermediate blocks
+    constexpr int D = mfma_depth<T, NKC>();   // input prefetch depth (divides NS)
+    // Mirrored groups reversed at use rather than on arrival, so that the
+    // wait for a load falls D blocks after it (costs registers: only with
+    // the peeled loop).
+    constexpr bool LATE_REV = mfma_peel<T, NKC>();
     const T* img = static_cast<const T*>(J.img);
     const int g = lane >> 4;
     const int c = lane & 15;
@@ -234,7 +256,7 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
 
     // Regular items: source column and order of each 8-element group.
     int src[NKR];
-    bool rev[NKR];
+    bool rev[NKR] = {};
     if (!EDGE) {
 #pragma unroll
         for (int kb = 0; kb < NKR; ++kb) {
@@ -260,7 +282,7 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
 #pragma unroll
             for (int kb = 0; kb < NKR; ++kb) {
                 const RawGroup v = In::load(row + src[kb]);
-                raw[kb] = select_raw<T>(rev[kb], In::reverse(v), v);
+                raw[kb] = LATE_REV ? v : select_raw<T>(rev[kb], In::reverse(v), v);
             }
         } else if (fast) {
 #pragma unroll
@@ -280,7 +302,11 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
     auto rowpass = [&](int hb, Raw& rw, Slot& out) {
         half8_t in_hi[NKR], in_lo[NKR];
 #pragma unroll
-        for (int kb = 0; kb < NKR; ++kb) In::convert(rw[kb], J.in_scale, in_hi[kb], in_lo[kb]);
+        for (int kb = 0; kb < NKR; ++kb) {
+            const RawGroup v = (EDGE || !LATE_REV) ? rw[kb]
+                                                   : select_raw<T>(rev[kb], In::reverse(rw[kb]), rw[kb]);
+            In::convert(v, J.in_scale, in_hi[kb], in_lo[kb]);
+        }
         fetch(hb + D, rw);
         float4_t a = {0.f, 0.f, 0.f, 0.f}, b = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -322,27 +348,51 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
     for (int q = 0; q < D; ++q) fetch(q, raw[q]);
 #pragma unroll
     for (int p = 0; p < NS - 1; ++p) rowpass(p, raw[p % D], ring[p]);
-    for (int t0 = 0; t0 < ntiles; t0 += NS) {
+    // Output block t at ring position p (= t mod NS).
+    auto step = [&](int t, int p) {
+        rowpass(t + NS - 1, raw[(p + NS - 1) % D], ring[(p + NS - 1) % NS]);
+        float4_t ra = {0.f, 0.f, 0.f, 0.f}, rb = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int p = 0; p < NS; ++p) {
-            const int t = t0 + p;
-            if (t >= ntiles) break;
-            rowpass(t + NS - 1, raw[(p + NS - 1) % D], ring[(p + NS - 1) % NS]);
-            float4_t ra = {0.f, 0.f, 0.f, 0.f}, rb = {0.f, 0.f, 0.f, 0.f};
+        for (int kb = 0; kb < NKC; ++kb) {
+            const Slot& sa = ring[(p + 2 * kb) % NS];
+            const Slot& sb = ring[(p + 2 * kb + 1) % NS];
+            const half8_t xh = cat(sa.ah, sb.ah), xl = cat(sa.al, sb.al);
+            const half8_t yh = cat(sa.bh, sb.bh), yl = cat(sa.bl, sb.bl);
+            ra = mfma16(xh, ct[kb][0], ra);
+            rb = mfma16(yh, ct[kb][2], rb);
+            ra = mfma16(xh, ct[kb][1], ra);
+            rb = mfma16(yh, ct[kb][3], rb);
+            ra = mfma16(xl, ct[kb][0], ra);
+            rb = mfma16(yl, ct[kb][2], rb);
+        }
+        store(t, (ra + rb) * J.out_scale);
+    };
+    if constexpr (mfma_peel<T, NKC>()) {
+        // Whole ring turns without exits, the first one peeled, then the
+        // remaining blocks: the loop is entered with the same memory
+        // operations in flight as at its back edge (loads of later rows, then
+        // stores), so the waits at its head need only the prefetched rows,
+        // not the last stores, to have landed.
+        int t0 = 0;
+        if (ntiles >= NS) {
 #pragma unroll
-            for (int kb = 0; kb < NKC; ++kb) {
-                const Slot& sa = ring[(p + 2 * kb) % NS];
-                const Slot& sb = ring[(p + 2 * kb + 1) % NS];
-                const half8_t xh = cat(sa.ah, sb.ah), xl = cat(sa.al, sb.al);
-                const half8_t yh = cat(sa.bh, sb.bh), yl = cat(sa.bl, sb.bl);
-                ra = mfma16(xh, ct[kb][0], ra);
-                rb = mfma16(yh, ct[kb][2], rb);
-                ra = mfma16(xh, ct[kb][1], ra);
-                rb = mfma16(yh, ct[kb][3], rb);
-                ra = mfma16(xl, ct[kb][0], ra);
-                rb = mfma16(yl, ct[kb][2], rb);
+            for (int p = 0; p < NS; ++p) step(p, p);
+            for (t0 = NS; t0 + NS <= ntiles; t0 += NS) {
+#pragma unroll
+                for (int p = 0; p < NS; ++p) step(t0 + p, p);
             }
-            store(t, (ra + rb) * J.out_scale);
+        }
+#pragma unroll
+        for (int p = 0; p < NS - 1; ++p)
+            if (t0 + p < ntiles) step(t0 + p, p);
+    } else {
+        // one copy of the turn (register-bound shapes)
+        for (int t0 = 0; t0 < ntiles; t0 += NS) {
+#pragma unroll
+            for (int p = 0; p < NS; ++p) {
+                if (t0 + p >= ntiles) break;
+                step(t0 + p, p);
+            }
         }
     }
 }
@@ -350,7 +400,7 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
 template <typename T, int NKR, int NKC>
 __device__ __forceinline__ void run_job(const WaveJob& J, const half8_t* __restrict__ fr,
                                         int lane) {
-    if (regular_job<NKR, NKC>(J))
+    if (regular_job<T, NKR, NKC>(J))
         wave_job<T, NKR, NKC, false>(J, fr, lane);
     else
         wave_job<T, NKR, NKC, true>(J, fr, lane);
@@ -454,18 +504,39 @@ void log_mfma_batch_kernel(int n_tiles, const BatchTile* __restrict__ tiles,
 // max |I| over rows [y, y+1) ... of an fp32 image: workgroups stride over
 // rows, lanes over columns (float4 where rows are 16-byte aligned); no
 // per-element division.
+__device__ __forceinline__ float absmax4(float4_t v) {
+    return fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3])));
+}
+
+// max |I| over rows row0, row0 + row_step, ... of an h x w fp32 image, the
+// wave's lanes reduced.  Four rows are read per pass while four remain, so
+// every lane keeps four loads in flight; then one row per pass.
 __device__ __forceinline__ float rows_absmax(const float* __restrict__ img, int h, int w,
                                              long long pitch, int row0, int row_step) {
     const bool v4 = (pitch % 4 == 0) && (reinterpret_cast<uintptr_t>(img) % 16 == 0);
     const int w4 = v4 ? (w >> 2) : 0;
     float m = 0.0f;
-    for (int y = row0; y < h; y += row_step) {
-        const float* row = img + static_cast<long long>(y) * pitch;
+    int y = row0;
+    for (; y + 3 * row_step < h; y += 4 * row_step) {
+        const float* r0 = img + static_cast<long long>(y) * pitch;
+        const float* r1 = r0 + row_step * pitch;
+        const float* r2 = r1 + row_step * pitch;
+        const float* r3 = r2 + row_step * pitch;
         for (int i = threadIdx.x; i < w4; i += blockDim.x) {
-            const float4_t v = reinterpret_cast<const float4_t*>(row)[i];
-            m = fmaxf(m, fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3]))));
+            const float4_t a = reinterpret_cast<const float4_t*>(r0)[i];
+            const float4_t b = reinterpret_cast<const float4_t*>(r1)[i];
+            const float4_t c = reinterpret_cast<const float4_t*>(r2)[i];
+            const float4_t d = reinterpret_cast<const float4_t*>(r3)[i];
+            m = fmaxf(m, fmaxf(fmaxf(absmax4(a), absmax4(b)), fmaxf(absmax4(c), absmax4(d))));
         }
-        for (int x = 4 * w4 + threadIdx.x; x < w; x += blockDim.x) m = fmaxf(m, fabsf(row[x]));
+        for (int x = 4 * w4 + threadIdx.x; x < w; x += blockDim.x)
+            m = fmaxf(m, fmaxf(fmaxf(fabsf(r0[x]), fabsf(r1[x])), fmaxf(fabsf(r2[x]), fabsf(r3[x]))));
+    }
+    for (; y < h; y += row_step) {
+        const float* r0 = img + static_cast<long long>(y) * pitch;
+        for (int i = threadIdx.x; i < w4; i += blockDim.x)
+            m = fmaxf(m, absmax4(reinterpret_cast<const float4_t*>(r0)[i]));
+        for (int x = 4 * w4 + threadIdx.x; x < w; x += blockDim.x) m = fmaxf(m, fabsf(r0[x]));
     }
 #pragma unroll
     for (int d = 32; d > 0; d >>= 1) m = fmaxf(m, __shfl_xor(m, d, 64));
@@ -480,18 +551,18 @@ __global__ void absmax_kernel(const float* __restrict__ img, int h, int w, long 
     if ((threadIdx.x & 63) == 0 && m > 0.0f) atomicMax(bits, __float_as_uint(m));
 }
 
-// Per-tile max |I| of a batch (bits[t] zero on entry): the workgroups split
-// the rows of every tile.
-__global__ void absmax_batch_kernel(int n_tiles, const BatchTile* __restrict__ tiles,
+// Per-tile max |I| of a batch (bits[t] zero on entry): workgroup row y of
+// the grid takes tile y, and the gridDim.x workgroups of that row split its
+// rows.
+__global__ void absmax_batch_kernel(const BatchTile* __restrict__ tiles,
                                     const BatchCounters* __restrict__ ctr,
                                     uint32_t* __restrict__ bits) {
     if (!ctr->valid) return;
-    for (int t = 0; t < n_tiles; ++t) {
-        const BatchTile& d = tiles[t];
-        const float m = rows_absmax(static_cast<const float*>(d.img), d.h, d.w, d.pitch,
-                                    blockIdx.x, gridDim.x);
-        if ((threadIdx.x & 63) == 0 && m > 0.0f) atomicMax(bits + t, __float_as_uint(m));
-    }
+    const int t = blockIdx.y;
+    const BatchTile& d = tiles[t];
+    const float m = rows_absmax(static_cast<const float*>(d.img), d.h, d.w, d.pitch, blockIdx.x,
+                                gridDim.x);
+    if ((threadIdx.x & 63) == 0 && m > 0.0f) atomicMax(bits + t, __float_as_uint(m));
 }
 
 __global__ void zero_words_kernel(uint32_t* __restrict__ p, int n) {
@@ -687,7 +758,8 @@ hipError_t launch_log_mfma(int in_dtype, int nkr, int nkc, const void* img, int 
 hipError_t launch_absmax(const float* img, int h, int w, int64_t pitch, uint32_t* bits,
                          hipStream_t s) {
     zero_words_kernel<<<1, 64, 0, s>>>(bits, 1);
-    const int blocks = h < 2048 ? h : 2048;  // a workgroup per row, up to 2048
+    // a workgroup per four rows, up to 2048 workgroups
+    const int blocks = (h + 3) / 4 < 2048 ? (h + 3) / 4 : 2048;
     absmax_kernel<<<blocks, 256, 0, s>>>(img, h, w, static_cast<long long>(pitch), bits);
     return hipGetLastError();
 }
@@ -695,7 +767,8 @@ hipError_t launch_absmax(const float* img, int h, int w, int64_t pitch, uint32_t
 hipError_t launch_absmax_batch(int n_tiles, const BatchTile* tiles, const BatchCounters* ctr,
                                uint32_t* bits, int grid, hipStream_t s) {
     zero_words_kernel<<<(n_tiles + 255) / 256, 256, 0, s>>>(bits, n_tiles);
-    absmax_batch_kernel<<<grid, 256, 0, s>>>(n_tiles, tiles, ctr, bits);
+    const int per_tile = grid / n_tiles > 4 ? grid / n_tiles : 4;
+    absmax_batch_kernel<<<dim3(per_tile, n_tiles), 256, 0, s>>>(tiles, ctr, bits);
     return hipGetLastError();
 }
 

@@ -494,11 +494,11 @@ int mfma_slot(const std::pair<int, int>& key) {
     return key.first - 1;
 }
 
-// Matrix-core launches of the u8 scales that have fragment tables, one per
+// Matrix-core launches of the scales that have fragment tables, one per
 // (nkr, nkc) instantiation, largest first.  A wave computes one 16-column
-// tile over a segment of rows and first recomputes 2 nkc - 1 intermediate
-// blocks of 16 rows; segments are about 8x that prologue, halved while a
-// launch has fewer than ~16 waves per compute unit.
+// tile over a segment of rows and first recomputes the intermediate blocks
+// its ring holds; segments are 1024 rows, halved while a launch has fewer
+// than 8 waves per compute unit.
 std::vector<std::pair<std::pair<int, int>, mhfd::MfmaLaunch>> mfma_launches(const mhfd_plan_s* p,
                                                                              int h, int w) {
     std::vector<std::pair<std::pair<int, int>, mhfd::MfmaLaunch>> out;
@@ -506,7 +506,9 @@ std::vector<std::pair<std::pair<int, int>, mhfd::MfmaLaunch>> mfma_launches(cons
     const int tiles_x = mhfd::mfma_wave_tiles(w);
     const int mw = mhfd::mfma_waves_per_block();
     const int groups_x = (tiles_x + mw - 1) / mw;
-    const long long target = 16LL * (p->n_cu > 0 ? p->n_cu : 256);
+    // at least 8 waves per CU, as few row segments as that allows: every
+    // segment repeats the ring's warm-up and the wave's set-up
+    const long long target = 8LL * (p->n_cu > 0 ? p->n_cu : 256);
     const int hr = (h + 15) / 16 * 16;
     for (const auto& key : mfma_shapes(p)) {
         std::vector<int> ks;
@@ -515,8 +517,7 @@ std::vector<std::pair<std::pair<int, int>, mhfd::MfmaLaunch>> mfma_launches(cons
             const mhfd::MfmaShape m = mhfd::mfma_shape(p->radii[k]);
             if (m.nkr == key.first && m.nkc == key.second) ks.push_back(k);
         }
-        int seg = 8 * 16 * (2 * key.second - 1);
-        seg = seg < hr ? seg : hr;
+        int seg = 1024 < hr ? 1024 : hr;
         auto waves = [&]() {
             return static_cast<long long>(ks.size()) * tiles_x * ((h + seg - 1) / seg);
         };
@@ -792,7 +793,7 @@ mhfd_status mhfd_detect_batched(mhfd_plan p, int32_t n, const mhfd_tile* d_tiles
     uint32_t* maxbits = reinterpret_cast<uint32_t*>(base + L.maxbits);
     const auto shapes = mfma_shapes(p);
     if (!shapes.empty() && p->dtype == MHFD_F32) {
-        e = mhfd::launch_absmax_batch(n, tiles, ctr, maxbits, 2 * p->n_cu, s);
+        e = mhfd::launch_absmax_batch(n, tiles, ctr, maxbits, 8 * p->n_cu, s);
         if (e != hipSuccess) return hip_fail(e, "batched input range pass");
     }
     for (const auto& key : shapes) {
