@@ -63,18 +63,28 @@ struct Sink {
 // K x H x W stack.  Lane l owns columns x0 + CW l ... x0 + CW l + CW - 1,
 // read as one aligned CW-float load per plane and row (W % CW == 0).  The
 // wave keeps rows y-1, y, y+1 of every plane in registers, rolling down the
-// run with row y+2 already in flight.  Horizontal neighbours come from DPP
-// wave shifts; the two columns beyond the strip (x0 - 1 and x0 + 64 CW) of
-// every plane come from one more load per row (lanes k and 32 + k hold plane
-// k's left and right halo), reduced vertically in those lanes and read out
-// per plane.  Every (row, strip) cell compacts its candidates in (x, k)
-// order with ballot/mbcnt offsets into its own pool slot and reserves the
-// overflow region with one atomic only when it has more.
+// run with row y+2 already in flight; the row loop is unrolled by the four
+// row buffers, so rolling renames registers instead of moving them.
+// Horizontal neighbours come from DPP wave shifts; the two columns beyond
+// the strip (x0 - 1 and x0 + 64 CW) of every plane come from one more load
+// per row (lanes k and 32 + k hold plane k's left and right halo), reduced
+// vertically in those lanes and read out per plane.
+//
+// Borders replicate the edge row or column (reads are clamped into the
+// image): a 3 x 3 maximum over a window that repeats one of its own members
+// equals the maximum over the members inside the image, which is what the
+// -inf padding of the definition gives.  Lanes past the right edge hold
+// copies of the last columns and report no candidates.
+//
+// Every (row, strip) cell compacts its candidates in (x, k) order with
+// ballot/mbcnt offsets into its own pool slot and reserves the overflow
+// region with one atomic only when it has more.
 template <int K, int CW, int SLOTS>
 __device__ __forceinline__ void wave(const float* __restrict__ st, int H, int W, float tau,
                                      int bpr, int strip, int run, const Sink& out) {
     static_assert(CW * K <= 32, "candidate mask is 32 bits");
     typedef float Vec __attribute__((ext_vector_type(CW)));
+    typedef Vec Row[K];
     const int lane = threadIdx.x & 63;
     const int x0 = strip * 64 * CW;
     const int xl = x0 + CW * lane;            // first column of the lane
@@ -83,30 +93,24 @@ __device__ __forceinline__ void wave(const float* __restrict__ st, int H, int W,
     const size_t plane = static_cast<size_t>(H) * W;
     const int y0 = run * ROWS;
     const int y1 = min(y0 + ROWS, H);
-    // halo lane: plane hk, column hx
-    const int hk = lane & 31;
-    const int hx = lane < 32 ? x0 - 1 : x0 + 64 * CW;
-    const bool h_ok = hk < K && hx >= 0 && hx < W;
-    const size_t h_off = static_cast<size_t>(h_ok ? hk : 0) * plane + (h_ok ? hx : 0);
+    // halo lane: plane hk, column hx (clamped into the image)
+    const int hk = (lane & 31) < K ? (lane & 31) : 0;
+    const int hx = min(max(lane < 32 ? x0 - 1 : x0 + 64 * CW, 0), W - 1);
+    const float* __restrict__ hbase = st + static_cast<size_t>(hk) * plane + hx;
 
-    auto load_row = [&](int y, Vec* v, float& hv) {
-        const bool ok = y >= 0 && y < H;
-        const int yy = y < 0 ? 0 : (y >= H ? H - 1 : y);
-        const float* p = st + static_cast<size_t>(yy) * W + xc;
+    // Plane k's rows start at the wave-uniform st + k plane; the lane's part
+    // is a 32-bit byte offset (a plane holds fewer than 2^29 pixels).
+    auto load_row = [&](int y, Row& v, float& hv) {
+        const int yy = min(max(y, 0), H - 1);
+        const uint32_t boff = static_cast<uint32_t>(yy * W + xc) * 4u;
 #pragma unroll
-        for (int k = 0; k < K; ++k) v[k] = *reinterpret_cast<const Vec*>(p + k * plane);
-        hv = st[h_off + static_cast<size_t>(yy) * W];
-#pragma unroll
-        for (int k = 0; k < K; ++k) v[k] = (ok && col_ok) ? v[k] : static_cast<Vec>(-INFINITY);
-        hv = (ok && h_ok) ? hv : -INFINITY;
+        for (int k = 0; k < K; ++k)
+            v[k] = *reinterpret_cast<const Vec*>(
+                reinterpret_cast<const char*>(st + static_cast<size_t>(k) * plane) + boff);
+        hv = hbase[static_cast<size_t>(yy) * W];
     };
-    Vec up[K], cur[K], dn[K], nx[K];
-    float hup, hcur, hdn, hnx;
-    load_row(y0 - 1, up, hup);
-    load_row(y0, cur, hcur);
-    load_row(y0 + 1, dn, hdn);
-    for (int y = y0; y < y1; ++y) {
-        load_row(y + 2, nx, hnx);  // in flight while row y is tested
+    auto test_row = [&](int y, const Row& up, const Row& cur, const Row& dn, float hup,
+                        float hcur, float hdn) {
         const float hm = fmax3(hup, hcur, hdn);
         Vec m3[K];
 #pragma unroll
@@ -131,8 +135,10 @@ __device__ __forceinline__ void wave(const float* __restrict__ st, int H, int W,
                 const float mp = k > 0 ? m3[k - 1][c] : -INFINITY;
                 const float mn = k + 1 < K ? m3[k + 1][c] : -INFINITY;
                 const float v = cur[k][c];
-                if (v > tau && v >= fmax3(mp, m3[k][c], mn)) mask |= 1u << (c * K + k);
+                const bool hit = (v > tau) & (v >= fmax3(mp, m3[k][c], mn));
+                mask |= static_cast<unsigned>(hit) << (c * K + k);
             }
+        mask = col_ok ? mask : 0u;
         const int cnt = __popc(mask);
         int n;
         const int pre = wave_exclusive_prefix<6>(cnt, &n);
@@ -147,38 +153,50 @@ __device__ __forceinline__ void wave(const float* __restrict__ st, int H, int W,
             out.blk_n[cell] = n;
             out.blk_o[cell] = o;
         }
+        if (n == 0) return;  // wave-uniform
         o = __shfl(o, 0, 64);
+        // The lane's candidates in (x, k) order: set bits of the mask from
+        // the lowest; the response is read back from the stack (cached).
         if (cnt > 0) {
             int j = pre;
             Cand* own = out.slots + cell * SLOTS;
-            Cand* over = out.over + o - SLOTS;
-#pragma unroll
-            for (int c = 0; c < CW; ++c)
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    if (mask & (1u << (c * K + k))) {
-                        Cand rec;
-                        rec.y = y;
-                        rec.x = xl + c;
-                        rec.k = k | out.k_tag;
-                        rec.r = cur[k][c];
-                        if (j < SLOTS)
-                            own[j] = rec;
-                        else if (o + (j - SLOTS) < out.cap)
-                            over[j] = rec;
-                        ++j;
-                    }
-                }
+            unsigned m = mask;
+            do {
+                const int bit = __builtin_ctz(m);
+                m &= m - 1u;
+                const int c = bit >= K ? 1 : 0;
+                const int k = bit - c * K;
+                Cand rec;
+                rec.y = y;
+                rec.x = xl + c;
+                rec.k = k | out.k_tag;
+                rec.r = st[static_cast<size_t>(k) * plane + static_cast<size_t>(y) * W + xl + c];
+                if (j < SLOTS)
+                    own[j] = rec;
+                else if (o + (j - SLOTS) < out.cap)
+                    out.over[o + (j - SLOTS)] = rec;
+                ++j;
+            } while (m);
         }
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            up[k] = cur[k];
-            cur[k] = dn[k];
-            dn[k] = nx[k];
-        }
-        hup = hcur;
-        hcur = hdn;
-        hdn = hnx;
+    };
+    Row b0, b1, b2, b3;
+    float h0, h1, h2, h3;
+    load_row(y0 - 1, b0, h0);
+    load_row(y0, b1, h1);
+    load_row(y0 + 1, b2, h2);
+    // rows y-1, y, y+1 in (b0, b1, b2) at the top of every pass
+    for (int y = y0; y < y1; y += 4) {
+        load_row(y + 2, b3, h3);
+        test_row(y, b0, b1, b2, h0, h1, h2);
+        if (y + 1 >= y1) break;
+        load_row(y + 3, b0, h0);
+        test_row(y + 1, b1, b2, b3, h1, h2, h3);
+        if (y + 2 >= y1) break;
+        load_row(y + 4, b1, h1);
+        test_row(y + 2, b2, b3, b0, h2, h3, h0);
+        if (y + 3 >= y1) break;
+        load_row(y + 5, b2, h2);
+        test_row(y + 3, b3, b0, b1, h3, h0, h1);
     }
 }
 
