@@ -212,10 +212,12 @@ __global__ __launch_bounds__(64 * NMS_WAVES) void nms_batch_kernel(
     }
 }
 
+// Also sets every candidate's keep flag to 1 (the prune clears flags).
 __global__ void order_batch_kernel(const int32_t* __restrict__ blk_off,
                                    const int32_t* __restrict__ blk_o, int n_blk_bound,
                                    const Cand* __restrict__ pool, Cand* __restrict__ cand,
-                                   int64_t cap, BatchCounters* __restrict__ ctr) {
+                                   int32_t* __restrict__ keep, int64_t cap,
+                                   BatchCounters* __restrict__ ctr) {
     const int n_blk = ctr->nms_blocks;
     const int64_t n = min(static_cast<int64_t>(ctr->n_cand), cap);
     if (blockIdx.x == 0 && threadIdx.x == 0 && ctr->n_cand > cap)
@@ -238,54 +240,51 @@ __global__ void order_batch_kernel(const int32_t* __restrict__ blk_off,
             const int64_t src = static_cast<int64_t>(blk_o[lo]) + (j - SLOT);
             if (src < cap) cand[i] = over[src];
         }
+        keep[i] = 1;
     }
 }
 
-__global__ void prune_batch_kernel(const Cand* __restrict__ cand,
-                                   const int32_t* __restrict__ blk_off,
-                                   const BatchTile* __restrict__ tiles, int K,
-                                   const int32_t* __restrict__ d2max, int reach,
-                                   int32_t* __restrict__ keep, int64_t cap,
-                                   const BatchCounters* __restrict__ ctr) {
+// Overlap prune over all tiles, one work item per (candidate, row offset)
+// as in the single-tile path; rows are those of the candidate's own tile.
+__global__ void prune_rows_batch_kernel(const Cand* __restrict__ cand,
+                                        const int32_t* __restrict__ blk_off,
+                                        const BatchTile* __restrict__ tiles, int K,
+                                        const int32_t* __restrict__ d2max, int reach,
+                                        int32_t* __restrict__ keep, int64_t cap,
+                                        const BatchCounters* __restrict__ ctr) {
     const int64_t n = min(static_cast<int64_t>(ctr->n_cand), cap);
-    const long long r2 = static_cast<long long>(reach) * reach;
+    const long long dy = static_cast<long long>(blockIdx.y) - reach;
+    const int xr = static_cast<int>(sqrt(static_cast<double>(
+        static_cast<long long>(reach) * reach - dy * dy)));
     for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const Cand b = cand[i];
         const int ti = b.k >> TILE_SHIFT, kb = b.k & ((1 << TILE_SHIFT) - 1);
         const BatchTile& T = tiles[ti];
-        int kp = 1;
-        if (d2max) {
-            const int32_t* dcol = d2max + kb;
-            const int ylo = max(0, b.y - reach), yhi = min(T.h - 1, b.y + reach);
-            for (int yy = ylo; yy <= yhi && kp; ++yy) {
-                const long long dy = yy - b.y;
-                const int xr = static_cast<int>(sqrt(static_cast<double>(r2 - dy * dy)));
-                int lo = blk_off[T.nms_base + yy * T.bpr];
-                const int hi = min(static_cast<int64_t>(blk_off[T.nms_base + (yy + 1) * T.bpr]), n);
-                int top = hi;
-                while (lo < top) {
-                    const int mid = (lo + top) >> 1;
-                    if (cand[mid].x < b.x - xr)
-                        lo = mid + 1;
-                    else
-                        top = mid;
-                }
-                for (int j = lo; j < hi; ++j) {
-                    const Cand a = cand[j];
-                    if (a.x > b.x + xr) break;
-                    const int ka = a.k & ((1 << TILE_SHIFT) - 1);
-                    const bool dom =
-                        ka > kb || (ka == kb && (a.y < b.y || (a.y == b.y && a.x < b.x)));
-                    const long long dx = a.x - b.x;
-                    if (dom && dy * dy + dx * dx <= dcol[ka * K]) {
-                        kp = 0;
-                        break;
-                    }
-                }
+        const long long yy = b.y + dy;
+        if (yy < 0 || yy >= T.h || !keep[i]) continue;
+        const int32_t* dcol = d2max + kb;
+        int lo = blk_off[T.nms_base + yy * T.bpr];
+        const int hi = min(static_cast<int64_t>(blk_off[T.nms_base + (yy + 1) * T.bpr]), n);
+        int top = hi;
+        while (lo < top) {
+            const int mid = (lo + top) >> 1;
+            if (cand[mid].x < b.x - xr)
+                lo = mid + 1;
+            else
+                top = mid;
+        }
+        for (int j = lo; j < hi; ++j) {
+            const Cand a = cand[j];
+            if (a.x > b.x + xr) break;
+            const int ka = a.k & ((1 << TILE_SHIFT) - 1);
+            const bool dom = ka > kb || (ka == kb && (a.y < b.y || (a.y == b.y && a.x < b.x)));
+            const long long dx = a.x - b.x;
+            if (dom && dy * dy + dx * dx <= dcol[ka * K]) {
+                keep[i] = 0;
+                break;
             }
         }
-        keep[i] = kp;
     }
 }
 
@@ -366,9 +365,12 @@ hipError_t launch_batch_tail(const BatchLaunchArgs& a, hipStream_t s) {
                       &a.ctr->n_cand, s);
     const int grid = 1024;
     order_batch_kernel<<<grid, 256, 0, s>>>(a.blk_off, a.blk_o, a.n_blk_bound, a.pool, a.cand,
-                                            a.cap, a.ctr);
-    prune_batch_kernel<<<grid, 256, 0, s>>>(a.cand, a.blk_off, a.tiles, a.K, a.d2max, a.reach,
                                             a.keep, a.cap, a.ctr);
+    if (a.d2max) {
+        const int span = 2 * a.reach + 1;
+        prune_rows_batch_kernel<<<dim3(prune_grid_x(span), span), 256, 0, s>>>(
+            a.cand, a.blk_off, a.tiles, a.K, a.d2max, a.reach, a.keep, a.cap, a.ctr);
+    }
     launch_batch_scan(a.keep, static_cast<int>(a.cap), &a.ctr->n_cand, a.scan_sums, a.keep_off,
                       &a.ctr->n_blobs, s);
     emit_batch_kernel<<<grid, 256, 0, s>>>(a.cand, a.keep, a.keep_off, a.blk_off, a.tiles,

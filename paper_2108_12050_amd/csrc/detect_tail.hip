@@ -194,9 +194,11 @@ void launch_scan(const int32_t* in, int n_host, const int32_t* n_dev, int32_t* s
     scan_apply_kernel<<<grid, SCAN_BT, 0, s>>>(in, n_host, n_dev, sums, out);
 }
 
+// Also sets every candidate's keep flag to 1 (the prune clears flags).
 __global__ void order_kernel(const int32_t* __restrict__ blk_off, const int32_t* __restrict__ blk_o,
                              int n_blk, const Cand* __restrict__ pool, Cand* __restrict__ cand,
-                             int64_t cap, const DetectCounters* __restrict__ ctr) {
+                             int32_t* __restrict__ keep, int64_t cap,
+                             const DetectCounters* __restrict__ ctr) {
     const int64_t n = min(static_cast<int64_t>(ctr->n_cand), cap);
     if (blockIdx.x == 0 && threadIdx.x == 0 && ctr->n_cand > cap)
         atomicOr(const_cast<int32_t*>(&ctr->flags), MHFD_FLAG_CAND_OVERFLOW);
@@ -219,64 +221,63 @@ __global__ void order_kernel(const int32_t* __restrict__ blk_off, const int32_t*
             const int64_t src = static_cast<int64_t>(blk_o[lo]) + (j - SLOT);
             if (src < cap) cand[i] = over[src];
         }
+        keep[i] = 1;
     }
 }
 
-// One thread per candidate b.  Candidates a that can remove b lie within
-// `reach` rows and, in row y_b + dy, within |dx| <= sqrt(reach^2 - dy^2);
-// rows come from the per-row offsets of the canonical list and the column
-// range from a binary search in the row (sorted by x).  The overlap test is
-// the plan's exact integer form: overlap(a, b) > theta iff
-// dy^2 + dx^2 <= d2max[k_a][k_b] (the lens fraction falls monotonically with
-// distance; the table is evaluated in double on the host).
-__global__ void prune_kernel(const Cand* __restrict__ cand, const int32_t* __restrict__ blk_off,
-                             int bpr, int H, int K, const int32_t* __restrict__ d2max, int reach,
-                             int32_t* __restrict__ keep, int64_t cap,
-                             const DetectCounters* __restrict__ ctr) {
+// Overlap prune.  Candidates a that can remove b lie within `reach` rows
+// and, in row y_b + dy, within |dx| <= sqrt(reach^2 - dy^2); rows come from
+// the per-row offsets of the canonical list and the column range from a
+// binary search in the row (sorted by x).  The overlap test is the plan's
+// exact integer form: overlap(a, b) > theta iff dy^2 + dx^2 <=
+// d2max[k_a][k_b] (the lens fraction falls monotonically with distance; the
+// table is evaluated in double on the host).
+//
+// One work item per (candidate, row offset): grid row blockIdx.y = dy +
+// reach, and the workgroups of that row stride over the candidates.  keep[]
+// starts at 1 (order_kernel); an item clears its candidate's flag when it
+// finds a dominating candidate within the overlap distance in row y + dy.
+// All writers write 0, so the order of the writes does not matter and the
+// flags equal those of a scan over all rows.  Threads of a wave take
+// consecutive candidates, which lie in nearly the same rows, so their
+// searches share cache lines.
+__global__ void prune_rows_kernel(const Cand* __restrict__ cand,
+                                  const int32_t* __restrict__ blk_off, int bpr, int H, int K,
+                                  const int32_t* __restrict__ d2max, int reach,
+                                  int32_t* __restrict__ keep, int64_t cap,
+                                  const DetectCounters* __restrict__ ctr) {
     const int64_t n = min(static_cast<int64_t>(ctr->n_cand), cap);
-    const long long r2 = static_cast<long long>(reach) * reach;
+    const long long dy = static_cast<long long>(blockIdx.y) - reach;
+    const int xr = static_cast<int>(sqrt(static_cast<double>(
+        static_cast<long long>(reach) * reach - dy * dy)));
     for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const Cand b = cand[i];
+        const long long yy = b.y + dy;
+        if (yy < 0 || yy >= H || !keep[i]) continue;
         const int32_t* dcol = d2max + b.k;  // d2max[ka * K + kb]
-        int kp = 1;
-        const int ylo = max(0, b.y - reach), yhi = min(H - 1, b.y + reach);
-        for (int yy = ylo; yy <= yhi && kp; ++yy) {
-            const long long dy = yy - b.y;
-            const int xr = static_cast<int>(sqrt(static_cast<double>(r2 - dy * dy)));
-            int lo = blk_off[yy * bpr];
-            const int hi = min(static_cast<int64_t>(blk_off[(yy + 1) * bpr]), n);
-            // first candidate of the row with x >= b.x - xr
-            int top = hi;
-            while (lo < top) {
-                const int mid = (lo + top) >> 1;
-                if (cand[mid].x < b.x - xr)
-                    lo = mid + 1;
-                else
-                    top = mid;
-            }
-            for (int j = lo; j < hi; ++j) {
-                const Cand a = cand[j];
-                if (a.x > b.x + xr) break;
-                const bool dom =
-                    a.k > b.k || (a.k == b.k && (a.y < b.y || (a.y == b.y && a.x < b.x)));
-                const long long dx = a.x - b.x;
-                if (dom && dy * dy + dx * dx <= dcol[a.k * K]) {
-                    kp = 0;
-                    break;
-                }
+        int lo = blk_off[yy * bpr];
+        const int hi = min(static_cast<int64_t>(blk_off[(yy + 1) * bpr]), n);
+        // first candidate of the row with x >= b.x - xr
+        int top = hi;
+        while (lo < top) {
+            const int mid = (lo + top) >> 1;
+            if (cand[mid].x < b.x - xr)
+                lo = mid + 1;
+            else
+                top = mid;
+        }
+        for (int j = lo; j < hi; ++j) {
+            const Cand a = cand[j];
+            if (a.x > b.x + xr) break;
+            const bool dom = a.k > b.k || (a.k == b.k && (a.y < b.y || (a.y == b.y && a.x < b.x)));
+            const long long dx = a.x - b.x;
+            if (dom && dy * dy + dx * dx <= dcol[a.k * K]) {
+                keep[i] = 0;
+                break;
             }
         }
-        keep[i] = kp;
     }
-}
-
-__global__ void keep_all_kernel(int32_t* __restrict__ keep, int64_t cap,
-                                const DetectCounters* __restrict__ ctr) {
-    const int64_t n = min(static_cast<int64_t>(ctr->n_cand), cap);
-    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
-         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
-        keep[i] = 1;
 }
 
 __global__ void emit_kernel(const Cand* __restrict__ cand, const int32_t* __restrict__ keep,
@@ -335,13 +336,13 @@ hipError_t launch_detect_tail(const DetectWorkspace& ws, int K, int h, int w, fl
     launch_nms(K, cw, wk, h, w, tau, s, std::make_integer_sequence<int, MHFD_MAX_SCALES>{});
     launch_scan(wk.blk_n, wk.n_blk, nullptr, ws.scan_sums, ws.blk_off, &ws.ctr->n_cand, s);
     const int grid = 1024;
-    order_kernel<<<grid, 256, 0, s>>>(wk.blk_off, wk.blk_o, wk.n_blk, ws.pool, ws.cand, ws.cap,
-                                      ws.ctr);
-    if (d2max)
-        prune_kernel<<<grid, 256, 0, s>>>(wk.cand, wk.blk_off, wk.blk_per_row, h, K, d2max, reach,
-                                          ws.keep, ws.cap, ws.ctr);
-    else
-        keep_all_kernel<<<grid, 256, 0, s>>>(ws.keep, ws.cap, ws.ctr);
+    order_kernel<<<grid, 256, 0, s>>>(wk.blk_off, wk.blk_o, wk.n_blk, ws.pool, ws.cand, ws.keep,
+                                      ws.cap, ws.ctr);
+    if (d2max) {
+        const int span = 2 * reach + 1;
+        prune_rows_kernel<<<dim3(prune_grid_x(span), span), 256, 0, s>>>(
+            wk.cand, wk.blk_off, wk.blk_per_row, h, K, d2max, reach, ws.keep, ws.cap, ws.ctr);
+    }
     launch_scan(ws.keep, static_cast<int>(ws.cap), &ws.ctr->n_cand, ws.scan_sums, ws.keep_off,
                 &ws.ctr->n_blobs, s);
     emit_kernel<<<grid, 256, 0, s>>>(ws.cand, ws.keep, ws.keep_off, sigmas_dev, blobs, capacity,

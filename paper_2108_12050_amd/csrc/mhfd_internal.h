@@ -174,6 +174,10 @@ size_t scan_sums_ints(int64_t n);
 
 int nms_blocks_per_row(int w);
 
+// Workgroups per row offset of the prune launches (grid rows = 2 reach + 1):
+// about 4096 workgroups in all.
+inline int prune_grid_x(int span) { return span >= 4096 ? 1 : (4096 + span - 1) / span; }
+
 // ---------------------------------------------------------------------------
 // Batched detection.  The setup kernel turns the caller's device descriptors
 // into this per-tile table and the work prefixes below.
