@@ -74,6 +74,11 @@ def lib():
         L.ora_soft_score_grad.argtypes = [_dp, C.c_int, C.c_int, C.c_int, C.c_int, _dp, _ip,
                                           C.c_double, C.c_double, _dp, _dp, _dp]
         L.ora_log_adjoint.argtypes = [_dp, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, _dp]
+        _u8p = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
+        _i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
+        _intp = C.POINTER(C.c_int)
+        L.ora_stretch_levels.argtypes = [_u8p, C.c_int, C.c_int, C.c_long, _i64p, _intp, _intp]
+        L.ora_stretch.argtypes = [_u8p, C.c_int, C.c_int, C.c_long, _dp, _intp, _intp]
         L.ora_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -220,6 +225,28 @@ def prune(ykx, sigmas, theta: float) -> np.ndarray:
     if len(ykx):
         lib().ora_prune(ykx, sg, len(ykx), float(theta), keep)
     return keep.astype(bool)
+
+
+def stretch_levels(img: np.ndarray):
+    """(low, high, hist) of the histogram stretch of an 8-bit image (section 4,
+    Algorithm 1 first step; 0.175% saturated at each end)."""
+    a = np.ascontiguousarray(img, dtype=np.uint8)
+    H, W = a.shape
+    hist = np.zeros(256, np.int64)
+    lo, hi = C.c_int(), C.c_int()
+    lib().ora_stretch_levels(a, H, W, W, hist, C.byref(lo), C.byref(hi))
+    return lo.value, hi.value, hist
+
+
+def stretch(img: np.ndarray) -> np.ndarray:
+    """The stretched image clip((v - low)/(high - low), 0, 1) in FP64 (0
+    where high = low)."""
+    a = np.ascontiguousarray(img, dtype=np.uint8)
+    H, W = a.shape
+    out = np.zeros((H, W), np.float64)
+    lo, hi = C.c_int(), C.c_int()
+    lib().ora_stretch(a, H, W, W, out, C.byref(lo), C.byref(hi))
+    return out
 
 
 def detect(img, sigmas, truncate: float = 4.0, tau: float = 0.1, theta: float = 0.5,

@@ -32,7 +32,14 @@
  *     scale-space window (the 3x3 maxpool-equality test of section 3,
  *     generalised from "local in space, global in scale" to local in both)
  *     and whose response is strictly above the threshold;
- *   - overlap pruning is one-shot dominance with blob radius sqrt(2)*sigma.
+ *   - overlap pruning is one-shot dominance with blob radius sqrt(2)*sigma;
+ *   - the histogram stretch of section 4 (Algorithm 1, first step) on 8-bit
+ *     images saturates the darkest and the lightest 0.175% of the pixels:
+ *     with q = 0.00175 N, the low level is the smallest code v with at
+ *     least q pixels <= v and the high level the largest code with at least
+ *     q pixels >= v; codes map to clip((v - low) / (high - low), 0, 1), and
+ *     to 0 when high = low.  Counts are compared with q exactly, in
+ *     integers: count >= 0.00175 N  <=>  100000 count >= 175 N.
  */
 #include <math.h>
 #include <stdint.h>
@@ -530,6 +537,52 @@ void ora_log_adjoint(const double *c, int H, int W, double sigma, double truncat
     for (size_t p = 0; p < N; ++p)
         out[p] *= s * sigma * sigma;
     free(g); free(h); free(T);
+}
+
+/* Histogram stretch levels of an 8-bit image (section 4; Algorithm 1, first
+ * step), from the definition: the histogram is counted, then the low level
+ * walks up from code 0 and the high level down from 255 until the running
+ * count reaches q = 0.00175 N.  hist[256] receives the counts. */
+void ora_stretch_levels(const uint8_t *img, int H, int W, long pitch, int64_t *hist,
+                        int *low, int *high)
+{
+    const int64_t N = (int64_t)H * W;
+    for (int v = 0; v < 256; ++v) hist[v] = 0;
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) hist[img[(long)y * pitch + x]] += 1;
+    int64_t run = 0;
+    int lo = 0;
+    for (; lo < 255; ++lo) {
+        run += hist[lo];
+        if (100000 * run >= 175 * N) break;
+    }
+    run = 0;
+    int hi = 255;
+    for (; hi > 0; --hi) {
+        run += hist[hi];
+        if (100000 * run >= 175 * N) break;
+    }
+    *low = lo;
+    *high = hi;
+}
+
+/* The stretched image in [0, 1] (FP64), H x W row-major. */
+void ora_stretch(const uint8_t *img, int H, int W, long pitch, double *out, int *low, int *high)
+{
+    int64_t hist[256];
+    ora_stretch_levels(img, H, W, pitch, hist, low, high);
+    const int lo = *low, hi = *high;
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            const int v = img[(long)y * pitch + x];
+            double o = 0.0;
+            if (hi > lo) {
+                o = (double)(v - lo) / (double)(hi - lo);
+                if (o < 0.0) o = 0.0;
+                if (o > 1.0) o = 1.0;
+            }
+            out[(long)y * W + x] = o;
+        }
 }
 
 /* Number of OpenMP threads the oracle's parallel loops use. */
