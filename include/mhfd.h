@@ -115,6 +115,13 @@ typedef struct mhfd_config {
     int32_t max_h, max_w;    /* largest image the plan will see                 */
     int64_t max_candidates;  /* candidate capacity of a detection workspace
                                 (0: max(65536, max_h*max_w/64))                 */
+    int32_t stretch;         /* 1: histogram-stretch every image first (section
+                                4, Algorithm 1's first step; see
+                                mhfd_stretch_levels).  8-bit plans whose radii
+                                all take the matrix-core path (<= 56) only;
+                                batched and focus-score calls refuse such a
+                                plan (MHFD_ERR_UNSUPPORTED).  0: no stretch    */
+    int32_t reserved;        /* must be 0                                       */
 } mhfd_config;
 
 typedef struct mhfd_plan_s *mhfd_plan;
@@ -155,9 +162,10 @@ mhfd_status mhfd_detect(mhfd_plan plan, const void *d_img, int32_t h, int32_t w,
 
 /*
  * Bytes of device scratch mhfd_log_stack needs for an h x w image (0 on bad
- * input, and for 8-bit plans, which need none).  fp32 plans keep one word:
- * the image's max |I|, from which the matrix-core kernels take an exact
- * power-of-two input scale.
+ * input, and for 8-bit plans without the stretch, which need none).  fp32
+ * plans keep one word: the image's max |I|, from which the matrix-core
+ * kernels take an exact power-of-two input scale.  Stretch plans keep the
+ * 256-bin histogram and the two levels (258 words).
  */
 size_t mhfd_log_stack_workspace_size(mhfd_plan plan, int32_t h, int32_t w);
 
@@ -172,6 +180,25 @@ size_t mhfd_log_stack_workspace_size(mhfd_plan plan, int32_t h, int32_t w);
  */
 mhfd_status mhfd_log_stack(mhfd_plan plan, const void *d_img, int32_t h, int32_t w, int64_t pitch,
                            float *d_stack, void *d_ws, size_t ws_bytes, void *stream);
+
+/*
+ * Histogram stretch levels of one 8-bit image (section 4; Algorithm 1, first
+ * step: 0.175% of the pixels saturated at each end).  With N = h w and
+ * q = 0.00175 N, low is the smallest code v with at least q pixels <= v and
+ * high the largest code with at least q pixels >= v (compared exactly in
+ * integers: 100000 count >= 175 N).  A stretch plan maps code v to
+ * clip((v - low) / (high - low), 0, 1), and every code to 0 when high = low.
+ *   d_img     h x w codes, row pitch `pitch` >= w bytes; h w < 2^31.
+ *   d_hist    256 int32, receives the histogram (count of each code).
+ *   d_levels  2 int32, receives {low, high}.
+ * Device pointers, caller-owned; enqueued on `stream` (the current device's
+ * compute units size the launch).  No plan and no workspace: the outputs are
+ * the scratch.  Errors: MHFD_ERR_INVALID_ARG for null pointers or bad sizes,
+ * MHFD_ERR_UNSUPPORTED above 2^31 - 1 pixels, MHFD_ERR_HIP for launch
+ * failures; nothing is enqueued on error.
+ */
+mhfd_status mhfd_stretch_levels(const uint8_t *d_img, int32_t h, int32_t w, int64_t pitch,
+                                int32_t *d_hist, int32_t *d_levels, void *stream);
 
 /*
  * The rest of mhfd_detect on a stack the caller already holds (as written by

@@ -8,7 +8,8 @@ from ._lib import MHFDError, MHFDLibraryError  # noqa: F401
 
 
 def __getattr__(name):
-    if name in ("Plan", "Detection", "split_blobs", "FocusScore", "focus_score"):
+    if name in ("Plan", "Detection", "split_blobs", "FocusScore", "focus_score",
+                "stretch_levels"):
         from . import api
         return getattr(api, name)
     if name in ("BatchRunner", "detect_batched"):

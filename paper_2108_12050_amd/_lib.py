@@ -27,7 +27,7 @@ STATUS = {0: "MHFD_OK", 1: "MHFD_ERR_INVALID_ARG", 2: "MHFD_ERR_UNSUPPORTED",
 # Every symbol include/mhfd.h declares.
 EXPORTS = ("mhfd_create_plan", "mhfd_destroy_plan", "mhfd_plan_scales",
            "mhfd_detect_workspace_size", "mhfd_detect", "mhfd_log_stack_workspace_size",
-           "mhfd_log_stack", "mhfd_detect_stack",
+           "mhfd_log_stack", "mhfd_detect_stack", "mhfd_stretch_levels",
            "mhfd_batch_workspace_size", "mhfd_detect_batched", "mhfd_focus_workspace_size",
            "mhfd_focus_score", "mhfd_focus_score_backward", "mhfd_status_string",
            "mhfd_last_error")
@@ -50,7 +50,7 @@ class Config(C.Structure):
                 ("sigmas", C.POINTER(C.c_float)), ("truncate", C.c_float),
                 ("threshold", C.c_float), ("overlap", C.c_float), ("polarity", C.c_int32),
                 ("in_dtype", C.c_int32), ("max_h", C.c_int32), ("max_w", C.c_int32),
-                ("max_candidates", C.c_int64)]
+                ("max_candidates", C.c_int64), ("stretch", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Blob(C.Structure):
@@ -104,6 +104,8 @@ def load(path: str | None = None):
     L.mhfd_log_stack.restype = C.c_int
     L.mhfd_detect_stack.argtypes = [vp, vp, i32, i32, vp, i32, vp, vp, sz, vp]
     L.mhfd_detect_stack.restype = C.c_int
+    L.mhfd_stretch_levels.argtypes = [vp, i32, i32, i64, vp, vp, vp]
+    L.mhfd_stretch_levels.restype = C.c_int
     L.mhfd_batch_workspace_size.argtypes = [vp, i32, i64]
     L.mhfd_batch_workspace_size.restype = sz
     L.mhfd_detect_batched.argtypes = [vp, i32, vp, i64, vp, sz, vp]

@@ -61,7 +61,8 @@ class Plan:
     def __init__(self, n_scales: int = 10, sigma_min: float = 1.0, sigma_max: float = 10.0,
                  sigmas=None, truncate: float = 4.0, threshold: float = 0.1,
                  overlap: float = 0.5, polarity: str = "bright", dtype: str = "f32",
-                 max_h: int = 4096, max_w: int = 4096, max_candidates: int = 0):
+                 max_h: int = 4096, max_w: int = 4096, max_candidates: int = 0,
+                 stretch: bool = False):
         self._L = _lib.load()
         self._handle = None
         cfg = _lib.Config()
@@ -79,6 +80,7 @@ class Plan:
         cfg.in_dtype = {"f32": _lib.MHFD_F32, "u8": _lib.MHFD_U8}[dtype]
         cfg.max_h, cfg.max_w = int(max_h), int(max_w)
         cfg.max_candidates = int(max_candidates)
+        cfg.stretch = 1 if stretch else 0
         h = C.c_void_p()
         _lib.check(self._L.mhfd_create_plan(C.byref(cfg), C.byref(h)), "mhfd_create_plan")
         self._handle = h
@@ -93,6 +95,7 @@ class Plan:
         self.dtype = dtype
         self.threshold, self.overlap, self.truncate = float(threshold), float(overlap), float(truncate)
         self.max_h, self.max_w = int(max_h), int(max_w)
+        self.stretch = bool(stretch)
         self._ws = {}
 
     def close(self):
@@ -222,6 +225,24 @@ class Plan:
                                                _stream_ptr(stream))
         _lib.check(st, "mhfd_focus_score_backward")
         return dI, ds
+
+
+def stretch_levels(img: torch.Tensor, stream=None):
+    """Histogram stretch levels of one 8-bit device image (mhfd_stretch_levels):
+    returns (levels, hist), int32 device tensors of 2 ({low, high}) and 256
+    counts, enqueued on `stream` (default: the current stream)."""
+    if img.dtype != torch.uint8 or img.dim() != 2 or not img.is_cuda:
+        raise ValueError("stretch_levels takes a 2-D uint8 device tensor")
+    if img.stride(1) != 1:
+        raise ValueError("rows must be contiguous")
+    L = _lib.load()
+    hist = torch.empty(256, dtype=torch.int32, device=img.device)
+    levels = torch.empty(2, dtype=torch.int32, device=img.device)
+    st = L.mhfd_stretch_levels(img.data_ptr(), int(img.shape[0]), int(img.shape[1]),
+                               int(img.stride(0)), hist.data_ptr(), levels.data_ptr(),
+                               _stream_ptr(stream))
+    _lib.check(st, "mhfd_stretch_levels")
+    return levels, hist
 
 
 class FocusScore(torch.autograd.Function):

@@ -37,6 +37,8 @@
 
 #include <vector>
 
+#include <type_traits>
+
 #include "mhfd_internal.h"
 
 namespace mhfd {
@@ -72,7 +74,7 @@ __device__ __forceinline__ half8_t cat(half4_t a, half4_t b) {
 
 // Eight u8 codes (two dwords) -> FP16: each byte b becomes the FP16 bit
 // pattern 0x64bb = 1024 + b, then 1024 is subtracted exactly.
-__device__ __forceinline__ half8_t codes_to_half(uint32_t d0, uint32_t d1) {
+__device__ __forceinline__ half8_t codes_plus_1024(uint32_t d0, uint32_t d1) {
     const uint32_t m = 0x64646464u;
     typedef uint32_t u4 __attribute__((ext_vector_type(4)));
     u4 q;
@@ -80,8 +82,10 @@ __device__ __forceinline__ half8_t codes_to_half(uint32_t d0, uint32_t d1) {
     q[1] = __builtin_amdgcn_perm(m, d0, 0x04030402u);
     q[2] = __builtin_amdgcn_perm(m, d1, 0x04010400u);
     q[3] = __builtin_amdgcn_perm(m, d1, 0x04030402u);
-    half8_t v = __builtin_bit_cast(half8_t, q);
-    return v - static_cast<half8_t>(static_cast<_Float16>(1024.0f));
+    return __builtin_bit_cast(half8_t, q);
+}
+__device__ __forceinline__ half8_t codes_to_half(uint32_t d0, uint32_t d1) {
+    return codes_plus_1024(d0, d1) - static_cast<half8_t>(static_cast<_Float16>(1024.0f));
 }
 
 // One wave's work item: a 16-column tile from x0 over rows [y0, y1).  (Two
@@ -96,7 +100,20 @@ struct WaveJob {
     int aligned;      // rows aligned for whole 8-element group loads
     int out_vec;      // 16-byte aligned output rows and w % 4 == 0
     float in_scale;   // fp32 input: exact power of two applied before the split
-    float out_scale;  // exact power of two
+    float out_scale;  // exact power of two (times 255 / (high - low) when stretched)
+    float s_lo, s_hi; // stretched u8 input: 1024 + low, 1024 + high (exact in FP16)
+};
+
+// 8-bit input with the histogram stretch applied as it is read (stretch.hip):
+// codes clamped to [low, high], minus low.
+struct U8Stretch {};
+template <typename T>
+struct Elem {
+    typedef T type;
+};
+template <>
+struct Elem<U8Stretch> {
+    typedef uint8_t type;
 };
 
 // fp32 input: the scale that brings max |I| just below 2^14, from the bit
@@ -168,8 +185,20 @@ struct Input<uint8_t> {
         for (int i = 0; i < 8; ++i) d[i >> 2] |= static_cast<uint32_t>(row[col[i]]) << (8 * (i & 3));
         return make_uint2(d[0], d[1]);
     }
-    __device__ static void convert(Raw v, float, half8_t& hi, half8_t&) {
+    __device__ static void convert(Raw v, const WaveJob&, half8_t& hi, half8_t&) {
         hi = codes_to_half(v.x, v.y);
+    }
+};
+
+template <>
+struct Input<U8Stretch> : Input<uint8_t> {
+    // 1024 + v is exact in FP16, so are the clamp to [1024 + low, 1024 + high]
+    // and the subtraction of 1024 + low
+    __device__ static void convert(Raw v, const WaveJob& J, half8_t& hi, half8_t&) {
+        const half8_t lo8 = static_cast<half8_t>(static_cast<_Float16>(J.s_lo));
+        const half8_t hi8 = static_cast<half8_t>(static_cast<_Float16>(J.s_hi));
+        const half8_t q = codes_plus_1024(v.x, v.y);
+        hi = __builtin_elementwise_min(__builtin_elementwise_max(q, lo8), hi8) - lo8;
     }
 };
 
@@ -200,10 +229,10 @@ struct Input<float> {
         }
         return r;
     }
-    __device__ static void convert(Raw v, float scale, half8_t& hi, half8_t& lo) {
+    __device__ static void convert(Raw v, const WaveJob& J, half8_t& hi, half8_t& lo) {
         half4_t h0, l0, h1, l1;
-        split(v.a * scale, h0, l0);
-        split(v.b * scale, h1, l1);
+        split(v.a * J.in_scale, h0, l0);
+        split(v.b * J.in_scale, h1, l1);
         hi = cat(h0, h1);
         lo = cat(l0, l1);
     }
@@ -214,6 +243,10 @@ __device__ __forceinline__ typename Input<T>::Raw select_raw(bool c, typename In
                                                              typename Input<T>::Raw b);
 template <>
 __device__ __forceinline__ uint2 select_raw<uint8_t>(bool c, uint2 a, uint2 b) {
+    return c ? a : b;
+}
+template <>
+__device__ __forceinline__ uint2 select_raw<U8Stretch>(bool c, uint2 a, uint2 b) {
     return c ? a : b;
 }
 template <>
@@ -236,7 +269,8 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
     // wait for a load falls D blocks after it (costs registers: only with
     // the peeled loop).
     constexpr bool LATE_REV = mfma_peel<T, NKC>();
-    const T* img = static_cast<const T*>(J.img);
+    typedef typename Elem<T>::type E;
+    const E* img = static_cast<const E*>(J.img);
     const int g = lane >> 4;
     const int c = lane & 15;
     const int h = J.h, w = J.w, x0 = J.x0, y0 = J.y0, y1 = J.y1;
@@ -277,7 +311,7 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
             const int r0 = yr ^ (yr >> 31);
             r = min(r0, 2 * h - 1 - r0);
         }
-        const T* row = img + static_cast<long long>(r) * J.pitch;
+        const E* row = img + static_cast<long long>(r) * J.pitch;
         if (!EDGE) {
 #pragma unroll
             for (int kb = 0; kb < NKR; ++kb) {
@@ -305,7 +339,7 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
         for (int kb = 0; kb < NKR; ++kb) {
             const RawGroup v = (EDGE || !LATE_REV) ? rw[kb]
                                                    : select_raw<T>(rev[kb], In::reverse(rw[kb]), rw[kb]);
-            In::convert(v, J.in_scale, in_hi[kb], in_lo[kb]);
+            In::convert(v, J, in_hi[kb], in_lo[kb]);
         }
         fetch(hb + D, rw);
         float4_t a = {0.f, 0.f, 0.f, 0.f}, b = {0.f, 0.f, 0.f, 0.f};
@@ -411,14 +445,15 @@ __device__ __forceinline__ void run_job(const WaveJob& J, const half8_t* __restr
 // whose item loop keeps more state; fp32 inputs carry twice the operands);
 // otherwise one wave per SIMD.
 template <typename T, int NKC>
-constexpr int mfma_waves() { return NKC <= (sizeof(T) == 1 ? 3 : 2) ? 2 : 1; }
+constexpr int mfma_waves() { return NKC <= (sizeof(typename Elem<T>::type) == 1 ? 3 : 2) ? 2 : 1; }
 template <typename T, int NKC>
 constexpr int mfma_batch_waves() { return NKC <= 2 ? 2 : 1; }
 
 template <typename T, int NKR, int NKC>
 __global__ __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(mfma_waves<T, NKC>(), 2)))
-void log_mfma_kernel(const T* __restrict__ img, int h, int w, long long pitch, int aligned,
-                     int out_vec, const uint32_t* __restrict__ maxbits,
+void log_mfma_kernel(const typename Elem<T>::type* __restrict__ img, int h, int w,
+                     long long pitch, int aligned, int out_vec,
+                     const uint32_t* __restrict__ maxbits,
                      const half8_t* __restrict__ frags, MfmaLaunch L, float* __restrict__ out,
                      long long plane_stride) {
     const int bid = blockIdx.x;
@@ -429,8 +464,18 @@ void log_mfma_kernel(const T* __restrict__ img, int h, int w, long long pitch, i
     const int seg = local / L.groups_x;
     const int wcol = (local - seg * L.groups_x) * MW + (threadIdx.x >> 6);
     if (wcol >= L.tiles_x) return;
-    const float in_s = maxbits ? input_scale(*maxbits) : 1.0f;
+    // fp32: maxbits = max |I| bits; stretched u8: maxbits = {low, high}
+    float in_s = 1.0f, stretch = 1.0f;
     WaveJob J;
+    J.s_lo = J.s_hi = 1024.0f;
+    if constexpr (std::is_same<T, U8Stretch>::value) {
+        const int lo = static_cast<int>(maxbits[0]), hi = static_cast<int>(maxbits[1]);
+        J.s_lo = 1024.0f + lo;
+        J.s_hi = 1024.0f + hi;
+        stretch = hi > lo ? 255.0f / static_cast<float>(hi - lo) : 0.0f;
+    } else if (maxbits) {
+        in_s = input_scale(*maxbits);
+    }
     J.img = img;
     J.pitch = pitch;
     J.plane = out + static_cast<long long>(sc.plane) * plane_stride;
@@ -444,7 +489,7 @@ void log_mfma_kernel(const T* __restrict__ img, int h, int w, long long pitch, i
     J.aligned = aligned;
     J.out_vec = out_vec;
     J.in_scale = in_s;
-    J.out_scale = sc.out_scale / in_s;
+    J.out_scale = sc.out_scale / in_s * stretch;
     run_job<T, NKR, NKC>(J, frags + sc.frag_off, threadIdx.x & 63);
 }
 
@@ -571,14 +616,16 @@ __global__ void zero_words_kernel(uint32_t* __restrict__ p, int n) {
 }
 
 template <typename T, int NKR, int NKC>
-hipError_t launch_one(const T* img, int h, int w, int64_t pitch, const uint32_t* maxbits,
+hipError_t launch_one(const typename Elem<T>::type* img, int h, int w, int64_t pitch,
+                      const uint32_t* maxbits,
                       const uint16_t* frags, const MfmaLaunch& L, float* out,
                       long long plane_stride, hipStream_t s) {
     int blocks = 0;
     for (int i = 0; i < L.n; ++i) blocks += L.sc[i].n_blocks;
     if (blocks == 0) return hipSuccess;
     const int aligned =
-        (pitch % 8 == 0) && (reinterpret_cast<uintptr_t>(img) % (8 * sizeof(T)) == 0);
+        (pitch % 8 == 0) &&
+        (reinterpret_cast<uintptr_t>(img) % (8 * sizeof(typename Elem<T>::type)) == 0);
     // float4 stores need 16-byte aligned rows and planes
     const int out_vec = (w % 4 == 0) && (plane_stride % 4 == 0) &&
                         (reinterpret_cast<uintptr_t>(out) % 16 == 0);
@@ -732,15 +779,20 @@ hipError_t launch_log_mfma_batch(int in_dtype, int nkr, int nkc, int n_tiles,
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_log_mfma(int in_dtype, int nkr, int nkc, const void* img, int h, int w,
-                           int64_t pitch, const uint32_t* maxbits, const uint16_t* frags,
+hipError_t launch_log_mfma(int in_dtype, int stretch, int nkr, int nkc, const void* img, int h,
+                           int w, int64_t pitch, const uint32_t* maxbits, const uint16_t* frags,
                            const MfmaLaunch& L, float* out, long long plane_stride,
                            hipStream_t s) {
-#define MHFD_MFMA_CASE(T, A)                                                                   \
-    if (nkr == A && nkc == A)                                                                  \
-        return launch_one<T, A, A>(static_cast<const T*>(img), h, w, pitch, maxbits, frags, L, \
-                                   out, plane_stride, s);
-    if (in_dtype == MHFD_U8) {
+#define MHFD_MFMA_CASE(T, A)                                                                \
+    if (nkr == A && nkc == A)                                                               \
+        return launch_one<T, A, A>(static_cast<const typename Elem<T>::type*>(img), h, w,   \
+                                   pitch, maxbits, frags, L, out, plane_stride, s);
+    if (in_dtype == MHFD_U8 && stretch) {
+        MHFD_MFMA_CASE(U8Stretch, 1)
+        MHFD_MFMA_CASE(U8Stretch, 2)
+        MHFD_MFMA_CASE(U8Stretch, 3)
+        MHFD_MFMA_CASE(U8Stretch, 4)
+    } else if (in_dtype == MHFD_U8) {
         MHFD_MFMA_CASE(uint8_t, 1)
         MHFD_MFMA_CASE(uint8_t, 2)
         MHFD_MFMA_CASE(uint8_t, 3)

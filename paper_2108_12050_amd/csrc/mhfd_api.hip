@@ -34,6 +34,7 @@ struct mhfd_plan_s {
     std::vector<int> mfma_off;   // first 8-half fragment of scale k
     std::vector<float> mfma_out_scale;
     uint16_t* d_frags = nullptr;
+    int stretch = 0;             // histogram stretch before the stack (u8 plans)
 };
 
 namespace {
@@ -126,6 +127,11 @@ int max_overlapping_d2(double ra, double rb, double theta) {
     return static_cast<int>(lo);
 }
 
+size_t log_stack_scratch_bytes(const mhfd_plan_s* p) {
+    if (p->stretch) return sizeof(int32_t) * (256 + 2);
+    return (p->d_frags && p->dtype == MHFD_F32) ? sizeof(uint32_t) : 0;
+}
+
 struct DetectLayout {
     size_t stack, blk_n, blk_o, blk_off, pool, cand, keep, keep_off, scan_sums, ctr, maxbits, total;
     int n_blk, bpr;
@@ -153,7 +159,7 @@ DetectLayout detect_layout(const mhfd_plan_s* p, int h, int w) {
     const int64_t longest = static_cast<int64_t>(cap) > L.n_blk ? static_cast<int64_t>(cap) : L.n_blk;
     L.scan_sums = take(sizeof(int32_t) * mhfd::scan_sums_ints(longest));
     L.ctr = take(sizeof(mhfd::DetectCounters));
-    L.maxbits = take(sizeof(uint32_t));
+    L.maxbits = take(log_stack_scratch_bytes(p));
     L.total = off;
     return L;
 }
@@ -206,6 +212,11 @@ mhfd_status mhfd_create_plan(const mhfd_config* cfg, mhfd_plan* out) {
     if (static_cast<int64_t>(cfg->max_h) * cfg->max_w > (int64_t(1) << 31) / 4)
         return fail(MHFD_ERR_UNSUPPORTED, "max_h * max_w above 2^29 pixels");
     if (cfg->max_candidates < 0) return fail(MHFD_ERR_INVALID_ARG, "max_candidates < 0");
+    if (cfg->reserved != 0) return fail(MHFD_ERR_INVALID_ARG, "reserved config field not 0");
+    if (cfg->stretch != 0 && cfg->stretch != 1)
+        return fail(MHFD_ERR_INVALID_ARG, "stretch must be 0 or 1");
+    if (cfg->stretch && cfg->in_dtype != MHFD_U8)
+        return fail(MHFD_ERR_UNSUPPORTED, "the histogram stretch is built for 8-bit plans");
 
     std::vector<float> sig(K);
     if (cfg->sigmas) {
@@ -237,6 +248,7 @@ mhfd_status mhfd_create_plan(const mhfd_config* cfg, mhfd_plan* out) {
     p->dtype = cfg->in_dtype;
     p->max_h = cfg->max_h;
     p->max_w = cfg->max_w;
+    p->stretch = cfg->stretch;
     int64_t dc = static_cast<int64_t>(cfg->max_h) * cfg->max_w / 64;
     p->max_cand = cfg->max_candidates > 0 ? cfg->max_candidates : (dc > 65536 ? dc : 65536);
     if (p->max_cand > (int64_t(1) << 30)) {
@@ -250,6 +262,12 @@ mhfd_status mhfd_create_plan(const mhfd_config* cfg, mhfd_plan* out) {
             delete p;
             return fail(MHFD_ERR_UNSUPPORTED, "radius %d of sigma %g exceeds %d", R,
                         static_cast<double>(sig[k]), MHFD_MAX_RADIUS);
+        }
+        if (cfg->stretch && !mhfd::mfma_radius_ok(R)) {
+            delete p;
+            return fail(MHFD_ERR_UNSUPPORTED,
+                        "the histogram stretch needs every radius on the matrix-core path "
+                        "(radius %d of sigma %g)", R, static_cast<double>(sig[k]));
         }
         const int P = mhfd::padded_radius(R < 1 ? 1 : R);
         p->radii.push_back(R);
@@ -545,10 +563,9 @@ std::vector<std::pair<std::pair<int, int>, mhfd::MfmaLaunch>> mfma_launches(cons
 }
 
 // Bytes of scratch the stack needs: the max |I| word of fp32 plans with
-// matrix-core scales.
-size_t log_stack_scratch(const mhfd_plan_s* p) {
-    return (p->d_frags && p->dtype == MHFD_F32) ? kAlign : 0;
-}
+// matrix-core scales; the 256-bin histogram and the two levels of stretch
+// plans.
+size_t log_stack_scratch(const mhfd_plan_s* p) { return log_stack_scratch_bytes(p); }
 
 mhfd_status enqueue_log_stack(const mhfd_plan_s* p, const void* d_img, int h, int w,
                               int64_t pitch, float* stack, uint32_t* maxbits, hipStream_t s) {
@@ -556,15 +573,24 @@ mhfd_status enqueue_log_stack(const mhfd_plan_s* p, const void* d_img, int h, in
     for (int k = 0; k < p->K; ++k)
         if (p->mfma_off.empty() || p->mfma_off[k] < 0) strip_scales.push_back(k);
     const auto mls = mfma_launches(p, h, w);
+    // fp32: max |I| word; stretch: histogram (256 counts), then {low, high}
+    const uint32_t* range = nullptr;
     if (!mls.empty() && p->dtype == MHFD_F32) {
         hipError_t e = mhfd::launch_absmax(static_cast<const float*>(d_img), h, w, pitch, maxbits, s);
         if (e != hipSuccess) return hip_fail(e, "input range pass");
+        range = maxbits;
+    }
+    if (p->stretch) {
+        int32_t* hist = reinterpret_cast<int32_t*>(maxbits);
+        hipError_t e = mhfd::launch_stretch_levels(static_cast<const uint8_t*>(d_img), h, w, pitch,
+                                                   hist, hist + 256, p->n_cu, s);
+        if (e != hipSuccess) return hip_fail(e, "histogram stretch levels");
+        range = reinterpret_cast<const uint32_t*>(hist + 256);
     }
     for (const auto& ml : mls) {
-        hipError_t e = mhfd::launch_log_mfma(p->dtype, ml.first.first, ml.first.second, d_img, h,
-                                             w, pitch, p->dtype == MHFD_F32 ? maxbits : nullptr,
-                                             p->d_frags, ml.second, stack,
-                                             static_cast<long long>(h) * w, s);
+        hipError_t e = mhfd::launch_log_mfma(p->dtype, p->stretch, ml.first.first, ml.first.second,
+                                             d_img, h, w, pitch, range, p->d_frags, ml.second,
+                                             stack, static_cast<long long>(h) * w, s);
         if (e != hipSuccess) return hip_fail(e, "LoG stack (matrix cores) launch");
     }
     auto launches = make_launches(
@@ -642,6 +668,7 @@ mhfd_status check_focus(const mhfd_plan_s* p, const float* d_imgs, int b, int h,
                         const float* d_sigmas, float beta, float tau, const void* d_ws,
                         size_t ws_bytes) {
     if (!p) return fail(MHFD_ERR_INVALID_ARG, "null plan");
+    if (p->stretch) return fail(MHFD_ERR_UNSUPPORTED, "the focus score does not take stretch plans");
     if (!d_imgs || !d_sigmas || !d_ws) return fail(MHFD_ERR_INVALID_ARG, "null pointer argument");
     if (b < 1 || h < 1 || w < 1) return fail(MHFD_ERR_INVALID_ARG, "empty batch %d x %d x %d", b, h, w);
     if (h > p->max_h || w > p->max_w)
@@ -714,7 +741,7 @@ mhfd_status mhfd_log_stack(mhfd_plan p, const void* d_img, int32_t h, int32_t w,
     if (!d_stack) return fail(MHFD_ERR_INVALID_ARG, "null stack");
     const size_t need = log_stack_scratch(p);
     if (need) {
-        if (!d_ws) return fail(MHFD_ERR_INVALID_ARG, "null workspace (fp32 plans need %zu bytes)", need);
+        if (!d_ws) return fail(MHFD_ERR_INVALID_ARG, "null workspace (this plan needs %zu bytes)", need);
         if (reinterpret_cast<uintptr_t>(d_ws) % 4)
             return fail(MHFD_ERR_INVALID_ARG, "workspace not 4-byte aligned");
         if (ws_bytes < need)
@@ -723,6 +750,25 @@ mhfd_status mhfd_log_stack(mhfd_plan p, const void* d_img, int32_t h, int32_t w,
     if ((st = check_device(p)) != MHFD_OK) return st;
     return enqueue_log_stack(p, d_img, h, w, pitch, d_stack, static_cast<uint32_t*>(d_ws),
                              static_cast<hipStream_t>(stream));
+}
+
+mhfd_status mhfd_stretch_levels(const uint8_t* d_img, int32_t h, int32_t w, int64_t pitch,
+                                int32_t* d_hist, int32_t* d_levels, void* stream) {
+    g_last_error.clear();
+    if (!d_img || !d_hist || !d_levels) return fail(MHFD_ERR_INVALID_ARG, "null pointer argument");
+    if (h < 1 || w < 1 || pitch < w)
+        return fail(MHFD_ERR_INVALID_ARG, "image %d x %d with pitch %lld", h, w,
+                    static_cast<long long>(pitch));
+    if (static_cast<int64_t>(h) * w > (int64_t(1) << 31) - 1)
+        return fail(MHFD_ERR_UNSUPPORTED, "image above 2^31 - 1 pixels");
+    int dev = 0, n_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = mhfd::launch_stretch_levels(d_img, h, w, pitch, d_hist, d_levels, n_cu,
+                                        static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "histogram stretch levels");
+    return MHFD_OK;
 }
 
 mhfd_status mhfd_detect_stack(mhfd_plan p, const float* d_stack, int32_t h, int32_t w,
@@ -768,6 +814,8 @@ mhfd_status mhfd_detect_batched(mhfd_plan p, int32_t n, const mhfd_tile* d_tiles
                                 int64_t max_pixels, void* d_ws, size_t ws_bytes, void* stream) {
     g_last_error.clear();
     if (!p) return fail(MHFD_ERR_INVALID_ARG, "null plan");
+    if (p->stretch)
+        return fail(MHFD_ERR_UNSUPPORTED, "batched detection does not take stretch plans");
     if (!d_tiles || !d_ws) return fail(MHFD_ERR_INVALID_ARG, "null tiles or workspace");
     BatchLayout L;
     if (!batch_layout(p, n, max_pixels, &L))

@@ -131,12 +131,18 @@ struct MfmaLaunch {
     MfmaScale sc[MHFD_MAX_SCALES];
 };
 
-// in_dtype MHFD_U8 or MHFD_F32.  maxbits: fp32 inputs only, the float bits of
-// the tile's max |I| (launch_absmax), which picks the exact input scale.
-hipError_t launch_log_mfma(int in_dtype, int nkr, int nkc, const void* img, int h, int w,
-                           int64_t pitch, const uint32_t* maxbits, const uint16_t* frags,
+// in_dtype MHFD_U8 or MHFD_F32.  maxbits: fp32 inputs, the float bits of the
+// tile's max |I| (launch_absmax), which picks the exact input scale;
+// stretched u8 inputs (stretch = 1), the levels {low, high}
+// (launch_stretch_levels); otherwise unused.
+hipError_t launch_log_mfma(int in_dtype, int stretch, int nkr, int nkc, const void* img, int h,
+                           int w, int64_t pitch, const uint32_t* maxbits, const uint16_t* frags,
                            const MfmaLaunch& L, float* out, long long plane_stride,
                            hipStream_t s);
+// Histogram stretch of an 8-bit image: hist[256] counts (zeroed first), then
+// levels[0] = low, levels[1] = high.
+hipError_t launch_stretch_levels(const uint8_t* img, int h, int w, long long pitch,
+                                 int32_t* hist, int32_t* levels, int n_cu, hipStream_t s);
 // *bits = float bits of max |I| over an fp32 image (zeroed first).
 hipError_t launch_absmax(const float* img, int h, int w, int64_t pitch, uint32_t* bits,
                          hipStream_t s);

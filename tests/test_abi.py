@@ -63,3 +63,34 @@ def test_null_arguments():
     assert L.mhfd_detect(None, None, 1, 1, 1, None, 0, None, None, None, 0, None) == 1
     assert L.mhfd_log_stack(None, None, 1, 1, 1, None, None, 0, None) == 1
     assert L.mhfd_log_stack_workspace_size(None, 1, 1) == 0
+
+
+@pytest.mark.parametrize("bad,status", [(dict(stretch=2), 1), (dict(reserved=1), 1),
+                                        (dict(stretch=1), 2),                 # fp32 plan
+                                        (dict(stretch=1, in_dtype=1, sigma_max=15.0), 2)])
+def test_stretch_plan_checks_on_host(bad, status):
+    """The histogram stretch takes 8-bit plans whose radii all use the
+    matrix-core path (sigma 15 -> radius 60 > 56); checked before any device
+    call."""
+    from paper_2108_12050_amd import _lib
+    L = _lib.load()
+    cfg = _lib.Config(n_scales=10, sigma_min=1.0, sigma_max=10.0, truncate=4.0, threshold=0.1,
+                      overlap=0.5, polarity=0, in_dtype=0, max_h=64, max_w=64, max_candidates=0)
+    for k, v in bad.items():
+        setattr(cfg, k, v)
+    h = C.c_void_p()
+    assert L.mhfd_create_plan(C.byref(cfg), C.byref(h)) == status
+    assert L.mhfd_last_error()
+    assert h.value is None
+
+
+def test_stretch_levels_argument_checks():
+    from paper_2108_12050_amd import _lib
+    L = _lib.load()
+    buf = (C.c_int32 * 258)()
+    p = C.cast(buf, C.c_void_p)
+    assert L.mhfd_stretch_levels(None, 4, 4, 4, p, p, None) == 1
+    assert L.mhfd_stretch_levels(p, 0, 4, 4, p, p, None) == 1
+    assert L.mhfd_stretch_levels(p, 4, 4, 3, p, p, None) == 1      # pitch < w
+    assert L.mhfd_stretch_levels(p, 4, 4, 4, None, p, None) == 1
+    assert L.mhfd_stretch_levels(p, 65536, 65536, 65536, p, p, None) == 2  # >= 2^31 pixels

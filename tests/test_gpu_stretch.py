@@ -1,0 +1,121 @@
+"""Histogram stretch (section 4; Algorithm 1, first step) on the GPU against
+the oracle: levels and histogram bit-exact, the stretched LoG stack within
+1e-5 of each plane's maximum, candidates exact outside the ambiguity
+margin, at small sizes and on the full 4096^2 SEM tile."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2108_12050_amd import synth
+
+from parity import as_set, compare_candidates, plane_rel_err
+
+pytestmark = pytest.mark.gpu
+
+STACK_TOL = 1e-5
+SIG10 = oracle.linear_sigmas(10, 1.0, 10.0)
+
+
+def images():
+    rng = np.random.default_rng(11)
+    out = {
+        "sem_low_contrast": (synth.sem_tile(4, psf_sigma=1.0, H=300, W=260) // 3 + 40).astype(np.uint8),
+        "skewed": np.minimum(255, rng.exponential(25.0, (123, 77))).astype(np.uint8),
+        "bimodal": np.where(rng.random((64, 301)) < 0.3, 12, 230).astype(np.uint8),
+        "constant": np.full((40, 56), 93, np.uint8),
+        "one_pixel": np.array([[7]], np.uint8),
+        "odd_row": rng.integers(0, 256, (1, 999)).astype(np.uint8),
+    }
+    return out
+
+
+@pytest.mark.parametrize("name", list(images()))
+def test_levels_and_histogram_bit_exact(name):
+    from paper_2108_12050_amd import stretch_levels
+    img = images()[name]
+    print(f"stretch levels {name} {img.shape}", flush=True)
+    lo, hi, hist = oracle.stretch_levels(img)
+    # a row pitch that is not a multiple of 4 exercises the byte loads
+    h, w = img.shape
+    buf = np.zeros((h, w + 3), np.uint8)
+    buf[:, :w] = img
+    t = torch.from_numpy(buf).cuda()[:, :w]
+    levels, ghist = stretch_levels(t)
+    assert levels.cpu().tolist() == [lo, hi]
+    assert np.array_equal(ghist.cpu().numpy().astype(np.int64), hist)
+
+
+def stretch_plan(max_hw, **kw):
+    from paper_2108_12050_amd import Plan
+    args = dict(n_scales=10, sigma_min=1, sigma_max=10, threshold=0.05, overlap=1.0, dtype="u8",
+                max_h=max_hw, max_w=max_hw, stretch=True)
+    args.update(kw)
+    return Plan(**args)
+
+
+def test_stretched_stack_and_candidates():
+    img = images()["sem_low_contrast"]
+    plan = stretch_plan(512)
+    d = plan.detect(torch.from_numpy(img).to(plan.device), return_stack=True)
+    st = d.stack.cpu().numpy()
+    I = oracle.stretch(img)
+    ora = oracle.log_stack(I, SIG10)
+    assert plane_rel_err(st, ora).max() <= STACK_TOL
+    tau = float(np.float32(0.05))
+    ykx, _ = oracle.candidates(ora, tau)
+    compare_candidates(st, as_set(d.yxk.cpu().numpy()), ora, as_set(ykx), tau)
+    assert len(ykx) > 20
+    # the stretch changes the result: without it the contrast is a third
+    from paper_2108_12050_amd import Plan
+    plain = Plan(n_scales=10, sigma_min=1, sigma_max=10, threshold=0.05, overlap=1.0, dtype="u8",
+                 max_h=512, max_w=512)
+    assert plain.detect(torch.from_numpy(img).to(plain.device)).count < d.count
+
+
+def test_constant_image_gives_empty_stack():
+    img = images()["constant"]
+    plan = stretch_plan(64)
+    d = plan.detect(torch.from_numpy(img).to(plan.device), return_stack=True)
+    assert not d.stack.any() and d.count == 0
+
+
+def test_batched_and_focus_refuse_stretch_plans():
+    from paper_2108_12050_amd import MHFDError, detect_batched
+    plan = stretch_plan(64)
+    with pytest.raises(MHFDError):
+        detect_batched(plan, [torch.zeros((32, 32), dtype=torch.uint8, device="cuda")])
+
+
+def test_full_size_sem_tile():
+    """4096^2 SEM tile as the benchmark runs it: levels exact, sampled stack
+    values against the oracle's point evaluation of the stretched image, and
+    three row bands (top, middle, bottom) compared whole."""
+    print("stretch full-size 4096x4096", flush=True)
+    img = (synth.sem_tile(1, psf_sigma=2.0) // 2 + 30).astype(np.uint8)
+    plan = stretch_plan(4096)
+    t = torch.from_numpy(img).to(plan.device)
+    from paper_2108_12050_amd import stretch_levels
+    lo, hi, _ = oracle.stretch_levels(img)
+    assert stretch_levels(t)[0].cpu().tolist() == [lo, hi]
+    d = plan.detect(t, return_stack=True)
+    st = d.stack.cpu().numpy()
+    I = oracle.stretch(img)
+    rng = np.random.default_rng(3)
+    pts = [(int(rng.integers(0, 10)), int(rng.integers(0, 4096)), int(rng.integers(0, 4096)))
+           for _ in range(200)]
+    pts += [(k, y, x) for k in (0, 9) for y in (0, 4095) for x in (0, 4095)]
+    for (k, y, x) in pts:
+        ref = oracle.log_point(I, SIG10[k], y, x)
+        assert abs(st[k, y, x] - ref) <= STACK_TOL * 0.5, (k, y, x, st[k, y, x], ref)
+    tau = float(np.float32(0.05))
+    gpu_c = as_set(d.yxk.cpu().numpy())
+    m, H = 42, 4096
+    for (y0, y1) in [(0, 128), (2048, 2176), (3968, 4096)]:
+        a, b = max(0, y0 - m), min(H, y1 + m)
+        ora = oracle.log_stack(I[a:b], SIG10)
+        lo_, hi_ = max(0, y0 - 1) - a, min(H, y1 + 1) - a
+        assert plane_rel_err(st[:, a + lo_:a + hi_], ora[:, lo_:hi_]).max() <= STACK_TOL
+        ykx, _ = oracle.candidates(ora, tau)
+        ykx[:, 0] += a
+        compare_candidates(st[:, a:b], gpu_c, ora, as_set(ykx), tau, rows=(y0, y1), row0=a)
