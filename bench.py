@@ -56,6 +56,7 @@ FLOP_PER_PX = sum(11 * r + 6 for r in RADII)
 PEAK_FP32_VECTOR = 157.3e12   # MI355X FP32 vector, packed FMA
 PEAK_FP32_VECTOR_UNPACKED = 78.6e12
 PEAK_FP16_MFMA = 2.5e15       # MI355X dense FP16 matrix
+PEAK_HBM = 8.0e12             # MI355X HBM3E bytes/s
 COUNTER_FILE = os.path.join(ROOT, "profiles", "log_mfma_4096_u8_counters.json")
 LOG_KERNEL = "log_mfma_kernel"  # log_mfma_kernel<T, nkr, nkc>; the batch kernel is named apart
 
@@ -96,6 +97,64 @@ def _timed(fn, reps):
         e1.record()
     torch.cuda.synchronize()
     return [e0.elapsed_time(e1) for e0, e1 in evs]
+
+
+def bench_stretch(imgs, ws_bytes: int, cap: int, warmup: int) -> dict:
+    """The detector with the histogram stretch (Algorithm 1's first step) on
+    the same 4096^2 tiles, one stream, and the levels pass alone against the
+    HBM roof (it reads the 16.8 MB image once)."""
+    import numpy as np
+    import torch
+
+    from paper_2108_12050_amd import Plan, _lib, stretch_levels
+    plan = Plan(n_scales=K, sigma_min=1.0, sigma_max=10.0, threshold=TAU, overlap=OVERLAP,
+                dtype="u8", max_h=H, max_w=W, stretch=True)
+    L = _lib.load()
+    ws = torch.empty(plan.detect_workspace_bytes(H, W), dtype=torch.uint8, device="cuda")
+    raw = torch.empty((cap, 5), dtype=torch.int32, device="cuda")
+    res = torch.zeros(3, dtype=torch.int64, device="cuda")
+    sptr = int(torch.cuda.current_stream().cuda_stream)
+
+    def detect(i):
+        _lib.check(L.mhfd_detect(plan._handle, imgs[i % len(imgs)].data_ptr(), H, W, W,
+                                 raw.data_ptr(), cap, res.data_ptr(), None, ws.data_ptr(),
+                                 ws.numel(), sptr), "mhfd_detect")
+
+    n = 40
+    for i in range(warmup):
+        detect(i)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(n):
+        detect(i)
+    e1.record()
+    e1.synchronize()
+    det_ms = e0.elapsed_time(e1) / n
+    detect(0)
+    count0 = int(res[0].item())
+    hist = torch.empty(256, dtype=torch.int32, device="cuda")
+    lev = torch.empty(2, dtype=torch.int32, device="cuda")
+
+    def levels_call(i):
+        _lib.check(L.mhfd_stretch_levels(imgs[i % len(imgs)].data_ptr(), H, W, W, hist.data_ptr(),
+                                         lev.data_ptr(), sptr), "mhfd_stretch_levels")
+
+    for i in range(warmup):
+        levels_call(i)
+    e0.record()
+    for i in range(n):
+        levels_call(i)
+    e1.record()
+    e1.synchronize()
+    lv_ms = e0.elapsed_time(e1) / n
+    levels, _ = stretch_levels(imgs[0])
+    gbs = H * W / (lv_ms * 1e-3) / 1e9
+    return {"workload": "4096x4096 u8 SEM tiles as above, 0.175% saturated at each end",
+            "detector_ms_per_tile": round(det_ms, 4),
+            "levels_us_per_call": round(lv_ms * 1e3, 2),
+            "levels_gbs": round(gbs, 1), "levels_hbm_frac": round(gbs * 1e9 / PEAK_HBM, 4),
+            "note": "levels: three launches per call (zero, histogram, levels), back to back",
+            "levels_tile0": levels.cpu().tolist(), "blobs_tile0": count0}
 
 
 def bench_batched(warmup: int) -> dict:
@@ -443,6 +502,17 @@ def main() -> int:
                          "frac": round(mfma_flop / log_s / PEAK_FP16_MFMA, 4)}},
         "focus": {"psf_sigma": list(PSF), "blobs": counts, "candidates": cands},
     }
+    # The LoG stack and the detector against the HBM roof: algorithmic bytes
+    # (1 B/px image in, 40 B/px stack out; the maxima pass reads the stack
+    # again) over the single-stream times.
+    det_s = el1 / a.steps
+    out["roofline"]["hbm_view"] = {
+        "peak_gbs": PEAK_HBM / 1e9,
+        "log_stack_bytes": 41 * H * W, "log_stack_gbs": round(41 * H * W / log_s / 1e9, 1),
+        "log_stack_frac": round(41 * H * W / log_s / PEAK_HBM, 4),
+        "detector_bytes": 81 * H * W, "detector_gbs": round(81 * H * W / det_s / 1e9, 1),
+        "detector_frac": round(81 * H * W / det_s / PEAK_HBM, 4)}
+    out["stretch"] = bench_stretch(imgs, nbytes, cap, a.warmup)
     if not a.no_forms:
         del bufs
         torch.cuda.empty_cache()

@@ -2,10 +2,11 @@
 // 0.175% of the pixels are saturated at each end and the codes between the
 // two levels are mapped linearly onto [0, 1].
 //
-//   hist    256-bin histogram.  Every workgroup counts its rows into eight
-//           copies of the histogram in LDS (lane l adds to copy l mod 8, so a
-//           run of equal codes conflicts at most 8 ways), then adds the sum
-//           of its copies to the global bins;
+//   hist    256-bin histogram.  Every workgroup counts its rows into 32
+//           copies of the histogram in LDS (lane l adds to copy l mod 32, bin
+//           b's copies in 32 consecutive words, so equal codes in a wave
+//           conflict at most 2 ways), then adds the sum of its copies to the
+//           global bins;
 //   levels  one workgroup: bin b's cumulative counts from below and from
 //           above against q = 0.00175 N, compared in integers
 //           (100000 count >= 175 N).  Below-counts are monotone in b, so the
@@ -23,7 +24,7 @@ namespace mhfd {
 namespace {
 
 constexpr int HIST_T = 256;
-constexpr int COPIES = 8;
+constexpr int COPIES = 32;
 
 __global__ void zero_hist_kernel(int32_t* __restrict__ hist) { hist[threadIdx.x] = 0; }
 
@@ -34,22 +35,29 @@ __global__ __launch_bounds__(HIST_T) void hist_kernel(const uint8_t* __restrict_
     for (int i = threadIdx.x; i < 256 * COPIES; i += HIST_T) bins[i] = 0u;
     __syncthreads();
     const int copy = threadIdx.x & (COPIES - 1);
-    const bool v4 = (pitch % 4 == 0) && (reinterpret_cast<uintptr_t>(img) % 4 == 0);
-    const int w4 = v4 ? (w >> 2) : 0;
+    auto add4 = [&](uint32_t d) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) atomicAdd(&bins[((d >> (8 * b)) & 255u) * COPIES + copy], 1u);
+    };
+    const bool v16 = (pitch % 16 == 0) && (reinterpret_cast<uintptr_t>(img) % 16 == 0);
+    const int w16 = v16 ? (w >> 4) : 0;
     for (int y = blockIdx.x; y < h; y += gridDim.x) {
         const uint8_t* row = img + static_cast<long long>(y) * pitch;
-        for (int i = threadIdx.x; i < w4; i += HIST_T) {
-            const uint32_t d = reinterpret_cast<const uint32_t*>(row)[i];
-#pragma unroll
-            for (int b = 0; b < 4; ++b) atomicAdd(&bins[((d >> (8 * b)) & 255u) * COPIES + copy], 1u);
+        for (int i = threadIdx.x; i < w16; i += HIST_T) {
+            const uint4 d = reinterpret_cast<const uint4*>(row)[i];
+            add4(d.x);
+            add4(d.y);
+            add4(d.z);
+            add4(d.w);
         }
-        for (int x = 4 * w4 + threadIdx.x; x < w; x += HIST_T)
+        for (int x = 16 * w16 + threadIdx.x; x < w; x += HIST_T)
             atomicAdd(&bins[row[x] * COPIES + copy], 1u);
     }
     __syncthreads();
     uint32_t n = 0;
 #pragma unroll
-    for (int c = 0; c < COPIES; ++c) n += bins[threadIdx.x * COPIES + c];
+    for (int c = 0; c < COPIES; ++c)  // rotated so the lanes read different banks
+        n += bins[threadIdx.x * COPIES + ((c + threadIdx.x) & (COPIES - 1))];
     if (n) atomicAdd(&hist[threadIdx.x], static_cast<int32_t>(n));
 }
 
