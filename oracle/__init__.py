@@ -79,6 +79,11 @@ def lib():
         _intp = C.POINTER(C.c_int)
         L.ora_stretch_levels.argtypes = [_u8p, C.c_int, C.c_int, C.c_long, _i64p, _intp, _intp]
         L.ora_stretch.argtypes = [_u8p, C.c_int, C.c_int, C.c_long, _dp, _intp, _intp]
+        L.ora_gauss_stack.argtypes = [_dp, C.c_int, C.c_int, C.c_int, _dp, C.c_double, _dp]
+        _i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+        L.ora_dog_criterion.argtypes = [_dp, C.c_int, C.c_int, C.c_int, _dp, C.c_double, _dp,
+                                        _i32p, _i32p, C.c_long]
+        L.ora_dog_criterion.restype = C.c_long
         L.ora_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -247,6 +252,32 @@ def stretch(img: np.ndarray) -> np.ndarray:
     lo, hi = C.c_int(), C.c_int()
     lib().ora_stretch(a, H, W, W, out, C.byref(lo), C.byref(hi))
     return out
+
+
+def gauss_stack(img, sigmas, truncate: float = 4.0) -> np.ndarray:
+    """Gaussian planes L_k = G_{sigma_k} * I (K x H x W, FP64)."""
+    I = to_f64(img)
+    sg = np.ascontiguousarray(np.asarray(sigmas, dtype=np.float64))
+    H, W = I.shape
+    out = np.zeros((len(sg), H, W), np.float64)
+    lib().ora_gauss_stack(I, H, W, len(sg), sg, float(truncate), out)
+    return out
+
+
+def dog_criterion(L: np.ndarray, sigmas, tau: float = -np.inf) -> dict:
+    """The paper's criterion (equations "dog" and "argmax", Algorithm 1) on
+    Gaussian planes L: M = max over i of t_i (L_{i+1} - L_i), idx its first
+    argmax, and the pixels whose M exceeds tau and equals its 3x3 maximum.
+    Returns dict(M, idx, yxk, count)."""
+    L = np.ascontiguousarray(L, dtype=np.float64)
+    K, H, W = L.shape
+    sg = np.ascontiguousarray(np.asarray(sigmas, dtype=np.float64))
+    M = np.zeros((H, W), np.float64)
+    idx = np.zeros((H, W), np.int32)
+    cap = H * W
+    yxk = np.zeros((cap, 3), np.int32)
+    n = lib().ora_dog_criterion(L, H, W, K, sg, float(tau), M, idx, yxk, cap)
+    return dict(M=M, idx=idx, yxk=yxk[:n], count=int(n))
 
 
 def detect(img, sigmas, truncate: float = 4.0, tau: float = 0.1, theta: float = 0.5,

@@ -39,7 +39,14 @@
  *     least q pixels <= v and the high level the largest code with at least
  *     q pixels >= v; codes map to clip((v - low) / (high - low), 0, 1), and
  *     to 0 when high = low.  Counts are compared with q exactly, in
- *     integers: count >= 0.00175 N  <=>  100000 count >= 175 N.
+ *     integers: count >= 0.00175 N  <=>  100000 count >= 175 N;
+ *   - the paper's own criterion (section 4, equations "dog" and "argmax",
+ *     Algorithm 1): Gaussian planes L_i = G_{t_i} * I on the same sampled,
+ *     truncated, reflected kernels; DoG_i = t_i (L_{i+1} - L_i) for
+ *     i < K - 1; per pixel the largest DoG over scale (the first scale on
+ *     ties, as an argmax gives); a pixel counts when that value equals the
+ *     maximum of its 3x3 neighbourhood (maxpool equality, windows clipped
+ *     at the image border) and exceeds the threshold.
  */
 #include <math.h>
 #include <stdint.h>
@@ -583,6 +590,79 @@ void ora_stretch(const uint8_t *img, int H, int W, long pitch, double *out, int 
             }
             out[(long)y * W + x] = o;
         }
+}
+
+/* Gaussian planes L_k = G_{sigma_k} * I (section 2.2), separable, reflected:
+ * out[k][y][x]. */
+void ora_gauss_stack(const double *img, int H, int W, int K, const double *sigmas,
+                     double truncate, double *out)
+{
+    size_t N = (size_t)H * W;
+    double *T = (double *)malloc(sizeof(double) * N);
+    for (int k = 0; k < K; ++k) {
+        int R = ora_radius(sigmas[k], truncate);
+        double *g = (double *)malloc(sizeof(double) * (2 * R + 1));
+        double *h = (double *)malloc(sizeof(double) * (2 * R + 1));
+        ora_taps(sigmas[k], R, g, h);
+        pass_x(img, H, W, g, R, T);
+        pass_y(T, H, W, g, R, out + (size_t)k * N);
+        free(g);
+        free(h);
+    }
+    free(T);
+}
+
+/*
+ * The paper's criterion on Gaussian planes L (K planes at scales t_k):
+ * DoG_i = t_i (L_{i+1} - L_i), i = 0..K-2 (equation "dog"); M = max_i DoG_i
+ * with idx = the first i attaining it (the inner argmax of equation
+ * "argmax"); C = pixels with M > tau and M equal to the maximum of M over
+ * their 3x3 neighbourhood, clipped at the border (the outer argmaxlocal as a
+ * maxpool comparison).  M and idx are H x W outputs; up to `cap` records
+ * (y, x, idx) are written in ascending (y, x) order; returns |C|.
+ */
+long ora_dog_criterion(const double *L, int H, int W, int K, const double *sigmas, double tau,
+                       double *M, int32_t *idx, int32_t *yxk, long cap)
+{
+    size_t N = (size_t)H * W;
+    for (size_t p = 0; p < N; ++p) {
+        double best = -INFINITY;
+        int bi = 0;
+        for (int i = 0; i + 1 < K; ++i) {
+            double d = sigmas[i] * (L[(size_t)(i + 1) * N + p] - L[(size_t)i * N + p]);
+            if (d > best) {
+                best = d;
+                bi = i;
+            }
+        }
+        M[p] = best;
+        idx[p] = bi;
+    }
+    long n = 0;
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            double v = M[(size_t)y * W + x];
+            if (!(v > tau))
+                continue;
+            double m = -INFINITY;
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    int yy = y + dy, xx = x + dx;
+                    if (yy < 0 || yy >= H || xx < 0 || xx >= W)
+                        continue;
+                    if (M[(size_t)yy * W + xx] > m)
+                        m = M[(size_t)yy * W + xx];
+                }
+            if (v >= m) {
+                if (n < cap) {
+                    yxk[3 * n + 0] = y;
+                    yxk[3 * n + 1] = x;
+                    yxk[3 * n + 2] = idx[(size_t)y * W + x];
+                }
+                ++n;
+            }
+        }
+    return n;
 }
 
 /* Number of OpenMP threads the oracle's parallel loops use. */
