@@ -101,6 +101,25 @@ typedef struct mhfd_result {
  * candidate and n_blobs and the list are not valid. */
 #define MHFD_FLAG_CAND_OVERFLOW 2
 
+/*
+ * Detection criterion of a plan.
+ *   LOG  the scale-normalised LoG stack and its 3x3x3 window maxima above
+ *        the threshold, then overlap pruning (the default; readings R1, R6).
+ *   DOG  the paper's own criterion (section 4, equations "dog" and
+ *        "argmax", Algorithm 1): Gaussian planes L_k at the K scales;
+ *        DoG_i = t_i (L_{i+1} - L_i) for i < K - 1; per pixel the largest
+ *        DoG over scale and its first argmax i; a blob at every pixel whose
+ *        largest DoG exceeds the threshold and equals the maximum of its
+ *        3x3 neighbourhood (clipped at the border).  Records carry k = that
+ *        argmax and sigma_k.  Needs K >= 2, every radius <= 56 (matrix-core
+ *        path) and overlap >= 1 (no pruning); the stack of mhfd_log_stack /
+ *        mhfd_detect (d_stack) then holds the Gaussian planes L_k.  The sign
+ *        is the paper's: dark blobs on a bright background respond
+ *        positively (the polarity field is ignored).
+ */
+#define MHFD_CRITERION_LOG 0
+#define MHFD_CRITERION_DOG 1
+
 typedef struct mhfd_config {
     int32_t n_scales;        /* K, 1..MHFD_MAX_SCALES */
     float sigma_min;         /* linear grid sigma_k = min + k (max - min)/(K - 1), */
@@ -121,7 +140,7 @@ typedef struct mhfd_config {
                                 all take the matrix-core path (<= 56) only;
                                 batched and focus-score calls refuse such a
                                 plan (MHFD_ERR_UNSUPPORTED).  0: no stretch    */
-    int32_t reserved;        /* must be 0                                       */
+    int32_t criterion;       /* MHFD_CRITERION_LOG (0) or MHFD_CRITERION_DOG (1) */
 } mhfd_config;
 
 typedef struct mhfd_plan_s *mhfd_plan;

@@ -16,6 +16,7 @@ MHFD_MAX_SCALES = 32
 MHFD_MAX_RADIUS = 64
 MHFD_F32, MHFD_U8 = 0, 1
 MHFD_BRIGHT, MHFD_DARK = 0, 1
+MHFD_CRITERION_LOG, MHFD_CRITERION_DOG = 0, 1
 MHFD_FLAG_BLOB_OVERFLOW = 1
 MHFD_FLAG_CAND_OVERFLOW = 2
 MHFD_FLAG_INVALID_TILE = 4
@@ -50,7 +51,7 @@ class Config(C.Structure):
                 ("sigmas", C.POINTER(C.c_float)), ("truncate", C.c_float),
                 ("threshold", C.c_float), ("overlap", C.c_float), ("polarity", C.c_int32),
                 ("in_dtype", C.c_int32), ("max_h", C.c_int32), ("max_w", C.c_int32),
-                ("max_candidates", C.c_int64), ("stretch", C.c_int32), ("reserved", C.c_int32)]
+                ("max_candidates", C.c_int64), ("stretch", C.c_int32), ("criterion", C.c_int32)]
 
 
 class Blob(C.Structure):

@@ -62,7 +62,7 @@ class Plan:
                  sigmas=None, truncate: float = 4.0, threshold: float = 0.1,
                  overlap: float = 0.5, polarity: str = "bright", dtype: str = "f32",
                  max_h: int = 4096, max_w: int = 4096, max_candidates: int = 0,
-                 stretch: bool = False):
+                 stretch: bool = False, criterion: str = "log"):
         self._L = _lib.load()
         self._handle = None
         cfg = _lib.Config()
@@ -81,6 +81,7 @@ class Plan:
         cfg.max_h, cfg.max_w = int(max_h), int(max_w)
         cfg.max_candidates = int(max_candidates)
         cfg.stretch = 1 if stretch else 0
+        cfg.criterion = {"log": _lib.MHFD_CRITERION_LOG, "dog": _lib.MHFD_CRITERION_DOG}[criterion]
         h = C.c_void_p()
         _lib.check(self._L.mhfd_create_plan(C.byref(cfg), C.byref(h)), "mhfd_create_plan")
         self._handle = h
@@ -96,6 +97,7 @@ class Plan:
         self.threshold, self.overlap, self.truncate = float(threshold), float(overlap), float(truncate)
         self.max_h, self.max_w = int(max_h), int(max_w)
         self.stretch = bool(stretch)
+        self.criterion = criterion
         self._ws = {}
 
     def close(self):

@@ -35,6 +35,7 @@ struct mhfd_plan_s {
     std::vector<float> mfma_out_scale;
     uint16_t* d_frags = nullptr;
     int stretch = 0;             // histogram stretch before the stack (u8 plans)
+    int criterion = MHFD_CRITERION_LOG;  // DOG: the stack holds Gaussian planes
 };
 
 namespace {
@@ -133,7 +134,8 @@ size_t log_stack_scratch_bytes(const mhfd_plan_s* p) {
 }
 
 struct DetectLayout {
-    size_t stack, blk_n, blk_o, blk_off, pool, cand, keep, keep_off, scan_sums, ctr, maxbits, total;
+    size_t stack, blk_n, blk_o, blk_off, pool, cand, keep, keep_off, scan_sums, ctr, maxbits,
+        dog_max, dog_arg, total;
     int n_blk, bpr;
 };
 
@@ -160,6 +162,9 @@ DetectLayout detect_layout(const mhfd_plan_s* p, int h, int w) {
     L.scan_sums = take(sizeof(int32_t) * mhfd::scan_sums_ints(longest));
     L.ctr = take(sizeof(mhfd::DetectCounters));
     L.maxbits = take(log_stack_scratch_bytes(p));
+    const bool dog = p->criterion == MHFD_CRITERION_DOG;
+    L.dog_max = take(dog ? sizeof(float) * static_cast<size_t>(h) * w : 0);
+    L.dog_arg = take(dog ? static_cast<size_t>(h) * w : 0);
     L.total = off;
     return L;
 }
@@ -212,7 +217,12 @@ mhfd_status mhfd_create_plan(const mhfd_config* cfg, mhfd_plan* out) {
     if (static_cast<int64_t>(cfg->max_h) * cfg->max_w > (int64_t(1) << 31) / 4)
         return fail(MHFD_ERR_UNSUPPORTED, "max_h * max_w above 2^29 pixels");
     if (cfg->max_candidates < 0) return fail(MHFD_ERR_INVALID_ARG, "max_candidates < 0");
-    if (cfg->reserved != 0) return fail(MHFD_ERR_INVALID_ARG, "reserved config field not 0");
+    if (cfg->criterion != MHFD_CRITERION_LOG && cfg->criterion != MHFD_CRITERION_DOG)
+        return fail(MHFD_ERR_INVALID_ARG, "unknown criterion %d", cfg->criterion);
+    if (cfg->criterion == MHFD_CRITERION_DOG && K < 2)
+        return fail(MHFD_ERR_INVALID_ARG, "the DoG criterion needs at least two scales");
+    if (cfg->criterion == MHFD_CRITERION_DOG && cfg->overlap < 1.0f)
+        return fail(MHFD_ERR_UNSUPPORTED, "the DoG criterion has no overlap pruning (overlap >= 1)");
     if (cfg->stretch != 0 && cfg->stretch != 1)
         return fail(MHFD_ERR_INVALID_ARG, "stretch must be 0 or 1");
     if (cfg->stretch && cfg->in_dtype != MHFD_U8)
@@ -249,6 +259,7 @@ mhfd_status mhfd_create_plan(const mhfd_config* cfg, mhfd_plan* out) {
     p->max_h = cfg->max_h;
     p->max_w = cfg->max_w;
     p->stretch = cfg->stretch;
+    p->criterion = cfg->criterion;
     int64_t dc = static_cast<int64_t>(cfg->max_h) * cfg->max_w / 64;
     p->max_cand = cfg->max_candidates > 0 ? cfg->max_candidates : (dc > 65536 ? dc : 65536);
     if (p->max_cand > (int64_t(1) << 30)) {
@@ -263,11 +274,11 @@ mhfd_status mhfd_create_plan(const mhfd_config* cfg, mhfd_plan* out) {
             return fail(MHFD_ERR_UNSUPPORTED, "radius %d of sigma %g exceeds %d", R,
                         static_cast<double>(sig[k]), MHFD_MAX_RADIUS);
         }
-        if (cfg->stretch && !mhfd::mfma_radius_ok(R)) {
+        if ((cfg->stretch || cfg->criterion == MHFD_CRITERION_DOG) && !mhfd::mfma_radius_ok(R)) {
             delete p;
             return fail(MHFD_ERR_UNSUPPORTED,
-                        "the histogram stretch needs every radius on the matrix-core path "
-                        "(radius %d of sigma %g)", R, static_cast<double>(sig[k]));
+                        "the histogram stretch and the DoG criterion need every radius on the "
+                        "matrix-core path (radius %d of sigma %g)", R, static_cast<double>(sig[k]));
         }
         const int P = mhfd::padded_radius(R < 1 ? 1 : R);
         p->radii.push_back(R);
@@ -309,8 +320,12 @@ mhfd_status mhfd_create_plan(const mhfd_config* cfg, mhfd_plan* out) {
             const size_t at = frags.size();
             frags.resize(at + mhfd::mfma_frag_halves(R));
             p->mfma_off[k] = static_cast<int>(at / 8);
+            // DoG criterion: Gaussian planes.  With g in place of h both
+            // separable terms are g(x) g(y), so norm 1/2 gives L exactly.
+            const bool dog = p->criterion == MHFD_CRITERION_DOG;
             p->mfma_out_scale[k] = mhfd::mfma_build_frags(
-                g.data(), h.data(), R, polarity_norm(static_cast<double>(sig[k]), p->polarity),
+                g.data(), dog ? g.data() : h.data(), R,
+                dog ? 0.5 : polarity_norm(static_cast<double>(sig[k]), p->polarity),
                 u8 ? 255.0 : 1.0, u8 ? 255.0 : 16384.0, frags.data() + at);
         }
     }
@@ -623,6 +638,20 @@ mhfd_status enqueue_tail(const mhfd_plan_s* p, const float* stack, int h, int w,
     ws.cap = p->max_cand;
     ws.n_blk = L.n_blk;
     ws.blk_per_row = L.bpr;
+    if (p->criterion == MHFD_CRITERION_DOG) {
+        // largest DoG over scale and its argmax, then the tail on that plane
+        float* M = reinterpret_cast<float*>(base + L.dog_max);
+        uint8_t* arg = reinterpret_cast<uint8_t*>(base + L.dog_arg);
+        hipError_t e = mhfd::launch_dog(stack, p->K, p->d_sigmas, h, w, M, arg, s);
+        if (e != hipSuccess) return hip_fail(e, "DoG launch");
+        ws.stack = M;
+        e = mhfd::launch_detect_tail(ws, 1, h, w, p->threshold, nullptr, 0, p->d_sigmas, d_blobs,
+                                     capacity, d_result, s);
+        if (e == hipSuccess) e = mhfd::launch_dog_label(d_blobs, capacity, d_result, arg, w,
+                                                        p->d_sigmas, s);
+        if (e != hipSuccess) return hip_fail(e, "detection launch");
+        return MHFD_OK;
+    }
     hipError_t e = mhfd::launch_detect_tail(ws, p->K, h, w, p->threshold, p->d_d2max, p->reach,
                                             p->d_sigmas, d_blobs, capacity, d_result, s);
     if (e != hipSuccess) return hip_fail(e, "detection launch");
@@ -668,7 +697,8 @@ mhfd_status check_focus(const mhfd_plan_s* p, const float* d_imgs, int b, int h,
                         const float* d_sigmas, float beta, float tau, const void* d_ws,
                         size_t ws_bytes) {
     if (!p) return fail(MHFD_ERR_INVALID_ARG, "null plan");
-    if (p->stretch) return fail(MHFD_ERR_UNSUPPORTED, "the focus score does not take stretch plans");
+    if (p->stretch || p->criterion != MHFD_CRITERION_LOG)
+        return fail(MHFD_ERR_UNSUPPORTED, "the focus score takes plain LoG plans only");
     if (!d_imgs || !d_sigmas || !d_ws) return fail(MHFD_ERR_INVALID_ARG, "null pointer argument");
     if (b < 1 || h < 1 || w < 1) return fail(MHFD_ERR_INVALID_ARG, "empty batch %d x %d x %d", b, h, w);
     if (h > p->max_h || w > p->max_w)
@@ -814,8 +844,8 @@ mhfd_status mhfd_detect_batched(mhfd_plan p, int32_t n, const mhfd_tile* d_tiles
                                 int64_t max_pixels, void* d_ws, size_t ws_bytes, void* stream) {
     g_last_error.clear();
     if (!p) return fail(MHFD_ERR_INVALID_ARG, "null plan");
-    if (p->stretch)
-        return fail(MHFD_ERR_UNSUPPORTED, "batched detection does not take stretch plans");
+    if (p->stretch || p->criterion != MHFD_CRITERION_LOG)
+        return fail(MHFD_ERR_UNSUPPORTED, "batched detection takes plain LoG plans only");
     if (!d_tiles || !d_ws) return fail(MHFD_ERR_INVALID_ARG, "null tiles or workspace");
     BatchLayout L;
     if (!batch_layout(p, n, max_pixels, &L))

@@ -139,6 +139,13 @@ hipError_t launch_log_mfma(int in_dtype, int stretch, int nkr, int nkc, const vo
                            int w, int64_t pitch, const uint32_t* maxbits, const uint16_t* frags,
                            const MfmaLaunch& L, float* out, long long plane_stride,
                            hipStream_t s);
+// The paper's DoG criterion: M = max_i sig_i (L_{i+1} - L_i) over K Gaussian
+// planes and its first argmax (u8); then the blob records' k and sigma from
+// the argmax plane (after the detection tail ran on M).
+hipError_t launch_dog(const float* L, int K, const float* sigmas_dev, int h, int w, float* M,
+                      uint8_t* arg, hipStream_t s);
+hipError_t launch_dog_label(mhfd_blob* blobs, int capacity, const mhfd_result* result,
+                            const uint8_t* arg, int w, const float* sigmas_dev, hipStream_t s);
 // Histogram stretch of an 8-bit image: hist[256] counts (zeroed first), then
 // levels[0] = low, levels[1] = high.
 hipError_t launch_stretch_levels(const uint8_t* img, int h, int w, long long pitch,

@@ -65,7 +65,7 @@ def test_null_arguments():
     assert L.mhfd_log_stack_workspace_size(None, 1, 1) == 0
 
 
-@pytest.mark.parametrize("bad,status", [(dict(stretch=2), 1), (dict(reserved=1), 1),
+@pytest.mark.parametrize("bad,status", [(dict(stretch=2), 1), (dict(criterion=2), 1),
                                         (dict(stretch=1), 2),                 # fp32 plan
                                         (dict(stretch=1, in_dtype=1, sigma_max=15.0), 2)])
 def test_stretch_plan_checks_on_host(bad, status):
@@ -94,3 +94,20 @@ def test_stretch_levels_argument_checks():
     assert L.mhfd_stretch_levels(p, 4, 4, 3, p, p, None) == 1      # pitch < w
     assert L.mhfd_stretch_levels(p, 4, 4, 4, None, p, None) == 1
     assert L.mhfd_stretch_levels(p, 65536, 65536, 65536, p, p, None) == 2  # >= 2^31 pixels
+
+
+@pytest.mark.parametrize("bad,status", [(dict(criterion=1), 2),                 # overlap 0.5
+                                        (dict(criterion=1, overlap=1.0, n_scales=1), 1),
+                                        (dict(criterion=1, overlap=1.0, sigma_max=15.0), 2)])
+def test_dog_plan_checks_on_host(bad, status):
+    """The paper's DoG criterion has no pruning (overlap >= 1), needs two
+    scales and every radius on the matrix-core path."""
+    from paper_2108_12050_amd import _lib
+    L = _lib.load()
+    cfg = _lib.Config(n_scales=10, sigma_min=1.0, sigma_max=10.0, truncate=4.0, threshold=0.1,
+                      overlap=0.5, polarity=0, in_dtype=0, max_h=64, max_w=64, max_candidates=0)
+    for k, v in bad.items():
+        setattr(cfg, k, v)
+    h = C.c_void_p()
+    assert L.mhfd_create_plan(C.byref(cfg), C.byref(h)) == status
+    assert h.value is None
