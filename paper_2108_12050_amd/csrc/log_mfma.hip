@@ -258,17 +258,19 @@ __device__ __forceinline__ Input<float>::Raw select_raw<float>(bool c, Input<flo
     return r;
 }
 
-template <typename T, int NKR, int NKC, bool EDGE>
+// CTL: the column-pass tap fragments are read from LDS (`cl`, the block's
+// copy) at every use instead of being held in registers.
+template <typename T, int NKR, int NKC, bool EDGE, bool CTL>
 __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __restrict__ fr,
-                                         int lane) {
+                                         const half8_t* cl, int lane) {
     typedef Input<T> In;
     typedef typename In::Raw RawGroup;
     constexpr int NS = mfma_ring<T, NKC>();   // ring of intermediate blocks
     constexpr int D = mfma_depth<T, NKC>();   // input prefetch depth (divides NS)
     // Mirrored groups reversed at use rather than on arrival, so that the
     // wait for a load falls D blocks after it (costs registers: only with
-    // the peeled loop).
-    constexpr bool LATE_REV = mfma_peel<T, NKC>();
+    // the peeled loop or with the column taps in LDS).
+    constexpr bool LATE_REV = mfma_peel<T, NKC>() || CTL;
     typedef typename Elem<T>::type E;
     const E* img = static_cast<const E*>(J.img);
     const int g = lane >> 4;
@@ -278,15 +280,17 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
     const int xw = x0 - J.rw8;  // first input column of the row-pass window
     const bool fast = !EDGE || (J.aligned && xw >= 0 && xw + 32 * NKR <= w);
 
-    half8_t rt[NKR][4], ct[NKC][4];
+    half8_t rt[NKR][4], ct[CTL ? 1 : NKC][4];
 #pragma unroll
     for (int kb = 0; kb < NKR; ++kb)
 #pragma unroll
         for (int t = 0; t < 4; ++t) rt[kb][t] = fr[(kb * 4 + t) * 64 + lane];
+    if constexpr (!CTL) {
 #pragma unroll
-    for (int kb = 0; kb < NKC; ++kb)
+        for (int kb = 0; kb < NKC; ++kb)
 #pragma unroll
-        for (int t = 0; t < 4; ++t) ct[kb][t] = fr[((NKR + kb) * 4 + t) * 64 + lane];
+            for (int t = 0; t < 4; ++t) ct[kb][t] = fr[((NKR + kb) * 4 + t) * 64 + lane];
+    }
 
     // Regular items: source column and order of each 8-element group.
     int src[NKR];
@@ -386,18 +390,29 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
     auto step = [&](int t, int p) {
         rowpass(t + NS - 1, raw[(p + NS - 1) % D], ring[(p + NS - 1) % NS]);
         float4_t ra = {0.f, 0.f, 0.f, 0.f}, rb = {0.f, 0.f, 0.f, 0.f};
+        // LDS form: an opaque lane offset per block keeps the reads in the
+        // loop (hoisted, they would be the registers this form saves)
+        int lo = lane;
+        if constexpr (CTL) asm volatile("" : "+v"(lo));
+        auto tap = [&](int kb, int t) -> half8_t {
+            if constexpr (CTL)
+                return cl[(kb * 4 + t) * 64 + lo];
+            else
+                return ct[kb][t];
+        };
 #pragma unroll
         for (int kb = 0; kb < NKC; ++kb) {
             const Slot& sa = ring[(p + 2 * kb) % NS];
             const Slot& sb = ring[(p + 2 * kb + 1) % NS];
             const half8_t xh = cat(sa.ah, sb.ah), xl = cat(sa.al, sb.al);
             const half8_t yh = cat(sa.bh, sb.bh), yl = cat(sa.bl, sb.bl);
-            ra = mfma16(xh, ct[kb][0], ra);
-            rb = mfma16(yh, ct[kb][2], rb);
-            ra = mfma16(xh, ct[kb][1], ra);
-            rb = mfma16(yh, ct[kb][3], rb);
-            ra = mfma16(xl, ct[kb][0], ra);
-            rb = mfma16(yl, ct[kb][2], rb);
+            const half8_t c0 = tap(kb, 0), c2 = tap(kb, 2);
+            ra = mfma16(xh, c0, ra);
+            rb = mfma16(yh, c2, rb);
+            ra = mfma16(xh, tap(kb, 1), ra);
+            rb = mfma16(yh, tap(kb, 3), rb);
+            ra = mfma16(xl, c0, ra);
+            rb = mfma16(yl, c2, rb);
         }
         store(t, (ra + rb) * J.out_scale);
     };
@@ -431,14 +446,20 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
     }
 }
 
-template <typename T, int NKR, int NKC>
+template <typename T, int NKR, int NKC, bool CTL = false>
 __device__ __forceinline__ void run_job(const WaveJob& J, const half8_t* __restrict__ fr,
-                                        int lane) {
+                                        int lane, const half8_t* cl = nullptr) {
     if (regular_job<T, NKR, NKC>(J))
-        wave_job<T, NKR, NKC, false>(J, fr, lane);
+        wave_job<T, NKR, NKC, false, CTL>(J, fr, cl, lane);
     else
-        wave_job<T, NKR, NKC, true>(J, fr, lane);
+        wave_job<T, NKR, NKC, true, CTL>(J, fr, cl, lane);
 }
+
+// Single-tile kernels of shapes with nkc >= 3 read their column taps from
+// LDS: the 4 nkc fragments (16 nkc KB per workgroup) would otherwise hold
+// 16 nkc of the wave's registers.
+template <int NKC>
+constexpr bool mfma_cols_in_lds() { return NKC >= 3; }
 
 // Two waves per SIMD where the live state fits 256 registers (u8: no spills
 // up to nkc = 3 in the single-tile kernel, nkc = 2 in the persistent one,
@@ -463,6 +484,13 @@ void log_mfma_kernel(const typename Elem<T>::type* __restrict__ img, int h, int 
     const int local = bid - sc.block_begin;
     const int seg = local / L.groups_x;
     const int wcol = (local - seg * L.groups_x) * MW + (threadIdx.x >> 6);
+    constexpr bool CTL = mfma_cols_in_lds<NKC>();
+    __shared__ half8_t cl[CTL ? NKC * 4 * 64 : 1];
+    if constexpr (CTL) {  // the block's scale's column fragments, before any wave leaves
+        const half8_t* src = frags + sc.frag_off + NKR * 4 * 64;
+        for (int i = threadIdx.x; i < NKC * 4 * 64; i += 64 * MW) cl[i] = src[i];
+        __syncthreads();
+    }
     if (wcol >= L.tiles_x) return;
     // fp32: maxbits = max |I| bits; stretched u8: maxbits = {low, high}
     float in_s = 1.0f, stretch = 1.0f;
@@ -490,7 +518,7 @@ void log_mfma_kernel(const typename Elem<T>::type* __restrict__ img, int h, int 
     J.out_vec = out_vec;
     J.in_scale = in_s;
     J.out_scale = sc.out_scale / in_s * stretch;
-    run_job<T, NKR, NKC>(J, frags + sc.frag_off, threadIdx.x & 63);
+    run_job<T, NKR, NKC, CTL>(J, frags + sc.frag_off, threadIdx.x & 63, cl);
 }
 
 // Persistent form over a batch of tiles: every wave pulls items (scale j of
