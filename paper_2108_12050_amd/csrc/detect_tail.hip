@@ -78,7 +78,10 @@ void launch_nms_k(const DetectWorkspace& ws, int h, int w, float tau, hipStream_
 template <int... Ks>
 void launch_nms(int K, int cw, const DetectWorkspace& ws, int h, int w, float tau, hipStream_t s,
                 std::integer_sequence<int, Ks...>) {
-    if (cw == 2) {
+    if (cw == 4) {
+        ((K == Ks + 1 && Ks + 1 <= 4 ? launch_nms_k<Ks + 1, (Ks + 1 <= 4 ? 4 : 1)>(ws, h, w, tau, s)
+                                     : void()), ...);
+    } else if (cw == 2) {
         ((K == Ks + 1 && Ks + 1 <= 16 ? launch_nms_k<Ks + 1, (Ks + 1 <= 16 ? 2 : 1)>(ws, h, w, tau, s)
                                       : void()), ...);
     } else {
@@ -328,9 +331,13 @@ hipError_t launch_detect_tail(const DetectWorkspace& ws, int K, int h, int w, fl
                               const int32_t* d2max, int reach, const float* sigmas_dev,
                               mhfd_blob* blobs, int capacity, mhfd_result* result, hipStream_t s) {
     init_counters_kernel<<<1, 64, 0, s>>>(ws.ctr);
-    // Two columns per lane when the planes allow aligned float2 loads.
+    // Two columns per lane when the planes allow aligned float2 loads; four
+    // (float4) for up to four planes, whose rows are otherwise too short a
+    // load to keep the memory busy.
     DetectWorkspace wk = ws;
-    const int cw = (K <= 16 && w % 2 == 0 && reinterpret_cast<uintptr_t>(ws.stack) % 8 == 0) ? 2 : 1;
+    const uintptr_t sa = reinterpret_cast<uintptr_t>(ws.stack);
+    const int cw = (K <= 4 && w % 4 == 0 && sa % 16 == 0) ? 4
+                   : (K <= 16 && w % 2 == 0 && sa % 8 == 0) ? 2 : 1;
     wk.blk_per_row = (w + 64 * cw - 1) / (64 * cw);
     wk.n_blk = h * wk.blk_per_row;
     launch_nms(K, cw, wk, h, w, tau, s, std::make_integer_sequence<int, MHFD_MAX_SCALES>{});

@@ -164,7 +164,7 @@ __device__ __forceinline__ void wave(const float* __restrict__ st, int H, int W,
             do {
                 const int bit = __builtin_ctz(m);
                 m &= m - 1u;
-                const int c = bit >= K ? 1 : 0;
+                const int c = bit / K;
                 const int k = bit - c * K;
                 Cand rec;
                 rec.y = y;

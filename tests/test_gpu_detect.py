@@ -159,6 +159,22 @@ def test_single_scale():
     compare_candidates(g["stack"], as_set(g["yxk"]), ora, as_set(ykx), TAU)
 
 
+@pytest.mark.parametrize("K,w", [(3, 300), (4, 516), (2, 260)])
+def test_four_columns_per_lane(K, w):
+    """Up to four planes the maxima pass reads four columns per lane (strips of
+    256 columns): widths past one strip, with a ragged last strip."""
+    plan = make_plan(n_scales=K, sigma_min=1.5, sigma_max=3.5, overlap=1.0, max_h=160,
+                     max_w=520)
+    sig = oracle.linear_sigmas(K, 1.5, 3.5)
+    img = synth.blob_field(20 + K, 150, w, n_blobs=60)
+    g = gpu_detect(plan, img)
+    ora = oracle.log_stack(img, sig)
+    assert plane_rel_err(g["stack"], ora).max() <= STACK_TOL
+    ykx, _ = oracle.candidates(ora, TAU)
+    compare_candidates(g["stack"], as_set(g["yxk"]), ora, as_set(ykx), TAU)
+    assert len(ykx) > 10
+
+
 def test_capacity_overflow_truncates_in_canonical_order(plans):
     img = synth.plain_tile(0)
     full = gpu_detect(plans["prune"], img, return_stack=False)
