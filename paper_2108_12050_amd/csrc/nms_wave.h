@@ -112,10 +112,10 @@ __device__ __forceinline__ void wave(const float* __restrict__ st, int H, int W,
     auto test_row = [&](int y, const Row& up, const Row& cur, const Row& dn, float hup,
                         float hcur, float hdn) {
         const float hm = fmax3(hup, hcur, hdn);
-        Vec m3[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            Vec vm;
+        // 3x3 maxima of plane k (vertical, then horizontal with DPP shifts
+        // and the halo lanes at the strip ends)
+        auto plane_max = [&](int k) {
+            Vec vm, m;
 #pragma unroll
             for (int c = 0; c < CW; ++c) vm[c] = fmax3(up[k][c], cur[k][c], dn[k][c]);
             const float left = wave_shr1(vm[CW - 1], lane_value(hm, k));
@@ -124,25 +124,37 @@ __device__ __forceinline__ void wave(const float* __restrict__ st, int H, int W,
             for (int c = 0; c < CW; ++c) {
                 const float l = c > 0 ? vm[c - 1] : left;
                 const float r = c + 1 < CW ? vm[c + 1] : right;
-                m3[k][c] = fmax3(l, vm[c], r);
+                m[c] = fmax3(l, vm[c], r);
             }
-        }
+            return m;
+        };
+        // planes k - 1, k, k + 1 in a rolling window
         unsigned mask = 0u;
+        Vec mp = static_cast<Vec>(-INFINITY), mk = plane_max(0);
 #pragma unroll
-        for (int c = 0; c < CW; ++c)
+        for (int k = 0; k < K; ++k) {
+            const Vec mn = k + 1 < K ? plane_max(k + 1) : static_cast<Vec>(-INFINITY);
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const float mp = k > 0 ? m3[k - 1][c] : -INFINITY;
-                const float mn = k + 1 < K ? m3[k + 1][c] : -INFINITY;
+            for (int c = 0; c < CW; ++c) {
                 const float v = cur[k][c];
-                const bool hit = (v > tau) & (v >= fmax3(mp, m3[k][c], mn));
+                const bool hit = (v > tau) & (v >= fmax3(mp[c], mk[c], mn[c]));
                 mask |= static_cast<unsigned>(hit) << (c * K + k);
             }
+            mp = mk;
+            mk = mn;
+        }
         mask = col_ok ? mask : 0u;
+        const int64_t cell = static_cast<int64_t>(y) * bpr + strip;
+        if (__ballot(mask != 0u) == 0ull) {  // wave-uniform: no candidate in the cell
+            if (lane == 0) {
+                out.blk_n[cell] = 0;
+                out.blk_o[cell] = 0;
+            }
+            return;
+        }
         const int cnt = __popc(mask);
         int n;
         const int pre = wave_exclusive_prefix<6>(cnt, &n);
-        const int64_t cell = static_cast<int64_t>(y) * bpr + strip;
         int o = 0;
         if (lane == 0) {
             if (n > SLOTS) {
@@ -153,7 +165,6 @@ __device__ __forceinline__ void wave(const float* __restrict__ st, int H, int W,
             out.blk_n[cell] = n;
             out.blk_o[cell] = o;
         }
-        if (n == 0) return;  // wave-uniform
         o = __shfl(o, 0, 64);
         // The lane's candidates in (x, k) order: set bits of the mask from
         // the lowest; the response is read back from the stack (cached).
