@@ -556,6 +556,9 @@ def main() -> int:
     # (1 B/px image in, 40 B/px stack out; the maxima pass reads the stack
     # again) over the single-stream times.
     det_s = el1 / a.steps
+    if traffic is not None:  # HBM bytes the counters saw, over the same LoG time
+        out["roofline"]["traffic_gbs"] = round(traffic / log_s / 1e9, 1)
+        out["roofline"]["traffic_hbm_frac"] = round(traffic / log_s / PEAK_HBM, 4)
     out["roofline"]["hbm_view"] = {
         "peak_gbs": PEAK_HBM / 1e9,
         "log_stack_bytes": 41 * H * W, "log_stack_gbs": round(41 * H * W / log_s / 1e9, 1),
