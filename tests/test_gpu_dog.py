@@ -112,3 +112,13 @@ def test_full_size_u8_bands():
         o_set = {(y + a, x, 0) for y, x, _ in ora["yxk"].tolist()}
         compare_candidates(M[None, a:b].astype(np.float32), g_set, ora["M"][None], o_set, tau,
                            rows=(y0, y1), row0=a)
+
+
+def test_batched_and_focus_refuse_dog_plans():
+    from paper_2108_12050_amd import MHFDError, detect_batched, focus_score
+    plan = dog_plan(64)
+    with pytest.raises(MHFDError):
+        detect_batched(plan, [torch.zeros((32, 32), dtype=torch.float32, device="cuda")])
+    with pytest.raises(MHFDError):
+        focus_score(torch.zeros((1, 32, 32), dtype=torch.float32, device="cuda"),
+                    torch.tensor(plan.sigmas, dtype=torch.float32, device="cuda"), plan)
