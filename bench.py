@@ -409,7 +409,55 @@ def traffic_summarize(fetch_dir: str, write_dir: str, mfma_dir: str) -> int:
     return 0
 
 
+def profile_run(kind: str) -> int:
+    """Fixed workloads for kernel traces (run under rocprofv3): `batch` tunes
+    the 64-tile fp32 batch, captures it into a HIP graph and replays it six
+    times; `stretch` and `dog` run 23 detections of the 4096^2 u8 SEM tile
+    with a stretch plan / the paper's criterion."""
+    import torch
+
+    from paper_2108_12050_amd import Plan, synth
+    if kind == "batch":
+        from paper_2108_12050_amd.autotune import Autotuner
+        from paper_2108_12050_amd.batch import BatchRunner
+        shapes = synth.mixed_batch_shapes(0, 64)
+        pool = {}
+        for i, (h, w, p) in enumerate(shapes):
+            key = (h, w, i % 2)
+            if key not in pool:
+                pool[key] = torch.from_numpy(synth.blob_field(1000 + len(pool), h, w,
+                                                              psf_sigma=p)).cuda()
+        imgs = [pool[(h, w, i % 2)] for i, (h, w, p) in enumerate(shapes)]
+        plan = Plan(n_scales=K, sigma_min=1.0, sigma_max=10.0, threshold=0.1, overlap=OVERLAP,
+                    max_h=4096, max_w=4096)
+        tuner = Autotuner(plan)
+        tuner.tune(sorted(set((h, w) for h, w, _ in shapes)), reps=1)
+        r = BatchRunner(plan, 64, sum(t.numel() for t in imgs), 1 << 17)
+        r.set_tiles(imgs, [tuner.seg_rows_for(*t.shape) for t in imgs])
+        g = r.capture()
+        for _ in range(6):
+            g.replay()
+    elif kind in ("stretch", "dog"):
+        img = torch.from_numpy(synth.sem_tile(0, psf_sigma=0.0)).cuda()
+        if kind == "stretch":
+            plan = Plan(n_scales=K, sigma_min=1.0, sigma_max=10.0, threshold=TAU, overlap=OVERLAP,
+                        dtype="u8", max_h=H, max_w=W, stretch=True)
+        else:
+            plan = Plan(n_scales=K, sigma_min=1.0, sigma_max=10.0, threshold=0.02, overlap=1.0,
+                        dtype="u8", max_h=H, max_w=W, criterion="dog")
+        for _ in range(23):
+            plan.detect(img)
+    else:
+        print(f"unknown profile run {kind!r}", file=sys.stderr)
+        return 2
+    torch.cuda.synchronize()
+    print(f"profile run {kind} done", flush=True)
+    return 0
+
+
 def main() -> int:
+    if len(sys.argv) > 2 and sys.argv[1] == "--profile-run":
+        return profile_run(sys.argv[2])
     if len(sys.argv) > 1 and sys.argv[1] == "--traffic-run":
         return traffic_run()
     if len(sys.argv) > 1 and sys.argv[1] == "--traffic-summarize":
