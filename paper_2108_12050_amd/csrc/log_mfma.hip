@@ -101,7 +101,8 @@ struct WaveJob {
     int out_vec;      // 16-byte aligned output rows and w % 4 == 0
     float in_scale;   // fp32 input: exact power of two applied before the split
     float out_scale;  // exact power of two (times 255 / (high - low) when stretched)
-    float s_lo, s_hi; // stretched u8 input: 1024 + low, 1024 + high (exact in FP16)
+    uint32_t s_lo, s_hi, s_nlo;  // stretched u8 input: 1024 + low, 1024 + high,
+                                 // -(1024 + low), each as an FP16 pair
 };
 
 // 8-bit input with the histogram stretch applied as it is read (stretch.hip):
@@ -195,10 +196,16 @@ struct Input<U8Stretch> : Input<uint8_t> {
     // 1024 + v is exact in FP16, so are the clamp to [1024 + low, 1024 + high]
     // and the subtraction of 1024 + low
     __device__ static void convert(Raw v, const WaveJob& J, half8_t& hi, half8_t&) {
-        const half8_t lo8 = static_cast<half8_t>(static_cast<_Float16>(J.s_lo));
-        const half8_t hi8 = static_cast<half8_t>(static_cast<_Float16>(J.s_hi));
-        const half8_t q = codes_plus_1024(v.x, v.y);
-        hi = __builtin_elementwise_min(__builtin_elementwise_max(q, lo8), hi8) - lo8;
+        // positive FP16 values order as their bit patterns: the clamp runs
+        // on 16-bit integers (no NaN handling), the shift in FP16
+        typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+        typedef uint16_t us8 __attribute__((ext_vector_type(8)));
+        const us8 lo8 = __builtin_bit_cast(us8, static_cast<u4>(J.s_lo));
+        const us8 hi8 = __builtin_bit_cast(us8, static_cast<u4>(J.s_hi));
+        const half8_t nlo8 = __builtin_bit_cast(half8_t, static_cast<u4>(J.s_nlo));
+        const us8 q = __builtin_bit_cast(us8, codes_plus_1024(v.x, v.y));
+        const us8 c = __builtin_elementwise_min(__builtin_elementwise_max(q, lo8), hi8);
+        hi = __builtin_bit_cast(half8_t, c) + nlo8;
     }
 };
 
@@ -495,11 +502,14 @@ void log_mfma_kernel(const typename Elem<T>::type* __restrict__ img, int h, int 
     // fp32: maxbits = max |I| bits; stretched u8: maxbits = {low, high}
     float in_s = 1.0f, stretch = 1.0f;
     WaveJob J;
-    J.s_lo = J.s_hi = 1024.0f;
+    J.s_lo = J.s_hi = 0x64006400u;
+    J.s_nlo = 0xE400E400u;
     if constexpr (std::is_same<T, U8Stretch>::value) {
+        // 1024 + c has FP16 bits 0x6400 + c for codes c in [0, 255]
         const int lo = static_cast<int>(maxbits[0]), hi = static_cast<int>(maxbits[1]);
-        J.s_lo = 1024.0f + lo;
-        J.s_hi = 1024.0f + hi;
+        J.s_lo = (0x6400u + static_cast<uint32_t>(lo)) * 0x10001u;
+        J.s_hi = (0x6400u + static_cast<uint32_t>(hi)) * 0x10001u;
+        J.s_nlo = (0xE400u + static_cast<uint32_t>(lo)) * 0x10001u;  // sign bit set
         stretch = hi > lo ? 255.0f / static_cast<float>(hi - lo) : 0.0f;
     } else if (maxbits) {
         in_s = input_scale(*maxbits);
