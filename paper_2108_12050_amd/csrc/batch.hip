@@ -3,16 +3,17 @@
 // checks them and builds the per-tile table, so the sequence can be captured
 // in a HIP graph and replayed with new descriptors.
 //
-//   setup      validate, per-tile LoG items / NMS workgroups / stack offsets
+//   setup      validate, per-tile LoG items / maxima cells and items / stack offsets
 //              and their prefix sums (one workgroup);
-//   LoG        u8 plans: persistent matrix-core waves per K-block shape
-//              (log_mfma.hip), the same per-wave arithmetic as the single-
-//              tile path; other scales: persistent strip workgroups per
-//              radius class (log_strip.hip);
+//   LoG        persistent matrix-core waves per K-block shape (log_mfma.hip;
+//              fp32 plans after a per-tile max |I| pass), the same per-wave
+//              arithmetic as the single-tile path; scales above the
+//              matrix-core radius: persistent strip workgroups per radius
+//              class (log_strip.hip);
 //   nms        persistent waves over every tile's (32-row run, strip) items,
 //              the per-wave body of the single-tile path (nms_wave.h); the
 //              tile index rides in the upper bits of k;
-//   scan       over all pieces, tile-major: the canonical list of every tile
+//   scan       over all cells, tile-major: the canonical list of every tile
 //              is one contiguous run of the global list;
 //   order, prune (rows of the candidate's own tile), keep scan, emit into the
 //              tile's buffer, per-tile results.

@@ -865,7 +865,7 @@ mhfd_status mhfd_detect_batched(mhfd_plan p, int32_t n, const mhfd_tile* d_tiles
     hipError_t e = mhfd::launch_batch_setup(d_tiles, n, max_pixels, p->K, p->max_h, p->max_w,
                                             p->dtype, p->d_frags ? 1 : 0, tiles, ctr, s);
     if (e != hipSuccess) return hip_fail(e, "batch setup");
-    // Matrix-core scales (u8 plans), one persistent launch per shape, the
+    // Matrix-core scales, one persistent launch per shape, the
     // costliest shape first; the same per-wave arithmetic as the single-tile
     // path, so every tile's stack equals its single-tile stack.
     uint32_t* maxbits = reinterpret_cast<uint32_t*>(base + L.maxbits);

@@ -209,7 +209,7 @@ struct BatchTile {
     int nms_base;           // prefix of h * bpr over earlier tiles
     int nms_cw;             // columns per maxima lane (1 or 2)
     int nitem_base;         // prefix of ceil(h / 32) * bpr (maxima wave items)
-    // matrix-core items (u8 plans): wave columns x row segments
+    // matrix-core items: wave columns x row segments
     int mtiles_x, msegs, mseg_rows;
     int mitem_base;         // prefix of mtiles_x * msegs over earlier tiles
 };
@@ -224,7 +224,7 @@ struct BatchCounters {
     int32_t n_cand;
     int32_t n_blobs;
     int32_t work[3];          // persistent LoG work counters, one per radius class
-    int32_t mitems_per_scale; // sum over tiles of mtiles_x * msegs (u8 plans)
+    int32_t mitems_per_scale; // sum over tiles of mtiles_x * msegs
     int32_t mwork[MFMA_SHAPES];  // persistent matrix-core work counters, one per shape
 };
 
@@ -270,7 +270,7 @@ struct BatchLaunchArgs {
     BatchCounters* ctr;
 };
 
-// mfma: the plan computes some scales on the matrix cores (u8 plans), so the
+// mfma: the plan computes some scales on the matrix cores, so the
 // setup also numbers the matrix-core items.
 hipError_t launch_batch_setup(const mhfd_tile* in, int n, long long max_pixels, int K, int max_h,
                               int max_w, int dtype, int mfma, BatchTile* tiles,
