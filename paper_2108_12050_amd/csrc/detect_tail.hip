@@ -188,11 +188,60 @@ __global__ __launch_bounds__(SCAN_BT) void scan_apply_kernel(const int32_t* __re
     }
 }
 
+// Second pass when there are at most SCAN_BT spans: every workgroup adds up
+// the span sums before its own (one per thread) instead of a separate scan
+// of the span sums, and the workgroup holding the last element writes the
+// total.  Same result as scan_top_kernel + scan_apply_kernel, one launch.
+__global__ __launch_bounds__(SCAN_BT) void scan_apply_small_kernel(
+    const int32_t* __restrict__ in, int n_host, const int32_t* __restrict__ n_dev,
+    const int32_t* __restrict__ sums, int32_t* __restrict__ out, int32_t* __restrict__ total_out) {
+    __shared__ int sh[SCAN_BT / 64];
+    __shared__ int offset;
+    const int n = scan_n(n_host, n_dev);
+    if (n == 0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            out[0] = 0;
+            if (total_out) *total_out = 0;
+        }
+        return;
+    }
+    if (blockIdx.x * SCAN_SPAN >= n) return;  // whole workgroup
+    {
+        const int before = block_inclusive_scan(
+            static_cast<int>(threadIdx.x) < static_cast<int>(blockIdx.x) ? sums[threadIdx.x] : 0, sh);
+        if (threadIdx.x == SCAN_BT - 1) offset = before;
+        __syncthreads();
+    }
+    const int base = blockIdx.x * SCAN_SPAN + threadIdx.x * SCAN_ITEMS;
+    int v[SCAN_ITEMS];
+    int s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        v[i] = base + i < n ? in[base + i] : 0;
+        s += v[i];
+    }
+    const int incl = block_inclusive_scan(s, sh);
+    int run = incl - s + offset;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        if (base + i < n) out[base + i] = run;
+        run += v[i];
+    }
+    if (threadIdx.x == SCAN_BT - 1 && (n - 1) / SCAN_SPAN == static_cast<int>(blockIdx.x)) {
+        out[n] = offset + incl;
+        if (total_out) *total_out = offset + incl;
+    }
+}
+
 void launch_scan(const int32_t* in, int n_host, const int32_t* n_dev, int32_t* sums,
                  int32_t* out, int32_t* total_out, hipStream_t s) {
     const int nb = (n_host + SCAN_SPAN - 1) / SCAN_SPAN;
     const int grid = nb > 0 ? nb : 1;
     scan_sums_kernel<<<grid, SCAN_BT, 0, s>>>(in, n_host, n_dev, sums);
+    if (grid <= SCAN_BT) {
+        scan_apply_small_kernel<<<grid, SCAN_BT, 0, s>>>(in, n_host, n_dev, sums, out, total_out);
+        return;
+    }
     scan_top_kernel<<<1, 1024, 0, s>>>(sums, grid, n_host, n_dev, out, total_out);
     scan_apply_kernel<<<grid, SCAN_BT, 0, s>>>(in, n_host, n_dev, sums, out);
 }
