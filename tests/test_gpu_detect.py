@@ -276,3 +276,65 @@ def test_full_size_sem_tile():
               flush=True)
         total += n_band
     assert total > 1000
+
+
+def test_max_size_f32_tile():
+    """8192 x 8192 fp32 tile (the largest size served), rendered like the
+    plain workload (51200 blobs), sigma 1..10, threshold 0.1: sampled stack
+    voxels against the 2-D definition; stack and candidate decisions
+    (ambiguity-aware) against the oracle on three full-width row bands; and
+    the overlap prune exactly, over the whole tile: a blob's fate depends only
+    on candidates within r_a + r_b <= 2 sqrt(2) sigma_max of it, so the GPU's
+    own candidate set, cut into 128-row strips with a 32-row margin, goes
+    through the oracle's prune and must give the GPU's pruned list."""
+    import torch
+    print("max-size 8192x8192 f32", flush=True)
+    H = W = 8192
+    img = synth.blob_field(5, H, W)
+    plan_c = make_plan(overlap=1.0, max_h=H, max_w=W)
+    plan_p = make_plan(max_h=H, max_w=W)
+    t = torch.from_numpy(img).to(plan_c.device)
+    d = plan_c.detect(t, return_stack=True)
+    cand = d.yxk.cpu().numpy().astype(np.int64)
+    assert d.n_candidates == len(cand) and d.count == len(cand)
+    I = oracle.to_f64(img)
+    rng = np.random.default_rng(1)
+    pts = [(int(rng.integers(0, 10)), int(rng.integers(0, H)), int(rng.integers(0, W)))
+           for _ in range(200)]
+    pts += [(k, y, x) for k in (0, 9) for y in (0, H - 1) for x in (0, 64, W - 1)]
+    idx = torch.tensor(pts, dtype=torch.long, device=d.stack.device)
+    vals = d.stack[idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy()
+    for (k, y, x), v in zip(pts, vals):
+        ref = oracle.log_point(I, SIG10[k], y, x)
+        assert abs(v - ref) <= STACK_TOL * 0.5, (k, y, x, v, ref)
+    m = 42   # > largest radius + 1: band rows [y0 - 1, y1 + 1) are exact
+    gpu_c = as_set(cand)
+    for (y0, y1) in [(0, 96), (4000, 4096), (H - 96, H)]:
+        a, b = max(0, y0 - m), min(H, y1 + m)
+        st = d.stack[:, a:b].cpu().numpy()
+        ora = oracle.log_stack(I[a:b], SIG10)
+        lo, hi = max(0, y0 - 1) - a, min(H, y1 + 1) - a
+        err = plane_rel_err(st[:, lo:hi], ora[:, lo:hi])
+        assert err.max() <= STACK_TOL, err
+        ykx, _ = oracle.candidates(ora, TAU)
+        ykx[:, 0] += a
+        n_amb, n_diff = compare_candidates(st, gpu_c, ora, as_set(ykx), TAU,
+                                           rows=(y0, y1), row0=a)
+        print(f"band {y0}-{y1}: ambiguous {n_amb} differing {n_diff}", flush=True)
+    del d, t
+    dp = plan_p.detect(torch.from_numpy(img).to(plan_p.device))
+    assert dp.n_candidates == len(cand)
+    kept = dp.yxk.cpu().numpy().astype(np.int64)
+    assert dp.count == len(kept)
+    step, margin = 128, 32
+    expect = []
+    for s0 in range(0, H, step):
+        sel = (cand[:, 0] >= s0 - margin) & (cand[:, 0] < s0 + step + margin)
+        sub = cand[sel]
+        keep = oracle.prune(sub[:, [0, 1, 2]], SIG10, 0.5)
+        own = (sub[:, 0] >= s0) & (sub[:, 0] < s0 + step)
+        expect.append(sub[keep & own])
+    expect = np.concatenate(expect)
+    print(f"candidates {len(cand)} kept {len(kept)}", flush=True)
+    np.testing.assert_array_equal(kept, expect)
+    assert 0 < len(kept) < len(cand)
