@@ -251,12 +251,11 @@ __global__ void prune_rows_batch_kernel(const Cand* __restrict__ cand,
                                         const int32_t* __restrict__ blk_off,
                                         const BatchTile* __restrict__ tiles, int K,
                                         const int32_t* __restrict__ d2max, int reach,
-                                        int32_t* __restrict__ keep, int64_t cap,
+                                        int d2top, int32_t* __restrict__ keep, int64_t cap,
                                         const BatchCounters* __restrict__ ctr) {
     const int64_t n = min(static_cast<int64_t>(ctr->n_cand), cap);
     const long long dy = static_cast<long long>(blockIdx.y) - reach;
-    const int xr = static_cast<int>(sqrt(static_cast<double>(
-        static_cast<long long>(reach) * reach - dy * dy)));
+    const int xr = static_cast<int>(sqrt(static_cast<double>(d2top - dy * dy)));
     for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const Cand b = cand[i];
@@ -370,7 +369,7 @@ hipError_t launch_batch_tail(const BatchLaunchArgs& a, hipStream_t s) {
     if (a.d2max) {
         const int span = 2 * a.reach + 1;
         prune_rows_batch_kernel<<<dim3(prune_grid_x(span), span), 256, 0, s>>>(
-            a.cand, a.blk_off, a.tiles, a.K, a.d2max, a.reach, a.keep, a.cap, a.ctr);
+            a.cand, a.blk_off, a.tiles, a.K, a.d2max, a.reach, a.d2top, a.keep, a.cap, a.ctr);
     }
     launch_batch_scan(a.keep, static_cast<int>(a.cap), &a.ctr->n_cand, a.scan_sums, a.keep_off,
                       &a.ctr->n_blobs, s);

@@ -278,7 +278,8 @@ __global__ void order_kernel(const int32_t* __restrict__ blk_off, const int32_t*
 }
 
 // Overlap prune.  Candidates a that can remove b lie within `reach` rows
-// and, in row y_b + dy, within |dx| <= sqrt(reach^2 - dy^2); rows come from
+// and, in row y_b + dy, within |dx| <= sqrt(d2top - dy^2), d2top being the
+// largest entry of the table (reach^2 can fall short of it); rows come from
 // the per-row offsets of the canonical list and the column range from a
 // binary search in the row (sorted by x).  The overlap test is the plan's
 // exact integer form: overlap(a, b) > theta iff dy^2 + dx^2 <=
@@ -295,13 +296,12 @@ __global__ void order_kernel(const int32_t* __restrict__ blk_off, const int32_t*
 // searches share cache lines.
 __global__ void prune_rows_kernel(const Cand* __restrict__ cand,
                                   const int32_t* __restrict__ blk_off, int bpr, int H, int K,
-                                  const int32_t* __restrict__ d2max, int reach,
+                                  const int32_t* __restrict__ d2max, int reach, int d2top,
                                   int32_t* __restrict__ keep, int64_t cap,
                                   const DetectCounters* __restrict__ ctr) {
     const int64_t n = min(static_cast<int64_t>(ctr->n_cand), cap);
     const long long dy = static_cast<long long>(blockIdx.y) - reach;
-    const int xr = static_cast<int>(sqrt(static_cast<double>(
-        static_cast<long long>(reach) * reach - dy * dy)));
+    const int xr = static_cast<int>(sqrt(static_cast<double>(d2top - dy * dy)));
     for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const Cand b = cand[i];
@@ -377,8 +377,9 @@ size_t nms_pool_records(int n_blk, int64_t cap) { return static_cast<size_t>(n_b
 size_t scan_sums_ints(int64_t n) { return static_cast<size_t>((n + SCAN_SPAN - 1) / SCAN_SPAN + 1); }
 
 hipError_t launch_detect_tail(const DetectWorkspace& ws, int K, int h, int w, float tau,
-                              const int32_t* d2max, int reach, const float* sigmas_dev,
-                              mhfd_blob* blobs, int capacity, mhfd_result* result, hipStream_t s) {
+                              const int32_t* d2max, int reach, int d2top,
+                              const float* sigmas_dev, mhfd_blob* blobs, int capacity,
+                              mhfd_result* result, hipStream_t s) {
     init_counters_kernel<<<1, 64, 0, s>>>(ws.ctr);
     // Two columns per lane when the planes allow aligned float2 loads; four
     // (float4) for up to four planes, whose rows are otherwise too short a
@@ -397,7 +398,8 @@ hipError_t launch_detect_tail(const DetectWorkspace& ws, int K, int h, int w, fl
     if (d2max) {
         const int span = 2 * reach + 1;
         prune_rows_kernel<<<dim3(prune_grid_x(span), span), 256, 0, s>>>(
-            wk.cand, wk.blk_off, wk.blk_per_row, h, K, d2max, reach, ws.keep, ws.cap, ws.ctr);
+            wk.cand, wk.blk_off, wk.blk_per_row, h, K, d2max, reach, d2top, ws.keep, ws.cap,
+            ws.ctr);
     }
     launch_scan(ws.keep, static_cast<int>(ws.cap), &ws.ctr->n_cand, ws.scan_sums, ws.keep_off,
                 &ws.ctr->n_blobs, s);

@@ -24,6 +24,7 @@ struct mhfd_plan_s {
     int max_h = 0, max_w = 0;
     int64_t max_cand = 0;
     int reach = 0;               // prune row reach, floor(sqrt(max d2max))
+    int d2_top = 0;              // max d2max: bounds the prune's column search
     int n_cu = 0;                // compute units of the plan's device
     float* d_taps = nullptr;     // device tap table
     int32_t* d_d2max = nullptr;  // K x K prune table (null: pruning off)
@@ -300,6 +301,7 @@ mhfd_status mhfd_create_plan(const mhfd_config* cfg, mhfd_plan* out) {
                 if (d2[a * K + b] > d2_top) d2_top = d2[a * K + b];
             }
     }
+    p->d2_top = d2_top;
     p->reach = static_cast<int>(floor(sqrt(static_cast<double>(d2_top))));
     std::vector<float> host(off, 0.0f);
     for (int k = 0; k < K; ++k)
@@ -645,15 +647,16 @@ mhfd_status enqueue_tail(const mhfd_plan_s* p, const float* stack, int h, int w,
         hipError_t e = mhfd::launch_dog(stack, p->K, p->d_sigmas, h, w, M, arg, s);
         if (e != hipSuccess) return hip_fail(e, "DoG launch");
         ws.stack = M;
-        e = mhfd::launch_detect_tail(ws, 1, h, w, p->threshold, nullptr, 0, p->d_sigmas, d_blobs,
-                                     capacity, d_result, s);
+        e = mhfd::launch_detect_tail(ws, 1, h, w, p->threshold, nullptr, 0, 0, p->d_sigmas,
+                                     d_blobs, capacity, d_result, s);
         if (e == hipSuccess) e = mhfd::launch_dog_label(d_blobs, capacity, d_result, arg, w,
                                                         p->d_sigmas, s);
         if (e != hipSuccess) return hip_fail(e, "detection launch");
         return MHFD_OK;
     }
     hipError_t e = mhfd::launch_detect_tail(ws, p->K, h, w, p->threshold, p->d_d2max, p->reach,
-                                            p->d_sigmas, d_blobs, capacity, d_result, s);
+                                            p->d2_top, p->d_sigmas, d_blobs, capacity,
+                                            d_result, s);
     if (e != hipSuccess) return hip_fail(e, "detection launch");
     return MHFD_OK;
 }
@@ -923,6 +926,7 @@ mhfd_status mhfd_detect_batched(mhfd_plan p, int32_t n, const mhfd_tile* d_tiles
     a.n_blk_bound = L.n_blk_bound;
     a.nms_grid = 8 * p->n_cu;
     a.reach = p->reach;
+    a.d2top = p->d2_top;
     a.tau = p->threshold;
     a.cap = L.cap;
     a.stack = stack;

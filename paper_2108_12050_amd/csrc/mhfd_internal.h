@@ -173,9 +173,10 @@ struct DetectWorkspace {
 
 // d2max: K x K table, d2max[ka * K + kb] = largest squared integer distance at
 // which blobs of scales ka and kb overlap by more than the plan's threshold
-// (-1: never); null disables pruning.  `reach` = floor(sqrt(max d2max)).
+// (-1: never); null disables pruning.  `d2top` = max d2max, `reach` =
+// floor(sqrt(d2top)).
 hipError_t launch_detect_tail(const DetectWorkspace& ws, int K, int h, int w, float tau,
-                              const int32_t* d2max, int reach, const float* sigmas_dev,
+                              const int32_t* d2max, int reach, int d2top, const float* sigmas_dev,
                               mhfd_blob* blobs, int capacity, mhfd_result* result, hipStream_t s);
 
 // Records of the unordered candidate pool: a fixed slot per NMS workgroup
@@ -258,7 +259,7 @@ hipError_t launch_log_batch(int cls, int in_dtype, int n_tiles, const BatchTile*
                             BatchCounters* ctr, int grid, hipStream_t s);
 
 struct BatchLaunchArgs {
-    int K, n_tiles, n_blk_bound, nms_grid, reach;
+    int K, n_tiles, n_blk_bound, nms_grid, reach, d2top;
     float tau;
     int64_t cap;
     const float* stack;

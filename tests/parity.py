@@ -102,3 +102,20 @@ def kink_bound(img: np.ndarray, sig, beta: float, tau: float, gbar: float, eps: 
         out += correlate1d(correlate1d(m, ag, axis=1, mode="reflect"), ah, axis=0, mode="reflect")
         out += correlate1d(correlate1d(m, ah, axis=1, mode="reflect"), ag, axis=0, mode="reflect")
     return out
+
+
+def strip_prune(cand: np.ndarray, sigmas, theta: float, H: int, step: int = 128,
+                margin: int = 32) -> np.ndarray:
+    """The oracle's one-shot prune of a canonical (y, x, k) candidate list,
+    run strip by strip: a candidate's fate depends only on candidates closer
+    than r_a + r_b, so each `step`-row strip is pruned together with the
+    candidates `margin` rows around it (margin must exceed that reach) and
+    keeps the decisions of its own rows.  Returns the kept records in order."""
+    out = []
+    for s0 in range(0, H, step):
+        sel = (cand[:, 0] >= s0 - margin) & (cand[:, 0] < s0 + step + margin)
+        sub = cand[sel]
+        keep = oracle.prune(sub[:, :3], sigmas, theta)
+        own = (sub[:, 0] >= s0) & (sub[:, 0] < s0 + step)
+        out.append(sub[keep & own])
+    return np.concatenate(out) if out else cand[:0]

@@ -18,7 +18,7 @@ import pytest
 import oracle
 from paper_2108_12050_amd import synth
 
-from parity import as_set, compare_candidates, gpu_detect, plane_rel_err
+from parity import as_set, compare_candidates, gpu_detect, plane_rel_err, strip_prune
 
 pytestmark = pytest.mark.gpu
 
@@ -326,15 +326,51 @@ def test_max_size_f32_tile():
     assert dp.n_candidates == len(cand)
     kept = dp.yxk.cpu().numpy().astype(np.int64)
     assert dp.count == len(kept)
-    step, margin = 128, 32
-    expect = []
-    for s0 in range(0, H, step):
-        sel = (cand[:, 0] >= s0 - margin) & (cand[:, 0] < s0 + step + margin)
-        sub = cand[sel]
-        keep = oracle.prune(sub[:, [0, 1, 2]], SIG10, 0.5)
-        own = (sub[:, 0] >= s0) & (sub[:, 0] < s0 + step)
-        expect.append(sub[keep & own])
-    expect = np.concatenate(expect)
+    assert 2 * np.sqrt(2) * SIG10[-1] < 32
+    expect = strip_prune(cand, SIG10, 0.5, H)
     print(f"candidates {len(cand)} kept {len(kept)}", flush=True)
     np.testing.assert_array_equal(kept, expect)
     assert 0 < len(kept) < len(cand)
+
+
+def test_benchmark_tiles_prune_and_focus_order():
+    """The benchmark's four 4096 x 4096 8-bit tiles (one scene, PSF sigma 0, 1,
+    2, 4), threshold 0.05, overlap 0.5, in its launch configuration: sampled
+    stack voxels against the 2-D definition, the prune exactly over each whole
+    tile (the GPU's candidates through the oracle's prune, strip by strip),
+    and the focus criterion's order: fewer blobs as the defocus grows."""
+    import torch
+    from paper_2108_12050_amd import Plan, detect_batched
+    kw = dict(n_scales=10, sigma_min=1, sigma_max=10, threshold=0.05, dtype="u8",
+              max_h=4096, max_w=4096)
+    plan_c, plan_p = Plan(overlap=1.0, **kw), Plan(overlap=0.5, **kw)
+    counts, tiles, expected = [], [], []
+    for psf in (0.0, 1.0, 2.0, 4.0):
+        print(f"benchmark tile psf {psf}", flush=True)
+        img = synth.sem_tile(0, psf_sigma=psf)
+        t = torch.from_numpy(img).to(plan_c.device)
+        d = plan_c.detect(t, return_stack=True)
+        cand = d.yxk.cpu().numpy().astype(np.int64)
+        I = oracle.to_f64(img)
+        rng = np.random.default_rng(int(psf))
+        pts = [(int(rng.integers(0, 10)), int(rng.integers(0, 4096)),
+                int(rng.integers(0, 4096))) for _ in range(60)]
+        idx = torch.tensor(pts, dtype=torch.long, device=d.stack.device)
+        vals = d.stack[idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy()
+        for (k, y, x), v in zip(pts, vals):
+            ref = oracle.log_point(I, SIG10[k], y, x)
+            assert abs(v - ref) <= STACK_TOL * 0.5, (psf, k, y, x, v, ref)
+        del d
+        dp = plan_p.detect(t)
+        kept = dp.yxk.cpu().numpy().astype(np.int64)
+        assert dp.n_candidates == len(cand) and dp.count == len(kept)
+        exp = strip_prune(cand, SIG10, 0.5, 4096)
+        np.testing.assert_array_equal(kept, exp)
+        print(f"psf {psf}: candidates {len(cand)} kept {len(kept)}", flush=True)
+        counts.append(len(kept))
+        tiles.append(t)
+        expected.append(exp)
+    assert counts == sorted(counts, reverse=True) and counts[-1] < counts[0] / 2, counts
+    print("batched, the same four tiles", flush=True)
+    for dt, exp in zip(detect_batched(plan_p, tiles, capacity=1 << 17), expected):
+        np.testing.assert_array_equal(dt.yxk.cpu().numpy().astype(np.int64), exp)
