@@ -119,3 +119,16 @@ def strip_prune(cand: np.ndarray, sigmas, theta: float, H: int, step: int = 128,
         own = (sub[:, 0] >= s0) & (sub[:, 0] < s0 + step)
         out.append(sub[keep & own])
     return np.concatenate(out) if out else cand[:0]
+
+
+def own_maxima(stack: np.ndarray, tau: float) -> np.ndarray:
+    """Canonical (y, x, k) list of the voxels of `stack` (K x H x W, the
+    GPU's own values) that equal the maximum of their 3x3x3 window (-inf
+    outside the volume) and exceed tau: the candidate rule applied to the
+    same FP32 values, so the GPU's candidate list must equal it exactly."""
+    from scipy.ndimage import maximum_filter
+    mx = maximum_filter(stack, size=3, mode="constant", cval=-np.inf)
+    mask = (stack == mx) & (stack > np.float32(tau))
+    del mx
+    y, x, k = np.nonzero(mask.transpose(1, 2, 0))
+    return np.stack([y, x, k], axis=1).astype(np.int64)

@@ -18,7 +18,8 @@ import pytest
 import oracle
 from paper_2108_12050_amd import synth
 
-from parity import as_set, compare_candidates, gpu_detect, plane_rel_err, strip_prune
+from parity import (as_set, compare_candidates, gpu_detect, own_maxima, plane_rel_err,
+                    strip_prune)
 
 pytestmark = pytest.mark.gpu
 
@@ -236,9 +237,10 @@ def test_split_entry_points_equal_detect(plans):
 def test_full_size_sem_tile():
     """4096 x 4096 8-bit tile, sigma 1..10, threshold 0.05, in the launch
     configuration the benchmark times: sampled stack voxels against the 2-D
-    definition over the whole tile; stack and candidate decisions
-    (ambiguity-aware) against the oracle on three full-width row bands
-    (top border, middle, bottom border)."""
+    definition over the whole tile; the whole candidate list against the
+    candidate rule applied to the GPU's own stack; stack and candidate
+    decisions (ambiguity-aware) against the oracle on three full-width row
+    bands (top border, middle, bottom border)."""
     import torch
     from paper_2108_12050_amd import Plan
     print("full-size 4096x4096 u8", flush=True)
@@ -249,6 +251,7 @@ def test_full_size_sem_tile():
     t = torch.from_numpy(img).to(plan_c.device)
     d = plan_c.detect(t, return_stack=True)
     st = d.stack.cpu().numpy()
+    np.testing.assert_array_equal(d.yxk.cpu().numpy().astype(np.int64), own_maxima(st, tau))
     gpu_c = as_set(d.yxk.cpu().numpy())
     I = oracle.to_f64(img)
     rng = np.random.default_rng(0)
@@ -281,7 +284,8 @@ def test_full_size_sem_tile():
 def test_max_size_f32_tile():
     """8192 x 8192 fp32 tile (the largest size served), rendered like the
     plain workload (51200 blobs), sigma 1..10, threshold 0.1: sampled stack
-    voxels against the 2-D definition; stack and candidate decisions
+    voxels against the 2-D definition; the whole candidate list against the
+    candidate rule on the GPU's own stack; stack and candidate decisions
     (ambiguity-aware) against the oracle on three full-width row bands; and
     the overlap prune exactly, over the whole tile: a blob's fate depends only
     on candidates within r_a + r_b <= 2 sqrt(2) sigma_max of it, so the GPU's
@@ -297,6 +301,7 @@ def test_max_size_f32_tile():
     d = plan_c.detect(t, return_stack=True)
     cand = d.yxk.cpu().numpy().astype(np.int64)
     assert d.n_candidates == len(cand) and d.count == len(cand)
+    np.testing.assert_array_equal(cand, own_maxima(d.stack.cpu().numpy(), TAU))
     I = oracle.to_f64(img)
     rng = np.random.default_rng(1)
     pts = [(int(rng.integers(0, 10)), int(rng.integers(0, H)), int(rng.integers(0, W)))
