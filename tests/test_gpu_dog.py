@@ -13,7 +13,7 @@ import torch
 import oracle
 from paper_2108_12050_amd import synth
 
-from parity import as_set, compare_candidates, plane_rel_err
+from parity import as_set, compare_candidates, own_maxima, plane_rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -87,9 +87,10 @@ def test_u8_stretched_sem_tile():
 
 def test_full_size_u8_bands():
     """4096^2 SEM tile (inverted: dark texture), as a user would run the
-    paper's criterion on it: three row bands compared with the oracle run
-    on the band plus a 42-row margin (rows y0 - 1 .. y1 of the planes are
-    then exact)."""
+    paper's criterion on it: over the whole tile, the blob list against the
+    maxpool-equality rule on M recomputed from the GPU's planes; three row
+    bands compared with the oracle run on the band plus a 42-row margin
+    (rows y0 - 1 .. y1 of the planes are then exact)."""
     print("dog full-size 4096x4096 u8", flush=True)
     img = (255 - synth.sem_tile(2, psf_sigma=0.0)).astype(np.uint8)
     plan = dog_plan(4096, dtype="u8", threshold=0.02)
@@ -102,6 +103,8 @@ def test_full_size_u8_bands():
     assert np.array_equal(got[:, 2], arg[got[:, 0], got[:, 1]])
     g_set = {(y, x, 0) for y, x, _ in got.tolist()}
     tau = float(np.float32(0.02))
+    own = own_maxima(M[None].astype(np.float32), tau)
+    np.testing.assert_array_equal(got[:, :2].astype(np.int64), own[:, :2])
     m, H = 42, 4096
     for (y0, y1) in [(0, 96), (2000, 2096), (4000, 4096)]:
         a, b = max(0, y0 - m), min(H, y1 + m)

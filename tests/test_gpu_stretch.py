@@ -9,7 +9,7 @@ import torch
 import oracle
 from paper_2108_12050_amd import synth
 
-from parity import as_set, compare_candidates, plane_rel_err
+from parity import as_set, compare_candidates, own_maxima, plane_rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -89,8 +89,9 @@ def test_batched_and_focus_refuse_stretch_plans():
 
 def test_full_size_sem_tile():
     """4096^2 SEM tile as the benchmark runs it: levels exact, sampled stack
-    values against the oracle's point evaluation of the stretched image, and
-    three row bands (top, middle, bottom) compared whole."""
+    values against the oracle's point evaluation of the stretched image, the
+    whole candidate list against the candidate rule on the GPU's own stack,
+    and three row bands (top, middle, bottom) compared whole."""
     print("stretch full-size 4096x4096", flush=True)
     img = (synth.sem_tile(1, psf_sigma=2.0) // 2 + 30).astype(np.uint8)
     plan = stretch_plan(4096)
@@ -109,6 +110,7 @@ def test_full_size_sem_tile():
         ref = oracle.log_point(I, SIG10[k], y, x)
         assert abs(st[k, y, x] - ref) <= STACK_TOL * 0.5, (k, y, x, st[k, y, x], ref)
     tau = float(np.float32(0.05))
+    np.testing.assert_array_equal(d.yxk.cpu().numpy().astype(np.int64), own_maxima(st, tau))
     gpu_c = as_set(d.yxk.cpu().numpy())
     m, H = 42, 4096
     for (y0, y1) in [(0, 128), (2048, 2176), (3968, 4096)]:
