@@ -10,7 +10,7 @@ import torch
 import oracle
 from paper_2108_12050_amd import synth
 
-from parity import as_set, compare_candidates
+from parity import as_set, compare_candidates, own_maxima, strip_prune
 
 pytestmark = pytest.mark.gpu
 
@@ -134,7 +134,8 @@ def test_full_size_mixed_batch():
     """64 tiles with sizes drawn from {1024^2, 2048x1536, 3072x2048, 4096^2},
     the batched workload's shapes (8 distinct rendered images, one per size
     class and defocus pair, reused across the 64 descriptors): every tile equals
-    the single-tile path."""
+    the single-tile path, and for every distinct image the blob list is the
+    candidate rule on the GPU's own stack followed by the oracle's prune."""
     from paper_2108_12050_amd import BatchRunner
     print("full-size mixed batch", flush=True)
     shapes = synth.mixed_batch_shapes(0, 64)
@@ -156,6 +157,16 @@ def test_full_size_mixed_batch():
         if k not in ref:
             ref[k] = plan.detect(im)
         same(g, ref[k])
+    plan_c = plan_f32(max_hw=4096, overlap=1.0)
+    tau = float(np.float32(0.1))
+    for im in {t.data_ptr(): t for t in imgs}.values():
+        print(f"whole-tile rule {tuple(im.shape)}", flush=True)
+        dc = plan_c.detect(im, return_stack=True)
+        cand = dc.yxk.cpu().numpy().astype(np.int64)
+        np.testing.assert_array_equal(cand, own_maxima(dc.stack.cpu().numpy(), tau))
+        del dc
+        kept = ref[im.data_ptr()].yxk.cpu().numpy().astype(np.int64)
+        np.testing.assert_array_equal(kept, strip_prune(cand, SIG10, 0.5, int(im.shape[0])))
 
 
 def test_u8_graph_replay_and_full_size_batch():
