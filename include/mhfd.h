@@ -104,11 +104,13 @@ typedef struct mhfd_result {
 /*
  * Detection criterion of a plan.
  *   LOG  the scale-normalised LoG stack and its 3x3x3 window maxima above
- *        the threshold, then overlap pruning (the default; readings R1, R6).
- *   DOG  the paper's own criterion (section 4, equations "dog" and
- *        "argmax", Algorithm 1): Gaussian planes L_k at the K scales;
- *        DoG_i = t_i (L_{i+1} - L_i) for i < K - 1; per pixel the largest
- *        DoG over scale and its first argmax i; a blob at every pixel whose
+ *        the threshold, then overlap pruning (the default: the exact
+ *        Laplacian that the DoG approximates, with local maxima in scale).
+ *   DOG  the paper's own criterion (equation "dog" of section 2.2,
+ *        equation "argmax" and Algorithm 1 of section 3): Gaussian
+ *        planes L_k at the K scales; DoG_i = t_i (L_{i+1} - L_i) for
+ *        i < K - 1; per pixel the largest DoG over scale and its first
+ *        argmax i; a blob at every pixel whose
  *        largest DoG exceeds the threshold and equals the maximum of its
  *        3x3 neighbourhood (clipped at the border).  Records carry k = that
  *        argmax and sigma_k.  Needs K >= 2, every radius <= 56 (matrix-core
@@ -201,7 +203,7 @@ mhfd_status mhfd_log_stack(mhfd_plan plan, const void *d_img, int32_t h, int32_t
                            float *d_stack, void *d_ws, size_t ws_bytes, void *stream);
 
 /*
- * Histogram stretch levels of one 8-bit image (section 4; Algorithm 1, first
+ * Histogram stretch levels of one 8-bit image (section 3; Algorithm 1, first
  * step: 0.175% of the pixels saturated at each end).  With N = h w and
  * q = 0.00175 N, low is the smallest code v with at least q pixels <= v and
  * high the largest code with at least q pixels >= v (compared exactly in

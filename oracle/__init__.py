@@ -233,7 +233,7 @@ def prune(ykx, sigmas, theta: float) -> np.ndarray:
 
 
 def stretch_levels(img: np.ndarray):
-    """(low, high, hist) of the histogram stretch of an 8-bit image (section 4,
+    """(low, high, hist) of the histogram stretch of an 8-bit image (section 3,
     Algorithm 1 first step; 0.175% saturated at each end)."""
     a = np.ascontiguousarray(img, dtype=np.uint8)
     H, W = a.shape

@@ -33,18 +33,19 @@
  *     generalised from "local in space, global in scale" to local in both)
  *     and whose response is strictly above the threshold;
  *   - overlap pruning is one-shot dominance with blob radius sqrt(2)*sigma;
- *   - the histogram stretch of section 4 (Algorithm 1, first step) on 8-bit
+ *   - the histogram stretch of section 3 (Algorithm 1, first step) on 8-bit
  *     images saturates the darkest and the lightest 0.175% of the pixels:
  *     with q = 0.00175 N, the low level is the smallest code v with at
  *     least q pixels <= v and the high level the largest code with at least
  *     q pixels >= v; codes map to clip((v - low) / (high - low), 0, 1), and
  *     to 0 when high = low.  Counts are compared with q exactly, in
  *     integers: count >= 0.00175 N  <=>  100000 count >= 175 N;
- *   - the paper's own criterion (section 4, equations "dog" and "argmax",
- *     Algorithm 1): Gaussian planes L_i = G_{t_i} * I on the same sampled,
- *     truncated, reflected kernels; DoG_i = t_i (L_{i+1} - L_i) for
- *     i < K - 1; per pixel the largest DoG over scale (the first scale on
- *     ties, as an argmax gives); a pixel counts when that value equals the
+ *   - the paper's own criterion (equation "dog" of section 2.2, equation
+ *     "argmax" and Algorithm 1 of section 3): Gaussian planes
+ *     L_i = G_{t_i} * I on the same sampled, truncated, reflected kernels;
+ *     DoG_i = t_i (L_{i+1} - L_i) for i < K - 1; per pixel the largest DoG
+ *     over scale (the first scale on ties, as an argmax gives); a pixel
+ *     counts when that value equals the
  *     maximum of its 3x3 neighbourhood (maxpool equality, windows clipped
  *     at the image border) and exceeds the threshold.
  */
@@ -546,7 +547,7 @@ void ora_log_adjoint(const double *c, int H, int W, double sigma, double truncat
     free(g); free(h); free(T);
 }
 
-/* Histogram stretch levels of an 8-bit image (section 4; Algorithm 1, first
+/* Histogram stretch levels of an 8-bit image (section 3; Algorithm 1, first
  * step), from the definition: the histogram is counted, then the low level
  * walks up from code 0 and the high level down from 255 until the running
  * count reaches q = 0.00175 N.  hist[256] receives the counts. */

@@ -1,8 +1,9 @@
 // Detection after the LoG stack: 3x3x3 maxima, threshold, compaction into
 // canonical (y, x, k) order, one-shot overlap pruning, blob list.
 //
-//   nms        one wave per (62-column strip, run of rows); a lane owns a
-//              column and walks down the rows.  A voxel is a candidate when
+//   nms        one wave per (strip of 64 CW columns, run of 32 rows); a lane
+//              owns CW adjacent columns and walks down the rows, taking its
+//              neighbours' edge columns by DPP shifts.  A voxel is a candidate when
 //              it equals the maximum of its 3x3x3 window (the maxpool-equality
 //              test of section 3, taken local in scale too) and is above the
 //              threshold.  Counts per lane become in-wave offsets with ballot
@@ -11,9 +12,10 @@
 //   scan       exclusive scan of the per-cell counts in cell order, i.e. in
 //              (y, x) order: the canonical position of every cell's run.
 //   order      copies each run from the pool to its canonical place.
-//   prune      one thread per candidate scans the candidates of the rows
-//              that can reach it (row ranges come from the scan) and applies
-//              the dominance rule with FP64 lens geometry.
+//   prune      one work item per (candidate, row offset) searches that row
+//              (row ranges come from the scan) for a dominating candidate
+//              within the plan's integer overlap distance, the exact form of
+//              the FP64 lens-overlap test.
 //   emit       scan of the keep flags, then the blob records.
 // No step depends on the order in which workgroups run, so the output is
 // deterministic.

@@ -1,6 +1,6 @@
-// The paper's own criterion (section 4, equations "dog" and "argmax";
-// Algorithm 1) on Gaussian planes L_k (K x h x w, from the matrix-core
-// kernel with Gaussian taps):
+// The paper's own criterion (equation "dog" of section 2.2; equation
+// "argmax" and Algorithm 1 of section 3) on Gaussian planes L_k (K x h x w,
+// from the matrix-core kernel with Gaussian taps):
 //
 //   dog     per pixel DoG_i = t_i (L_{i+1} - L_i), i < K - 1, their maximum M
 //           and its first argmax (the inner argmax over scale).  Reads the K

@@ -1,4 +1,4 @@
-// Histogram stretch of 8-bit images (section 4; Algorithm 1, first step):
+// Histogram stretch of 8-bit images (section 3; Algorithm 1, first step):
 // 0.175% of the pixels are saturated at each end and the codes between the
 // two levels are mapped linearly onto [0, 1].
 //

@@ -1,4 +1,4 @@
-"""The paper's own criterion (section 4: DoG of equation "dog", argmax over
+"""The paper's own criterion (section 3: DoG of equation "dog", argmax over
 scale and 3x3 maxpool equality of equation "argmax", the count of
 Algorithm 1) on the GPU against the oracle.  The Gaussian planes the
 matrix-core kernel writes are compared within 1e-5 of each plane's

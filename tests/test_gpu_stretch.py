@@ -1,4 +1,4 @@
-"""Histogram stretch (section 4; Algorithm 1, first step) on the GPU against
+"""Histogram stretch (section 3; Algorithm 1, first step) on the GPU against
 the oracle: levels and histogram bit-exact, the stretched LoG stack within
 1e-5 of each plane's maximum, candidates exact outside the ambiguity
 margin, at small sizes and on the full 4096^2 SEM tile."""

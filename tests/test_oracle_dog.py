@@ -1,5 +1,5 @@
 """Pins of the oracle's Gaussian planes and of the paper's own criterion
-(section 4: DoG of equation "dog", argmax over scale and 3x3 maxpool
+(section 3: DoG of equation "dog", argmax over scale and 3x3 maxpool
 equality of equation "argmax", the count of Algorithm 1), against
 independent libraries and closed forms."""
 import numpy as np

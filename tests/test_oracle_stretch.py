@@ -1,4 +1,4 @@
-"""Pins of the oracle's histogram stretch (section 4; Algorithm 1, first
+"""Pins of the oracle's histogram stretch (section 3; Algorithm 1, first
 step: 0.175% of the pixels saturated at each end, the rest mapped linearly
 to [0, 1]), against definitions that do not go through its histogram walk:
 order statistics of the sorted pixels, saturation counts, a hand-built
