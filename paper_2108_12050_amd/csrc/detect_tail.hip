@@ -1,7 +1,7 @@
 // Detection after the LoG stack: 3x3x3 maxima, threshold, compaction into
 // canonical (y, x, k) order, one-shot overlap pruning, blob list.
 //
-//   nms        one wave per (strip of 64 CW columns, run of 32 rows); a lane
+//   nms        one wave per (strip of 64 CW columns, run of 16 rows); a lane
 //              owns CW adjacent columns and walks down the rows, taking its
 //              neighbours' edge columns by DPP shifts.  A voxel is a candidate when
 //              it equals the maximum of its 3x3x3 window (the maxpool-equality

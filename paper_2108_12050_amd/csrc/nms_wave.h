@@ -10,7 +10,7 @@
 namespace mhfd {
 namespace nms {
 
-constexpr int ROWS = 32;  // rows per wave
+constexpr int ROWS = 16;  // rows per wave
 
 __device__ __forceinline__ float fmax3(float a, float b, float c) { return fmaxf(a, fmaxf(b, c)); }
 
