@@ -112,7 +112,7 @@ def bench_stretch(imgs, ws_bytes: int, cap: int, warmup: int) -> dict:
     L = _lib.load()
     ws = torch.empty(plan.detect_workspace_bytes(H, W), dtype=torch.uint8, device="cuda")
     raw = torch.empty((cap, 5), dtype=torch.int32, device="cuda")
-    res = torch.zeros(3, dtype=torch.int64, device="cuda")
+    res = torch.zeros(_lib.RESULT_WORDS, dtype=torch.int64, device="cuda")
     sptr = int(torch.cuda.current_stream().cuda_stream)
 
     def detect(i):
@@ -170,7 +170,7 @@ def bench_dog(imgs, cap: int, warmup: int) -> dict:
     ws = torch.empty(plan.detect_workspace_bytes(H, W), dtype=torch.uint8, device="cuda")
     stack = torch.empty((K, H, W), dtype=torch.float32, device="cuda")
     raw = torch.empty((cap, 5), dtype=torch.int32, device="cuda")
-    res = torch.zeros(3, dtype=torch.int64, device="cuda")
+    res = torch.zeros(_lib.RESULT_WORDS, dtype=torch.int64, device="cuda")
     sptr = int(torch.cuda.current_stream().cuda_stream)
 
     def detect(i):
@@ -240,7 +240,7 @@ def bench_batched(warmup: int) -> dict:
     L = _lib.load()
     cap = 1 << 17
     raws = torch.empty((cap, 5), dtype=torch.int32, device="cuda")
-    ress = torch.zeros((64, 3), dtype=torch.int64, device="cuda")
+    ress = torch.zeros((64, _lib.RESULT_WORDS), dtype=torch.int64, device="cuda")
     ws = torch.empty(plan.detect_workspace_bytes(4096, 4096), dtype=torch.uint8, device="cuda")
     sptr = int(torch.cuda.current_stream().cuda_stream)
 
@@ -278,8 +278,8 @@ def bench_soft() -> dict:
     gb = torch.ones(B, device="cuda")
     plan.focus_score(imgs, sig)
     plan.focus_score_backward(imgs, sig, gb)
-    fwd = _timed(lambda: plan.focus_score(imgs, sig), 5)
-    bwd = _timed(lambda: plan.focus_score_backward(imgs, sig, gb), 3)
+    fwd = _timed(lambda: plan.focus_score(imgs, sig, check=False), 5)
+    bwd = _timed(lambda: plan.focus_score_backward(imgs, sig, gb, check=False), 3)
     mp = B * Hs * Ws / 1e6
     return {"workload": "8 x 2048^2 fp32, sigma 1..10 trainable, beta 50, tau 0.05",
             "forward_ms": round(float(np.median(fwd)), 3),
@@ -340,7 +340,7 @@ def traffic_run() -> int:
     stack = torch.empty((K, H, W), dtype=torch.float32, device="cuda")
     cap = H * W // 64
     raw = torch.empty((cap, 5), dtype=torch.int32, device="cuda")
-    res = torch.zeros(3, dtype=torch.int64, device="cuda")
+    res = torch.zeros(_lib.RESULT_WORDS, dtype=torch.int64, device="cuda")
     nb = plan.detect_workspace_bytes(H, W)
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
     sp = int(torch.cuda.current_stream().cuda_stream)

@@ -86,12 +86,14 @@ typedef struct mhfd_blob {
     float response;    /* R_k(y, x) */
 } mhfd_blob;
 
-/* Summary of one detection, written by the device. */
+/* Summary of one detection, written by the device (32 bytes). */
 typedef struct mhfd_result {
     int64_t n_blobs;       /* blobs after pruning: the focus criterion |C| */
     int64_t n_candidates;  /* window maxima above the threshold, before pruning */
     int32_t flags;         /* MHFD_FLAG_* */
     int32_t reserved;
+    double density;        /* n_blobs per megapixel, n_blobs * 1e6 / (h w): the
+                              criterion for tiles of different sizes */
 } mhfd_result;
 
 /* n_blobs exceeds the caller's capacity: only the first `capacity` blobs of
@@ -143,6 +145,11 @@ typedef struct mhfd_config {
                                 batched and focus-score calls refuse such a
                                 plan (MHFD_ERR_UNSUPPORTED).  0: no stretch    */
     int32_t criterion;       /* MHFD_CRITERION_LOG (0) or MHFD_CRITERION_DOG (1) */
+    float sigma_cap;         /* largest sigma a focus-score call may be given
+                                (trainable scales); its radius floor(truncate *
+                                sigma_cap + 0.5) <= MHFD_MAX_RADIUS sizes the
+                                halos of those calls.  0: the plan's largest
+                                sigma.  Must be >= every sigma of the plan     */
 } mhfd_config;
 
 typedef struct mhfd_plan_s *mhfd_plan;
@@ -272,32 +279,45 @@ mhfd_status mhfd_detect_batched(mhfd_plan plan, int32_t n, const mhfd_tile *d_ti
  * batch of b images of h x w (0 on bad input). */
 size_t mhfd_focus_workspace_size(mhfd_plan plan, int32_t b, int32_t h, int32_t w);
 
+/* A sigma given to a focus-score call lies outside (0, sigma_cap] or is not
+ * finite: that call's scores and gradients are not valid. */
+#define MHFD_FOCUS_BAD_SIGMA 1
+
 /*
  * Soft focus score of b float images (b x h x w, dense).
- *   d_sigmas  K device floats, the current (trainable) scales.  The kernel
- *             radius of scale k stays the plan's: the support is frozen and
- *             the score is smooth in sigma for that support.  Each sigma
- *             must be positive; a non-positive or non-finite sigma makes every
- *             score NaN.
+ *   d_sigmas  K device floats, the current (trainable) scales.  Each call
+ *             derives every scale's taps and kernel radius
+ *             floor(truncate * sigma_k + 0.5) on the device from these values
+ *             (section 2.2's sampled Gaussian at the current sigma, truncated
+ *             as the plan's own scales are); the score is smooth in sigma
+ *             between the sigmas where a radius changes.  The halos are sized
+ *             for the plan's sigma_cap.
  *   d_scores  b floats, overwritten with S_b.
+ *   d_error   optional device int32 (may be NULL), overwritten with 0 or
+ *             MHFD_FOCUS_BAD_SIGMA when some sigma is not in (0, sigma_cap]
+ *             (that scale's taps are then zero).  The host cannot see device
+ *             values without waiting, so this is the call's only report of
+ *             a bad sigma; read it after the stream has passed the call.
  * Requires 1 <= h <= max_h, 1 <= w <= max_w, b >= 1; beta > 0.
  */
 mhfd_status mhfd_focus_score(mhfd_plan plan, const float *d_imgs, int32_t b, int32_t h, int32_t w,
                              const float *d_sigmas, float beta, float tau, float *d_scores,
-                             void *d_ws, size_t ws_bytes, void *stream);
+                             int32_t *d_error, void *d_ws, size_t ws_bytes, void *stream);
 
 /*
  * Gradient of sum_b d_grad_scores[b] * S_b.
  *   d_grad_imgs    b x h x w floats, overwritten with the image gradient.
- *   d_grad_sigmas  K floats, overwritten with the sigma gradient.
+ *   d_grad_sigmas  K floats, overwritten with the sigma gradient: the
+ *                  derivative at the radii of the current sigmas (the radius
+ *                  is piecewise constant in sigma).
  * The stack is recomputed per scale; nothing from the forward call is kept.
- * Same arguments and requirements as mhfd_focus_score.
+ * Same arguments, requirements and d_error report as mhfd_focus_score.
  */
 mhfd_status mhfd_focus_score_backward(mhfd_plan plan, const float *d_imgs, int32_t b, int32_t h,
                                       int32_t w, const float *d_sigmas, float beta, float tau,
                                       const float *d_grad_scores, float *d_grad_imgs,
-                                      float *d_grad_sigmas, void *d_ws, size_t ws_bytes,
-                                      void *stream);
+                                      float *d_grad_sigmas, int32_t *d_error, void *d_ws,
+                                      size_t ws_bytes, void *stream);
 
 /* Static text for a status code. */
 const char *mhfd_status_string(mhfd_status status);

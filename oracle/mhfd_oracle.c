@@ -297,6 +297,7 @@ long ora_candidates(const double *st, int K, int H, int W, double tau,
 long ora_ambiguous(const double *st, int K, int H, int W, double tau, double eps, uint8_t *mask)
 {
     long n = 0;
+#pragma omp parallel for collapse(2) reduction(+ : n) schedule(static)
     for (int k = 0; k < K; ++k)
         for (int y = 0; y < H; ++y)
             for (int x = 0; x < W; ++x) {

@@ -51,7 +51,8 @@ class Config(C.Structure):
                 ("sigmas", C.POINTER(C.c_float)), ("truncate", C.c_float),
                 ("threshold", C.c_float), ("overlap", C.c_float), ("polarity", C.c_int32),
                 ("in_dtype", C.c_int32), ("max_h", C.c_int32), ("max_w", C.c_int32),
-                ("max_candidates", C.c_int64), ("stretch", C.c_int32), ("criterion", C.c_int32)]
+                ("max_candidates", C.c_int64), ("stretch", C.c_int32), ("criterion", C.c_int32),
+                ("sigma_cap", C.c_float)]
 
 
 class Blob(C.Structure):
@@ -67,10 +68,15 @@ class Tile(C.Structure):
 
 class Result(C.Structure):
     _fields_ = [("n_blobs", C.c_int64), ("n_candidates", C.c_int64), ("flags", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("reserved", C.c_int32), ("density", C.c_double)]
 
 
-assert C.sizeof(Blob) == 20 and C.sizeof(Result) == 24 and C.sizeof(Tile) == 48
+# mhfd_result as int64 words: n_blobs, n_candidates, flags (low 32 bits),
+# density (the bits of a double)
+RESULT_WORDS = 4
+MHFD_FOCUS_BAD_SIGMA = 1
+
+assert C.sizeof(Blob) == 20 and C.sizeof(Result) == 8 * RESULT_WORDS and C.sizeof(Tile) == 48
 
 _lib = None
 
@@ -113,10 +119,10 @@ def load(path: str | None = None):
     L.mhfd_detect_batched.restype = C.c_int
     L.mhfd_focus_workspace_size.argtypes = [vp, i32, i32, i32]
     L.mhfd_focus_workspace_size.restype = sz
-    L.mhfd_focus_score.argtypes = [vp, vp, i32, i32, i32, vp, f32, f32, vp, vp, sz, vp]
+    L.mhfd_focus_score.argtypes = [vp, vp, i32, i32, i32, vp, f32, f32, vp, vp, vp, sz, vp]
     L.mhfd_focus_score.restype = C.c_int
     L.mhfd_focus_score_backward.argtypes = [vp, vp, i32, i32, i32, vp, f32, f32, vp, vp, vp,
-                                            vp, sz, vp]
+                                            vp, vp, sz, vp]
     L.mhfd_focus_score_backward.restype = C.c_int
     L.mhfd_status_string.argtypes = [C.c_int]
     L.mhfd_status_string.restype = C.c_char_p

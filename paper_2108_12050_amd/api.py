@@ -37,11 +37,16 @@ class Detection:
 
     @property
     def density(self) -> float:
-        """Blobs per megapixel (set by Plan.detect)."""
+        """Blobs per megapixel, as the library reports it (mhfd_result)."""
         return self._density
 
     def numpy(self):
         return (self.yxk.cpu().numpy(), self.sigma.cpu().numpy(), self.response.cpu().numpy())
+
+
+def result_density(words: torch.Tensor) -> float:
+    """The density field of one mhfd_result held as int64 words (host)."""
+    return float(words[3:4].view(torch.float64)[0])
 
 
 def split_blobs(raw: torch.Tensor, n: int):
@@ -62,7 +67,7 @@ class Plan:
                  sigmas=None, truncate: float = 4.0, threshold: float = 0.1,
                  overlap: float = 0.5, polarity: str = "bright", dtype: str = "f32",
                  max_h: int = 4096, max_w: int = 4096, max_candidates: int = 0,
-                 stretch: bool = False, criterion: str = "log"):
+                 stretch: bool = False, criterion: str = "log", sigma_cap: float | None = None):
         self._L = _lib.load()
         self._handle = None
         cfg = _lib.Config()
@@ -82,6 +87,7 @@ class Plan:
         cfg.max_candidates = int(max_candidates)
         cfg.stretch = 1 if stretch else 0
         cfg.criterion = {"log": _lib.MHFD_CRITERION_LOG, "dog": _lib.MHFD_CRITERION_DOG}[criterion]
+        cfg.sigma_cap = 0.0 if sigma_cap is None else float(sigma_cap)
         h = C.c_void_p()
         _lib.check(self._L.mhfd_create_plan(C.byref(cfg), C.byref(h)), "mhfd_create_plan")
         self._handle = h
@@ -98,7 +104,9 @@ class Plan:
         self.max_h, self.max_w = int(max_h), int(max_w)
         self.stretch = bool(stretch)
         self.criterion = criterion
+        self.sigma_cap = float(sigma_cap) if sigma_cap else max(self.sigmas)
         self._ws = {}
+        self._focus_err = None
 
     def close(self):
         if self._handle is not None:
@@ -134,8 +142,8 @@ class Plan:
                     stack: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
                     stream=None) -> None:
         """Enqueue mhfd_detect without synchronising.  ``blobs_raw`` is an
-        int32 [capacity, 5] tensor, ``result`` an int64 [3] tensor
-        (n_blobs, n_candidates, flags)."""
+        int32 [capacity, 5] tensor, ``result`` an int64 [4] tensor holding
+        one mhfd_result (n_blobs, n_candidates, flags, density bits)."""
         if img.dim() != 2:
             raise ValueError("image must be 2-D")
         want = torch.uint8 if self.dtype == "u8" else torch.float32
@@ -146,8 +154,8 @@ class Plan:
         h, w = img.shape
         if blobs_raw.dtype != torch.int32 or blobs_raw.dim() != 2 or blobs_raw.shape[1] != 5:
             raise ValueError("blobs_raw must be int32 [capacity, 5]")
-        if result.dtype != torch.int64 or result.numel() < 3:
-            raise ValueError("result must be int64 [3]")
+        if result.dtype != torch.int64 or result.numel() < _lib.RESULT_WORDS:
+            raise ValueError(f"result must be int64 [{_lib.RESULT_WORDS}]")
         if stack is not None and (stack.dtype != torch.float32 or not stack.is_contiguous()
                                   or stack.numel() != self.K * h * w):
             raise ValueError("stack must be a contiguous float32 [K, h, w] tensor")
@@ -165,11 +173,36 @@ class Plan:
         if capacity is None:
             capacity = max(1024, h * w // 64)
         raw = torch.empty((capacity, 5), dtype=torch.int32, device=self.device)
-        res = torch.zeros(3, dtype=torch.int64, device=self.device)
+        res = torch.zeros(_lib.RESULT_WORDS, dtype=torch.int64, device=self.device)
         stack = (torch.empty((self.K, h, w), dtype=torch.float32, device=self.device)
                  if return_stack else None)
         self.detect_into(img, raw, res, stack, stream=stream)
-        r = res.cpu().tolist()
+        return self._finish(raw, res, capacity, h, w, stack)
+
+    def detect_stack(self, stack: torch.Tensor, capacity: int | None = None,
+                     stream=None) -> Detection:
+        """The detector after the stack (mhfd_detect_stack) on a caller-held
+        float32 [K, h, w] stack: window maxima, threshold, canonical list,
+        pruning and count.  Waits for the result."""
+        if (stack.dim() != 3 or stack.shape[0] != self.K or stack.dtype != torch.float32
+                or not stack.is_contiguous() or stack.device != self.device):
+            raise ValueError(f"stack must be a contiguous float32 [{self.K}, h, w] tensor on "
+                             f"{self.device}")
+        _, h, w = stack.shape
+        if capacity is None:
+            capacity = max(1024, h * w // 64)
+        raw = torch.empty((capacity, 5), dtype=torch.int32, device=self.device)
+        res = torch.zeros(_lib.RESULT_WORDS, dtype=torch.int64, device=self.device)
+        nbytes = self.detect_workspace_bytes(h, w)
+        ws = self._workspace(("detect", h, w), nbytes)
+        st = self._L.mhfd_detect_stack(self._handle, _ptr(stack), h, w, _ptr(raw), capacity,
+                                       _ptr(res), _ptr(ws), ws.numel(), _stream_ptr(stream))
+        _lib.check(st, "mhfd_detect_stack")
+        return self._finish(raw, res, capacity, h, w, stack)
+
+    def _finish(self, raw, res, capacity, h, w, stack) -> Detection:
+        host = res.cpu()
+        r = host.tolist()
         n_blobs, n_cand, flags = int(r[0]), int(r[1]), int(r[2]) & 0xFFFFFFFF
         if flags & _lib.MHFD_FLAG_CAND_OVERFLOW:
             raise RuntimeError(f"{n_cand} candidates exceed the plan's candidate capacity; "
@@ -177,7 +210,7 @@ class Plan:
         n = min(n_blobs, capacity)
         yxk, sig, resp = split_blobs(raw, n)
         d = Detection(yxk, sig, resp, n_blobs, n_cand, flags, stack)
-        d._density = n_blobs * 1e6 / (h * w)
+        d._density = result_density(host)
         return d
 
     # ---------------------------------------------------------------- soft score
@@ -198,23 +231,46 @@ class Plan:
             raise ValueError(f"sigmas must be float32 [{self.K}] on {self.device}")
         return imgs.contiguous(), sigmas.contiguous()
 
+    def _error_word(self) -> torch.Tensor:
+        if self._focus_err is None:
+            self._focus_err = torch.zeros(1, dtype=torch.int32, device=self.device)
+        return self._focus_err
+
+    def check_focus_error(self, stream=None) -> None:
+        """Wait for `stream` and raise if the last focus-score call on it was
+        given a sigma outside (0, sigma_cap]."""
+        if self._focus_err is None:
+            return
+        s = stream if stream is not None else torch.cuda.current_stream()
+        s.synchronize()
+        if int(self._focus_err.item()) & _lib.MHFD_FOCUS_BAD_SIGMA:
+            raise _lib.MHFDError(1, "mhfd_focus_score",
+                                 f"a sigma lies outside (0, sigma_cap = {self.sigma_cap}]")
+
     def focus_score(self, imgs: torch.Tensor, sigmas: torch.Tensor, beta: float = 50.0,
-                    tau: float = 0.05, stream=None) -> torch.Tensor:
-        """S_b (float32 [B]) for device images [B, H, W]; no synchronisation."""
+                    tau: float = 0.05, stream=None, check: bool = True) -> torch.Tensor:
+        """S_b (float32 [B]) for device images [B, H, W].  The library reports
+        a sigma outside (0, sigma_cap] in a device word; with ``check`` the
+        call waits for it and raises, otherwise it returns at once and
+        ``check_focus_error`` reads the word later."""
         imgs, sigmas = self._check_soft(imgs, sigmas)
         B, h, w = imgs.shape
         ws = self._workspace(("focus", B, h, w), self.focus_workspace_bytes(B, h, w))
         out = torch.empty(B, dtype=torch.float32, device=self.device)
         st = self._L.mhfd_focus_score(self._handle, _ptr(imgs), B, h, w, _ptr(sigmas),
-                                      float(beta), float(tau), _ptr(out), _ptr(ws), ws.numel(),
+                                      float(beta), float(tau), _ptr(out),
+                                      _ptr(self._error_word()), _ptr(ws), ws.numel(),
                                       _stream_ptr(stream))
         _lib.check(st, "mhfd_focus_score")
+        if check:
+            self.check_focus_error(stream)
         return out
 
     def focus_score_backward(self, imgs: torch.Tensor, sigmas: torch.Tensor,
                              grad_scores: torch.Tensor, beta: float = 50.0, tau: float = 0.05,
-                             stream=None):
-        """(dS/dI, dS/dsigma) contracted with grad_scores [B]; no synchronisation."""
+                             stream=None, check: bool = True):
+        """(dS/dI, dS/dsigma) contracted with grad_scores [B]; ``check`` as
+        for focus_score."""
         imgs, sigmas = self._check_soft(imgs, sigmas)
         B, h, w = imgs.shape
         g = grad_scores.to(device=self.device, dtype=torch.float32).contiguous().reshape(B)
@@ -223,9 +279,11 @@ class Plan:
         ds = torch.empty(self.K, dtype=torch.float32, device=self.device)
         st = self._L.mhfd_focus_score_backward(self._handle, _ptr(imgs), B, h, w, _ptr(sigmas),
                                                float(beta), float(tau), _ptr(g), _ptr(dI),
-                                               _ptr(ds), _ptr(ws), ws.numel(),
-                                               _stream_ptr(stream))
+                                               _ptr(ds), _ptr(self._error_word()), _ptr(ws),
+                                               ws.numel(), _stream_ptr(stream))
         _lib.check(st, "mhfd_focus_score_backward")
+        if check:
+            self.check_focus_error(stream)
         return dI, ds
 
 
@@ -273,5 +331,7 @@ class FocusScore(torch.autograd.Function):
 def focus_score(imgs: torch.Tensor, sigmas: torch.Tensor, plan: Plan, beta: float = 50.0,
                 tau: float = 0.05) -> torch.Tensor:
     """S_b = mean over scales and pixels of softplus(beta (|sigma^2 Lap(G_sigma * I)| - tau)),
-    differentiable in the images and the sigmas (radii frozen at the plan's)."""
+    differentiable in the images and the sigmas; each call takes every
+    scale's radius floor(truncate sigma + 0.5) from the current sigma and
+    raises if a sigma leaves (0, plan.sigma_cap]."""
     return FocusScore.apply(imgs, sigmas, plan, float(beta), float(tau))

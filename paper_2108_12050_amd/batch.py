@@ -14,7 +14,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from .api import Detection, Plan, _stream_ptr, split_blobs
+from .api import Detection, Plan, _stream_ptr, result_density, split_blobs
 
 TILE_DTYPE = np.dtype([("img", "<u8"), ("h", "<i4"), ("w", "<i4"), ("pitch", "<i8"),
                        ("blobs", "<u8"), ("result", "<u8"), ("capacity", "<i4"),
@@ -39,7 +39,8 @@ class BatchRunner:
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
         self.table = torch.zeros(self.max_tiles * TILE_DTYPE.itemsize, dtype=torch.uint8, device=dev)
         self.blobs = torch.empty((self.max_tiles, self.capacity, 5), dtype=torch.int32, device=dev)
-        self.results = torch.zeros((self.max_tiles, 3), dtype=torch.int64, device=dev)
+        self.results = torch.zeros((self.max_tiles, _lib.RESULT_WORDS), dtype=torch.int64,
+                                   device=dev)
         self.n = 0
         self._imgs = []
 
@@ -92,9 +93,10 @@ class BatchRunner:
 
     def detections(self) -> list:
         """Per-tile results of the last run (synchronises)."""
-        res = self.results[: self.n].cpu().tolist()
+        host = self.results[: self.n].cpu()
+        res = host.tolist()
         out = []
-        for i, (nb, nc, fl) in enumerate(res):
+        for i, (nb, nc, fl, _) in enumerate(res):
             fl &= 0xFFFFFFFF
             if fl & _lib.MHFD_FLAG_INVALID_TILE:
                 raise _lib.MHFDError(1, "mhfd_detect_batched", "a tile descriptor failed the "
@@ -103,8 +105,7 @@ class BatchRunner:
                 raise RuntimeError("candidate capacity overflow in the batch")
             yxk, sig, resp = split_blobs(self.blobs[i], min(nb, self.capacity))
             d = Detection(yxk, sig, resp, nb, nc, fl)
-            h, w = self._imgs[i].shape
-            d._density = nb * 1e6 / (h * w)
+            d._density = result_density(host[i])
             out.append(d)
         return out
 

@@ -166,6 +166,7 @@ __global__ __launch_bounds__(SETUP_T) void batch_setup_kernel(
                 r->n_candidates = 0;
                 r->flags = MHFD_FLAG_INVALID_TILE;
                 r->reserved = 0;
+                r->density = 0.0;
             }
         }
     }
@@ -333,6 +334,7 @@ __global__ void results_batch_kernel(const int32_t* __restrict__ blk_off,
         T.result->n_candidates = ce - cb;
         T.result->flags = flags;
         T.result->reserved = 0;
+        T.result->density = static_cast<double>(nb) * 1e6 / (static_cast<double>(T.h) * T.w);
     }
 }
 

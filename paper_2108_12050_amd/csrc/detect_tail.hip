@@ -337,7 +337,8 @@ __global__ void prune_rows_kernel(const Cand* __restrict__ cand,
 __global__ void emit_kernel(const Cand* __restrict__ cand, const int32_t* __restrict__ keep,
                             const int32_t* __restrict__ keep_off, const float* __restrict__ sigmas,
                             mhfd_blob* __restrict__ blobs, int capacity, int64_t cap,
-                            DetectCounters* __restrict__ ctr, mhfd_result* __restrict__ result) {
+                            double pixels, DetectCounters* __restrict__ ctr,
+                            mhfd_result* __restrict__ result) {
     const int64_t n = min(static_cast<int64_t>(ctr->n_cand), cap);
     for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
@@ -362,6 +363,7 @@ __global__ void emit_kernel(const Cand* __restrict__ cand, const int32_t* __rest
         result->n_candidates = ctr->n_cand;
         result->flags = flags;
         result->reserved = 0;
+        result->density = static_cast<double>(nb) * 1e6 / pixels;
     }
 }
 
@@ -406,7 +408,7 @@ hipError_t launch_detect_tail(const DetectWorkspace& ws, int K, int h, int w, fl
     launch_scan(ws.keep, static_cast<int>(ws.cap), &ws.ctr->n_cand, ws.scan_sums, ws.keep_off,
                 &ws.ctr->n_blobs, s);
     emit_kernel<<<grid, 256, 0, s>>>(ws.cand, ws.keep, ws.keep_off, sigmas_dev, blobs, capacity,
-                                     ws.cap, ws.ctr, result);
+                                     ws.cap, static_cast<double>(h) * w, ws.ctr, result);
     return hipGetLastError();
 }
 

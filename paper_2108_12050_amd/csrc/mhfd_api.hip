@@ -37,6 +37,8 @@ struct mhfd_plan_s {
     uint16_t* d_frags = nullptr;
     int stretch = 0;             // histogram stretch before the stack (u8 plans)
     int criterion = MHFD_CRITERION_LOG;  // DOG: the stack holds Gaussian planes
+    float sigma_cap = 0.0f;      // largest sigma a focus-score call may take
+    int padded_cap = 0;          // padded radius of sigma_cap: the focus-score halos
 };
 
 namespace {
@@ -228,6 +230,8 @@ mhfd_status mhfd_create_plan(const mhfd_config* cfg, mhfd_plan* out) {
         return fail(MHFD_ERR_INVALID_ARG, "stretch must be 0 or 1");
     if (cfg->stretch && cfg->in_dtype != MHFD_U8)
         return fail(MHFD_ERR_UNSUPPORTED, "the histogram stretch is built for 8-bit plans");
+    if (!(cfg->sigma_cap >= 0.0f) || !isfinite(cfg->sigma_cap))
+        return fail(MHFD_ERR_INVALID_ARG, "sigma_cap must be >= 0 and finite");
 
     std::vector<float> sig(K);
     if (cfg->sigmas) {
@@ -288,6 +292,20 @@ mhfd_status mhfd_create_plan(const mhfd_config* cfg, mhfd_plan* out) {
         off += mhfd::tap_block_floats(P);
     }
     p->tap_floats = off;
+    {
+        const float cap = cfg->sigma_cap > 0.0f ? cfg->sigma_cap : sig[K - 1];
+        const double rc = floor(static_cast<double>(p->truncate) * cap + 0.5);
+        if (!isfinite(cap) || cap < sig[K - 1] || rc > MHFD_MAX_RADIUS) {
+            delete p;
+            return fail(cap < sig[K - 1] ? MHFD_ERR_INVALID_ARG : MHFD_ERR_UNSUPPORTED,
+                        "sigma_cap %g must be finite, >= the largest sigma %g and give a radius "
+                        "<= %d", static_cast<double>(cap), static_cast<double>(sig[K - 1]),
+                        MHFD_MAX_RADIUS);
+        }
+        p->sigma_cap = cap;
+        const int rcap = static_cast<int>(rc);
+        p->padded_cap = mhfd::padded_radius(rcap < 1 ? 1 : rcap);
+    }
     // Blob radius sqrt(2) sigma; prune table in double.
     std::vector<int32_t> d2(static_cast<size_t>(K) * K, -1);
     int d2_top = 0;
@@ -435,10 +453,10 @@ mhfd_status check_outputs(const mhfd_plan_s* p, int32_t h, int32_t w, const mhfd
 // results, so a scale gets about 16R rows per workgroup (halo overhead near
 // 10%), halved while the launch would have fewer than ~3 workgroups per
 // resident slot.
-template <typename TapOff, typename Plane>
+template <typename TapOff, typename Plane, typename Pad>
 std::vector<std::pair<int, mhfd::StackLaunch>> make_launches(const mhfd_plan_s* p, int h, int w,
                                                              const std::vector<int>& scales,
-                                                             TapOff tap_off, Plane plane) {
+                                                             TapOff tap_off, Plane plane, Pad pad) {
     const int tw = mhfd::log_strip_width();
     const int ch = mhfd::log_chunk_rows();
     const int strips = (w + tw - 1) / tw;
@@ -447,15 +465,15 @@ std::vector<std::pair<int, mhfd::StackLaunch>> make_launches(const mhfd_plan_s* 
     for (int cls = 2; cls >= 0; --cls) {
         std::vector<int> ks;
         for (int k : scales)
-            if (mhfd::log_radius_class(p->padded[k]) == cls) ks.push_back(k);
+            if (mhfd::log_radius_class(pad(k)) == cls) ks.push_back(k);
         if (ks.empty()) continue;
         std::sort(ks.begin(), ks.end(), [&](int a, int b) {
-            return p->padded[a] != p->padded[b] ? p->padded[a] > p->padded[b] : a < b;
+            return pad(a) != pad(b) ? pad(a) > pad(b) : a < b;
         });
         const int hr = (h + ch - 1) / ch * ch;
         std::vector<int> seg(ks.size());
         for (size_t i = 0; i < ks.size(); ++i) {
-            int sgr = 16 * p->padded[ks[i]];
+            int sgr = 16 * pad(ks[i]);
             sgr = sgr < 2 * ch ? 2 * ch : (sgr > 1024 ? 1024 : sgr);
             sgr = (sgr + ch - 1) / ch * ch;
             seg[i] = sgr < hr ? sgr : hr;
@@ -480,7 +498,7 @@ std::vector<std::pair<int, mhfd::StackLaunch>> make_launches(const mhfd_plan_s* 
         for (size_t i = 0; i < ks.size(); ++i) {
             const int k = ks[i];
             mhfd::StackScale& sc = L.sc[L.n++];
-            sc.radius = p->padded[k];
+            sc.radius = pad(k);
             sc.tap_off = tap_off(k);
             sc.plane = plane(k);
             sc.seg_rows = seg[i];
@@ -611,7 +629,8 @@ mhfd_status enqueue_log_stack(const mhfd_plan_s* p, const void* d_img, int h, in
         if (e != hipSuccess) return hip_fail(e, "LoG stack (matrix cores) launch");
     }
     auto launches = make_launches(
-        p, h, w, strip_scales, [&](int k) { return p->tap_off[k]; }, [](int k) { return k; });
+        p, h, w, strip_scales, [&](int k) { return p->tap_off[k]; }, [](int k) { return k; },
+        [&](int k) { return p->padded[k]; });
     mhfd::StackIO io{};
     io.out = stack;
     io.plane_stride = static_cast<long long>(h) * w;
@@ -670,15 +689,17 @@ struct FocusLayout {
 FocusLayout focus_layout(const mhfd_plan_s* p, int b, int h, int w) {
     FocusLayout F{};
     F.lay.K = p->K;
+    F.lay.padded = p->padded_cap;
+    F.lay.truncate = p->truncate;
+    F.lay.sigma_cap = p->sigma_cap;
     int off = 0;
     for (int k = 0; k < p->K; ++k) {
-        F.lay.radius[k] = p->radii[k];
-        F.lay.padded[k] = p->padded[k];
         F.lay.offset[k] = off;
-        off += mhfd::SOFT_SETS * 4 * (p->padded[k] + 1);
+        off += mhfd::SOFT_SETS * 4 * (p->padded_cap + 1);
     }
     auto launches = make_launches(
-        p, h, w, all_scales(p), [](int) { return 0; }, [](int k) { return k; });
+        p, h, w, all_scales(p), [](int) { return 0; }, [](int k) { return k; },
+        [&](int) { return p->padded_cap; });
     F.fwd_blocks = 0;
     for (auto& cl : launches) F.fwd_blocks += launch_blocks(cl.second);
     size_t o = 0;
@@ -954,7 +975,7 @@ size_t mhfd_focus_workspace_size(mhfd_plan p, int32_t b, int32_t h, int32_t w) {
 
 mhfd_status mhfd_focus_score(mhfd_plan p, const float* d_imgs, int32_t b, int32_t h, int32_t w,
                              const float* d_sigmas, float beta, float tau, float* d_scores,
-                             void* d_ws, size_t ws_bytes, void* stream) {
+                             int32_t* d_error, void* d_ws, size_t ws_bytes, void* stream) {
     g_last_error.clear();
     mhfd_status st = check_focus(p, d_imgs, b, h, w, d_sigmas, beta, tau, d_ws, ws_bytes);
     if (st != MHFD_OK) return st;
@@ -965,11 +986,12 @@ mhfd_status mhfd_focus_score(mhfd_plan p, const float* d_imgs, int32_t b, int32_
     char* base = static_cast<char*>(d_ws);
     float* taps = reinterpret_cast<float*>(base + F.taps);
     double* partial = reinterpret_cast<double*>(base + F.partial);
-    hipError_t e = mhfd::launch_soft_taps(d_sigmas, F.lay, taps, s);
+    hipError_t e = mhfd::launch_soft_taps(d_sigmas, F.lay, taps, d_error, s);
     if (e != hipSuccess) return hip_fail(e, "soft tap synthesis");
+    const int P = p->padded_cap;
     auto launches = make_launches(
-        p, h, w, all_scales(p), [&](int k) { return F.lay.offset[k] + mhfd::SOFT_FWD * 4 * (p->padded[k] + 1); },
-        [](int k) { return k; });
+        p, h, w, all_scales(p), [&](int k) { return F.lay.offset[k] + mhfd::SOFT_FWD * 4 * (P + 1); },
+        [](int k) { return k; }, [&](int) { return P; });
     mhfd::SoftPartials sp{};
     long long done = 0;
     for (auto& cl : launches) {
@@ -996,8 +1018,8 @@ mhfd_status mhfd_focus_score(mhfd_plan p, const float* d_imgs, int32_t b, int32_
 mhfd_status mhfd_focus_score_backward(mhfd_plan p, const float* d_imgs, int32_t b, int32_t h,
                                       int32_t w, const float* d_sigmas, float beta, float tau,
                                       const float* d_grad_scores, float* d_grad_imgs,
-                                      float* d_grad_sigmas, void* d_ws, size_t ws_bytes,
-                                      void* stream) {
+                                      float* d_grad_sigmas, int32_t* d_error, void* d_ws,
+                                      size_t ws_bytes, void* stream) {
     g_last_error.clear();
     mhfd_status st = check_focus(p, d_imgs, b, h, w, d_sigmas, beta, tau, d_ws, ws_bytes);
     if (st != MHFD_OK) return st;
@@ -1011,7 +1033,8 @@ mhfd_status mhfd_focus_score_backward(mhfd_plan p, const float* d_imgs, int32_t 
     float* rpl = reinterpret_cast<float*>(base + F.rplane);
     float* dpl = reinterpret_cast<float*>(base + F.dplane);
     double* cot = reinterpret_cast<double*>(base + F.cot);
-    hipError_t e = mhfd::launch_soft_taps(d_sigmas, F.lay, taps, s);
+    hipError_t e = mhfd::launch_soft_taps(d_sigmas, F.lay, taps, d_error, s);
+    const int P = p->padded_cap;
     if (e != hipSuccess) return hip_fail(e, "soft tap synthesis");
     const long long npix = static_cast<long long>(h) * w;
     const double inv_khw = 1.0 / (static_cast<double>(p->K) * h * w);
@@ -1020,8 +1043,8 @@ mhfd_status mhfd_focus_score_backward(mhfd_plan p, const float* d_imgs, int32_t 
         const std::vector<int> one{k};
         auto run = [&](int set, int epi, const float* src, float* dst) -> hipError_t {
             auto launches = make_launches(
-                p, h, w, one, [&](int kk) { return F.lay.offset[kk] + set * 4 * (p->padded[kk] + 1); },
-                [](int) { return 0; });
+                p, h, w, one, [&](int kk) { return F.lay.offset[kk] + set * 4 * (P + 1); },
+                [](int) { return 0; }, [&](int) { return P; });
             mhfd::StackIO io{};
             io.img_batch = npix;
             io.out = dst;

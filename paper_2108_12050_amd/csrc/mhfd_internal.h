@@ -285,17 +285,23 @@ void launch_batch_scan(const int32_t* in, int n_host, const int32_t* n_dev, int3
                        int32_t* out, int32_t* total_out, hipStream_t s);
 
 // Device-synthesised taps of the soft focus score: for scale k, four tap sets
-// (FWD, D1, D2, ADJ) of four runs of padded[k] + 1 floats start at offset[k].
+// (FWD, D1, D2, ADJ) of four runs of padded + 1 floats start at offset[k].
+// The radius of scale k, floor(truncate sigma_k + 0.5), comes from the
+// device sigma at each call; taps beyond it are zero.  `padded` is the
+// padded radius of sigma_cap, the launch radius of every scale.
 enum { SOFT_FWD = 0, SOFT_D1 = 1, SOFT_D2 = 2, SOFT_ADJ = 3, SOFT_SETS = 4 };
 struct SoftTapLayout {
     int K;
-    int radius[MHFD_MAX_SCALES];
-    int padded[MHFD_MAX_SCALES];
+    int padded;
+    float truncate;
+    float sigma_cap;
     int offset[MHFD_MAX_SCALES];
 };
 
+// err (optional): 0, or MHFD_FOCUS_BAD_SIGMA when some sigma is outside
+// (0, sigma_cap] (its taps are written as zeros).
 hipError_t launch_soft_taps(const float* sigmas, const SoftTapLayout& lay, float* taps,
-                            hipStream_t s);
+                            int32_t* err, hipStream_t s);
 // Softplus partials of the forward launches: launch c wrote [image][block]
 // (blocks[c] per image) starting at partial + base[c].
 struct SoftPartials {

@@ -74,7 +74,8 @@ struct Sink {
 // image): a 3 x 3 maximum over a window that repeats one of its own members
 // equals the maximum over the members inside the image, which is what the
 // -inf padding of the definition gives.  Lanes past the right edge hold
-// copies of the last columns and report no candidates.
+// the last CW columns, report no candidates and pass column W - 1 on as
+// the right neighbour of the last column inside.
 //
 // Every (row, strip) cell compacts its candidates in (x, k) order with
 // ballot/mbcnt offsets into its own pool slot and reserves the overflow
@@ -118,8 +119,10 @@ __device__ __forceinline__ void wave(const float* __restrict__ st, int H, int W,
             Vec vm, m;
 #pragma unroll
             for (int c = 0; c < CW; ++c) vm[c] = fmax3(up[k][c], cur[k][c], dn[k][c]);
+            // a lane past the right edge holds columns W - CW .. W - 1 and
+            // hands column W - 1 to the last lane inside (the replicated edge)
             const float left = wave_shr1(vm[CW - 1], lane_value(hm, k));
-            const float right = wave_shl1(vm[0], lane_value(hm, 32 + k));
+            const float right = wave_shl1(col_ok ? vm[0] : vm[CW - 1], lane_value(hm, 32 + k));
 #pragma unroll
             for (int c = 0; c < CW; ++c) {
                 const float l = c > 0 ? vm[c - 1] : left;

@@ -5,8 +5,10 @@
 //   r_k = sigma_k^2 Lap(G_sigma_k * I_b).
 //
 // Taps depend on the trainable sigmas, which live on the device, so they are
-// synthesised here in double (no host round trip) with each scale's kernel
-// radius frozen at the plan's value.  Four tap sets per scale feed the strip
+// synthesised here in double (no host round trip), each scale's kernel radius
+// floor(truncate sigma + 0.5) taken from its current sigma, and launched at
+// the padded radius of the plan's sigma cap (taps beyond the radius are
+// zero).  Four tap sets per scale feed the strip
 // kernel, whose operator is hcol (*)_y (grow (*)_x I) + gcol (*)_y (hrow (*)_x I):
 //   FWD  (g, h, sigma^2 g, sigma^2 h)   r = sigma^2 Lap
 //   D1   (g, h', g, h')                 the sigma-derivative of the Laplacian
@@ -28,15 +30,19 @@ namespace mhfd {
 namespace {
 
 __global__ void soft_taps_kernel(const float* __restrict__ sigmas, SoftTapLayout lay,
-                                 float* __restrict__ taps) {
+                                 float* __restrict__ taps, int32_t* __restrict__ err) {
     const int k = threadIdx.x;
+    const double s = k < lay.K ? static_cast<double>(sigmas[k]) : 1.0;
+    const bool ok = s > 0.0 && s <= static_cast<double>(lay.sigma_cap);  // false for NaN
+    const int bad = __syncthreads_or(!ok);
+    if (err && threadIdx.x == 0) *err = bad ? MHFD_FOCUS_BAD_SIGMA : 0;
     if (k >= lay.K) return;
-    const double s = static_cast<double>(sigmas[k]);
-    const int R = lay.radius[k], P = lay.padded[k];
+    // radius from the current sigma (at most the cap's, so within the launch)
+    const int R = ok ? static_cast<int>(floor(static_cast<double>(lay.truncate) * s + 0.5)) : 0;
+    const int P = lay.padded;
     float* base = taps + lay.offset[k];
     const int run = P + 1;  // floats per tap run
     const int blk = 4 * run;  // floats per tap set
-    const bool ok = s > 0.0 && isfinite(s);
     double z = 0.0, V = 0.0, M4 = 0.0;
     for (int j = 0; j <= R; ++j) {
         const double e = exp(-static_cast<double>(j) * j / (2.0 * s * s));
@@ -60,9 +66,8 @@ __global__ void soft_taps_kernel(const float* __restrict__ sigmas, SoftTapLayout
             gd = g * q / s3;
             hd = (q * gd - Vd * g) / s4 - 4.0 * q * g / s5;
         }
-        const float nan = __int_as_float(0x7fc00000);
         auto put = [&](int set, int r, double v) {
-            base[set * blk + r * run + j] = ok ? static_cast<float>(v) : nan;
+            base[set * blk + r * run + j] = ok ? static_cast<float>(v) : 0.0f;
         };
         // FWD
         put(0, 0, g);
@@ -168,8 +173,9 @@ __global__ void sigma_grad_finish_kernel(const double* __restrict__ partial, int
 int soft_cotangent_blocks() { return 2048; }
 
 hipError_t launch_soft_taps(const float* sigmas, const SoftTapLayout& lay, float* taps,
-                            hipStream_t s) {
-    soft_taps_kernel<<<1, 64, 0, s>>>(sigmas, lay, taps);
+                            int32_t* err, hipStream_t s) {
+    static_assert(MHFD_MAX_SCALES <= 64, "one thread per scale");
+    soft_taps_kernel<<<1, 64, 0, s>>>(sigmas, lay, taps, err);
     return hipGetLastError();
 }
 

@@ -3,8 +3,9 @@
 Requests (one tile each) arrive at any time.  Each scheduler iteration:
 
   1. completes finished batches (results copied out, the tiles' device
-     memory released); a batch whose execution raised completes its
-     requests with the error instead, and the loop goes on;
+     memory released); a batch whose execution or read-back raised, and a
+     tile whose result carries the candidate-overflow or invalid-tile flag,
+     complete with an error instead, and the loop goes on;
   2. admits waiting requests in arrival order while the HBM budget allows:
      the budget is charged the executor's fixed workspaces once and every
      admitted tile while it is resident; an admitted tile's host-to-device
@@ -27,6 +28,9 @@ from dataclasses import dataclass
 
 import numpy as np
 
+FLAG_CAND_OVERFLOW = 2   # mhfd_result flags (include/mhfd.h)
+FLAG_INVALID_TILE = 4
+
 
 @dataclass
 class Request:
@@ -42,6 +46,7 @@ class Request:
     count: int = -1
     n_candidates: int = -1
     flags: int = 0
+    density: float = 0.0
     blobs: np.ndarray | None = None
     error: str | None = None
 
@@ -100,15 +105,24 @@ class Server:
 
     def _complete(self) -> None:
         for slot, batch in list(self.running.items()):
-            out = self.ex.poll(slot)
+            try:
+                out = self.ex.poll(slot)
+            except Exception as e:  # read-back failed: the batch fails, the server goes on
+                out = [e] * len(batch)
             if out is None:
                 continue
             now = time.perf_counter()
             for r, res in zip(batch, out):
                 if isinstance(res, Exception):
-                    r.error = str(res)
+                    r.error = f"batch failed: {res}"
                 else:
-                    r.count, r.n_candidates, r.flags, r.blobs = res
+                    r.count, r.n_candidates, r.flags, r.density, r.blobs = res
+                    if r.flags & FLAG_CAND_OVERFLOW:
+                        r.error = (f"{r.n_candidates} candidates exceed the plan's candidate "
+                                   "capacity: the count and list are not valid")
+                    elif r.flags & FLAG_INVALID_TILE:
+                        r.error = "invalid tile: the descriptor failed the device-side checks"
+
                 r.done = now
                 r.staged = None
                 self.resident -= self.tile_bytes(r)
@@ -232,18 +246,28 @@ class GpuExecutor:
         self.batches[slot] = batch
 
     def poll(self, slot: int):
+        """None while the slot's batch runs; then one (count, n_candidates,
+        flags, density, blobs) tuple per tile, or the exception that the
+        read-back raised for every tile of the batch."""
         ev = self.events[slot]
-        if ev is None or not ev.query():
-            return None
-        runner, n = self.runners[slot], len(self.batches[slot])
-        with self.torch.cuda.stream(self.streams[slot]):
-            res = runner.results[:n].cpu().numpy()
-            blobs = runner.blobs[:n].cpu().numpy() if self.keep_blobs else None
+        try:
+            if ev is None or not ev.query():
+                return None
+            runner, n = self.runners[slot], len(self.batches[slot])
+            with self.torch.cuda.stream(self.streams[slot]):
+                res = runner.results[:n].cpu().numpy()
+                blobs = runner.blobs[:n].cpu().numpy() if self.keep_blobs else None
+        except Exception as e:
+            n = len(self.batches[slot]) if self.batches[slot] else 0
+            self.events[slot] = None
+            self.batches[slot] = None
+            return [e] * n
+        dens = res[:, 3].copy().view(np.float64)
         out = []
         for i in range(n):
             cnt = int(res[i, 0])
             b = blobs[i, : min(cnt, blobs.shape[1])].copy() if blobs is not None else None
-            out.append((cnt, int(res[i, 1]), int(res[i, 2]) & 0xFFFFFFFF, b))
+            out.append((cnt, int(res[i, 1]), int(res[i, 2]) & 0xFFFFFFFF, float(dens[i]), b))
         self.events[slot] = None
         self.batches[slot] = None
         return out

@@ -63,14 +63,19 @@ def test_plain_512_stack_and_blobs(plans, seed):
                                        as_set(ora["cand"]), TAU)
     assert g_c["n_cand"] == len(g_c["yxk"])
     g_p = gpu_detect(plans["prune"], img, return_stack=False)
+    # The GPU's pruned list is the oracle's prune of the GPU's own candidates
+    # (which agree with the oracle's at every unambiguous voxel, above).
+    keep = oracle.prune(g_c["yxk"], SIG10, 0.5)
+    np.testing.assert_array_equal(g_p["yxk"], g_c["yxk"][keep])
+    np.testing.assert_array_equal(g_p["resp"], g_c["resp"][keep])
+    np.testing.assert_array_equal(g_p["sigma"], np.float32(SIG10[g_c["yxk"][keep][:, 2]]))
+    assert g_p["count"] == int(keep.sum()) and g_p["n_cand"] == len(g_c["yxk"])
     if n_diff == 0:
         np.testing.assert_array_equal(g_p["yxk"], ora["blobs"])
-        np.testing.assert_array_equal(g_p["sigma"], np.float32(ora["blob_sigma"]))
         np.testing.assert_allclose(g_p["resp"], ora["blob_resp"], rtol=0,
                                    atol=STACK_TOL * np.abs(ora["stack"]).max())
         assert g_p["count"] == ora["count"]
-    else:
-        assert abs(g_p["count"] - ora["count"]) <= n_diff
+    print(f"seed {seed}: ambiguous {n_amb} differing {n_diff} blobs {g_p['count']}", flush=True)
 
 
 def test_strict_seeds_bit_exact(plans):
@@ -127,14 +132,25 @@ def test_u8_input_and_pitch():
                 dtype="u8", max_h=512, max_w=512)
     big = np.zeros((300, 300), np.uint8)
     big[:, :260] = img
+    plan_c = Plan(n_scales=10, sigma_min=1, sigma_max=10, threshold=0.05, overlap=1.0,
+                  dtype="u8", max_h=512, max_w=512)
     t = torch.from_numpy(big).to(plan.device)[:, :260]
     assert t.stride(0) == 300
+    tau = float(np.float32(0.05))
     d = plan.detect(t, return_stack=True)
-    ora = oracle.detect(img, SIG10, 4.0, float(np.float32(0.05)), 0.5)
-    assert plane_rel_err(d.stack.cpu().numpy(), ora["stack"]).max() <= STACK_TOL
-    yxk = d.yxk.cpu().numpy()
-    diff = as_set(yxk) ^ as_set(ora["blobs"])
-    assert len(diff) <= 4, sorted(diff)
+    dc = plan_c.detect(t, return_stack=True)
+    ora = oracle.detect(img, SIG10, 4.0, tau, 0.5)
+    st = dc.stack.cpu().numpy()
+    assert torch.equal(d.stack, dc.stack)
+    assert plane_rel_err(st, ora["stack"]).max() <= STACK_TOL
+    cand = dc.yxk.cpu().numpy().astype(np.int64)
+    n_amb, n_diff = compare_candidates(st, as_set(cand), ora["stack"], as_set(ora["cand"]), tau)
+    keep = oracle.prune(cand, SIG10, 0.5)
+    np.testing.assert_array_equal(d.yxk.cpu().numpy().astype(np.int64), cand[keep])
+    assert d.count == int(keep.sum()) and d.n_candidates == len(cand)
+    if n_diff == 0:
+        np.testing.assert_array_equal(cand[keep], ora["blobs"])
+    print(f"u8 pitch: ambiguous {n_amb} differing {n_diff} blobs {d.count}", flush=True)
 
 
 def test_dark_polarity_and_scale_grid():
@@ -222,7 +238,7 @@ def test_split_entry_points_equal_detect(plans):
                                 lws.data_ptr(), nl, s), "ls")
     cap = 4096
     raw = torch.empty((cap, 5), dtype=torch.int32, device=p.device)
-    res = torch.zeros(3, dtype=torch.int64, device=p.device)
+    res = torch.zeros(_lib.RESULT_WORDS, dtype=torch.int64, device=p.device)
     nb = p.detect_workspace_bytes(512, 512)
     ws = torch.empty(nb, dtype=torch.uint8, device=p.device)
     _lib.check(L.mhfd_detect_stack(p._handle, st.data_ptr(), 512, 512, raw.data_ptr(), cap,
@@ -236,49 +252,42 @@ def test_split_entry_points_equal_detect(plans):
 
 def test_full_size_sem_tile():
     """4096 x 4096 8-bit tile, sigma 1..10, threshold 0.05, in the launch
-    configuration the benchmark times: sampled stack voxels against the 2-D
-    definition over the whole tile; the whole candidate list against the
-    candidate rule applied to the GPU's own stack; stack and candidate
-    decisions (ambiguity-aware) against the oracle on three full-width row
-    bands (top border, middle, bottom border)."""
+    configuration the benchmark times, against one whole-tile oracle run:
+    every voxel of the stack within 1e-5 of its plane's maximum, every
+    candidate decision equal to the oracle's outside the ambiguity margin
+    (ambiguous ones consistent with the GPU's own stack), the whole candidate
+    list equal to the candidate rule on the GPU's own stack, and the pruned
+    list equal to the oracle's prune of the GPU's candidates (and to the
+    oracle's own list when no decision differs)."""
     import torch
     from paper_2108_12050_amd import Plan
     print("full-size 4096x4096 u8", flush=True)
     img = synth.sem_tile(0, psf_sigma=0.0)
     tau = float(np.float32(0.05))
-    plan_c = Plan(n_scales=10, sigma_min=1, sigma_max=10, threshold=0.05, overlap=1.0,
-                  dtype="u8", max_h=4096, max_w=4096)
+    kw = dict(n_scales=10, sigma_min=1, sigma_max=10, threshold=0.05, dtype="u8",
+              max_h=4096, max_w=4096)
+    plan_c, plan_p = Plan(overlap=1.0, **kw), Plan(overlap=0.5, **kw)
     t = torch.from_numpy(img).to(plan_c.device)
     d = plan_c.detect(t, return_stack=True)
     st = d.stack.cpu().numpy()
-    np.testing.assert_array_equal(d.yxk.cpu().numpy().astype(np.int64), own_maxima(st, tau))
-    gpu_c = as_set(d.yxk.cpu().numpy())
-    I = oracle.to_f64(img)
-    rng = np.random.default_rng(0)
-    pts = [(int(rng.integers(0, 10)), int(rng.integers(0, 4096)), int(rng.integers(0, 4096)))
-           for _ in range(300)]
-    pts += [(k, y, x) for k in (0, 9) for y in (0, 1, 4095) for x in (0, 63, 64, 4095)]
-    for (k, y, x) in pts:
-        ref = oracle.log_point(I, SIG10[k], y, x)
-        assert abs(st[k, y, x] - ref) <= STACK_TOL * 0.5, (k, y, x, st[k, y, x], ref)
-    H = 4096
-    m = 42   # > largest radius + 1: band rows [y0 - 1, y1 + 1) are exact
-    total = 0
-    for (y0, y1) in [(0, 256), (2000, 2256), (3840, 4096)]:
-        a, b = max(0, y0 - m), min(H, y1 + m)
-        ora = oracle.log_stack(I[a:b], SIG10)
-        lo, hi = max(0, y0 - 1) - a, min(H, y1 + 1) - a
-        err = plane_rel_err(st[:, a + lo:a + hi], ora[:, lo:hi])
-        assert err.max() <= STACK_TOL, err
-        ykx, _ = oracle.candidates(ora, tau)
-        ykx[:, 0] += a
-        n_amb, n_diff = compare_candidates(st[:, a:b], gpu_c, ora, as_set(ykx), tau,
-                                           rows=(y0, y1), row0=a)
-        n_band = sum(1 for c in gpu_c if y0 <= c[0] < y1)
-        print(f"band {y0}-{y1}: gpu candidates {n_band} ambiguous {n_amb} differing {n_diff}",
-              flush=True)
-        total += n_band
-    assert total > 1000
+    d.stack = None
+    cand = d.yxk.cpu().numpy().astype(np.int64)
+    np.testing.assert_array_equal(cand, own_maxima(st, tau))
+    kept = plan_p.detect(t).yxk.cpu().numpy().astype(np.int64)
+    print("oracle stack, whole tile", flush=True)
+    ora = oracle.log_stack(oracle.to_f64(img), SIG10)
+    err = plane_rel_err(st, ora)
+    print(f"stack: largest plane error {err.max():.2e}", flush=True)
+    assert err.max() <= STACK_TOL, err
+    ykx, _ = oracle.candidates(ora, tau)
+    n_amb, n_diff = compare_candidates(st, as_set(cand), ora, as_set(ykx), tau)
+    print(f"candidates gpu {len(cand)} oracle {len(ykx)} ambiguous {n_amb} differing {n_diff}",
+          flush=True)
+    del ora, st
+    np.testing.assert_array_equal(kept, strip_prune(cand, SIG10, 0.5, 4096))
+    if n_diff == 0:
+        np.testing.assert_array_equal(kept, strip_prune(ykx.astype(np.int64), SIG10, 0.5, 4096))
+    assert len(kept) > 1000
 
 
 def test_max_size_f32_tile():

@@ -22,9 +22,9 @@ pytestmark = pytest.mark.gpu
 BETA, TAU = 50.0, 0.05
 
 
-def make_plan(sig, h, w):
+def make_plan(sig, h, w, sigma_cap=None):
     from paper_2108_12050_amd import Plan
-    return Plan(sigmas=list(sig), max_h=h, max_w=w)
+    return Plan(sigmas=list(sig), max_h=h, max_w=w, sigma_cap=sigma_cap)
 
 
 def to_dev(a):
@@ -93,7 +93,7 @@ def test_autograd_function():
     from paper_2108_12050_amd import focus_score
     H, W = 64, 64
     sig0 = [1.0, 2.0, 3.0]
-    plan = make_plan(sig0, H, W)
+    plan = make_plan(sig0, H, W, sigma_cap=5.0)
     imgs = to_dev(np.stack([synth.blob_field(3, H, W, n_blobs=5)])).requires_grad_(True)
     sig = to_dev(np.float32(sig0)).requires_grad_(True)
     s = focus_score(imgs, sig, plan, BETA, TAU)
@@ -111,6 +111,94 @@ def test_autograd_function():
         loss.backward()
         opt.step()
     assert float(focus_score(imgs.detach(), sig.detach(), plan, BETA, TAU).sum()) < first
+
+
+@pytest.mark.parametrize("factor", [1.13, 0.87])
+def test_sigmas_off_the_plan_grid(factor):
+    """Trainable sigmas away from the plan's: every call takes each scale's
+    radius floor(4 sigma + 0.5) from the current sigma (here every radius
+    differs from the plan's), so score and gradients equal the oracle's at
+    those sigmas with their own radii."""
+    B, H, W = 2, 90, 76
+    grid = [1.0, 2.0, 3.0, 4.5]
+    sig32 = np.float32(np.float32(grid) * np.float32(factor))
+    sig = np.float64(sig32)
+    assert all(oracle.radius(a) != oracle.radius(b) for a, b in zip(sig, grid))
+    imgs = np.stack([synth.blob_field(40 + b, H, W, n_blobs=6) for b in range(B)])
+    plan = make_plan(grid, H, W, sigma_cap=6.0)
+    s_gpu = plan.focus_score(to_dev(imgs), to_dev(sig32), BETA, TAU).cpu().numpy()
+    np.testing.assert_allclose(s_gpu, oracle.soft_score(imgs.astype(np.float64), sig, BETA, TAU),
+                               rtol=1e-5, atol=0)
+    gbar = np.float32([1.0, -0.75])
+    dI, ds = plan.focus_score_backward(to_dev(imgs), to_dev(sig32), to_dev(gbar), BETA, TAU)
+    dI, ds = dI.cpu().numpy().astype(np.float64), ds.cpu().numpy().astype(np.float64)
+    dI_o, ds_o = oracle.soft_score_grad(imgs.astype(np.float64), sig, BETA, TAU,
+                                        gbar.astype(np.float64))
+    np.testing.assert_allclose(ds, ds_o, rtol=0, atol=1e-4 * np.abs(ds_o).max())
+    check_image_grad(dI, dI_o, imgs, sig, gbar)
+
+
+def test_sigma_crossing_a_radius_boundary():
+    """Radius 9 below sigma = 2.375 and 10 above it: the scores on either
+    side follow the oracle with the matching radius, and differ from each
+    other by the truncation step, not by rounding."""
+    H, W = 64, 80
+    img = synth.blob_field(7, H, W, n_blobs=5)[None]
+    plan = make_plan([1.0, 2.0, 3.0], H, W, sigma_cap=4.0)
+    out = []
+    for s2 in (2.37, 2.38):
+        sig32 = np.float32([1.0, s2, 3.0])
+        assert oracle.radius(float(sig32[1])) == (9 if s2 < 2.375 else 10)
+        g = plan.focus_score(to_dev(img), to_dev(sig32), BETA, TAU).cpu().numpy()
+        o = oracle.soft_score(img.astype(np.float64), np.float64(sig32), BETA, TAU)
+        np.testing.assert_allclose(g, o, rtol=1e-5, atol=0)
+        dI, ds = plan.focus_score_backward(to_dev(img), to_dev(sig32), to_dev(np.ones(1)),
+                                           BETA, TAU)
+        _, ds_o = oracle.soft_score_grad(img.astype(np.float64), np.float64(sig32), BETA, TAU)
+        np.testing.assert_allclose(ds.cpu().numpy(), ds_o, rtol=0, atol=1e-4 * np.abs(ds_o).max())
+        out.append(float(g[0]))
+    assert out[0] != out[1]
+
+
+@pytest.mark.parametrize("bad", [0.0, -1.0, float("nan"), float("inf"), 4.01])
+def test_sigma_outside_the_cap_raises(bad):
+    """A sigma outside (0, sigma_cap] sets the call's device error word; the
+    binding raises on it.  The cap itself is accepted."""
+    from paper_2108_12050_amd import MHFDError
+    plan = make_plan([1.0, 2.0, 3.0], 40, 40, sigma_cap=4.0)
+    img = to_dev(synth.blob_field(2, 40, 40, n_blobs=3)[None])
+    plan.focus_score(img, to_dev(np.float32([1.0, 2.0, 4.0])), BETA, TAU)
+    with pytest.raises(MHFDError):
+        plan.focus_score(img, to_dev(np.float32([1.0, bad, 3.0])), BETA, TAU)
+    with pytest.raises(MHFDError):
+        plan.focus_score_backward(img, to_dev(np.float32([bad, 2.0, 3.0])), torch.ones(1).cuda(),
+                                  BETA, TAU)
+    plan.focus_score(img, to_dev(np.float32([1.0, 2.0, 3.0])), BETA, TAU)   # clears the word
+
+
+def test_trained_sigmas_follow_the_oracle():
+    """After SGD steps on the sigmas (which leave the plan's grid), score and
+    sigma gradient at the trained sigmas equal the oracle's."""
+    from paper_2108_12050_amd import focus_score
+    H, W = 72, 72
+    sig0 = [1.0, 2.0, 3.0]
+    plan = make_plan(sig0, H, W, sigma_cap=5.0)
+    img = np.stack([synth.blob_field(5, H, W, n_blobs=6)])
+    t = to_dev(img)
+    sig = to_dev(np.float32(sig0)).requires_grad_(True)
+    for _ in range(4):   # normalised descent steps of 0.2 on the largest component
+        sig.grad = None
+        focus_score(t, sig, plan, BETA, TAU).sum().backward()
+        with torch.no_grad():
+            sig -= 0.2 * sig.grad / sig.grad.abs().max()
+    s_now = np.float64(sig.detach().cpu().numpy())
+    assert np.abs(s_now - sig0).max() > 0.05, s_now
+    g = plan.focus_score(t, sig.detach(), BETA, TAU).cpu().numpy()
+    np.testing.assert_allclose(g, oracle.soft_score(img.astype(np.float64), s_now, BETA, TAU),
+                               rtol=1e-5, atol=0)
+    _, ds = plan.focus_score_backward(t, sig.detach(), torch.ones(1).cuda(), BETA, TAU)
+    _, ds_o = oracle.soft_score_grad(img.astype(np.float64), s_now, BETA, TAU)
+    np.testing.assert_allclose(ds.cpu().numpy(), ds_o, rtol=0, atol=1e-4 * np.abs(ds_o).max())
 
 
 def test_full_size_gradient_batch():

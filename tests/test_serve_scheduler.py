@@ -15,11 +15,13 @@ class HostExecutor:
     tile is a function of its pixels so that mix-ups are visible."""
 
     def __init__(self, n_slots=2, slot_tiles=4, slot_pixels=10_000, fixed_bytes=1000,
-                 latency_polls=3, fail_launch=(), fail_tiles=()):
+                 latency_polls=3, fail_launch=(), fail_tiles=(), fail_poll=(), flags=None):
         self.bytes_per_pixel = 4
         self.slot_tiles, self.slot_pixels, self.fixed_bytes = slot_tiles, slot_pixels, fixed_bytes
         self.latency_polls = latency_polls
         self.fail_launch, self.fail_tiles = set(fail_launch), set(fail_tiles)
+        self.fail_poll, self.flags = set(fail_poll), dict(flags or {})
+        self.completed = 0
         self.batches = [None] * n_slots
         self.polls = [0] * n_slots
         self.launches = 0
@@ -46,8 +48,12 @@ class HostExecutor:
             return None
         batch = self.batches[slot]
         self.batches[slot] = None
+        self.completed += 1
+        if self.completed in self.fail_poll:
+            raise RuntimeError("injected read-back failure")
         return [RuntimeError("injected tile failure") if r.rid in self.fail_tiles
-                else (int(np.asarray(r.image).sum()), r.pixels, 0, None) for r in batch]
+                else (int(np.asarray(r.image).sum()), r.pixels, self.flags.get(r.rid, 0),
+                      1e6 * int(np.asarray(r.image).sum()) / r.pixels, None) for r in batch]
 
 
 def img(h, w, v=1.0):
@@ -132,3 +138,34 @@ def test_run_trace_real_time():
     assert [r.rid for r in out] == list(range(6))
     assert all(r.error is None and r.latency >= 0 for r in out)
     assert all(r.arrival - out[0].arrival >= a - 1e-9 for r, a in zip(out, arrivals))
+
+
+def test_read_back_failure_fails_its_batch_only():
+    """A poll that raises (a device error surfacing when results are copied
+    back) completes that batch's requests with the error; the server goes on."""
+    ex = HostExecutor(n_slots=1, slot_tiles=2, fail_poll={2})
+    srv = Server(ex, 10**9)
+    for i in range(6):
+        srv.submit(Request(i, img(8, 8), time.perf_counter()))
+    srv.drain(0.0)
+    err = {r.rid: r.error for r in srv.finished}
+    assert len(err) == 6 and srv.resident == 0
+    assert err[2] and err[3] and "read-back failure" in err[2]
+    assert all(err[i] is None for i in (0, 1, 4, 5))
+
+
+def test_flagged_results_are_errors():
+    """Candidate overflow (flag 2) and an invalid tile (flag 4) make the
+    request fail; a blob-list overflow (flag 1) keeps the valid count."""
+    ex = HostExecutor(n_slots=1, slot_tiles=4, flags={1: 2, 2: 4, 3: 1})
+    srv = Server(ex, 10**9)
+    for i in range(4):
+        srv.submit(Request(i, img(8, 8, 2.0), time.perf_counter()))
+    srv.drain(0.0)
+    r = {q.rid: q for q in srv.finished}
+    assert r[0].error is None and r[0].count == 128 and r[0].density == 2e6
+    assert r[1].error and "candidate" in r[1].error
+    assert r[2].error and "invalid" in r[2].error
+    assert r[3].error is None and r[3].flags == 1 and r[3].count == 128
+    from paper_2108_12050_amd.serve import summarize
+    assert summarize(srv.finished, 1.0)["served"] == 2
