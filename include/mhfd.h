@@ -210,6 +210,23 @@ mhfd_status mhfd_log_stack(mhfd_plan plan, const void *d_img, int32_t h, int32_t
                            float *d_stack, void *d_ws, size_t ws_bytes, void *stream);
 
 /*
+ * mhfd_log_stack without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The call's scratch (the fp32 range word,
+ * or the stretch histogram and levels: at most MHFD_STATIC_SCRATCH_BYTES) is
+ * a static array of the library, one per device, kept until the process
+ * ends; the call allocates nothing.  Every call on a device shares that
+ * array: calls that overlap in time on one device (on different streams, or
+ * from several host threads) race and give wrong stacks, so serialise them;
+ * each call clears what it uses.  Same arguments, results and errors as
+ * mhfd_log_stack, plus MHFD_ERR_UNSUPPORTED if the plan needed more scratch
+ * than the array holds.
+ */
+#define MHFD_STATIC_SCRATCH_BYTES 2048
+mhfd_status mhfd_log_stack_static(mhfd_plan plan, const void *d_img, int32_t h, int32_t w,
+                                  int64_t pitch, float *d_stack, void *stream);
+
+/*
  * Histogram stretch levels of one 8-bit image (section 3; Algorithm 1, first
  * step: 0.175% of the pixels saturated at each end).  With N = h w and
  * q = 0.00175 N, low is the smallest code v with at least q pixels <= v and

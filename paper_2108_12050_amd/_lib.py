@@ -28,7 +28,7 @@ STATUS = {0: "MHFD_OK", 1: "MHFD_ERR_INVALID_ARG", 2: "MHFD_ERR_UNSUPPORTED",
 # Every symbol include/mhfd.h declares.
 EXPORTS = ("mhfd_create_plan", "mhfd_destroy_plan", "mhfd_plan_scales",
            "mhfd_detect_workspace_size", "mhfd_detect", "mhfd_log_stack_workspace_size",
-           "mhfd_log_stack", "mhfd_detect_stack", "mhfd_stretch_levels",
+           "mhfd_log_stack", "mhfd_log_stack_static", "mhfd_detect_stack", "mhfd_stretch_levels",
            "mhfd_batch_workspace_size", "mhfd_detect_batched", "mhfd_focus_workspace_size",
            "mhfd_focus_score", "mhfd_focus_score_backward", "mhfd_status_string",
            "mhfd_last_error")
@@ -109,6 +109,8 @@ def load(path: str | None = None):
     L.mhfd_log_stack_workspace_size.restype = sz
     L.mhfd_log_stack.argtypes = [vp, vp, i32, i32, i64, vp, vp, sz, vp]
     L.mhfd_log_stack.restype = C.c_int
+    L.mhfd_log_stack_static.argtypes = [vp, vp, i32, i32, i64, vp, vp]
+    L.mhfd_log_stack_static.restype = C.c_int
     L.mhfd_detect_stack.argtypes = [vp, vp, i32, i32, vp, i32, vp, vp, sz, vp]
     L.mhfd_detect_stack.restype = C.c_int
     L.mhfd_stretch_levels.argtypes = [vp, i32, i32, i64, vp, vp, vp]

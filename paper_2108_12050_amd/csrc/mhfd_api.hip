@@ -6,11 +6,42 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
 
 #include "mhfd_internal.h"
+
+// Scratch of mhfd_log_stack_static, for callers that cannot allocate: the
+// fp32 input-range word, or the stretch histogram and levels, of one call.
+// Each device holds its own copy until the process ends.  In host code the
+// array's name is not a device address: kernels get the address that
+// hipGetSymbolAddress returns for the current device (looked up once per
+// device when a plan is created there).
+static __device__ __align__(256) uint32_t scratch[MHFD_STATIC_SCRATCH_BYTES / sizeof(uint32_t)];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint32_t* g_scratch[kMaxDevices] = {};
+
+// This device's address of `scratch`; `dev` must be the current device.
+hipError_t static_scratch_address(int dev, uint32_t** out) {
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch[dev] = static_cast<uint32_t*>(ptr);
+    }
+    *out = g_scratch[dev];
+    return hipSuccess;
+}
+
+}  // namespace
 
 struct mhfd_plan_s {
     int device = 0;
@@ -39,6 +70,7 @@ struct mhfd_plan_s {
     int criterion = MHFD_CRITERION_LOG;  // DOG: the stack holds Gaussian planes
     float sigma_cap = 0.0f;      // largest sigma a focus-score call may take
     int padded_cap = 0;          // padded radius of sigma_cap: the focus-score halos
+    uint32_t* d_scratch = nullptr;  // this device's static scratch (mhfd_log_stack_static)
 };
 
 namespace {
@@ -353,6 +385,7 @@ mhfd_status mhfd_create_plan(const mhfd_config* cfg, mhfd_plan* out) {
     hipError_t e = hipGetDevice(&p->device);
     if (e == hipSuccess)
         e = hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device);
+    if (e == hipSuccess) e = static_scratch_address(p->device, &p->d_scratch);
     if (e != hipSuccess) {
         delete p;
         return hip_fail(e, "device query");
@@ -803,6 +836,22 @@ mhfd_status mhfd_log_stack(mhfd_plan p, const void* d_img, int32_t h, int32_t w,
     }
     if ((st = check_device(p)) != MHFD_OK) return st;
     return enqueue_log_stack(p, d_img, h, w, pitch, d_stack, static_cast<uint32_t*>(d_ws),
+                             static_cast<hipStream_t>(stream));
+}
+
+mhfd_status mhfd_log_stack_static(mhfd_plan p, const void* d_img, int32_t h, int32_t w,
+                                  int64_t pitch, float* d_stack, void* stream) {
+    g_last_error.clear();
+    mhfd_status st = check_image(p, d_img, h, w, pitch);
+    if (st != MHFD_OK) return st;
+    if (!d_stack) return fail(MHFD_ERR_INVALID_ARG, "null stack");
+    const size_t need = log_stack_scratch(p);
+    if (need > MHFD_STATIC_SCRATCH_BYTES)
+        return fail(MHFD_ERR_UNSUPPORTED, "the plan needs %zu bytes of scratch, the static array "
+                    "holds %d", need, MHFD_STATIC_SCRATCH_BYTES);
+    if ((st = check_device(p)) != MHFD_OK) return st;
+    if (!p->d_scratch) return fail(MHFD_ERR_HIP, "no static scratch on device %d", p->device);
+    return enqueue_log_stack(p, d_img, h, w, pitch, d_stack, p->d_scratch,
                              static_cast<hipStream_t>(stream));
 }
 

@@ -38,7 +38,8 @@ def test_status_strings():
 
 @pytest.mark.parametrize("bad", [dict(n_scales=0), dict(n_scales=33), dict(truncate=0.0),
                                  dict(overlap=-1.0), dict(polarity=5), dict(in_dtype=7),
-                                 dict(max_h=0), dict(sigma_min=-1.0)])
+                                 dict(max_h=0), dict(sigma_min=-1.0), dict(sigma_cap=-1.0),
+                                 dict(sigma_cap=9.5), dict(sigma_cap=float("nan"))])
 def test_create_plan_rejects_bad_config_on_host(bad):
     """Validation happens before any device call, so it runs without a GPU."""
     from paper_2108_12050_amd import _lib
@@ -51,6 +52,17 @@ def test_create_plan_rejects_bad_config_on_host(bad):
     assert L.mhfd_create_plan(C.byref(cfg), C.byref(h)) == 1
     assert L.mhfd_last_error()
     assert h.value is None
+
+
+def test_sigma_cap_beyond_the_largest_radius_is_unsupported():
+    from paper_2108_12050_amd import _lib
+    L = _lib.load()
+    cfg = _lib.Config(n_scales=10, sigma_min=1.0, sigma_max=10.0, truncate=4.0, threshold=0.1,
+                      overlap=0.5, polarity=0, in_dtype=0, max_h=64, max_w=64, max_candidates=0,
+                      sigma_cap=16.2)   # radius 65 > MHFD_MAX_RADIUS
+    h = C.c_void_p()
+    assert L.mhfd_create_plan(C.byref(cfg), C.byref(h)) == 2
+    assert b"sigma_cap" in L.mhfd_last_error()
 
 
 def test_null_arguments():
