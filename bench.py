@@ -497,12 +497,18 @@ def main() -> int:
     S = max(1, a.streams)
     streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(S - 1)]
     # per stream: stack, workspace, raw blob buffer, one result per image
+    nact = L.mhfd_activity_bytes(plan._handle, H, W)
     bufs = [dict(stack=torch.empty((K, H, W), dtype=torch.float32, device=dev),
+                 act=torch.empty(nact // 8, dtype=torch.int64, device=dev),
                  ws=torch.empty(nbytes, dtype=torch.uint8, device=dev),
                  raw=torch.empty((cap, 5), dtype=torch.int32, device=dev),
-                 res=[torch.full((3,), -1, dtype=torch.int64, device=dev) for _ in PSF])
+                 res=[torch.full((_lib.RESULT_WORDS,), -1, dtype=torch.int64, device=dev)
+                      for _ in PSF])
             for _ in range(S)]
 
+    # One step = the detector on one tile as mhfd_detect runs it without a
+    # caller stack (threshold-sparse), through its two public halves so that
+    # events can bracket the LoG launches.
     def step(i, n_streams, ev=None):
         j = i % len(PSF)
         st = streams[i % n_streams]
@@ -510,13 +516,15 @@ def main() -> int:
         sptr = int(st.cuda_stream)
         if ev is not None:
             ev[0].record(st)
-        _lib.check(L.mhfd_log_stack(plan._handle, imgs[j].data_ptr(), H, W, W,
-                                    b["stack"].data_ptr(), None, 0, sptr), "mhfd_log_stack")
+        _lib.check(L.mhfd_log_stack_sparse(plan._handle, imgs[j].data_ptr(), H, W, W,
+                                           b["stack"].data_ptr(), b["act"].data_ptr(), None, 0,
+                                           sptr), "mhfd_log_stack_sparse")
         if ev is not None:
             ev[1].record(st)
-        _lib.check(L.mhfd_detect_stack(plan._handle, b["stack"].data_ptr(), H, W,
-                                       b["raw"].data_ptr(), cap, b["res"][j].data_ptr(),
-                                       b["ws"].data_ptr(), nbytes, sptr), "mhfd_detect_stack")
+        _lib.check(L.mhfd_detect_stack_sparse(plan._handle, b["stack"].data_ptr(),
+                                              b["act"].data_ptr(), H, W, b["raw"].data_ptr(), cap,
+                                              b["res"][j].data_ptr(), b["ws"].data_ptr(), nbytes,
+                                              sptr), "mhfd_detect_stack_sparse")
         if ev is not None:
             ev[2].record(st)
 

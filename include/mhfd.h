@@ -178,7 +178,9 @@ size_t mhfd_detect_workspace_size(mhfd_plan plan, int32_t h, int32_t w);
  *             min(n_blobs, capacity) are written in ascending (y, x, k).
  *   d_result  one mhfd_result, always written.
  *   d_stack   optional K x h x w float array (plane k at k*h*w) that receives
- *             the LoG stack R; NULL keeps the stack inside the workspace.
+ *             the whole LoG stack R; with NULL the detector keeps only the
+ *             part above the threshold, in the workspace (threshold-sparse,
+ *             see mhfd_log_stack_sparse), when the plan allows it.
  *   d_ws      workspace of at least mhfd_detect_workspace_size(plan, h, w)
  *             bytes, 256-byte aligned; its contents need no initialisation
  *             and are scratch after the call.
@@ -254,6 +256,34 @@ mhfd_status mhfd_stretch_levels(const uint8_t *d_img, int32_t h, int32_t w, int6
 mhfd_status mhfd_detect_stack(mhfd_plan plan, const float *d_stack, int32_t h, int32_t w,
                               mhfd_blob *d_blobs, int32_t capacity, mhfd_result *d_result,
                               void *d_ws, size_t ws_bytes, void *stream);
+
+/*
+ * The two halves of mhfd_detect in the form it takes without a caller stack
+ * (threshold-sparse).  A voxel at or below the threshold can neither be a
+ * candidate nor block one (a neighbour that blocks a candidate exceeds it,
+ * and so the threshold), so the detector writes and reads only the 4-pixel
+ * row groups of the stack that hold a value above the threshold, and marks
+ * them in activity words: word [k][by][bx] (by < ceil(h/16), bx <
+ * ceil(w/16)) has bit 16 g + r set when row 16 by + r, columns 16 bx + 4 g
+ * ... 16 bx + 4 g + 3 of plane k hold such a value (those four values are
+ * then written; the other groups of d_stack are left as they were).
+ *   mhfd_activity_bytes  bytes of the activity words for an h x w image;
+ *                        0 for plans without this form (the DoG criterion,
+ *                        or a radius above 56) and on bad input.
+ *   mhfd_log_stack_sparse   as mhfd_log_stack, plus d_act (8-byte aligned,
+ *                           mhfd_activity_bytes bytes, every word written).
+ *   mhfd_detect_stack_sparse  as mhfd_detect_stack on such a stack.
+ * mhfd_log_stack_sparse followed by mhfd_detect_stack_sparse gives exactly
+ * what mhfd_detect gives; MHFD_ERR_UNSUPPORTED for plans without the form.
+ */
+size_t mhfd_activity_bytes(mhfd_plan plan, int32_t h, int32_t w);
+mhfd_status mhfd_log_stack_sparse(mhfd_plan plan, const void *d_img, int32_t h, int32_t w,
+                                  int64_t pitch, float *d_stack, uint64_t *d_act, void *d_ws,
+                                  size_t ws_bytes, void *stream);
+mhfd_status mhfd_detect_stack_sparse(mhfd_plan plan, const float *d_stack, const uint64_t *d_act,
+                                     int32_t h, int32_t w, mhfd_blob *d_blobs, int32_t capacity,
+                                     mhfd_result *d_result, void *d_ws, size_t ws_bytes,
+                                     void *stream);
 
 /* One image of a batch (device-resident descriptor, 48 bytes). */
 typedef struct mhfd_tile {

@@ -29,6 +29,7 @@ STATUS = {0: "MHFD_OK", 1: "MHFD_ERR_INVALID_ARG", 2: "MHFD_ERR_UNSUPPORTED",
 EXPORTS = ("mhfd_create_plan", "mhfd_destroy_plan", "mhfd_plan_scales",
            "mhfd_detect_workspace_size", "mhfd_detect", "mhfd_log_stack_workspace_size",
            "mhfd_log_stack", "mhfd_log_stack_static", "mhfd_detect_stack", "mhfd_stretch_levels",
+           "mhfd_activity_bytes", "mhfd_log_stack_sparse", "mhfd_detect_stack_sparse",
            "mhfd_batch_workspace_size", "mhfd_detect_batched", "mhfd_focus_workspace_size",
            "mhfd_focus_score", "mhfd_focus_score_backward", "mhfd_status_string",
            "mhfd_last_error")
@@ -111,6 +112,12 @@ def load(path: str | None = None):
     L.mhfd_log_stack.restype = C.c_int
     L.mhfd_log_stack_static.argtypes = [vp, vp, i32, i32, i64, vp, vp]
     L.mhfd_log_stack_static.restype = C.c_int
+    L.mhfd_activity_bytes.argtypes = [vp, i32, i32]
+    L.mhfd_activity_bytes.restype = sz
+    L.mhfd_log_stack_sparse.argtypes = [vp, vp, i32, i32, i64, vp, vp, vp, sz, vp]
+    L.mhfd_log_stack_sparse.restype = C.c_int
+    L.mhfd_detect_stack_sparse.argtypes = [vp, vp, vp, i32, i32, vp, i32, vp, vp, sz, vp]
+    L.mhfd_detect_stack_sparse.restype = C.c_int
     L.mhfd_detect_stack.argtypes = [vp, vp, i32, i32, vp, i32, vp, vp, sz, vp]
     L.mhfd_detect_stack.restype = C.c_int
     L.mhfd_stretch_levels.argtypes = [vp, i32, i32, i64, vp, vp, vp]

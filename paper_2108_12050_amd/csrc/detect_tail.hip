@@ -49,11 +49,11 @@ __global__ void init_counters_kernel(DetectCounters* ctr) {
 
 // One wave per (strip of 64 CW columns, run of nms::ROWS rows); a workgroup
 // holds NMS_WAVES independent waves.  The per-wave body is nms::wave.
-template <int K, int CW>
+template <int K, int CW, bool SPARSE>
 __global__ __launch_bounds__(64 * NMS_WAVES) void nms_kernel(
     const float* __restrict__ st, int H, int W, float tau, int bpr, int n_runs,
     int32_t* __restrict__ blk_n, int32_t* __restrict__ blk_o, Cand* __restrict__ pool,
-    int64_t n_cells, int64_t cap, DetectCounters* __restrict__ ctr) {
+    int64_t n_cells, int64_t cap, DetectCounters* __restrict__ ctr, nms::Active act) {
     const int wid = blockIdx.x * NMS_WAVES + (threadIdx.x >> 6);  // (run, strip), strip fastest
     if (wid >= n_runs * bpr) return;
     nms::Sink out;
@@ -65,16 +65,23 @@ __global__ __launch_bounds__(64 * NMS_WAVES) void nms_kernel(
     out.pool_used = &ctr->pool_used;
     out.flags = &ctr->flags;
     out.k_tag = 0;
-    nms::wave<K, CW, SLOT>(st, H, W, tau, bpr, wid % bpr, wid / bpr, out);
+    nms::wave<K, CW, SLOT, SPARSE>(st, H, W, tau, bpr, wid % bpr, wid / bpr, out, act);
 }
 
 template <int K, int CW>
 void launch_nms_k(const DetectWorkspace& ws, int h, int w, float tau, hipStream_t s) {
     const int runs = (h + nms::ROWS - 1) / nms::ROWS;
     const int waves = runs * ws.blk_per_row;
-    nms_kernel<K, CW><<<(waves + NMS_WAVES - 1) / NMS_WAVES, 64 * NMS_WAVES, 0, s>>>(
-        ws.stack, h, w, tau, ws.blk_per_row, runs, ws.blk_n, ws.blk_o, ws.pool, ws.n_blk, ws.cap,
-        ws.ctr);
+    const int grid = (waves + NMS_WAVES - 1) / NMS_WAVES;
+    const nms::Active act{ws.act, ws.act_bx, ws.act_by};
+    if (ws.act)
+        nms_kernel<K, CW, true><<<grid, 64 * NMS_WAVES, 0, s>>>(
+            ws.stack, h, w, tau, ws.blk_per_row, runs, ws.blk_n, ws.blk_o, ws.pool, ws.n_blk,
+            ws.cap, ws.ctr, act);
+    else
+        nms_kernel<K, CW, false><<<grid, 64 * NMS_WAVES, 0, s>>>(
+            ws.stack, h, w, tau, ws.blk_per_row, runs, ws.blk_n, ws.blk_o, ws.pool, ws.n_blk,
+            ws.cap, ws.ctr, act);
 }
 
 template <int... Ks>

@@ -103,6 +103,11 @@ struct WaveJob {
     float out_scale;  // exact power of two (times 255 / (high - low) when stretched)
     uint32_t s_lo, s_hi, s_nlo;  // stretched u8 input: 1024 + low, 1024 + high,
                                  // -(1024 + low), each as an FP16 pair
+    // Threshold-sparse output (SPARSE kernels): the plane's activity words
+    // (ceil(h/16) x act_bx) and the threshold.
+    uint64_t* act;
+    int act_bx;
+    float tau;
 };
 
 // 8-bit input with the histogram stretch applied as it is read (stretch.hip):
@@ -267,7 +272,11 @@ __device__ __forceinline__ Input<float>::Raw select_raw<float>(bool c, Input<flo
 
 // CTL: the column-pass tap fragments are read from LDS (`cl`, the block's
 // copy) at every use instead of being held in registers.
-template <typename T, int NKR, int NKC, bool EDGE, bool CTL>
+// SPARSE: the stack is written only for the 4-pixel row groups that hold a
+// value above J.tau, and every 16 x 16 output block's groups are marked in
+// one activity word (bit 16 g + r: row r, columns 4 g ... 4 g + 3 of the
+// block), which the maxima pass reads instead of the unwritten groups.
+template <typename T, int NKR, int NKC, bool EDGE, bool CTL, bool SPARSE>
 __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __restrict__ fr,
                                          const half8_t* cl, int lane) {
     typedef Input<T> In;
@@ -372,6 +381,16 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
     const bool vec = !EDGE || (J.out_vec && x0 + 16 <= w);
     auto store = [&](int t, float4_t v) {
         const int y = y0 + 16 * t + c;
+        if constexpr (SPARSE) {
+            bool a = false;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                a |= (!EDGE || x0 + 4 * g + i < w) && v[i] > J.tau;
+            if (EDGE) a &= y < y1;
+            const uint64_t m = __ballot(a);
+            if (lane == 0) J.act[static_cast<long long>((y0 >> 4) + t) * J.act_bx + (x0 >> 4)] = m;
+            if (!a) return;
+        }
         if (EDGE && y >= y1) return;
         float* o = J.plane + static_cast<long long>(y) * w + x0 + 4 * g;
         if (!EDGE) {
@@ -453,13 +472,13 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
     }
 }
 
-template <typename T, int NKR, int NKC, bool CTL = false>
+template <typename T, int NKR, int NKC, bool CTL = false, bool SPARSE = false>
 __device__ __forceinline__ void run_job(const WaveJob& J, const half8_t* __restrict__ fr,
                                         int lane, const half8_t* cl = nullptr) {
     if (regular_job<T, NKR, NKC>(J))
-        wave_job<T, NKR, NKC, false, CTL>(J, fr, cl, lane);
+        wave_job<T, NKR, NKC, false, CTL, SPARSE>(J, fr, cl, lane);
     else
-        wave_job<T, NKR, NKC, true, CTL>(J, fr, cl, lane);
+        wave_job<T, NKR, NKC, true, CTL, SPARSE>(J, fr, cl, lane);
 }
 
 // Single-tile kernels of shapes with nkc >= 3 read their column taps from
@@ -477,13 +496,13 @@ constexpr int mfma_waves() { return NKC <= (sizeof(typename Elem<T>::type) == 1 
 template <typename T, int NKC>
 constexpr int mfma_batch_waves() { return NKC <= 2 ? 2 : 1; }
 
-template <typename T, int NKR, int NKC>
+template <typename T, int NKR, int NKC, bool SPARSE>
 __global__ __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(mfma_waves<T, NKC>(), 2)))
 void log_mfma_kernel(const typename Elem<T>::type* __restrict__ img, int h, int w,
                      long long pitch, int aligned, int out_vec,
                      const uint32_t* __restrict__ maxbits,
                      const half8_t* __restrict__ frags, MfmaLaunch L, float* __restrict__ out,
-                     long long plane_stride) {
+                     long long plane_stride, ActOut act) {
     const int bid = blockIdx.x;
     int si = 0;
     while (si + 1 < L.n && bid >= L.sc[si + 1].block_begin) ++si;
@@ -528,7 +547,10 @@ void log_mfma_kernel(const typename Elem<T>::type* __restrict__ img, int h, int 
     J.out_vec = out_vec;
     J.in_scale = in_s;
     J.out_scale = sc.out_scale / in_s * stretch;
-    run_job<T, NKR, NKC, CTL>(J, frags + sc.frag_off, threadIdx.x & 63, cl);
+    J.act = act.mask + static_cast<long long>(sc.plane) * act.by * act.bx;
+    J.act_bx = act.bx;
+    J.tau = act.tau;
+    run_job<T, NKR, NKC, CTL, SPARSE>(J, frags + sc.frag_off, threadIdx.x & 63, cl);
 }
 
 // Persistent form over a batch of tiles: every wave pulls items (scale j of
@@ -657,7 +679,7 @@ template <typename T, int NKR, int NKC>
 hipError_t launch_one(const typename Elem<T>::type* img, int h, int w, int64_t pitch,
                       const uint32_t* maxbits,
                       const uint16_t* frags, const MfmaLaunch& L, float* out,
-                      long long plane_stride, hipStream_t s) {
+                      long long plane_stride, const ActOut& act, hipStream_t s) {
     int blocks = 0;
     for (int i = 0; i < L.n; ++i) blocks += L.sc[i].n_blocks;
     if (blocks == 0) return hipSuccess;
@@ -667,9 +689,14 @@ hipError_t launch_one(const typename Elem<T>::type* img, int h, int w, int64_t p
     // float4 stores need 16-byte aligned rows and planes
     const int out_vec = (w % 4 == 0) && (plane_stride % 4 == 0) &&
                         (reinterpret_cast<uintptr_t>(out) % 16 == 0);
-    log_mfma_kernel<T, NKR, NKC><<<blocks, 64 * MW, 0, s>>>(
-        img, h, w, static_cast<long long>(pitch), aligned, out_vec, maxbits,
-        reinterpret_cast<const half8_t*>(frags), L, out, plane_stride);
+    if (act.mask)
+        log_mfma_kernel<T, NKR, NKC, true><<<blocks, 64 * MW, 0, s>>>(
+            img, h, w, static_cast<long long>(pitch), aligned, out_vec, maxbits,
+            reinterpret_cast<const half8_t*>(frags), L, out, plane_stride, act);
+    else
+        log_mfma_kernel<T, NKR, NKC, false><<<blocks, 64 * MW, 0, s>>>(
+            img, h, w, static_cast<long long>(pitch), aligned, out_vec, maxbits,
+            reinterpret_cast<const half8_t*>(frags), L, out, plane_stride, act);
     return hipGetLastError();
 }
 
@@ -820,11 +847,11 @@ hipError_t launch_log_mfma_batch(int in_dtype, int nkr, int nkc, int n_tiles,
 hipError_t launch_log_mfma(int in_dtype, int stretch, int nkr, int nkc, const void* img, int h,
                            int w, int64_t pitch, const uint32_t* maxbits, const uint16_t* frags,
                            const MfmaLaunch& L, float* out, long long plane_stride,
-                           hipStream_t s) {
+                           const ActOut& act, hipStream_t s) {
 #define MHFD_MFMA_CASE(T, A)                                                                \
     if (nkr == A && nkc == A)                                                               \
         return launch_one<T, A, A>(static_cast<const typename Elem<T>::type*>(img), h, w,   \
-                                   pitch, maxbits, frags, L, out, plane_stride, s);
+                                   pitch, maxbits, frags, L, out, plane_stride, act, s);
     if (in_dtype == MHFD_U8 && stretch) {
         MHFD_MFMA_CASE(U8Stretch, 1)
         MHFD_MFMA_CASE(U8Stretch, 2)

@@ -170,9 +170,20 @@ size_t log_stack_scratch_bytes(const mhfd_plan_s* p) {
 
 struct DetectLayout {
     size_t stack, blk_n, blk_o, blk_off, pool, cand, keep, keep_off, scan_sums, ctr, maxbits,
-        dog_max, dog_arg, total;
+        dog_max, dog_arg, act, total;
     int n_blk, bpr;
+    int act_bx, act_by;  // activity words of the threshold-sparse stack (0: dense plans)
 };
+
+// A detection without a caller stack keeps only the above-threshold part of
+// the stack (plus activity words) when every scale runs on the matrix cores
+// and the criterion is the LoG's; otherwise the whole stack.
+bool sparse_stack(const mhfd_plan_s* p) {
+    if (p->criterion != MHFD_CRITERION_LOG || !p->d_frags) return false;
+    for (int k = 0; k < p->K; ++k)
+        if (p->mfma_off[k] < 0) return false;
+    return true;
+}
 
 DetectLayout detect_layout(const mhfd_plan_s* p, int h, int w) {
     DetectLayout L{};
@@ -200,6 +211,10 @@ DetectLayout detect_layout(const mhfd_plan_s* p, int h, int w) {
     const bool dog = p->criterion == MHFD_CRITERION_DOG;
     L.dog_max = take(dog ? sizeof(float) * static_cast<size_t>(h) * w : 0);
     L.dog_arg = take(dog ? static_cast<size_t>(h) * w : 0);
+    const bool sp = sparse_stack(p);
+    L.act_bx = sp ? (w + 15) / 16 : 0;
+    L.act_by = sp ? (h + 15) / 16 : 0;
+    L.act = take(sizeof(uint64_t) * static_cast<size_t>(p->K) * L.act_bx * L.act_by);
     L.total = off;
     return L;
 }
@@ -636,7 +651,8 @@ std::vector<std::pair<std::pair<int, int>, mhfd::MfmaLaunch>> mfma_launches(cons
 size_t log_stack_scratch(const mhfd_plan_s* p) { return log_stack_scratch_bytes(p); }
 
 mhfd_status enqueue_log_stack(const mhfd_plan_s* p, const void* d_img, int h, int w,
-                              int64_t pitch, float* stack, uint32_t* maxbits, hipStream_t s) {
+                              int64_t pitch, float* stack, uint32_t* maxbits, hipStream_t s,
+                              const mhfd::ActOut& act = mhfd::ActOut{nullptr, 0, 0, 0.0f}) {
     std::vector<int> strip_scales;
     for (int k = 0; k < p->K; ++k)
         if (p->mfma_off.empty() || p->mfma_off[k] < 0) strip_scales.push_back(k);
@@ -658,7 +674,7 @@ mhfd_status enqueue_log_stack(const mhfd_plan_s* p, const void* d_img, int h, in
     for (const auto& ml : mls) {
         hipError_t e = mhfd::launch_log_mfma(p->dtype, p->stretch, ml.first.first, ml.first.second,
                                              d_img, h, w, pitch, range, p->d_frags, ml.second,
-                                             stack, static_cast<long long>(h) * w, s);
+                                             stack, static_cast<long long>(h) * w, act, s);
         if (e != hipSuccess) return hip_fail(e, "LoG stack (matrix cores) launch");
     }
     auto launches = make_launches(
@@ -677,8 +693,13 @@ mhfd_status enqueue_log_stack(const mhfd_plan_s* p, const void* d_img, int h, in
 
 mhfd_status enqueue_tail(const mhfd_plan_s* p, const float* stack, int h, int w,
                          const DetectLayout& L, char* base, mhfd_blob* d_blobs, int capacity,
-                         mhfd_result* d_result, hipStream_t s) {
+                         mhfd_result* d_result, hipStream_t s, const uint64_t* act = nullptr) {
     mhfd::DetectWorkspace ws;
+    if (act) {
+        ws.act = act;
+        ws.act_bx = (w + 15) / 16;
+        ws.act_by = (h + 15) / 16;
+    }
     ws.stack = stack;
     ws.blk_n = reinterpret_cast<int32_t*>(base + L.blk_n);
     ws.blk_o = reinterpret_cast<int32_t*>(base + L.blk_o);
@@ -888,6 +909,57 @@ mhfd_status mhfd_detect_stack(mhfd_plan p, const float* d_stack, int32_t h, int3
                         static_cast<hipStream_t>(stream));
 }
 
+size_t mhfd_activity_bytes(mhfd_plan p, int32_t h, int32_t w) {
+    if (!p || h < 1 || w < 1 || h > p->max_h || w > p->max_w || !sparse_stack(p)) return 0;
+    return sizeof(uint64_t) * static_cast<size_t>(p->K) * ((h + 15) / 16) * ((w + 15) / 16);
+}
+
+mhfd_status mhfd_log_stack_sparse(mhfd_plan p, const void* d_img, int32_t h, int32_t w,
+                                  int64_t pitch, float* d_stack, uint64_t* d_act, void* d_ws,
+                                  size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    mhfd_status st = check_image(p, d_img, h, w, pitch);
+    if (st != MHFD_OK) return st;
+    if (!sparse_stack(p))
+        return fail(MHFD_ERR_UNSUPPORTED, "this plan has no threshold-sparse stack (DoG criterion "
+                    "or a radius above 56)");
+    if (!d_stack || !d_act) return fail(MHFD_ERR_INVALID_ARG, "null stack or activity words");
+    if (reinterpret_cast<uintptr_t>(d_act) % 8)
+        return fail(MHFD_ERR_INVALID_ARG, "activity words not 8-byte aligned");
+    const size_t need = log_stack_scratch(p);
+    if (need) {
+        if (!d_ws) return fail(MHFD_ERR_INVALID_ARG, "null workspace (this plan needs %zu bytes)", need);
+        if (reinterpret_cast<uintptr_t>(d_ws) % 4)
+            return fail(MHFD_ERR_INVALID_ARG, "workspace not 4-byte aligned");
+        if (ws_bytes < need)
+            return fail(MHFD_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
+    }
+    if ((st = check_device(p)) != MHFD_OK) return st;
+    const mhfd::ActOut act{d_act, (w + 15) / 16, (h + 15) / 16, p->threshold};
+    return enqueue_log_stack(p, d_img, h, w, pitch, d_stack, static_cast<uint32_t*>(d_ws),
+                             static_cast<hipStream_t>(stream), act);
+}
+
+mhfd_status mhfd_detect_stack_sparse(mhfd_plan p, const float* d_stack, const uint64_t* d_act,
+                                     int32_t h, int32_t w, mhfd_blob* d_blobs, int32_t capacity,
+                                     mhfd_result* d_result, void* d_ws, size_t ws_bytes,
+                                     void* stream) {
+    g_last_error.clear();
+    mhfd_status st = check_image(p, d_stack, h, w, w);
+    if (st != MHFD_OK) return st;
+    if (!sparse_stack(p))
+        return fail(MHFD_ERR_UNSUPPORTED, "this plan has no threshold-sparse stack (DoG criterion "
+                    "or a radius above 56)");
+    if (!d_act || reinterpret_cast<uintptr_t>(d_act) % 8)
+        return fail(MHFD_ERR_INVALID_ARG, "null or misaligned activity words");
+    DetectLayout L;
+    if ((st = check_outputs(p, h, w, d_blobs, capacity, d_result, d_ws, ws_bytes, &L)) != MHFD_OK)
+        return st;
+    if ((st = check_device(p)) != MHFD_OK) return st;
+    return enqueue_tail(p, d_stack, h, w, L, static_cast<char*>(d_ws), d_blobs, capacity, d_result,
+                        static_cast<hipStream_t>(stream), d_act);
+}
+
 mhfd_status mhfd_detect(mhfd_plan p, const void* d_img, int32_t h, int32_t w, int64_t pitch,
                         mhfd_blob* d_blobs, int32_t capacity, mhfd_result* d_result,
                         float* d_stack, void* d_ws, size_t ws_bytes, void* stream) {
@@ -901,10 +973,15 @@ mhfd_status mhfd_detect(mhfd_plan p, const void* d_img, int32_t h, int32_t w, in
     hipStream_t s = static_cast<hipStream_t>(stream);
     char* base = static_cast<char*>(d_ws);
     float* stack = d_stack ? d_stack : reinterpret_cast<float*>(base + L.stack);
+    // Without a caller stack, only the part of the stack above the threshold
+    // is written and read (the rest cannot change a decision).
+    const bool sparse = !d_stack && L.act_bx > 0;
+    const mhfd::ActOut act{sparse ? reinterpret_cast<uint64_t*>(base + L.act) : nullptr,
+                           L.act_bx, L.act_by, p->threshold};
     if ((st = enqueue_log_stack(p, d_img, h, w, pitch, stack,
-                                reinterpret_cast<uint32_t*>(base + L.maxbits), s)) != MHFD_OK)
+                                reinterpret_cast<uint32_t*>(base + L.maxbits), s, act)) != MHFD_OK)
         return st;
-    return enqueue_tail(p, stack, h, w, L, base, d_blobs, capacity, d_result, s);
+    return enqueue_tail(p, stack, h, w, L, base, d_blobs, capacity, d_result, s, act.mask);
 }
 
 size_t mhfd_batch_workspace_size(mhfd_plan p, int32_t max_tiles, int64_t max_pixels) {

@@ -131,6 +131,16 @@ struct MfmaLaunch {
     MfmaScale sc[MHFD_MAX_SCALES];
 };
 
+// Threshold-sparse stack output (mask null: the dense stack): only the
+// 4-pixel row groups holding a value above tau are written; activity word
+// [k][by][bx] (by < ceil(h/16), bx < ceil(w/16)) marks them, bit 16 g + r
+// for row 16 by + r, columns 16 bx + 4 g ... + 3.
+struct ActOut {
+    uint64_t* mask;
+    int bx, by;
+    float tau;
+};
+
 // in_dtype MHFD_U8 or MHFD_F32.  maxbits: fp32 inputs, the float bits of the
 // tile's max |I| (launch_absmax), which picks the exact input scale;
 // stretched u8 inputs (stretch = 1), the levels {low, high}
@@ -138,7 +148,7 @@ struct MfmaLaunch {
 hipError_t launch_log_mfma(int in_dtype, int stretch, int nkr, int nkc, const void* img, int h,
                            int w, int64_t pitch, const uint32_t* maxbits, const uint16_t* frags,
                            const MfmaLaunch& L, float* out, long long plane_stride,
-                           hipStream_t s);
+                           const ActOut& act, hipStream_t s);
 // The paper's DoG criterion: M = max_i sig_i (L_{i+1} - L_i) over K Gaussian
 // planes and its first argmax (u8); then the blob records' k and sigma from
 // the argmax plane (after the detection tail ran on M).
@@ -169,6 +179,12 @@ struct DetectWorkspace {
     int64_t cap;             // candidate capacity
     int n_blk;               // number of NMS blocks
     int blk_per_row;         // NMS blocks per image row
+    // Threshold-sparse stack (null: dense): K x act_by x act_bx words, bit
+    // 16 g + r of word [k][by][bx] set when row 16 by + r, columns 16 bx +
+    // 4 g ... + 3 of plane k hold a value above the threshold and were
+    // written; other groups of the stack are not read.
+    const uint64_t* act = nullptr;
+    int act_bx = 0, act_by = 0;
 };
 
 // d2max: K x K table, d2max[ka * K + kb] = largest squared integer distance at

@@ -80,9 +80,24 @@ struct Sink {
 // Every (row, strip) cell compacts its candidates in (x, k) order with
 // ballot/mbcnt offsets into its own pool slot and reserves the overflow
 // region with one atomic only when it has more.
-template <int K, int CW, int SLOTS>
+//
+// Threshold-sparse stacks (SPARSE): the LoG wrote only the 4-pixel row
+// groups holding a value above tau, and marked them in `act` (bit 16 g + r
+// of word [k][by][bx]: row 16 by + r, columns 16 bx + 4 g ... + 3; every
+// word is written).  A value at or below tau can neither be a candidate
+// nor block one (a blocking neighbour exceeds the candidate, which exceeds
+// tau), so every unmarked group reads as -inf: the same decisions as the
+// dense stack, and only marked groups are fetched.  Rows outside the image
+// read as -inf too, which the -inf padding of the definition allows.
+struct Active {
+    const uint64_t* mask;  // K x mby x mbx words
+    int mbx, mby;
+};
+
+template <int K, int CW, int SLOTS, bool SPARSE = false>
 __device__ __forceinline__ void wave(const float* __restrict__ st, int H, int W, float tau,
-                                     int bpr, int strip, int run, const Sink& out) {
+                                     int bpr, int strip, int run, const Sink& out,
+                                     const Active& act = Active{nullptr, 0, 0}) {
     static_assert(CW * K <= 32, "candidate mask is 32 bits");
     typedef float Vec __attribute__((ext_vector_type(CW)));
     typedef Vec Row[K];
@@ -99,16 +114,46 @@ __device__ __forceinline__ void wave(const float* __restrict__ st, int H, int W,
     const int hx = min(max(lane < 32 ? x0 - 1 : x0 + 64 * CW, 0), W - 1);
     const float* __restrict__ hbase = st + static_cast<size_t>(hk) * plane + hx;
 
+    // SPARSE: marks of rows y0 - 1 ... y0 + 16 (bit i: row y0 - 1 + i) of the
+    // lane's group in every plane, and of the halo lane's group.
+    uint32_t abits[SPARSE ? K : 1] = {};
+    uint32_t hbits = 0;
+    if constexpr (SPARSE) {
+        const int by = y0 >> 4;
+        auto run_bits = [&](int k, int x) -> uint32_t {
+            const int sh = 16 * ((x >> 2) & 3);
+            const uint64_t* m = act.mask + static_cast<size_t>(k) * act.mby * act.mbx + (x >> 4);
+            const uint32_t cur = static_cast<uint32_t>(m[static_cast<size_t>(by) * act.mbx] >> sh) & 0xFFFFu;
+            const uint32_t up = y0 > 0
+                ? static_cast<uint32_t>(m[static_cast<size_t>(by - 1) * act.mbx] >> (sh + 15)) & 1u : 0u;
+            const uint32_t dn = y0 + 16 < H
+                ? static_cast<uint32_t>(m[static_cast<size_t>(by + 1) * act.mbx] >> sh) & 1u : 0u;
+            return up | (cur << 1) | (dn << 17);
+        };
+#pragma unroll
+        for (int k = 0; k < K; ++k) abits[k] = run_bits(k, xc);
+        hbits = run_bits(hk, hx);
+    }
+
     // Plane k's rows start at the wave-uniform st + k plane; the lane's part
     // is a 32-bit byte offset (a plane holds fewer than 2^29 pixels).
     auto load_row = [&](int y, Row& v, float& hv) {
         const int yy = min(max(y, 0), H - 1);
         const uint32_t boff = static_cast<uint32_t>(yy * W + xc) * 4u;
+        const int bit = y - y0 + 1;  // 0 .. 18
 #pragma unroll
-        for (int k = 0; k < K; ++k)
-            v[k] = *reinterpret_cast<const Vec*>(
+        for (int k = 0; k < K; ++k) {
+            const Vec* p = reinterpret_cast<const Vec*>(
                 reinterpret_cast<const char*>(st + static_cast<size_t>(k) * plane) + boff);
-        hv = hbase[static_cast<size_t>(yy) * W];
+            if constexpr (SPARSE)
+                v[k] = (abits[k] >> bit) & 1u ? *p : static_cast<Vec>(-INFINITY);
+            else
+                v[k] = *p;
+        }
+        if constexpr (SPARSE)
+            hv = (hbits >> bit) & 1u ? hbase[static_cast<size_t>(yy) * W] : -INFINITY;
+        else
+            hv = hbase[static_cast<size_t>(yy) * W];
     };
     auto test_row = [&](int y, const Row& up, const Row& cur, const Row& dn, float hup,
                         float hcur, float hdn) {

@@ -248,6 +248,34 @@ def test_split_entry_points_equal_detect(plans):
     n = int(res[0])
     assert n == d.count
     assert torch.equal(raw[:n, :3], d.yxk)
+    # the threshold-sparse halves give what mhfd_detect without a stack gives
+    na = L.mhfd_activity_bytes(p._handle, 512, 512)
+    assert na == 8 * 10 * 32 * 32
+    act = torch.empty(na // 8, dtype=torch.int64, device=p.device)
+    sp = torch.full_like(st, float("nan"))
+    _lib.check(L.mhfd_log_stack_sparse(p._handle, img.data_ptr(), 512, 512, 512, sp.data_ptr(),
+                                       act.data_ptr(), lws.data_ptr(), nl, s), "lss")
+    res2 = torch.zeros(_lib.RESULT_WORDS, dtype=torch.int64, device=p.device)
+    raw2 = torch.empty((cap, 5), dtype=torch.int32, device=p.device)
+    _lib.check(L.mhfd_detect_stack_sparse(p._handle, sp.data_ptr(), act.data_ptr(), 512, 512,
+                                          raw2.data_ptr(), cap, res2.data_ptr(), ws.data_ptr(),
+                                          nb, s), "dss")
+    d2 = p.detect(img)
+    torch.cuda.synchronize()
+    assert int(res2[0]) == d2.count == n and int(res2[1]) == d2.n_candidates
+    assert torch.equal(raw2[:n], raw[:n])
+    # written groups hold the dense stack's values, and every value above the
+    # threshold lies in a written group
+    bits = act.cpu().numpy().view(np.uint64).reshape(10, 32, 32)
+    g = np.zeros((10, 512, 128), bool)
+    for r in range(16):
+        for q in range(4):
+            g[:, r::16, q::4] = ((bits >> np.uint64(16 * q + r)) & np.uint64(1)).astype(bool)
+    full = np.repeat(g, 4, axis=2)
+    dense, spv = st.cpu().numpy(), sp.cpu().numpy()
+    np.testing.assert_array_equal(spv[full], dense[full])
+    assert not np.any(dense[~full] > np.float32(0.1))
+    assert np.all(np.isnan(spv[~full])) and 0.02 < full.mean() < 0.6
 
 
 def test_full_size_sem_tile():
@@ -388,3 +416,53 @@ def test_benchmark_tiles_prune_and_focus_order():
     print("batched, the same four tiles", flush=True)
     for dt, exp in zip(detect_batched(plan_p, tiles, capacity=1 << 17), expected):
         np.testing.assert_array_equal(dt.yxk.cpu().numpy().astype(np.int64), exp)
+
+
+@pytest.mark.parametrize("dtype,shape,K,seed", [("f32", (512, 512), 10, 0), ("f32", (97, 130), 10, 1),
+                                                ("f32", (200, 129), 4, 2), ("u8", (300, 260), 10, 3),
+                                                ("u8", (33, 65), 10, 4), ("u8", (1, 50), 3, 5),
+                                                ("f32", (64, 64), 1, 6), ("u8", (1000, 1000), 10, 7)])
+def test_threshold_sparse_stack_equals_dense(dtype, shape, K, seed):
+    """Without a caller stack the detector writes and reads only the 4-pixel
+    groups above the threshold; with one it writes the whole stack.  Both
+    must give the same candidates, responses, blobs and counts (values at or
+    below the threshold can neither be candidates nor block one)."""
+    import torch
+    from paper_2108_12050_amd import Plan
+    print(f"sparse vs dense {dtype} {shape} K={K}", flush=True)
+    H, W = shape
+    if dtype == "u8":
+        img = synth.sem_tile(seed, psf_sigma=1.0, H=H, W=W)
+        tau = 0.05
+    else:
+        img = synth.blob_field(seed, H, W, n_blobs=max(1, H * W // 1300))
+        tau = 0.1
+    for overlap in (1.0, 0.5):
+        plan = Plan(n_scales=K, sigma_min=1.0, sigma_max=max(1.0, K * 1.0), threshold=tau,
+                    overlap=overlap, dtype=dtype, max_h=1024, max_w=1024)
+        t = torch.from_numpy(img).to(plan.device)
+        dense = plan.detect(t, return_stack=True)
+        sparse = plan.detect(t)
+        assert torch.equal(dense.yxk, sparse.yxk)
+        assert torch.equal(dense.response, sparse.response)
+        assert (dense.count, dense.n_candidates) == (sparse.count, sparse.n_candidates)
+        own = own_maxima(dense.stack.cpu().numpy(), tau)
+        if overlap >= 1.0:
+            np.testing.assert_array_equal(sparse.yxk.cpu().numpy().astype(np.int64), own)
+
+
+def test_threshold_sparse_dark_polarity_and_stretch():
+    import torch
+    from paper_2108_12050_amd import Plan
+    img = 1.0 - synth.blob_field(9, 160, 200, n_blobs=20)
+    plan = Plan(n_scales=6, sigma_min=1.0, sigma_max=6.0, polarity="dark", threshold=0.1,
+                overlap=0.5, max_h=256, max_w=256)
+    t = torch.from_numpy(img).to(plan.device)
+    a, b = plan.detect(t, return_stack=True), plan.detect(t)
+    assert torch.equal(a.yxk, b.yxk) and a.count == b.count > 3
+    u8 = synth.sem_tile(2, psf_sigma=0.0, H=256, W=320)
+    plan = Plan(n_scales=10, sigma_min=1.0, sigma_max=10.0, threshold=0.05, overlap=0.5,
+                dtype="u8", stretch=True, max_h=256, max_w=320)
+    t = torch.from_numpy(u8).to(plan.device)
+    a, b = plan.detect(t, return_stack=True), plan.detect(t)
+    assert torch.equal(a.yxk, b.yxk) and torch.equal(a.response, b.response) and a.count > 10
