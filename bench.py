@@ -29,7 +29,7 @@ Besides the headline line the JSON carries:
                  sizes 512..8192), p50 / p99 latency and throughput;
   cpu_baseline   the FP64 oracle on the same 4096^2 tile, on this host's cores.
 
-    python bench.py [--gpus 1] [--steps 200] [--warmup 10] [--serve-seconds 10]
+    python bench.py [--gpus 1] [--steps 200] [--warmup 10] [--serve-seconds 60]
 """
 from __future__ import annotations
 
@@ -58,6 +58,7 @@ PEAK_FP32_VECTOR_UNPACKED = 78.6e12
 PEAK_FP16_MFMA = 2.5e15       # MI355X dense FP16 matrix
 PEAK_HBM = 8.0e12             # MI355X HBM3E bytes/s
 COUNTER_FILE = os.path.join(ROOT, "profiles", "log_mfma_4096_u8_counters.json")
+BATCH_LANES = 3   # concurrent sub-batches of the batched form (one captured graph)
 LOG_KERNEL = "log_mfma_kernel"  # log_mfma_kernel<T, nkr, nkc>; the batch kernel is named apart
 
 
@@ -66,25 +67,48 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def cpu_baseline(img, rows: int) -> dict:
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(img, rows: int, rows_1t: int = 256) -> dict:
     """The oracle as it stands on rows [0, rows) of the tile (plus the 42-row
-    halo that the largest kernel needs), timed once."""
+    halo that the largest kernel needs), timed once on every host thread,
+    and on rows [0, rows_1t) with one thread."""
     import numpy as np
 
     import oracle
     sig = oracle.linear_sigmas(K, 1.0, 10.0)
-    band = img[:rows + 42]
     oracle.lib()
-    t0 = time.perf_counter()
-    st = oracle.log_stack(band, sig)
-    ykx, _ = oracle.candidates(st[:, :rows + 1], float(np.float32(TAU)))
-    ykx = ykx[ykx[:, 0] < rows]
-    oracle.prune(ykx, sig, OVERLAP)
-    dt = time.perf_counter() - t0
+
+    def run(n_rows):
+        band = img[:n_rows + 42]
+        t0 = time.perf_counter()
+        st = oracle.log_stack(band, sig)
+        ykx, _ = oracle.candidates(st[:, :n_rows + 1], float(np.float32(TAU)))
+        ykx = ykx[ykx[:, 0] < n_rows]
+        oracle.prune(ykx, sig, OVERLAP)
+        return time.perf_counter() - t0
+
+    cores = oracle.threads()
+    dt = run(rows)
+    oracle.set_threads(1)
+    dt1 = run(rows_1t)
+    oracle.set_threads(cores)
     return {"value": round(rows * W / dt / 1e6, 4), "unit": "MPix/s",
-            "cores": oracle.threads(), "kind": "oracle",
+            "cores": cores, "kind": "oracle", "nproc": os.cpu_count(),
+            "cpu_model": _cpu_model(),
+            "single_thread_mpix_s": round(rows_1t * W / dt1 / 1e6, 4),
             "sample": f"rows 0..{rows - 1} of the 4096x4096 in-focus tile (+42 halo rows), "
-                      f"full detector (stack, maxima, prune) in FP64, one run, {dt:.1f} s"}
+                      f"full detector (stack, maxima, prune) in FP64, one run on {cores} "
+                      f"threads, {dt:.1f} s; single thread: rows 0..{rows_1t - 1}, "
+                      f"{dt1:.1f} s"}
 
 
 def _timed(fn, reps):
@@ -228,7 +252,7 @@ def bench_batched(warmup: int) -> dict:
     classes = sorted(set((h, w) for h, w, _ in shapes))
     report = tuner.tune(classes, reps=3)
     segs = [tuner.seg_rows_for(*t.shape) for t in imgs]
-    r = BatchRunner(plan, 64, px, 1 << 17)
+    r = BatchRunner(plan, 64, px, 1 << 17, lanes=BATCH_LANES)
     r.set_tiles(imgs, segs)
     g = r.capture()
     for _ in range(max(1, warmup // 5)):
@@ -252,6 +276,27 @@ def bench_batched(warmup: int) -> dict:
     plain_all()
     plain_ms = _timed(plain_all, 3)
     counts_p = ress[:, 0].cpu().tolist()
+    # the same calls round-robin on three streams (independent tiles, as the
+    # headline issues them), each stream with its own workspace and outputs
+    streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(2)]
+    ws3 = [ws] + [torch.empty_like(ws) for _ in range(2)]
+    raws3 = [raws] + [torch.empty_like(raws) for _ in range(2)]
+    ress3 = torch.zeros_like(ress)
+
+    def plain_3s():
+        for s_ in streams[1:]:
+            s_.wait_stream(streams[0])
+        for i, t in enumerate(imgs):
+            j = i % 3
+            _lib.check(L.mhfd_detect(plan._handle, t.data_ptr(), t.shape[0], t.shape[1],
+                                     t.stride(0), raws3[j].data_ptr(), cap, ress3[i].data_ptr(),
+                                     None, ws3[j].data_ptr(), ws.numel(),
+                                     int(streams[j].cuda_stream)), "mhfd_detect")
+        for s_ in streams[1:]:
+            streams[0].wait_stream(s_)
+    plain_3s()
+    plain3_ms = _timed(plain_3s, 3)
+    counts_p3 = ress3[:, 0].cpu().tolist()
     mp = px / 1e6
     return {"workload": "64 fp32 tiles, sizes {1024^2, 2048x1536, 3072x2048, 4096^2}, "
                         "sigma 1..10, threshold 0.1, overlap 0.5",
@@ -259,9 +304,12 @@ def bench_batched(warmup: int) -> dict:
             "batched_graph_mpix_s": round(mp / (np.median(graph_ms) * 1e-3), 1),
             "batched_eager_mpix_s": round(mp / (np.median(eager_ms) * 1e-3), 1),
             "plain_per_tile_mpix_s": round(mp / (np.median(plain_ms) * 1e-3), 1),
+            "plain_per_tile_3streams_mpix_s": round(mp / (np.median(plain3_ms) * 1e-3), 1),
             "batched_graph_ms": round(float(np.median(graph_ms)), 3),
             "plain_per_tile_ms": round(float(np.median(plain_ms)), 3),
-            "identical_counts": counts_b == counts_p,
+            "plain_per_tile_3streams_ms": round(float(np.median(plain3_ms)), 3),
+            "identical_counts": counts_b == counts_p == counts_p3,
+            "lanes": BATCH_LANES,
             "seg_rows": {f"{h}x{w}": report[(h, w)][0] for (h, w) in classes}}
 
 
@@ -289,16 +337,20 @@ def bench_soft() -> dict:
 
 
 def bench_serving(seconds: float) -> dict:
-    """Serving workload slice: Poisson arrivals at 50/s, square sizes
+    """Serving workload: Poisson arrivals at 50/s for `seconds`, square sizes
     {512, 1024, 2048, 4096, 8192} with probabilities {.1, .2, .3, .3, .1},
     plain-workload content from a pool of 2 rendered tiles per size in pinned
-    host memory, 64 GB HBM budget, two batch slots."""
+    host memory, 64 GB HBM budget, two batch slots; latency end to end (host
+    copy included) and on the device.  Then the same mix at saturation (4000
+    requests/s for 2 s, above what the GPU detects) with the pool already on
+    the device, served by the batched server and by the same scheduler
+    issuing one plain mhfd_detect call per tile on three streams."""
     import time
 
     import torch
 
     from paper_2108_12050_amd import Plan, synth
-    from paper_2108_12050_amd.serve import GpuExecutor, Server, summarize
+    from paper_2108_12050_amd.serve import GpuExecutor, PlainExecutor, Server, summarize
     times, sizes = synth.arrivals(0, 50.0, seconds)
     pool = {}
     for sz in sorted(set(sizes)):
@@ -306,25 +358,41 @@ def bench_serving(seconds: float) -> dict:
             pool[(sz, j)] = torch.from_numpy(synth.blob_field(2000 + 10 * sz + j, sz, sz)).pin_memory()
     plan = Plan(n_scales=K, sigma_min=1.0, sigma_max=10.0, threshold=0.1, overlap=OVERLAP,
                 max_h=8192, max_w=8192)
-    ex = GpuExecutor(plan, n_slots=2, slot_tiles=16, slot_pixels=1 << 27)
-    srv = Server(ex, 64 << 30)
-    t0 = time.perf_counter()
-    out = srv.run_trace(times, [pool[(s, i % 2)] for i, s in enumerate(sizes)])
-    wall = time.perf_counter() - t0
-    st = summarize(out, wall)
-    return {"workload": f"{seconds:g} s of Poisson arrivals at 50/s, sizes 512..8192",
-            "requests": st["requests"], "served": st["served"],
-            "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
-            "mpix_per_s": round(st["mpix_per_s"], 1),
-            "offered_mpix_per_s": round(st["mpix"] / seconds, 1),
-            "max_batches_in_flight": srv.max_inflight}
+
+    def run(ex, arrivals, szs, imgs):
+        srv = Server(ex, 64 << 30)
+        t0 = time.perf_counter()
+        out = srv.run_trace(arrivals, [imgs[(s, i % 2)] for i, s in enumerate(szs)])
+        wall = time.perf_counter() - t0
+        st = summarize(out, wall)
+        r3 = lambda v: None if v is None else round(v, 3)  # noqa: E731
+        return {"requests": st["requests"], "served": st["served"],
+                "p50_ms": r3(st["p50_ms"]), "p99_ms": r3(st["p99_ms"]),
+                "device_p50_ms": r3(st["device_p50_ms"]), "device_p99_ms": r3(st["device_p99_ms"]),
+                "mpix_per_s": round(st["mpix_per_s"], 1),
+                "offered_mpix_per_s": round(st["mpix"] / max(arrivals[-1], 1e-9), 1),
+                "max_batches_in_flight": srv.max_inflight}
+
+    batched = GpuExecutor(plan, n_slots=2, slot_tiles=16, slot_pixels=1 << 27)
+    out = {"trace": dict(workload=f"{seconds:g} s of Poisson arrivals at 50/s, sizes "
+                                  "512..8192, host tiles (copy included)",
+                         **run(batched, times, sizes, pool))}
+    dev_pool = {k: v.cuda() for k, v in pool.items()}
+    st_times, st_sizes = synth.arrivals(1, 4000.0, 2.0)
+    plain = PlainExecutor(plan, n_slots=3, max_h=8192, max_w=8192)
+    out["saturation"] = {
+        "workload": "2 s of Poisson arrivals at 4000/s (same size mix), tiles on the device",
+        "batched": run(batched, st_times, st_sizes, dev_pool),
+        "plain_per_tile_3streams": run(plain, st_times, st_sizes, dev_pool)}
+    return out
 
 
 def traffic_run() -> int:
-    """Workload for the HBM-traffic counter runs (rocprofv3 --pmc FETCH_SIZE,
-    then --pmc WRITE_SIZE): first a plain elementwise copy of exactly 256 MiB
-    (the calibration of the counters), then three 4096^2 u8 tiles through
-    mhfd_log_stack and mhfd_detect_stack."""
+    """Workload for the counter runs (rocprofv3 --pmc FETCH_SIZE, then --pmc
+    WRITE_SIZE, then the SQ instruction counters): first a plain elementwise
+    copy of exactly 256 MiB (the calibration of the byte counters), then
+    three 4096^2 u8 tiles through the detector as the benchmark times it
+    (mhfd_log_stack_sparse and mhfd_detect_stack_sparse)."""
     import torch
 
     from paper_2108_12050_amd import Plan, _lib, synth
@@ -338,6 +406,8 @@ def traffic_run() -> int:
                 dtype="u8", max_h=H, max_w=W)
     L = _lib.load()
     stack = torch.empty((K, H, W), dtype=torch.float32, device="cuda")
+    act = torch.empty(L.mhfd_activity_bytes(plan._handle, H, W) // 8, dtype=torch.int64,
+                      device="cuda")
     cap = H * W // 64
     raw = torch.empty((cap, 5), dtype=torch.int32, device="cuda")
     res = torch.zeros(_lib.RESULT_WORDS, dtype=torch.int64, device="cuda")
@@ -345,10 +415,11 @@ def traffic_run() -> int:
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
     sp = int(torch.cuda.current_stream().cuda_stream)
     for _ in range(3):
-        _lib.check(L.mhfd_log_stack(plan._handle, img.data_ptr(), H, W, W, stack.data_ptr(),
-                                    None, 0, sp), "ls")
-        _lib.check(L.mhfd_detect_stack(plan._handle, stack.data_ptr(), H, W, raw.data_ptr(), cap,
-                                       res.data_ptr(), ws.data_ptr(), nb, sp), "ds")
+        _lib.check(L.mhfd_log_stack_sparse(plan._handle, img.data_ptr(), H, W, W,
+                                           stack.data_ptr(), act.data_ptr(), None, 0, sp), "ls")
+        _lib.check(L.mhfd_detect_stack_sparse(plan._handle, stack.data_ptr(), act.data_ptr(), H,
+                                              W, raw.data_ptr(), cap, res.data_ptr(),
+                                              ws.data_ptr(), nb, sp), "ds")
     torch.cuda.synchronize()
     print("traffic run done", flush=True)
     return 0
@@ -432,11 +503,30 @@ def profile_run(kind: str) -> int:
                     max_h=4096, max_w=4096)
         tuner = Autotuner(plan)
         tuner.tune(sorted(set((h, w) for h, w, _ in shapes)), reps=1)
-        r = BatchRunner(plan, 64, sum(t.numel() for t in imgs), 1 << 17)
+        r = BatchRunner(plan, 64, sum(t.numel() for t in imgs), 1 << 17, lanes=BATCH_LANES)
         r.set_tiles(imgs, [tuner.seg_rows_for(*t.shape) for t in imgs])
         g = r.capture()
         for _ in range(6):
             g.replay()
+    elif kind == "plain_f32":
+        # the batched form's 64 tiles through single-tile mhfd_detect calls,
+        # one stream, six passes
+        shapes = synth.mixed_batch_shapes(0, 64)
+        pool = {}
+        for i, (h, w, p) in enumerate(shapes):
+            key = (h, w, i % 2)
+            if key not in pool:
+                pool[key] = torch.from_numpy(synth.blob_field(1000 + len(pool), h, w,
+                                                              psf_sigma=p)).cuda()
+        imgs = [pool[(h, w, i % 2)] for i, (h, w, p) in enumerate(shapes)]
+        plan = Plan(n_scales=K, sigma_min=1.0, sigma_max=10.0, threshold=0.1, overlap=OVERLAP,
+                    max_h=4096, max_w=4096)
+        raw = torch.empty((1 << 17, 5), dtype=torch.int32, device="cuda")
+        res = torch.zeros(4, dtype=torch.int64, device="cuda")
+        ws = torch.empty(plan.detect_workspace_bytes(4096, 4096), dtype=torch.uint8, device="cuda")
+        for _ in range(6):
+            for t in imgs:
+                plan.detect_into(t, raw, res, None, ws)
     elif kind in ("stretch", "dog"):
         img = torch.from_numpy(synth.sem_tile(0, psf_sigma=0.0)).cuda()
         if kind == "stretch":
@@ -471,7 +561,7 @@ def main() -> int:
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the batched, soft-score and serving forms and the stretched and "
                          "paper-criterion detectors")
-    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--streams", type=int, default=3,
                     help="streams the plain per-tile calls alternate over (independent tiles)")
     a = ap.parse_args()
@@ -579,7 +669,7 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f16-split MFMA (hi*hi + hi*lo + lo*hi), f32 accumulate",
         "data": "synthetic",
         "config": {"workload": "SEM-tile 4096x4096 u8, sigma 1..10 (K=10, radius 4 sigma), "
                                "threshold 0.05, overlap 0.5, psf sigma {0,1,2,4}, plain per-tile",

@@ -145,11 +145,14 @@ typedef struct mhfd_config {
                                 batched and focus-score calls refuse such a
                                 plan (MHFD_ERR_UNSUPPORTED).  0: no stretch    */
     int32_t criterion;       /* MHFD_CRITERION_LOG (0) or MHFD_CRITERION_DOG (1) */
-    float sigma_cap;         /* largest sigma a focus-score call may be given
-                                (trainable scales); its radius floor(truncate *
-                                sigma_cap + 0.5) <= MHFD_MAX_RADIUS sizes the
-                                halos of those calls.  0: the plan's largest
-                                sigma.  Must be >= every sigma of the plan     */
+    float sigma_cap;         /* focus-score calls (trainable scales): > 0, the
+                                largest sigma any scale may be given; its
+                                radius floor(truncate * sigma_cap + 0.5) <=
+                                MHFD_MAX_RADIUS sizes the halos of every scale
+                                (>= every sigma of the plan).  0: each scale's
+                                halo is its plan radius rounded up to a
+                                multiple of 4, and a sigma may move while its
+                                radius stays within that                       */
 } mhfd_config;
 
 typedef struct mhfd_plan_s *mhfd_plan;
@@ -269,7 +272,8 @@ mhfd_status mhfd_detect_stack(mhfd_plan plan, const float *d_stack, int32_t h, i
  * then written; the other groups of d_stack are left as they were).
  *   mhfd_activity_bytes  bytes of the activity words for an h x w image;
  *                        0 for plans without this form (the DoG criterion,
- *                        or a radius above 56) and on bad input.
+ *                        a radius above 56, or a negative threshold) and on
+ *                        bad input.
  *   mhfd_log_stack_sparse   as mhfd_log_stack, plus d_act (8-byte aligned,
  *                           mhfd_activity_bytes bytes, every word written).
  *   mhfd_detect_stack_sparse  as mhfd_detect_stack on such a stack.
@@ -326,8 +330,9 @@ mhfd_status mhfd_detect_batched(mhfd_plan plan, int32_t n, const mhfd_tile *d_ti
  * batch of b images of h x w (0 on bad input). */
 size_t mhfd_focus_workspace_size(mhfd_plan plan, int32_t b, int32_t h, int32_t w);
 
-/* A sigma given to a focus-score call lies outside (0, sigma_cap] or is not
- * finite: that call's scores and gradients are not valid. */
+/* A sigma given to a focus-score call is outside what the plan's halos
+ * allow (see mhfd_config.sigma_cap) or not finite: that call's scores and
+ * gradients are not valid. */
 #define MHFD_FOCUS_BAD_SIGMA 1
 
 /*
@@ -341,7 +346,8 @@ size_t mhfd_focus_workspace_size(mhfd_plan plan, int32_t b, int32_t h, int32_t w
  *             for the plan's sigma_cap.
  *   d_scores  b floats, overwritten with S_b.
  *   d_error   optional device int32 (may be NULL), overwritten with 0 or
- *             MHFD_FOCUS_BAD_SIGMA when some sigma is not in (0, sigma_cap]
+ *             MHFD_FOCUS_BAD_SIGMA when some sigma is not positive, exceeds
+ *             sigma_cap, or (sigma_cap = 0) has a radius above its halo
  *             (that scale's taps are then zero).  The host cannot see device
  *             values without waiting, so this is the call's only report of
  *             a bad sigma; read it after the stream has passed the call.

@@ -85,6 +85,8 @@ def lib():
                                         _i32p, _i32p, C.c_long]
         L.ora_dog_criterion.restype = C.c_long
         L.ora_threads.restype = C.c_int
+        L.ora_set_threads.argtypes = [C.c_int]
+        L.ora_set_threads.restype = None
         _lib = L
     return _lib
 
@@ -92,6 +94,11 @@ def lib():
 def threads() -> int:
     """OpenMP threads the oracle's parallel loops use."""
     return int(lib().ora_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads for the oracle's parallel loops from now on (timing only)."""
+    lib().ora_set_threads(int(n))
 
 
 # ----------------------------------------------------------------------------

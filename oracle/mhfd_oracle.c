@@ -682,3 +682,15 @@ int ora_threads(void)
     }
     return n;
 }
+
+/* Set the number of OpenMP threads of the oracle's parallel loops (timing
+ * of the single-thread baseline); n < 1 leaves it unchanged. */
+void ora_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

@@ -104,7 +104,9 @@ class Plan:
         self.max_h, self.max_w = int(max_h), int(max_w)
         self.stretch = bool(stretch)
         self.criterion = criterion
-        self.sigma_cap = float(sigma_cap) if sigma_cap else max(self.sigmas)
+        # None / 0: each scale may move while its radius stays within its
+        # plan radius rounded up to a multiple of 4
+        self.sigma_cap = float(sigma_cap) if sigma_cap else None
         self._ws = {}
         self._focus_err = None
 
@@ -244,8 +246,10 @@ class Plan:
         s = stream if stream is not None else torch.cuda.current_stream()
         s.synchronize()
         if int(self._focus_err.item()) & _lib.MHFD_FOCUS_BAD_SIGMA:
-            raise _lib.MHFDError(1, "mhfd_focus_score",
-                                 f"a sigma lies outside (0, sigma_cap = {self.sigma_cap}]")
+            allowed = (f"(0, sigma_cap = {self.sigma_cap}]" if self.sigma_cap else
+                       "(0, the largest sigma whose radius fits the scale's halo]; create "
+                       "the plan with sigma_cap to train further")
+            raise _lib.MHFDError(1, "mhfd_focus_score", f"a sigma lies outside {allowed}")
 
     def focus_score(self, imgs: torch.Tensor, sigmas: torch.Tensor, beta: float = 50.0,
                     tau: float = 0.05, stream=None, check: bool = True) -> torch.Tensor:

@@ -5,6 +5,13 @@ of tile descriptors, the workspace and the per-tile outputs -- at fixed
 addresses, so one HIP graph captured around ``run()`` can be replayed after
 ``set_tiles()`` has written new descriptors (new images, other sizes within
 the bounds) without capturing again.
+
+With ``lanes`` > 1 the tiles are dealt, largest first, to that many
+sub-batches of near-equal pixel counts, each one mhfd_detect_batched call
+with its own workspace on its own stream, forked from and joined back to
+the caller's stream (and captured the same way): the phases of one
+sub-batch (LoG, maxima, the small tail launches) overlap those of the
+others, as independent per-tile calls on several streams overlap.
 """
 from __future__ import annotations
 
@@ -24,24 +31,37 @@ assert TILE_DTYPE.itemsize == C.sizeof(_lib.Tile)
 
 class BatchRunner:
     """Fixed-address state for batches of up to ``max_tiles`` tiles holding at
-    most ``max_pixels`` pixels, each with room for ``capacity`` blobs."""
+    most ``max_pixels`` pixels, each with room for ``capacity`` blobs, run as
+    ``lanes`` concurrent sub-batches."""
 
-    def __init__(self, plan: Plan, max_tiles: int, max_pixels: int, capacity: int):
+    def __init__(self, plan: Plan, max_tiles: int, max_pixels: int, capacity: int,
+                 lanes: int = 1):
         self.plan = plan
         self.L = plan._L
         self.max_tiles, self.max_pixels, self.capacity = int(max_tiles), int(max_pixels), int(capacity)
+        self.lanes = max(1, min(int(lanes), self.max_tiles))
         dev = plan.device
-        self.ws_bytes = int(self.L.mhfd_batch_workspace_size(plan._handle, self.max_tiles,
-                                                             self.max_pixels))
-        if self.ws_bytes == 0:
+        # snake dealing of tiles sorted by size keeps every lane within
+        # total / lanes + one tile
+        self.lane_pixels = (self.max_pixels if self.lanes == 1 else
+                            min(self.max_pixels, -(-self.max_pixels // self.lanes)
+                                + plan.max_h * plan.max_w))
+        self.lane_ws_bytes = int(self.L.mhfd_batch_workspace_size(plan._handle, self.max_tiles,
+                                                                  self.lane_pixels))
+        if self.lane_ws_bytes == 0:
             raise _lib.MHFDError(1, "mhfd_batch_workspace_size",
-                                 f"{max_tiles} tiles / {max_pixels} pixels out of range")
-        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
-        self.table = torch.zeros(self.max_tiles * TILE_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+                                 f"{max_tiles} tiles / {self.lane_pixels} pixels out of range")
+        self.ws_bytes = self.lane_ws_bytes * self.lanes
+        self.ws = [torch.empty(self.lane_ws_bytes, dtype=torch.uint8, device=dev)
+                   for _ in range(self.lanes)]
+        self.table = torch.zeros(self.lanes * self.max_tiles * TILE_DTYPE.itemsize,
+                                 dtype=torch.uint8, device=dev)
         self.blobs = torch.empty((self.max_tiles, self.capacity, 5), dtype=torch.int32, device=dev)
         self.results = torch.zeros((self.max_tiles, _lib.RESULT_WORDS), dtype=torch.int64,
                                    device=dev)
+        self.streams = [torch.cuda.Stream() for _ in range(self.lanes - 1)]
         self.n = 0
+        self.lane_n = [0] * self.lanes
         self._imgs = []
 
     def set_tiles(self, imgs, seg_rows=None, stream=None) -> None:
@@ -52,18 +72,31 @@ class BatchRunner:
         if not 1 <= n <= self.max_tiles:
             raise ValueError(f"{n} tiles, runner holds 1..{self.max_tiles}")
         want = torch.uint8 if self.plan.dtype == "u8" else torch.float32
-        t = np.zeros(n, dtype=TILE_DTYPE)
         for i, im in enumerate(imgs):
             if im.dim() != 2 or im.dtype != want or im.device != self.plan.device or im.stride(1) != 1:
                 raise ValueError(f"tile {i}: expected a 2-D {want} tensor with contiguous rows "
                                  f"on {self.plan.device}")
-            t[i]["img"] = im.data_ptr()
-            t[i]["h"], t[i]["w"] = im.shape
-            t[i]["pitch"] = im.stride(0)
-            t[i]["blobs"] = self.blobs[i].data_ptr()
-            t[i]["result"] = self.results[i].data_ptr()
-            t[i]["capacity"] = self.capacity
-            t[i]["seg_rows"] = 0 if seg_rows is None else int(seg_rows[i])
+        # deal tiles largest first in snake order (lanes 0, 1, .., L-1, L-1,
+        # .., 0, 0, ..): near-equal pixels per lane, and tile counts per lane
+        # that depend on n only, so a captured graph stays valid for new
+        # tiles of any sizes
+        lanes = [[] for _ in range(self.lanes)]
+        for rank, i in enumerate(sorted(range(n), key=lambda i: (-imgs[i].numel(), i))):
+            turn, pos = divmod(rank, self.lanes)
+            lanes[pos if turn % 2 == 0 else self.lanes - 1 - pos].append(i)
+        t = np.zeros(self.lanes * self.max_tiles, dtype=TILE_DTYPE)
+        for j, members in enumerate(lanes):
+            for q, i in enumerate(sorted(members)):
+                im = imgs[i]
+                r = t[j * self.max_tiles + q]
+                r["img"] = im.data_ptr()
+                r["h"], r["w"] = im.shape
+                r["pitch"] = im.stride(0)
+                r["blobs"] = self.blobs[i].data_ptr()
+                r["result"] = self.results[i].data_ptr()
+                r["capacity"] = self.capacity
+                r["seg_rows"] = 0 if seg_rows is None else int(seg_rows[i])
+        self.lane_n = [len(m) for m in lanes]
         host = torch.from_numpy(t.view(np.uint8).copy())
         s = stream if stream is not None else torch.cuda.current_stream()
         with torch.cuda.stream(s):
@@ -73,11 +106,23 @@ class BatchRunner:
         self._imgs = list(imgs)
 
     def run(self, stream=None) -> None:
-        """Enqueue mhfd_detect_batched for the current table (no sync)."""
-        st = self.L.mhfd_detect_batched(self.plan._handle, self.n, self.table.data_ptr(),
-                                        self.max_pixels, self.ws.data_ptr(), self.ws_bytes,
-                                        _stream_ptr(stream))
-        _lib.check(st, "mhfd_detect_batched")
+        """Enqueue mhfd_detect_batched for every lane's sub-batch (no sync):
+        lane 0 on `stream` (default: the current stream), the others on
+        side streams that wait for it and that it waits for."""
+        main = stream if stream is not None else torch.cuda.current_stream()
+        active = [j for j in range(self.lanes) if self.lane_n[j]]
+        side = {j: self.streams[j - 1] for j in active if j > 0}
+        for st_ in side.values():
+            st_.wait_stream(main)
+        for j in active:
+            st_ = main if j == 0 else side[j]
+            table = self.table.data_ptr() + j * self.max_tiles * TILE_DTYPE.itemsize
+            status = self.L.mhfd_detect_batched(self.plan._handle, self.lane_n[j], table,
+                                                self.lane_pixels, self.ws[j].data_ptr(),
+                                                self.lane_ws_bytes, int(st_.cuda_stream))
+            _lib.check(status, "mhfd_detect_batched")
+        for st_ in side.values():
+            main.wait_stream(st_)
 
     def capture(self) -> torch.cuda.CUDAGraph:
         """Capture run() into a HIP graph for the current tile count."""
@@ -110,10 +155,11 @@ class BatchRunner:
         return out
 
 
-def detect_batched(plan: Plan, imgs, capacity: int = 1 << 16, seg_rows=None) -> list:
+def detect_batched(plan: Plan, imgs, capacity: int = 1 << 16, seg_rows=None,
+                   lanes: int = 1) -> list:
     """One-shot batched detection of a list of device images."""
     px = sum(int(i.shape[0]) * int(i.shape[1]) for i in imgs)
-    r = BatchRunner(plan, len(imgs), px, capacity)
+    r = BatchRunner(plan, len(imgs), px, capacity, lanes)
     r.set_tiles(imgs, seg_rows)
     r.run()
     return r.detections()

@@ -67,6 +67,11 @@ __device__ __forceinline__ long long stack_floats(int h, int w, int K) {
     return (static_cast<long long>(h) * w * K + 3) / 4 * 4;
 }
 
+// Activity words of a tile's threshold-sparse stack.
+__device__ __forceinline__ long long act_words(int h, int w, int K) {
+    return static_cast<long long>(K) * ((h + 15) / 16) * ((w + 15) / 16);
+}
+
 // Rows per matrix-core work item: a wave recomputes 2 nkc - 1 intermediate
 // blocks of 16 rows per item, so items are tall unless the tile is short.
 __device__ int default_mfma_seg_rows(int h) {
@@ -83,7 +88,7 @@ __global__ __launch_bounds__(SETUP_T) void batch_setup_kernel(
     __syncthreads();
     const int per = (n + SETUP_T - 1) / SETUP_T;
     const int t0 = min(n, static_cast<int>(threadIdx.x) * per), t1 = min(n, t0 + per);
-    long long items = 0, nms = 0, pix = 0, mitems = 0, nitems = 0, sfl = 0;
+    long long items = 0, nms = 0, pix = 0, mitems = 0, nitems = 0, sfl = 0, acw = 0;
     for (int t = t0; t < t1; ++t) {
         const mhfd_tile d = in[t];
         bool ok = d.img && d.result && d.h >= 1 && d.w >= 1 && d.h <= max_h && d.w <= max_w &&
@@ -109,14 +114,16 @@ __global__ __launch_bounds__(SETUP_T) void batch_setup_kernel(
         bt.bpr = (bt.w + 64 * bt.nms_cw - 1) / (64 * bt.nms_cw);
         bt.mseg_rows = d.seg_rows && ok ? d.seg_rows : default_mfma_seg_rows(bt.h);
         bt.mtiles_x = mfma ? (bt.w + MFMA_WAVE_COLS - 1) / MFMA_WAVE_COLS : 0;
+        bt.mgroups_x = (bt.mtiles_x + MFMA_GROUP_WAVES - 1) / MFMA_GROUP_WAVES;
         bt.msegs = (bt.h + bt.mseg_rows - 1) / bt.mseg_rows;
         tiles[t] = bt;
-        mitems += static_cast<long long>(bt.mtiles_x) * bt.msegs;
+        mitems += static_cast<long long>(bt.mgroups_x) * bt.msegs;
         items += static_cast<long long>(bt.strips) * bt.segs;
         nms += static_cast<long long>(bt.h) * bt.bpr;
         nitems += static_cast<long long>(nms_runs(bt.h)) * bt.bpr;
         pix += static_cast<long long>(bt.h) * bt.w;
         sfl += stack_floats(bt.h, bt.w, K);
+        acw += act_words(bt.h, bt.w, K);
     }
     long long tot_items, tot_nms, tot_pix, tot_mitems, tot_nitems, tot_sfl;
     const long long b_items = block_exclusive_scan(items, shl, &tot_items);
@@ -125,9 +132,12 @@ __global__ __launch_bounds__(SETUP_T) void batch_setup_kernel(
     const long long b_mitems = block_exclusive_scan(mitems, shl, &tot_mitems);
     const long long b_nitems = block_exclusive_scan(nitems, shl, &tot_nitems);
     const long long b_sfl = block_exclusive_scan(sfl, shl, &tot_sfl);
+    long long tot_acw;
+    const long long b_acw = block_exclusive_scan(acw, shl, &tot_acw);
     (void)b_pix;
     (void)tot_sfl;
-    long long ri = b_items, rn = b_nms, rm = b_mitems, rq = b_nitems, rs = b_sfl;
+    (void)tot_acw;
+    long long ri = b_items, rn = b_nms, rm = b_mitems, rq = b_nitems, rs = b_sfl, ra = b_acw;
     for (int t = t0; t < t1; ++t) {
         BatchTile& bt = tiles[t];
         bt.item_base = static_cast<int>(ri);
@@ -135,9 +145,11 @@ __global__ __launch_bounds__(SETUP_T) void batch_setup_kernel(
         bt.mitem_base = static_cast<int>(rm);
         bt.nitem_base = static_cast<int>(rq);
         bt.stack_off = rs;
+        bt.act_off = ra;
+        ra += act_words(bt.h, bt.w, K);
         ri += static_cast<long long>(bt.strips) * bt.segs;
         rn += static_cast<long long>(bt.h) * bt.bpr;
-        rm += static_cast<long long>(bt.mtiles_x) * bt.msegs;
+        rm += static_cast<long long>(bt.mgroups_x) * bt.msegs;
         rq += static_cast<long long>(nms_runs(bt.h)) * bt.bpr;
         rs += stack_floats(bt.h, bt.w, K);
     }
@@ -175,11 +187,12 @@ __global__ __launch_bounds__(SETUP_T) void batch_setup_kernel(
 // Persistent maxima waves over every tile's (run of nms::ROWS rows, strip of
 // 64 nms_cw columns) items, the per-wave body of the single-tile pass; the
 // tile index rides in the upper bits of every record's k.
-template <int K>
+template <int K, bool SPARSE>
 __global__ __launch_bounds__(64 * NMS_WAVES) void nms_batch_kernel(
     const float* __restrict__ stack, const BatchTile* __restrict__ tiles, int n_tiles, float tau,
     int n_blk_bound, int32_t* __restrict__ blk_n, int32_t* __restrict__ blk_o,
-    Cand* __restrict__ pool, int64_t cap, BatchCounters* __restrict__ ctr) {
+    Cand* __restrict__ pool, int64_t cap, BatchCounters* __restrict__ ctr,
+    const uint64_t* __restrict__ act) {
     const int total = ctr->nms_items;
     const int n_waves = gridDim.x * NMS_WAVES;
     for (int item = blockIdx.x * NMS_WAVES + (threadIdx.x >> 6); item < total; item += n_waves) {
@@ -204,13 +217,14 @@ __global__ __launch_bounds__(64 * NMS_WAVES) void nms_batch_kernel(
         out.flags = &ctr->flags;
         out.k_tag = lo << TILE_SHIFT;
         const float* st = stack + T.stack_off;
+        const nms::Active a{SPARSE ? act + T.act_off : nullptr, (T.w + 15) / 16, (T.h + 15) / 16};
         if constexpr (2 * K <= 32) {
             if (T.nms_cw == 2) {
-                nms::wave<K, 2, SLOT>(st, T.h, T.w, tau, T.bpr, strip, run, out);
+                nms::wave<K, 2, SLOT, SPARSE>(st, T.h, T.w, tau, T.bpr, strip, run, out, a);
                 continue;
             }
         }
-        nms::wave<K, 1, SLOT>(st, T.h, T.w, tau, T.bpr, strip, run, out);
+        nms::wave<K, 1, SLOT, SPARSE>(st, T.h, T.w, tau, T.bpr, strip, run, out, a);
     }
 }
 
@@ -340,9 +354,14 @@ __global__ void results_batch_kernel(const int32_t* __restrict__ blk_off,
 
 template <int K>
 void launch_nms_batch_k(const BatchLaunchArgs& a, hipStream_t s) {
-    nms_batch_kernel<K><<<a.nms_grid, 64 * NMS_WAVES, 0, s>>>(a.stack, a.tiles, a.n_tiles, a.tau,
-                                                     a.n_blk_bound, a.blk_n, a.blk_o, a.pool,
-                                                     a.cap, a.ctr);
+    if (a.act)
+        nms_batch_kernel<K, true><<<a.nms_grid, 64 * NMS_WAVES, 0, s>>>(
+            a.stack, a.tiles, a.n_tiles, a.tau, a.n_blk_bound, a.blk_n, a.blk_o, a.pool, a.cap,
+            a.ctr, a.act);
+    else
+        nms_batch_kernel<K, false><<<a.nms_grid, 64 * NMS_WAVES, 0, s>>>(
+            a.stack, a.tiles, a.n_tiles, a.tau, a.n_blk_bound, a.blk_n, a.blk_o, a.pool, a.cap,
+            a.ctr, a.act);
 }
 
 template <int... Ks>

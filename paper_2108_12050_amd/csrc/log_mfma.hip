@@ -49,7 +49,7 @@ typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
 typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
-constexpr int MW = 4;          // waves per workgroup, one 16-column tile each
+constexpr int MW = MFMA_GROUP_WAVES;  // waves per workgroup, one 16-column tile each
 constexpr int MAX_RADIUS = 56;  // largest radius with nkr, nkc <= 4
 
 __device__ __forceinline__ float4_t mfma16(half8_t a, half8_t b, float4_t c) {
@@ -481,20 +481,17 @@ __device__ __forceinline__ void run_job(const WaveJob& J, const half8_t* __restr
         wave_job<T, NKR, NKC, true, CTL, SPARSE>(J, fr, cl, lane);
 }
 
-// Single-tile kernels of shapes with nkc >= 3 read their column taps from
-// LDS: the 4 nkc fragments (16 nkc KB per workgroup) would otherwise hold
-// 16 nkc of the wave's registers.
+// Kernels of shapes with nkc >= 3 read their column taps from LDS: the
+// 4 nkc fragments (16 nkc KB per workgroup) would otherwise hold 16 nkc of
+// the wave's registers.
 template <int NKC>
 constexpr bool mfma_cols_in_lds() { return NKC >= 3; }
 
 // Two waves per SIMD where the live state fits 256 registers (u8: no spills
-// up to nkc = 3 in the single-tile kernel, nkc = 2 in the persistent one,
-// whose item loop keeps more state; fp32 inputs carry twice the operands);
-// otherwise one wave per SIMD.
+// up to nkc = 3; fp32 inputs carry twice the operands); otherwise one wave
+// per SIMD.
 template <typename T, int NKC>
 constexpr int mfma_waves() { return NKC <= (sizeof(typename Elem<T>::type) == 1 ? 3 : 2) ? 2 : 1; }
-template <typename T, int NKC>
-constexpr int mfma_batch_waves() { return NKC <= 2 ? 2 : 1; }
 
 template <typename T, int NKR, int NKC, bool SPARSE>
 __global__ __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(mfma_waves<T, NKC>(), 2)))
@@ -553,25 +550,43 @@ void log_mfma_kernel(const typename Elem<T>::type* __restrict__ img, int h, int 
     run_job<T, NKR, NKC, CTL, SPARSE>(J, frags + sc.frag_off, threadIdx.x & 63, cl);
 }
 
-// Persistent form over a batch of tiles: every wave pulls items (scale j of
-// the launch, tile, row segment, wave column) from a counter.  Items are
-// numbered scale-major, so a launch finishes its scales in order.
-template <typename T, int NKR, int NKC>
-__global__ __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(mfma_batch_waves<T, NKC>(), 2)))
+// Persistent form over a batch of tiles: every workgroup pulls items (scale j
+// of the launch, tile, row segment, group of MW adjacent wave columns) from a
+// counter, and its waves run the single-tile path's per-wave body on them.
+// Items are numbered scale-major, so a launch finishes its scales in order
+// and a workgroup mostly keeps its scale from one item to the next; for
+// nkc >= 3 the scale's column taps sit in LDS as in the single-tile kernel,
+// copied again only when the scale changes.
+template <typename T, int NKR, int NKC, bool SPARSE>
+__global__ __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(mfma_waves<T, NKC>(), 2)))
 void log_mfma_batch_kernel(int n_tiles, const BatchTile* __restrict__ tiles,
                            const uint32_t* __restrict__ maxbits, float* __restrict__ stack,
                            const half8_t* __restrict__ frags, MfmaBatchScales sc,
-                           BatchCounters* __restrict__ ctr, int slot) {
+                           BatchCounters* __restrict__ ctr, int slot, uint64_t* act, float tau) {
     const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    constexpr bool CTL = mfma_cols_in_lds<NKC>();
+    __shared__ half8_t cl[CTL ? NKC * 4 * 64 : 1];
+    __shared__ int s_item;
     const int per_scale = ctr->mitems_per_scale;
     const int total = ctr->valid ? per_scale * sc.n : 0;
+    int loaded = -1;  // scale whose column taps are in LDS (uniform)
     for (;;) {
-        int item = 0;
-        if (lane == 0) item = atomicAdd(&ctr->mwork[slot], 1);
-        item = __shfl(item, 0, 64);
+        __syncthreads();  // every wave is done with s_item and the LDS taps
+        if (threadIdx.x == 0) s_item = atomicAdd(&ctr->mwork[slot], 1);
+        __syncthreads();
+        const int item = s_item;
         if (item >= total) break;
         const int j = item / per_scale;
         const int rem = item - j * per_scale;
+        if constexpr (CTL) {
+            if (j != loaded) {
+                const half8_t* src = frags + sc.frag_off[j] + NKR * 4 * 64;
+                for (int i = threadIdx.x; i < NKC * 4 * 64; i += 64 * MW) cl[i] = src[i];
+                __syncthreads();
+                loaded = j;
+            }
+        }
         int lo = 0, hi = n_tiles;  // last tile with mitem_base <= rem
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
@@ -582,8 +597,9 @@ void log_mfma_batch_kernel(int n_tiles, const BatchTile* __restrict__ tiles,
         }
         const BatchTile& t = tiles[lo];
         const int local = rem - t.mitem_base;
-        const int seg = local / t.mtiles_x;
-        const int wcol = local - seg * t.mtiles_x;
+        const int seg = local / t.mgroups_x;
+        const int wcol = (local - seg * t.mgroups_x) * MW + wv;
+        if (wcol >= t.mtiles_x) continue;
         const float in_s = maxbits ? input_scale(maxbits[lo]) : 1.0f;
         WaveJob J;
         J.img = t.img;
@@ -602,7 +618,12 @@ void log_mfma_batch_kernel(int n_tiles, const BatchTile* __restrict__ tiles,
                     (reinterpret_cast<uintptr_t>(stack) % 16 == 0);
         J.in_scale = in_s;
         J.out_scale = sc.out_scale[j] / in_s;
-        run_job<T, NKR, NKC>(J, frags + sc.frag_off[j], lane);
+        if constexpr (SPARSE) {
+            J.act_bx = (t.w + 15) / 16;
+            J.act = act + t.act_off + static_cast<long long>(sc.plane[j]) * ((t.h + 15) / 16) * J.act_bx;
+            J.tau = tau;
+        }
+        run_job<T, NKR, NKC, CTL, SPARSE>(J, frags + sc.frag_off[j], lane, cl);
     }
 }
 
@@ -648,26 +669,36 @@ __device__ __forceinline__ float rows_absmax(const float* __restrict__ img, int 
     return m;
 }
 
+// The workgroup's largest value (256 threads), valid in thread 0.  One
+// atomic per workgroup: atomics on one word serialise, and one per wave
+// made the pass several times slower than its loads.
+__device__ __forceinline__ float block_max256(float m) {
+    __shared__ float sh[4];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+    __syncthreads();
+    return fmaxf(fmaxf(sh[0], sh[1]), fmaxf(sh[2], sh[3]));
+}
+
 // max |I| of an fp32 image as float bits (non-negative floats order as their
 // bit patterns), for the input scale.  `bits` must be zero on entry.
-__global__ void absmax_kernel(const float* __restrict__ img, int h, int w, long long pitch,
-                              uint32_t* __restrict__ bits) {
-    const float m = rows_absmax(img, h, w, pitch, blockIdx.x, gridDim.x);
-    if ((threadIdx.x & 63) == 0 && m > 0.0f) atomicMax(bits, __float_as_uint(m));
+__global__ __launch_bounds__(256) void absmax_kernel(const float* __restrict__ img, int h, int w,
+                                                     long long pitch, uint32_t* __restrict__ bits) {
+    const float m = block_max256(rows_absmax(img, h, w, pitch, blockIdx.x, gridDim.x));
+    if (threadIdx.x == 0 && m > 0.0f) atomicMax(bits, __float_as_uint(m));
 }
 
 // Per-tile max |I| of a batch (bits[t] zero on entry): workgroup row y of
 // the grid takes tile y, and the gridDim.x workgroups of that row split its
 // rows.
-__global__ void absmax_batch_kernel(const BatchTile* __restrict__ tiles,
-                                    const BatchCounters* __restrict__ ctr,
-                                    uint32_t* __restrict__ bits) {
+__global__ __launch_bounds__(256) void absmax_batch_kernel(const BatchTile* __restrict__ tiles,
+                                                           const BatchCounters* __restrict__ ctr,
+                                                           uint32_t* __restrict__ bits) {
     if (!ctr->valid) return;
     const int t = blockIdx.y;
     const BatchTile& d = tiles[t];
-    const float m = rows_absmax(static_cast<const float*>(d.img), d.h, d.w, d.pitch, blockIdx.x,
-                                gridDim.x);
-    if ((threadIdx.x & 63) == 0 && m > 0.0f) atomicMax(bits + t, __float_as_uint(m));
+    const float m = block_max256(rows_absmax(static_cast<const float*>(d.img), d.h, d.w, d.pitch,
+                                             blockIdx.x, gridDim.x));
+    if (threadIdx.x == 0 && m > 0.0f) atomicMax(bits + t, __float_as_uint(m));
 }
 
 __global__ void zero_words_kernel(uint32_t* __restrict__ p, int n) {
@@ -820,13 +851,18 @@ int mfma_waves_per_block() { return MW; }
 hipError_t launch_log_mfma_batch(int in_dtype, int nkr, int nkc, int n_tiles,
                                  const BatchTile* tiles, const uint32_t* maxbits, float* stack,
                                  const uint16_t* frags, const MfmaBatchScales& sc,
-                                 BatchCounters* ctr, int slot, int grid, hipStream_t s) {
+                                 BatchCounters* ctr, int slot, int grid, uint64_t* act, float tau,
+                                 hipStream_t s) {
     if (sc.n == 0) return hipSuccess;
     const half8_t* f = reinterpret_cast<const half8_t*>(frags);
 #define MHFD_MFMA_BATCH_CASE(T, A)                                                            \
     if (nkr == A && nkc == A) {                                                               \
-        log_mfma_batch_kernel<T, A, A><<<grid, 64 * MW, 0, s>>>(n_tiles, tiles, maxbits, stack, \
-                                                                f, sc, ctr, slot);            \
+        if (act)                                                                              \
+            log_mfma_batch_kernel<T, A, A, true><<<grid, 64 * MW, 0, s>>>(                    \
+                n_tiles, tiles, maxbits, stack, f, sc, ctr, slot, act, tau);                  \
+        else                                                                                  \
+            log_mfma_batch_kernel<T, A, A, false><<<grid, 64 * MW, 0, s>>>(                   \
+                n_tiles, tiles, maxbits, stack, f, sc, ctr, slot, act, tau);                  \
         return hipGetLastError();                                                             \
     }
     if (in_dtype == MHFD_U8) {
@@ -875,8 +911,8 @@ hipError_t launch_log_mfma(int in_dtype, int stretch, int nkr, int nkc, const vo
 hipError_t launch_absmax(const float* img, int h, int w, int64_t pitch, uint32_t* bits,
                          hipStream_t s) {
     zero_words_kernel<<<1, 64, 0, s>>>(bits, 1);
-    // a workgroup per four rows, up to 2048 workgroups
-    const int blocks = (h + 3) / 4 < 2048 ? (h + 3) / 4 : 2048;
+    // a workgroup per four rows, up to 512 workgroups
+    const int blocks = (h + 3) / 4 < 512 ? (h + 3) / 4 : 512;
     absmax_kernel<<<blocks, 256, 0, s>>>(img, h, w, static_cast<long long>(pitch), bits);
     return hipGetLastError();
 }

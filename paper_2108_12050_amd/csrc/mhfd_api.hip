@@ -68,8 +68,11 @@ struct mhfd_plan_s {
     uint16_t* d_frags = nullptr;
     int stretch = 0;             // histogram stretch before the stack (u8 plans)
     int criterion = MHFD_CRITERION_LOG;  // DOG: the stack holds Gaussian planes
-    float sigma_cap = 0.0f;      // largest sigma a focus-score call may take
-    int padded_cap = 0;          // padded radius of sigma_cap: the focus-score halos
+    // Focus-score calls: the largest sigma any scale may take (uniform cap),
+    // or +inf when each scale is bounded by its own launch radius instead,
+    // and every scale's launch radius (padded).
+    float sigma_cap = 0.0f;
+    std::vector<int> focus_padded;
     uint32_t* d_scratch = nullptr;  // this device's static scratch (mhfd_log_stack_static)
 };
 
@@ -176,10 +179,12 @@ struct DetectLayout {
 };
 
 // A detection without a caller stack keeps only the above-threshold part of
-// the stack (plus activity words) when every scale runs on the matrix cores
-// and the criterion is the LoG's; otherwise the whole stack.
+// the stack (plus activity words) when every scale runs on the matrix cores,
+// the criterion is the LoG's and the threshold is not negative; otherwise
+// the whole stack.
 bool sparse_stack(const mhfd_plan_s* p) {
-    if (p->criterion != MHFD_CRITERION_LOG || !p->d_frags) return false;
+    // the maxima pass reads unwritten groups as 0, which must not exceed tau
+    if (p->criterion != MHFD_CRITERION_LOG || !p->d_frags || !(p->threshold >= 0.0f)) return false;
     for (int k = 0; k < p->K; ++k)
         if (p->mfma_off[k] < 0) return false;
     return true;
@@ -339,19 +344,24 @@ mhfd_status mhfd_create_plan(const mhfd_config* cfg, mhfd_plan* out) {
         off += mhfd::tap_block_floats(P);
     }
     p->tap_floats = off;
-    {
-        const float cap = cfg->sigma_cap > 0.0f ? cfg->sigma_cap : sig[K - 1];
+    if (cfg->sigma_cap > 0.0f) {
+        // uniform cap: every scale's halo sized for the cap's radius
+        const float cap = cfg->sigma_cap;
         const double rc = floor(static_cast<double>(p->truncate) * cap + 0.5);
-        if (!isfinite(cap) || cap < sig[K - 1] || rc > MHFD_MAX_RADIUS) {
+        if (cap < sig[K - 1] || rc > MHFD_MAX_RADIUS) {
             delete p;
             return fail(cap < sig[K - 1] ? MHFD_ERR_INVALID_ARG : MHFD_ERR_UNSUPPORTED,
-                        "sigma_cap %g must be finite, >= the largest sigma %g and give a radius "
-                        "<= %d", static_cast<double>(cap), static_cast<double>(sig[K - 1]),
+                        "sigma_cap %g must be >= the largest sigma %g and give a radius <= %d",
+                        static_cast<double>(cap), static_cast<double>(sig[K - 1]),
                         MHFD_MAX_RADIUS);
         }
         p->sigma_cap = cap;
         const int rcap = static_cast<int>(rc);
-        p->padded_cap = mhfd::padded_radius(rcap < 1 ? 1 : rcap);
+        p->focus_padded.assign(K, mhfd::padded_radius(rcap < 1 ? 1 : rcap));
+    } else {
+        // each scale within its own padded plan radius
+        p->sigma_cap = INFINITY;
+        p->focus_padded = p->padded;
     }
     // Blob radius sqrt(2) sigma; prune table in double.
     std::vector<int32_t> d2(static_cast<size_t>(K) * K, -1);
@@ -743,17 +753,17 @@ struct FocusLayout {
 FocusLayout focus_layout(const mhfd_plan_s* p, int b, int h, int w) {
     FocusLayout F{};
     F.lay.K = p->K;
-    F.lay.padded = p->padded_cap;
     F.lay.truncate = p->truncate;
     F.lay.sigma_cap = p->sigma_cap;
     int off = 0;
     for (int k = 0; k < p->K; ++k) {
+        F.lay.padded[k] = p->focus_padded[k];
         F.lay.offset[k] = off;
-        off += mhfd::SOFT_SETS * 4 * (p->padded_cap + 1);
+        off += mhfd::SOFT_SETS * 4 * (p->focus_padded[k] + 1);
     }
     auto launches = make_launches(
         p, h, w, all_scales(p), [](int) { return 0; }, [](int k) { return k; },
-        [&](int) { return p->padded_cap; });
+        [&](int k) { return p->focus_padded[k]; });
     F.fwd_blocks = 0;
     for (auto& cl : launches) F.fwd_blocks += launch_blocks(cl.second);
     size_t o = 0;
@@ -794,7 +804,7 @@ mhfd_status check_focus(const mhfd_plan_s* p, const float* d_imgs, int b, int h,
 
 struct BatchLayout {
     size_t stack, tiles, ctr, blk_n, blk_o, blk_off, pool, cand, keep, keep_off, scan_sums, maxbits,
-        total;
+        act, total;
     int n_blk_bound;
     int64_t cap;
 };
@@ -828,6 +838,8 @@ bool batch_layout(const mhfd_plan_s* p, int n, int64_t max_pixels, BatchLayout* 
     L->keep_off = take(sizeof(int32_t) * (cap + 1));
     L->scan_sums = take(sizeof(int32_t) * mhfd::scan_sums_ints(nbb > cap ? nbb : cap));
     L->maxbits = take(sizeof(uint32_t) * n);
+    L->act = take(sparse_stack(p) ? sizeof(uint64_t) * mhfd::batch_act_words(
+                                        p->K, n, max_pixels, p->max_h, p->max_w) : 0);
     L->total = off;
     return true;
 }
@@ -1010,6 +1022,9 @@ mhfd_status mhfd_detect_batched(mhfd_plan p, int32_t n, const mhfd_tile* d_tiles
     hipStream_t s = static_cast<hipStream_t>(stream);
     char* base = static_cast<char*>(d_ws);
     float* stack = reinterpret_cast<float*>(base + L.stack);
+    // threshold-sparse stacks when the plan allows them (as mhfd_detect
+    // without a caller stack)
+    uint64_t* act = sparse_stack(p) ? reinterpret_cast<uint64_t*>(base + L.act) : nullptr;
     auto* tiles = reinterpret_cast<mhfd::BatchTile*>(base + L.tiles);
     auto* ctr = reinterpret_cast<mhfd::BatchCounters*>(base + L.ctr);
     hipError_t e = mhfd::launch_batch_setup(d_tiles, n, max_pixels, p->K, p->max_h, p->max_w,
@@ -1043,7 +1058,8 @@ mhfd_status mhfd_detect_batched(mhfd_plan p, int32_t n, const mhfd_tile* d_tiles
                         key.first, key.second);
         e = mhfd::launch_log_mfma_batch(p->dtype, key.first, key.second, n, tiles,
                                         p->dtype == MHFD_F32 ? maxbits : nullptr, stack,
-                                        p->d_frags, sc, ctr, slot, 2 * p->n_cu, s);
+                                        p->d_frags, sc, ctr, slot, 2 * p->n_cu, act,
+                                        p->threshold, s);
         if (e != hipSuccess) return hip_fail(e, "batched LoG (matrix cores) launch");
     }
     for (int cls = 2; cls >= 0; --cls) {
@@ -1077,6 +1093,7 @@ mhfd_status mhfd_detect_batched(mhfd_plan p, int32_t n, const mhfd_tile* d_tiles
     a.tau = p->threshold;
     a.cap = L.cap;
     a.stack = stack;
+    a.act = act;
     a.tiles = tiles;
     a.blk_n = reinterpret_cast<int32_t*>(base + L.blk_n);
     a.blk_o = reinterpret_cast<int32_t*>(base + L.blk_o);
@@ -1114,10 +1131,11 @@ mhfd_status mhfd_focus_score(mhfd_plan p, const float* d_imgs, int32_t b, int32_
     double* partial = reinterpret_cast<double*>(base + F.partial);
     hipError_t e = mhfd::launch_soft_taps(d_sigmas, F.lay, taps, d_error, s);
     if (e != hipSuccess) return hip_fail(e, "soft tap synthesis");
-    const int P = p->padded_cap;
+    const std::vector<int>& P = p->focus_padded;
     auto launches = make_launches(
-        p, h, w, all_scales(p), [&](int k) { return F.lay.offset[k] + mhfd::SOFT_FWD * 4 * (P + 1); },
-        [](int k) { return k; }, [&](int) { return P; });
+        p, h, w, all_scales(p),
+        [&](int k) { return F.lay.offset[k] + mhfd::SOFT_FWD * 4 * (P[k] + 1); },
+        [](int k) { return k; }, [&](int k) { return P[k]; });
     mhfd::SoftPartials sp{};
     long long done = 0;
     for (auto& cl : launches) {
@@ -1160,7 +1178,7 @@ mhfd_status mhfd_focus_score_backward(mhfd_plan p, const float* d_imgs, int32_t 
     float* dpl = reinterpret_cast<float*>(base + F.dplane);
     double* cot = reinterpret_cast<double*>(base + F.cot);
     hipError_t e = mhfd::launch_soft_taps(d_sigmas, F.lay, taps, d_error, s);
-    const int P = p->padded_cap;
+    const std::vector<int>& P = p->focus_padded;
     if (e != hipSuccess) return hip_fail(e, "soft tap synthesis");
     const long long npix = static_cast<long long>(h) * w;
     const double inv_khw = 1.0 / (static_cast<double>(p->K) * h * w);
@@ -1169,8 +1187,8 @@ mhfd_status mhfd_focus_score_backward(mhfd_plan p, const float* d_imgs, int32_t 
         const std::vector<int> one{k};
         auto run = [&](int set, int epi, const float* src, float* dst) -> hipError_t {
             auto launches = make_launches(
-                p, h, w, one, [&](int kk) { return F.lay.offset[kk] + set * 4 * (P + 1); },
-                [](int) { return 0; }, [&](int) { return P; });
+                p, h, w, one, [&](int kk) { return F.lay.offset[kk] + set * 4 * (P[kk] + 1); },
+                [](int) { return 0; }, [&](int kk) { return P[kk]; });
             mhfd::StackIO io{};
             io.img_batch = npix;
             io.out = dst;

@@ -100,6 +100,7 @@ struct MfmaShape {
 };
 constexpr int MFMA_SHAPES = 4;  // (nkr, nkc) instantiations: (1,1) ... (4,4)
 constexpr int MFMA_WAVE_COLS = 16;  // image columns per matrix-core wave
+constexpr int MFMA_GROUP_WAVES = 4;  // waves (adjacent wave columns) per matrix-core workgroup
 bool mfma_radius_ok(int radius);
 MfmaShape mfma_shape(int radius);
 // FP16 fragment table of one scale: (nkr + nkc) * 4 * 64 lanes * 8 halves.
@@ -226,10 +227,21 @@ struct BatchTile {
     int nms_base;           // prefix of h * bpr over earlier tiles
     int nms_cw;             // columns per maxima lane (1 or 2)
     int nitem_base;         // prefix of ceil(h / 32) * bpr (maxima wave items)
-    // matrix-core items: wave columns x row segments
+    // matrix-core items: workgroups of MFMA_GROUP_WAVES wave columns x row
+    // segments
     int mtiles_x, msegs, mseg_rows;
-    int mitem_base;         // prefix of mtiles_x * msegs over earlier tiles
+    int mgroups_x;          // ceil(mtiles_x / MFMA_GROUP_WAVES)
+    int mitem_base;         // prefix of mgroups_x * msegs over earlier tiles
+    long long act_off;      // first activity word of the tile (threshold-sparse stack):
+                            // K x ceil(h/16) x ceil(w/16) words
 };
+
+// Activity words a batch may need: K x sum over tiles of ceil(h/16) ceil(w/16)
+// <= K (max_pixels / 256 + n ((max_h + max_w) / 16 + 1)).
+inline long long batch_act_words(int K, int n, long long max_pixels, int max_h, int max_w) {
+    return static_cast<long long>(K) *
+           (max_pixels / 256 + static_cast<long long>(n) * ((max_h + max_w) / 16 + 2));
+}
 
 struct BatchCounters {
     int32_t items_per_scale;  // sum over tiles of strips * segs
@@ -241,7 +253,7 @@ struct BatchCounters {
     int32_t n_cand;
     int32_t n_blobs;
     int32_t work[3];          // persistent LoG work counters, one per radius class
-    int32_t mitems_per_scale; // sum over tiles of mtiles_x * msegs
+    int32_t mitems_per_scale; // sum over tiles of mgroups_x * msegs (workgroup items)
     int32_t mwork[MFMA_SHAPES];  // persistent matrix-core work counters, one per shape
 };
 
@@ -253,10 +265,12 @@ struct MfmaBatchScales {
     float out_scale[MHFD_MAX_SCALES];
 };
 
+// act: the batch's activity words (null: dense stacks), tau the threshold.
 hipError_t launch_log_mfma_batch(int in_dtype, int nkr, int nkc, int n_tiles,
                                  const BatchTile* tiles, const uint32_t* maxbits, float* stack,
                                  const uint16_t* frags, const MfmaBatchScales& sc,
-                                 BatchCounters* ctr, int slot, int grid, hipStream_t s);
+                                 BatchCounters* ctr, int slot, int grid, uint64_t* act, float tau,
+                                 hipStream_t s);
 // bits[t] = float bits of max |I| of fp32 tile t (zeroed first; nothing for an
 // invalid batch).
 hipError_t launch_absmax_batch(int n_tiles, const BatchTile* tiles, const BatchCounters* ctr,
@@ -279,6 +293,7 @@ struct BatchLaunchArgs {
     float tau;
     int64_t cap;
     const float* stack;
+    const uint64_t* act;    // threshold-sparse stacks' activity words (null: dense)
     const BatchTile* tiles;
     int32_t *blk_n, *blk_o, *blk_off, *keep, *keep_off, *scan_sums;
     Cand *pool, *cand;
@@ -292,6 +307,7 @@ struct BatchLaunchArgs {
 hipError_t launch_batch_setup(const mhfd_tile* in, int n, long long max_pixels, int K, int max_h,
                               int max_w, int dtype, int mfma, BatchTile* tiles,
                               BatchCounters* ctr, hipStream_t s);
+
 hipError_t launch_batch_tail(const BatchLaunchArgs& a, hipStream_t s);
 
 // Exclusive scan of n = min(n_host, *n_dev) ints (n_dev may be null):
@@ -301,21 +317,22 @@ void launch_batch_scan(const int32_t* in, int n_host, const int32_t* n_dev, int3
                        int32_t* out, int32_t* total_out, hipStream_t s);
 
 // Device-synthesised taps of the soft focus score: for scale k, four tap sets
-// (FWD, D1, D2, ADJ) of four runs of padded + 1 floats start at offset[k].
+// (FWD, D1, D2, ADJ) of four runs of padded[k] + 1 floats start at offset[k].
 // The radius of scale k, floor(truncate sigma_k + 0.5), comes from the
-// device sigma at each call; taps beyond it are zero.  `padded` is the
-// padded radius of sigma_cap, the launch radius of every scale.
+// device sigma at each call; taps beyond it are zero.  padded[k] is scale
+// k's launch radius: a sigma is accepted when it lies in (0, sigma_cap] and
+// its radius fits the launch radius.
 enum { SOFT_FWD = 0, SOFT_D1 = 1, SOFT_D2 = 2, SOFT_ADJ = 3, SOFT_SETS = 4 };
 struct SoftTapLayout {
     int K;
-    int padded;
     float truncate;
-    float sigma_cap;
+    float sigma_cap;                 // +inf: bounded by the launch radii only
+    int padded[MHFD_MAX_SCALES];
     int offset[MHFD_MAX_SCALES];
 };
 
-// err (optional): 0, or MHFD_FOCUS_BAD_SIGMA when some sigma is outside
-// (0, sigma_cap] (its taps are written as zeros).
+// err (optional): 0, or MHFD_FOCUS_BAD_SIGMA when some sigma is not accepted
+// (its taps are written as zeros).
 hipError_t launch_soft_taps(const float* sigmas, const SoftTapLayout& lay, float* taps,
                             int32_t* err, hipStream_t s);
 // Softplus partials of the forward launches: launch c wrote [image][block]

@@ -81,14 +81,20 @@ struct Sink {
 // ballot/mbcnt offsets into its own pool slot and reserves the overflow
 // region with one atomic only when it has more.
 //
-// Threshold-sparse stacks (SPARSE): the LoG wrote only the 4-pixel row
-// groups holding a value above tau, and marked them in `act` (bit 16 g + r
-// of word [k][by][bx]: row 16 by + r, columns 16 bx + 4 g ... + 3; every
-// word is written).  A value at or below tau can neither be a candidate
-// nor block one (a blocking neighbour exceeds the candidate, which exceeds
-// tau), so every unmarked group reads as -inf: the same decisions as the
-// dense stack, and only marked groups are fetched.  Rows outside the image
-// read as -inf too, which the -inf padding of the definition allows.
+// Threshold-sparse stacks (SPARSE, tau >= 0): the LoG wrote only the
+// 4-pixel row groups holding a value above tau, and marked them in `act`
+// (bit 16 g + r of word [k][by][bx]: row 16 by + r, columns 16 bx + 4 g
+// ... + 3; every word is written).  A value at or below tau can neither be
+// a candidate nor block one (a blocking neighbour exceeds the candidate,
+// which exceeds tau), so any value at or below tau may stand in for it:
+// unmarked groups, and rows outside the image, read as 0 <= tau.  The
+// decisions are those of the dense stack, and only marked groups are
+// fetched.
+//
+// Third word of a raw buffer resource on gfx9-family devices (32-bit data
+// format, no swizzle): loads past its num_records return 0.
+constexpr int kBufferFlags = 0x00020000;
+
 struct Active {
     const uint64_t* mask;  // K x mby x mbx words
     int mbx, mby;
@@ -120,14 +126,18 @@ __device__ __forceinline__ void wave(const float* __restrict__ st, int H, int W,
     uint32_t hbits = 0;
     if constexpr (SPARSE) {
         const int by = y0 >> 4;
+        // The three words are loaded unconditionally (rows clamped into the
+        // image) so that their loads overlap; the selects drop the rows
+        // outside it.
         auto run_bits = [&](int k, int x) -> uint32_t {
             const int sh = 16 * ((x >> 2) & 3);
             const uint64_t* m = act.mask + static_cast<size_t>(k) * act.mby * act.mbx + (x >> 4);
-            const uint32_t cur = static_cast<uint32_t>(m[static_cast<size_t>(by) * act.mbx] >> sh) & 0xFFFFu;
-            const uint32_t up = y0 > 0
-                ? static_cast<uint32_t>(m[static_cast<size_t>(by - 1) * act.mbx] >> (sh + 15)) & 1u : 0u;
-            const uint32_t dn = y0 + 16 < H
-                ? static_cast<uint32_t>(m[static_cast<size_t>(by + 1) * act.mbx] >> sh) & 1u : 0u;
+            const uint64_t wu = m[static_cast<size_t>(max(by - 1, 0)) * act.mbx];
+            const uint64_t wc = m[static_cast<size_t>(by) * act.mbx];
+            const uint64_t wd = m[static_cast<size_t>(min(by + 1, act.mby - 1)) * act.mbx];
+            const uint32_t cur = static_cast<uint32_t>(wc >> sh) & 0xFFFFu;
+            const uint32_t up = y0 > 0 ? static_cast<uint32_t>(wu >> (sh + 15)) & 1u : 0u;
+            const uint32_t dn = y0 + 16 < H ? static_cast<uint32_t>(wd >> sh) & 1u : 0u;
             return up | (cur << 1) | (dn << 17);
         };
 #pragma unroll
@@ -143,15 +153,26 @@ __device__ __forceinline__ void wave(const float* __restrict__ st, int H, int W,
         const int bit = y - y0 + 1;  // 0 .. 18
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const Vec* p = reinterpret_cast<const Vec*>(
-                reinterpret_cast<const char*>(st + static_cast<size_t>(k) * plane) + boff);
-            if constexpr (SPARSE)
-                v[k] = (abits[k] >> bit) & 1u ? *p : static_cast<Vec>(-INFINITY);
-            else
-                v[k] = *p;
+            const char* pk = reinterpret_cast<const char*>(st + static_cast<size_t>(k) * plane);
+            if constexpr (SPARSE) {
+                // Unmarked groups: an offset past the plane, for which the
+                // buffer load fetches nothing and returns 0 (no branch).
+                const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                    const_cast<char*>(pk), static_cast<short>(0),
+                    static_cast<int>(static_cast<uint32_t>(plane * 4)), kBufferFlags);
+                const uint32_t off = (abits[k] >> bit) & 1u ? boff : 0x80000000u;
+                if constexpr (CW == 1)
+                    v[k] = __builtin_bit_cast(Vec, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+                else if constexpr (CW == 2)
+                    v[k] = __builtin_bit_cast(Vec, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+                else
+                    v[k] = __builtin_bit_cast(Vec, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+            } else {
+                v[k] = *reinterpret_cast<const Vec*>(pk + boff);
+            }
         }
         if constexpr (SPARSE)
-            hv = (hbits >> bit) & 1u ? hbase[static_cast<size_t>(yy) * W] : -INFINITY;
+            hv = (hbits >> bit) & 1u ? hbase[static_cast<size_t>(yy) * W] : 0.0f;
         else
             hv = hbase[static_cast<size_t>(yy) * W];
     };

@@ -33,13 +33,15 @@ __global__ void soft_taps_kernel(const float* __restrict__ sigmas, SoftTapLayout
                                  float* __restrict__ taps, int32_t* __restrict__ err) {
     const int k = threadIdx.x;
     const double s = k < lay.K ? static_cast<double>(sigmas[k]) : 1.0;
-    const bool ok = s > 0.0 && s <= static_cast<double>(lay.sigma_cap);  // false for NaN
+    const int P = k < lay.K ? lay.padded[k] : 1;
+    // radius from the current sigma; accepted within (0, sigma_cap] and the
+    // launch radius (comparisons are false for NaN)
+    const double rr = floor(static_cast<double>(lay.truncate) * s + 0.5);
+    const bool ok = k >= lay.K || (s > 0.0 && s <= static_cast<double>(lay.sigma_cap) && rr <= P);
     const int bad = __syncthreads_or(!ok);
     if (err && threadIdx.x == 0) *err = bad ? MHFD_FOCUS_BAD_SIGMA : 0;
     if (k >= lay.K) return;
-    // radius from the current sigma (at most the cap's, so within the launch)
-    const int R = ok ? static_cast<int>(floor(static_cast<double>(lay.truncate) * s + 0.5)) : 0;
-    const int P = lay.padded;
+    const int R = ok ? static_cast<int>(rr) : 0;
     float* base = taps + lay.offset[k];
     const int run = P + 1;  // floats per tap run
     const int blk = 4 * run;  // floats per tap set

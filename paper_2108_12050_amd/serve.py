@@ -47,6 +47,7 @@ class Request:
     n_candidates: int = -1
     flags: int = 0
     density: float = 0.0
+    device_ms: float = -1.0      # the request's batch on the device (start to end)
     blobs: np.ndarray | None = None
     error: str | None = None
 
@@ -116,7 +117,9 @@ class Server:
                 if isinstance(res, Exception):
                     r.error = f"batch failed: {res}"
                 else:
-                    r.count, r.n_candidates, r.flags, r.density, r.blobs = res
+                    r.count, r.n_candidates, r.flags, r.density, r.blobs = res[:5]
+                    if len(res) > 5:
+                        r.device_ms = res[5]
                     if r.flags & FLAG_CAND_OVERFLOW:
                         r.error = (f"{r.n_candidates} candidates exceed the plan's candidate "
                                    "capacity: the count and list are not valid")
@@ -194,30 +197,27 @@ class Server:
         return sorted(self.finished + self.rejected, key=lambda r: r.rid)
 
 
-class GpuExecutor:
-    """Slots = BatchRunners, each with its own stream; tile copies on a
-    separate copy stream."""
+class _GpuSlots:
+    """What both GPU executors share: per-slot streams, staging of host
+    tiles on a copy stream (tiles already on the device are used in place),
+    start/end events around each slot's work and the read-back of results."""
 
-    def __init__(self, plan, n_slots: int = 2, slot_tiles: int = 32, slot_pixels: int = 1 << 27,
-                 capacity: int = 1 << 16, autotuner=None, keep_blobs: bool = False):
+    def _init_slots(self, plan, n_slots: int, keep_blobs: bool):
         import torch
-
-        from .batch import BatchRunner
         self.torch = torch
         self.plan = plan
         self.bytes_per_pixel = 1 if plan.dtype == "u8" else 4
-        self.slot_tiles, self.slot_pixels = slot_tiles, slot_pixels
-        self.autotuner, self.keep_blobs = autotuner, keep_blobs
+        self.keep_blobs = keep_blobs
         self.copy_stream = torch.cuda.Stream()
-        self.runners = [BatchRunner(plan, slot_tiles, slot_pixels, capacity) for _ in range(n_slots)]
         self.streams = [torch.cuda.Stream() for _ in range(n_slots)]
         self.events = [None] * n_slots
+        self.starts = [None] * n_slots
         self.batches = [None] * n_slots
-        self.fixed_bytes = sum(r.ws_bytes + r.blobs.numel() * 4 + r.results.numel() * 8
-                               for r in self.runners)
 
     def stage(self, r: Request):
         torch = self.torch
+        if getattr(r.image, "is_cuda", False):
+            return r.image, None
         with torch.cuda.stream(self.copy_stream):
             dev = torch.empty(r.image.shape, dtype=r.image.dtype, device=self.plan.device)
             dev.copy_(r.image, non_blocking=True)
@@ -228,35 +228,40 @@ class GpuExecutor:
     def idle_slots(self):
         return [i for i, b in enumerate(self.batches) if b is None]
 
-    def launch(self, slot: int, batch) -> None:
+    def _begin(self, slot: int, batch):
         s = self.streams[slot]
         for r in batch:
             dev, ev = r.staged
-            s.wait_event(ev)
-            dev.record_stream(s)
-        imgs = [r.staged[0] for r in batch]
-        segs = ([self.autotuner.seg_rows_for(r.h, r.w) for r in batch]
-                if self.autotuner else None)
-        runner = self.runners[slot]
-        runner.set_tiles(imgs, segs, stream=s)
-        runner.run(s)
-        ev = self.torch.cuda.Event()
-        ev.record(s)
+            if ev is not None:
+                s.wait_event(ev)
+                dev.record_stream(s)
+        start = self.torch.cuda.Event(enable_timing=True)
+        start.record(s)
+        self.starts[slot] = start
+        return s
+
+    def _end(self, slot: int, batch):
+        ev = self.torch.cuda.Event(enable_timing=True)
+        ev.record(self.streams[slot])
         self.events[slot] = ev
         self.batches[slot] = batch
 
+    def _results(self, slot: int, n: int):
+        """(result words [n, 4], blob records or None) of the slot's batch."""
+        raise NotImplementedError
+
     def poll(self, slot: int):
         """None while the slot's batch runs; then one (count, n_candidates,
-        flags, density, blobs) tuple per tile, or the exception that the
-        read-back raised for every tile of the batch."""
+        flags, density, blobs, device ms) tuple per tile, or the exception
+        that the read-back raised for every tile of the batch."""
         ev = self.events[slot]
         try:
             if ev is None or not ev.query():
                 return None
-            runner, n = self.runners[slot], len(self.batches[slot])
+            n = len(self.batches[slot])
             with self.torch.cuda.stream(self.streams[slot]):
-                res = runner.results[:n].cpu().numpy()
-                blobs = runner.blobs[:n].cpu().numpy() if self.keep_blobs else None
+                res, blobs = self._results(slot, n)
+            dev_ms = self.starts[slot].elapsed_time(ev)
         except Exception as e:
             n = len(self.batches[slot]) if self.batches[slot] else 0
             self.events[slot] = None
@@ -266,19 +271,85 @@ class GpuExecutor:
         out = []
         for i in range(n):
             cnt = int(res[i, 0])
-            b = blobs[i, : min(cnt, blobs.shape[1])].copy() if blobs is not None else None
-            out.append((cnt, int(res[i, 1]), int(res[i, 2]) & 0xFFFFFFFF, float(dens[i]), b))
+            b = blobs[i][: min(cnt, len(blobs[i]))].copy() if blobs is not None else None
+            out.append((cnt, int(res[i, 1]), int(res[i, 2]) & 0xFFFFFFFF, float(dens[i]), b,
+                        dev_ms))
         self.events[slot] = None
         self.batches[slot] = None
         return out
 
 
+class GpuExecutor(_GpuSlots):
+    """Slots = BatchRunners (mhfd_detect_batched), each with its own stream;
+    tile copies on a separate copy stream."""
+
+    def __init__(self, plan, n_slots: int = 2, slot_tiles: int = 32, slot_pixels: int = 1 << 27,
+                 capacity: int = 1 << 16, autotuner=None, keep_blobs: bool = False):
+        from .batch import BatchRunner
+        self._init_slots(plan, n_slots, keep_blobs)
+        self.slot_tiles, self.slot_pixels = slot_tiles, slot_pixels
+        self.autotuner = autotuner
+        self.runners = [BatchRunner(plan, slot_tiles, slot_pixels, capacity) for _ in range(n_slots)]
+        self.fixed_bytes = sum(r.ws_bytes + r.blobs.numel() * 4 + r.results.numel() * 8
+                               for r in self.runners)
+
+    def launch(self, slot: int, batch) -> None:
+        s = self._begin(slot, batch)
+        imgs = [r.staged[0] for r in batch]
+        segs = ([self.autotuner.seg_rows_for(r.h, r.w) for r in batch]
+                if self.autotuner else None)
+        runner = self.runners[slot]
+        runner.set_tiles(imgs, segs, stream=s)
+        runner.run(s)
+        self._end(slot, batch)
+
+    def _results(self, slot: int, n: int):
+        runner = self.runners[slot]
+        res = runner.results[:n].cpu().numpy()
+        blobs = runner.blobs[:n].cpu().numpy() if self.keep_blobs else None
+        return res, blobs
+
+
+class PlainExecutor(_GpuSlots):
+    """The comparison point of the batched server: the same scheduler, but
+    every slot runs one tile at a time through plain mhfd_detect calls on its
+    own stream (no batching), with workspaces for the largest tile."""
+
+    def __init__(self, plan, n_slots: int = 3, max_h: int = 8192, max_w: int = 8192,
+                 capacity: int = 1 << 16, keep_blobs: bool = False):
+        import torch
+        self._init_slots(plan, n_slots, keep_blobs)
+        self.slot_tiles, self.slot_pixels = 1, max_h * max_w
+        nb = plan.detect_workspace_bytes(max_h, max_w)
+        dev = plan.device
+        self.ws = [torch.empty(nb, dtype=torch.uint8, device=dev) for _ in range(n_slots)]
+        self.raw = [torch.empty((capacity, 5), dtype=torch.int32, device=dev)
+                    for _ in range(n_slots)]
+        self.res = [torch.zeros((1, 4), dtype=torch.int64, device=dev) for _ in range(n_slots)]
+        self.capacity = capacity
+        self.fixed_bytes = n_slots * (nb + capacity * 20 + 32)
+
+    def launch(self, slot: int, batch) -> None:
+        s = self._begin(slot, batch)
+        (r,) = batch
+        self.plan.detect_into(r.staged[0], self.raw[slot], self.res[slot][0], None,
+                              self.ws[slot], stream=s)
+        self._end(slot, batch)
+
+    def _results(self, slot: int, n: int):
+        res = self.res[slot][:n].cpu().numpy()
+        blobs = self.raw[slot][None].cpu().numpy() if self.keep_blobs else None
+        return res, blobs
+
+
 def summarize(reqs, wall: float) -> dict:
     ok = [r for r in reqs if r.error is None]
     lat = np.array([r.latency for r in ok]) * 1e3
+    dev = np.array([r.device_ms for r in ok if r.device_ms >= 0])
     mpix = sum(r.pixels for r in ok) / 1e6
+    pct = lambda a, q: float(np.percentile(a, q)) if len(a) else None  # noqa: E731
     return {"requests": len(reqs), "served": len(ok),
-            "p50_ms": float(np.percentile(lat, 50)) if len(lat) else None,
-            "p99_ms": float(np.percentile(lat, 99)) if len(lat) else None,
+            "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
             "mean_ms": float(lat.mean()) if len(lat) else None,
+            "device_p50_ms": pct(dev, 50), "device_p99_ms": pct(dev, 99),
             "mpix": mpix, "mpix_per_s": mpix / wall}

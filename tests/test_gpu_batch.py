@@ -223,3 +223,31 @@ def test_odd_shapes_and_one_column_lanes(K):
     for im, g in zip(imgs, got):
         same(g, plan.detect(im))
     assert sum(g.count for g in got) > 20
+
+
+@pytest.mark.parametrize("lanes", [2, 3])
+def test_lanes_equal_one_batch_and_replay(lanes):
+    """Tiles dealt to concurrent sub-batches (lanes) give every tile the same
+    result as the single-tile path, eagerly and from a captured graph
+    replayed with new tiles of other sizes."""
+    from paper_2108_12050_amd import BatchRunner
+    plan = plan_f32()
+    a = small_mixed(6, 8)
+    b = small_mixed(7, 8)
+    px = max(sum(t.numel() for t in a), sum(t.numel() for t in b))
+    r = BatchRunner(plan, 8, px, 1 << 14, lanes=lanes)
+    r.set_tiles(a)
+    assert sum(r.lane_n) == 8 and all(n > 0 for n in r.lane_n)
+    r.run()
+    torch.cuda.synchronize()
+    ref_a = [plan.detect(t) for t in a]
+    for d, ref in zip(r.detections(), ref_a):
+        same(d, ref)
+    g = r.capture()
+    ref_b = [plan.detect(t) for t in b]
+    r.set_tiles(b)
+    for _ in range(2):
+        g.replay()
+        torch.cuda.synchronize()
+        for d, ref in zip(r.detections(), ref_b):
+            same(d, ref)

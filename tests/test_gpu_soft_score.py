@@ -226,3 +226,22 @@ def test_full_size_gradient_batch():
     dI_o, ds_o = oracle.soft_score_grad(I0, np.float64(sig), BETA, TAU, np.ones(1))
     np.testing.assert_allclose(ds, ds_o, rtol=0, atol=1e-4 * np.abs(ds_o).max())
     check_image_grad(dI0[None], dI_o, imgs[0:1], np.float64(sig), [1.0])
+
+
+def test_default_halos_follow_the_plan_radii():
+    """Without sigma_cap each scale's halo is its plan radius rounded up to a
+    multiple of 4: a sigma may move while its radius fits (scores then equal
+    the oracle's at that sigma), and one whose radius outgrows it raises."""
+    from paper_2108_12050_amd import MHFDError
+    H, W = 60, 70
+    img = synth.blob_field(8, H, W, n_blobs=5)[None]
+    plan = make_plan([1.0, 2.0, 3.0], H, W)            # radii 4, 8, 12: halos 4, 8, 12
+    sig32 = np.float32([1.1, 1.9, 3.12])                # radii 4, 8, 12
+    g = plan.focus_score(to_dev(img), to_dev(sig32), BETA, TAU).cpu().numpy()
+    np.testing.assert_allclose(g, oracle.soft_score(img.astype(np.float64), np.float64(sig32),
+                                                    BETA, TAU), rtol=1e-5, atol=0)
+    _, ds = plan.focus_score_backward(to_dev(img), to_dev(sig32), torch.ones(1).cuda(), BETA, TAU)
+    _, ds_o = oracle.soft_score_grad(img.astype(np.float64), np.float64(sig32), BETA, TAU)
+    np.testing.assert_allclose(ds.cpu().numpy(), ds_o, rtol=0, atol=1e-4 * np.abs(ds_o).max())
+    with pytest.raises(MHFDError):   # radius 5 > halo 4
+        plan.focus_score(to_dev(img), to_dev(np.float32([1.2, 2.0, 3.0])), BETA, TAU)
