@@ -22,7 +22,8 @@ Besides the headline line the JSON carries:
   focus          blob count per PSF sigma (the focus criterion);
   forms.batched  64 fp32 tiles of sizes {1024^2, 2048x1536, 3072x2048, 4096^2}
                  (8 rendered images reused across the 64 descriptors):
-                 autotuned segment heights, one captured HIP graph replayed,
+                 autotuned segment heights and launch shape, one captured
+                 HIP graph replayed,
                  against a loop of single-tile calls on the same tiles;
   forms.soft_score  8 x 2048^2 fp32, K = 10: forward and backward times;
   forms.serving  a slice of the serving workload (Poisson arrivals at 50/s,
@@ -236,7 +237,6 @@ def bench_batched(warmup: int) -> dict:
 
     from paper_2108_12050_amd import Plan, _lib, synth
     from paper_2108_12050_amd.autotune import Autotuner
-    from paper_2108_12050_amd.batch import BatchRunner
     shapes = synth.mixed_batch_shapes(0, 64)
     pool = {}
     for i, (h, w, p) in enumerate(shapes):
@@ -252,7 +252,8 @@ def bench_batched(warmup: int) -> dict:
     classes = sorted(set((h, w) for h, w, _ in shapes))
     report = tuner.tune(classes, reps=3)
     segs = [tuner.seg_rows_for(*t.shape) for t in imgs]
-    r = BatchRunner(plan, 64, px, 1 << 17, lanes=BATCH_LANES)
+    launch = tuner.tune_launch(imgs, reps=2)
+    r = tuner.runner(64, px, 1 << 17)
     r.set_tiles(imgs, segs)
     g = r.capture()
     for _ in range(max(1, warmup // 5)):
@@ -309,8 +310,15 @@ def bench_batched(warmup: int) -> dict:
             "plain_per_tile_ms": round(float(np.median(plain_ms)), 3),
             "plain_per_tile_3streams_ms": round(float(np.median(plain3_ms)), 3),
             "identical_counts": counts_b == counts_p == counts_p3,
-            "lanes": BATCH_LANES,
-            "seg_rows": {f"{h}x{w}": report[(h, w)][0] for (h, w) in classes}}
+            "autotune": {
+                "seg_rows": {f"{h}x{w}": report[(h, w)][0] for (h, w) in classes},
+                "per_class_ms_default_vs_tuned": {
+                    f"{h}x{w}": [round(report[(h, w)][1][0], 3),
+                                 round(report[(h, w)][1][report[(h, w)][0]], 3)]
+                    for (h, w) in classes},
+                "launch": launch["best"],
+                "batch_ms_default_vs_tuned_launch": [round(launch["default_ms"], 3),
+                                                     round(launch["best_ms"], 3)]}}
 
 
 def bench_soft() -> dict:
@@ -490,7 +498,6 @@ def profile_run(kind: str) -> int:
     from paper_2108_12050_amd import Plan, synth
     if kind == "batch":
         from paper_2108_12050_amd.autotune import Autotuner
-        from paper_2108_12050_amd.batch import BatchRunner
         shapes = synth.mixed_batch_shapes(0, 64)
         pool = {}
         for i, (h, w, p) in enumerate(shapes):
@@ -503,7 +510,8 @@ def profile_run(kind: str) -> int:
                     max_h=4096, max_w=4096)
         tuner = Autotuner(plan)
         tuner.tune(sorted(set((h, w) for h, w, _ in shapes)), reps=1)
-        r = BatchRunner(plan, 64, sum(t.numel() for t in imgs), 1 << 17, lanes=BATCH_LANES)
+        tuner.launch = {"log_groups_per_cu": 2, "nms_groups_per_cu": 8, "lanes": BATCH_LANES}
+        r = tuner.runner(64, sum(t.numel() for t in imgs), 1 << 17)
         r.set_tiles(imgs, [tuner.seg_rows_for(*t.shape) for t in imgs])
         g = r.capture()
         for _ in range(6):

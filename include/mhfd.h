@@ -305,6 +305,17 @@ typedef struct mhfd_tile {
  * workspace bounds); nothing was computed for the batch. */
 #define MHFD_FLAG_INVALID_TILE 4
 
+/* Launch shape of a batched call; NULL (or a field of 0) takes the default.
+ * The results do not depend on it, only the time does (the autotuner of the
+ * Python layer chooses it).
+ *   log_groups_per_cu  persistent LoG workgroups per compute unit, 1..8 (2)
+ *   nms_groups_per_cu  persistent maxima workgroups per compute unit, 1..32 (8)
+ * Values outside the ranges give MHFD_ERR_INVALID_ARG. */
+typedef struct mhfd_batch_opts {
+    int32_t log_groups_per_cu;
+    int32_t nms_groups_per_cu;
+} mhfd_batch_opts;
+
 /* Workspace bytes mhfd_detect_batched needs for up to max_tiles tiles with at
  * most max_pixels pixels in total (0 on bad input). */
 size_t mhfd_batch_workspace_size(mhfd_plan plan, int32_t max_tiles, int64_t max_pixels);
@@ -320,11 +331,13 @@ size_t mhfd_batch_workspace_size(mhfd_plan plan, int32_t max_tiles, int64_t max_
  *             MHFD_FLAG_INVALID_TILE with zero counts and no tile is processed.
  *   max_pixels, d_ws, ws_bytes  bounds the workspace was sized for
  *             (mhfd_batch_workspace_size(plan, n_max, max_pixels), n <= n_max).
+ *   opts      launch shape (mhfd_batch_opts), NULL for the defaults.
  * Scales of a radius class run as persistent workgroups that pull
  * (scale, tile, strip, segment) items, largest radius first.
  */
 mhfd_status mhfd_detect_batched(mhfd_plan plan, int32_t n, const mhfd_tile *d_tiles,
-                                int64_t max_pixels, void *d_ws, size_t ws_bytes, void *stream);
+                                int64_t max_pixels, const struct mhfd_batch_opts *opts,
+                                void *d_ws, size_t ws_bytes, void *stream);
 
 /* Workspace bytes mhfd_focus_score and mhfd_focus_score_backward need for a
  * batch of b images of h x w (0 on bad input). */

@@ -67,6 +67,10 @@ class Tile(C.Structure):
                 ("seg_rows", C.c_int32)]
 
 
+class BatchOpts(C.Structure):
+    _fields_ = [("log_groups_per_cu", C.c_int32), ("nms_groups_per_cu", C.c_int32)]
+
+
 class Result(C.Structure):
     _fields_ = [("n_blobs", C.c_int64), ("n_candidates", C.c_int64), ("flags", C.c_int32),
                 ("reserved", C.c_int32), ("density", C.c_double)]
@@ -124,7 +128,7 @@ def load(path: str | None = None):
     L.mhfd_stretch_levels.restype = C.c_int
     L.mhfd_batch_workspace_size.argtypes = [vp, i32, i64]
     L.mhfd_batch_workspace_size.restype = sz
-    L.mhfd_detect_batched.argtypes = [vp, i32, vp, i64, vp, sz, vp]
+    L.mhfd_detect_batched.argtypes = [vp, i32, vp, i64, C.POINTER(BatchOpts), vp, sz, vp]
     L.mhfd_detect_batched.restype = C.c_int
     L.mhfd_focus_workspace_size.argtypes = [vp, i32, i32, i32]
     L.mhfd_focus_workspace_size.restype = sz

@@ -1,23 +1,36 @@
-"""Autotuner for the batched detector's per-size-class launch parameter.
+"""Autotuner of the batched detector's launch parameters.
 
-The LoG strip kernel gives each workgroup one (scale, 64-column strip,
-segment of rows).  The strip width and the 32-row chunk are fixed by the
-register and LDS layout, and a workgroup holds one scale.  What remains free
-is the segment height: every segment recomputes a 2R-row halo of row-pass
-results before its first output row, so tall segments waste less work,
-while short segments give more workgroups to balance across the 256 compute
-units.  The best height depends on the tile size and the plan's radii.
+The batched form (mhfd_detect_batched) runs the matrix-core LoG as
+persistent workgroups that pull (scale, tile, row segment, four 16-column
+wave tiles) items, then a persistent maxima pass.  What is free:
 
-`Autotuner.tune` times mhfd_detect_batched on a synthetic tile of each size
-class for each candidate height (HIP events, median of repeats), keeps the
-fastest, and caches the choice in a JSON file keyed by GPU architecture,
-library build and plan (scales, radii, dtype).  `seg_rows_for` returns the
-tuned height for a tile (nearest size class by pixel count), or 0 -- the
-library default -- when nothing was tuned.
+  * per size class, the segment height of a tile's LoG items (a multiple of
+    32 rows): every segment re-runs its ring's warm-up, 2 nkc - 1 blocks of
+    16 intermediate rows per wave, so tall segments waste less work while
+    short ones give more items to balance across the 256 compute units;
+  * per batch, the launch shape: persistent LoG workgroups per compute unit
+    (1, 2 or 4) and maxima workgroups per compute unit (4, 8 or 16)
+    (mhfd_batch_opts), and the number of concurrent sub-batches ("lanes",
+    one stream each, whose phases overlap).
+
+Fixed by the kernels and therefore not tuned: the 16-column wave tile and
+the 32-row K-block of the MFMA operands, the per-scale halo (the exact
+column window, R rows above the block), and the scales a workgroup holds
+(one per item: its column taps in LDS, a ring per wave; items are numbered
+scale-major, so a workgroup keeps its taps over consecutive items).
+
+`Autotuner.tune` times one-tile batches of each size class for each
+candidate height (HIP events, median of repeats) beside the library default
+(0), keeps the fastest, and caches the choice in a JSON file keyed by GPU
+architecture, library build and plan (scales, radii, dtype).
+`tune_launch` times a representative batch over the launch shapes and
+lanes.  `seg_rows_for` returns the tuned height for a tile (nearest size
+class by pixel count), or 0 -- the library default -- when nothing was tuned.
 """
 from __future__ import annotations
 
 import hashlib
+import itertools
 import json
 import os
 
@@ -29,6 +42,10 @@ from .api import Plan
 from .batch import BatchRunner
 
 CANDIDATES = (64, 128, 256, 384, 512, 768, 1024)
+LOG_GROUPS = (1, 2, 4)
+NMS_GROUPS = (4, 8, 16)
+LANES = (1, 2, 3)
+DEFAULT_LAUNCH = {"log_groups_per_cu": 2, "nms_groups_per_cu": 8, "lanes": 1}
 
 
 def _lib_hash() -> str:
@@ -41,18 +58,33 @@ def _arch() -> str:
     return getattr(p, "gcnArchName", p.name).split(":")[0]
 
 
+def _median_ms(fn, reps: int) -> float:
+    times = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        times.append(a.elapsed_time(b))
+    return float(np.median(times))
+
+
 class Autotuner:
     def __init__(self, plan: Plan, cache_path: str | None = None):
         self.plan = plan
         self.cache_path = cache_path
         self.table: dict[tuple[int, int], int] = {}
+        self.launch = dict(DEFAULT_LAUNCH)
         self.key = json.dumps({"arch": _arch(), "lib": _lib_hash(), "sigmas": plan.sigmas,
                                "radii": plan.radii, "dtype": plan.dtype}, sort_keys=True)
         if cache_path and os.path.exists(cache_path):
             with open(cache_path) as f:
                 entry = json.load(f).get(self.key)
             if entry:
-                self.table = {tuple(map(int, k.split("x"))): int(v) for k, v in entry.items()}
+                self.table = {tuple(map(int, k.split("x"))): int(v)
+                              for k, v in entry.get("seg_rows", {}).items()}
+                self.launch.update(entry.get("launch", {}))
 
     def _tile(self, h: int, w: int, seed: int) -> torch.Tensor:
         from . import synth
@@ -63,39 +95,62 @@ class Autotuner:
         return torch.from_numpy(a).to(self.plan.device)
 
     def time_one(self, tile: torch.Tensor, seg: int, reps: int = 5) -> float:
-        """Median device milliseconds of one batched detection of `tile`."""
+        """Median device milliseconds of one batched detection of `tile`
+        (seg = 0: the library's default segment height)."""
         r = BatchRunner(self.plan, 1, tile.numel(), 1 << 12)
         r.set_tiles([tile], seg_rows=[seg])
         r.run()
-        times = []
-        for _ in range(reps):
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record()
-            r.run()
-            b.record()
-            b.synchronize()
-            times.append(a.elapsed_time(b))
-        return float(np.median(times))
+        return _median_ms(r.run, reps)
 
     def tune(self, sizes, candidates=CANDIDATES, reps: int = 5) -> dict:
-        """Tune each (h, w) in `sizes`; returns {size: (best_seg, {seg: ms})}."""
+        """Tune each (h, w) in `sizes`; returns {size: (best_seg, {seg: ms})},
+        where seg 0 is the library default the gain is measured against."""
         report = {}
         for i, (h, w) in enumerate(sizes):
             tile = self._tile(int(h), int(w), 500 + i)
             cands = [c for c in candidates if c <= max(32, (h + 31) // 32 * 32)] or [32]
-            t = {c: self.time_one(tile, c, reps) for c in cands}
-            best = min(t, key=t.get)
+            t = {c: self.time_one(tile, c, reps) for c in [0] + cands}
+            best = min(cands, key=t.get)
             self.table[(int(h), int(w))] = best
             report[(int(h), int(w))] = (best, t)
-        if self.cache_path:
-            data = {}
-            if os.path.exists(self.cache_path):
-                with open(self.cache_path) as f:
-                    data = json.load(f)
-            data[self.key] = {f"{h}x{w}": s for (h, w), s in self.table.items()}
-            with open(self.cache_path, "w") as f:
-                json.dump(data, f, indent=1)
+        self._save()
         return report
+
+    def tune_launch(self, imgs, reps: int = 3) -> dict:
+        """Time the batch `imgs` (device tiles, tuned segment heights) for
+        every launch shape and lane count; keep the fastest.  Returns
+        {"best": shape, "default_ms", "best_ms", "times": {shape: ms}}."""
+        px = sum(t.numel() for t in imgs)
+        segs = [self.seg_rows_for(*t.shape) for t in imgs]
+        times = {}
+        for lg, ng, ln in itertools.product(LOG_GROUPS, NMS_GROUPS, LANES):
+            r = BatchRunner(self.plan, len(imgs), px, 1 << 12, lanes=ln,
+                            log_groups_per_cu=lg, nms_groups_per_cu=ng)
+            r.set_tiles(imgs, segs)
+            r.run()
+            times[(lg, ng, ln)] = _median_ms(r.run, reps)
+            del r
+        best = min(times, key=times.get)
+        self.launch = {"log_groups_per_cu": best[0], "nms_groups_per_cu": best[1],
+                       "lanes": best[2]}
+        self._save()
+        d = (DEFAULT_LAUNCH["log_groups_per_cu"], DEFAULT_LAUNCH["nms_groups_per_cu"],
+             DEFAULT_LAUNCH["lanes"])
+        return {"best": dict(self.launch), "default_ms": times[d], "best_ms": times[best],
+                "times": {f"log{k[0]}_nms{k[1]}_lanes{k[2]}": round(v, 3)
+                          for k, v in times.items()}}
+
+    def _save(self) -> None:
+        if not self.cache_path:
+            return
+        data = {}
+        if os.path.exists(self.cache_path):
+            with open(self.cache_path) as f:
+                data = json.load(f)
+        data[self.key] = {"seg_rows": {f"{h}x{w}": s for (h, w), s in self.table.items()},
+                          "launch": self.launch}
+        with open(self.cache_path, "w") as f:
+            json.dump(data, f, indent=1)
 
     def seg_rows_for(self, h: int, w: int) -> int:
         if not self.table:
@@ -105,3 +160,8 @@ class Autotuner:
         px = h * w
         near = min(self.table, key=lambda s: abs(np.log(s[0] * s[1]) - np.log(px)))
         return self.table[near]
+
+    def runner(self, max_tiles: int, max_pixels: int, capacity: int) -> BatchRunner:
+        """A BatchRunner with the tuned launch shape and lanes."""
+        return BatchRunner(self.plan, max_tiles, max_pixels, capacity, self.launch["lanes"],
+                           self.launch["log_groups_per_cu"], self.launch["nms_groups_per_cu"])

@@ -35,7 +35,7 @@ class BatchRunner:
     ``lanes`` concurrent sub-batches."""
 
     def __init__(self, plan: Plan, max_tiles: int, max_pixels: int, capacity: int,
-                 lanes: int = 1):
+                 lanes: int = 1, log_groups_per_cu: int = 0, nms_groups_per_cu: int = 0):
         self.plan = plan
         self.L = plan._L
         self.max_tiles, self.max_pixels, self.capacity = int(max_tiles), int(max_pixels), int(capacity)
@@ -60,6 +60,8 @@ class BatchRunner:
         self.results = torch.zeros((self.max_tiles, _lib.RESULT_WORDS), dtype=torch.int64,
                                    device=dev)
         self.streams = [torch.cuda.Stream() for _ in range(self.lanes - 1)]
+        # launch shape of every call (0: the library's default)
+        self.opts = _lib.BatchOpts(int(log_groups_per_cu), int(nms_groups_per_cu))
         self.n = 0
         self.lane_n = [0] * self.lanes
         self._imgs = []
@@ -67,7 +69,11 @@ class BatchRunner:
     def set_tiles(self, imgs, seg_rows=None, stream=None) -> None:
         """Write descriptors for `imgs` (device tensors of the plan's dtype,
         rows contiguous) into the device table, on `stream` (default: the
-        current stream).  The tensors must stay alive while the batch runs."""
+        current stream).  The tensors must stay alive while the batch runs.
+        A graph captured by `capture` processes the tile count it was
+        captured with: replay it after set_tiles with that many tiles (with
+        one lane, fewer tiles also run, and the later descriptors of the
+        capture are processed again as they were)."""
         n = len(imgs)
         if not 1 <= n <= self.max_tiles:
             raise ValueError(f"{n} tiles, runner holds 1..{self.max_tiles}")
@@ -97,7 +103,9 @@ class BatchRunner:
                 r["capacity"] = self.capacity
                 r["seg_rows"] = 0 if seg_rows is None else int(seg_rows[i])
         self.lane_n = [len(m) for m in lanes]
-        host = torch.from_numpy(t.view(np.uint8).copy())
+        # one lane: only the n descriptors written (a graph captured for more
+        # tiles keeps reading its later descriptors as they were)
+        host = torch.from_numpy((t[:n] if self.lanes == 1 else t).view(np.uint8).copy())
         s = stream if stream is not None else torch.cuda.current_stream()
         with torch.cuda.stream(s):
             self.table[: host.numel()].copy_(host.pin_memory(), non_blocking=True)
@@ -118,8 +126,9 @@ class BatchRunner:
             st_ = main if j == 0 else side[j]
             table = self.table.data_ptr() + j * self.max_tiles * TILE_DTYPE.itemsize
             status = self.L.mhfd_detect_batched(self.plan._handle, self.lane_n[j], table,
-                                                self.lane_pixels, self.ws[j].data_ptr(),
-                                                self.lane_ws_bytes, int(st_.cuda_stream))
+                                                self.lane_pixels, C.byref(self.opts),
+                                                self.ws[j].data_ptr(), self.lane_ws_bytes,
+                                                int(st_.cuda_stream))
             _lib.check(status, "mhfd_detect_batched")
         for st_ in side.values():
             main.wait_stream(st_)

@@ -1003,9 +1003,15 @@ size_t mhfd_batch_workspace_size(mhfd_plan p, int32_t max_tiles, int64_t max_pix
 }
 
 mhfd_status mhfd_detect_batched(mhfd_plan p, int32_t n, const mhfd_tile* d_tiles,
-                                int64_t max_pixels, void* d_ws, size_t ws_bytes, void* stream) {
+                                int64_t max_pixels, const mhfd_batch_opts* opts, void* d_ws,
+                                size_t ws_bytes, void* stream) {
     g_last_error.clear();
     if (!p) return fail(MHFD_ERR_INVALID_ARG, "null plan");
+    const int log_per_cu = opts && opts->log_groups_per_cu ? opts->log_groups_per_cu : 2;
+    const int nms_per_cu = opts && opts->nms_groups_per_cu ? opts->nms_groups_per_cu : 8;
+    if (log_per_cu < 1 || log_per_cu > 8 || nms_per_cu < 1 || nms_per_cu > 32)
+        return fail(MHFD_ERR_INVALID_ARG, "batch options out of range (log %d of 1..8, maxima %d "
+                    "of 1..32 workgroups per compute unit)", log_per_cu, nms_per_cu);
     if (p->stretch || p->criterion != MHFD_CRITERION_LOG)
         return fail(MHFD_ERR_UNSUPPORTED, "batched detection takes plain LoG plans only");
     if (!d_tiles || !d_ws) return fail(MHFD_ERR_INVALID_ARG, "null tiles or workspace");
@@ -1058,7 +1064,7 @@ mhfd_status mhfd_detect_batched(mhfd_plan p, int32_t n, const mhfd_tile* d_tiles
                         key.first, key.second);
         e = mhfd::launch_log_mfma_batch(p->dtype, key.first, key.second, n, tiles,
                                         p->dtype == MHFD_F32 ? maxbits : nullptr, stack,
-                                        p->d_frags, sc, ctr, slot, 2 * p->n_cu, act,
+                                        p->d_frags, sc, ctr, slot, log_per_cu * p->n_cu, act,
                                         p->threshold, s);
         if (e != hipSuccess) return hip_fail(e, "batched LoG (matrix cores) launch");
     }
@@ -1080,14 +1086,14 @@ mhfd_status mhfd_detect_batched(mhfd_plan p, int32_t n, const mhfd_tile* d_tiles
         }
         if (!sc.n) continue;
         e = mhfd::launch_log_batch(cls, p->dtype, n, tiles, p->K, stack, p->d_taps, sc, ctr,
-                                   2 * p->n_cu, s);
+                                   log_per_cu * p->n_cu, s);
         if (e != hipSuccess) return hip_fail(e, "batched LoG launch");
     }
     mhfd::BatchLaunchArgs a{};
     a.K = p->K;
     a.n_tiles = n;
     a.n_blk_bound = L.n_blk_bound;
-    a.nms_grid = 8 * p->n_cu;
+    a.nms_grid = nms_per_cu * p->n_cu;
     a.reach = p->reach;
     a.d2top = p->d2_top;
     a.tau = p->threshold;

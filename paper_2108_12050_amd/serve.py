@@ -284,12 +284,14 @@ class GpuExecutor(_GpuSlots):
     tile copies on a separate copy stream."""
 
     def __init__(self, plan, n_slots: int = 2, slot_tiles: int = 32, slot_pixels: int = 1 << 27,
-                 capacity: int = 1 << 16, autotuner=None, keep_blobs: bool = False):
+                 capacity: int = 1 << 16, autotuner=None, keep_blobs: bool = False,
+                 lanes: int = 1):
         from .batch import BatchRunner
         self._init_slots(plan, n_slots, keep_blobs)
         self.slot_tiles, self.slot_pixels = slot_tiles, slot_pixels
         self.autotuner = autotuner
-        self.runners = [BatchRunner(plan, slot_tiles, slot_pixels, capacity) for _ in range(n_slots)]
+        self.runners = [BatchRunner(plan, slot_tiles, slot_pixels, capacity, lanes)
+                        for _ in range(n_slots)]
         self.fixed_bytes = sum(r.ws_bytes + r.blobs.numel() * 4 + r.results.numel() * 8
                                for r in self.runners)
 

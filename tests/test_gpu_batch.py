@@ -251,3 +251,44 @@ def test_lanes_equal_one_batch_and_replay(lanes):
         torch.cuda.synchronize()
         for d, ref in zip(r.detections(), ref_b):
             same(d, ref)
+
+
+def test_autotuner_choices_keep_results():
+    """The autotuner picks a segment height per size class and a launch shape
+    for a batch from its candidates; the tuned runner's results equal the
+    single-tile path's (launch parameters change the time only)."""
+    import os
+    import tempfile
+    from paper_2108_12050_amd.autotune import CANDIDATES, LANES, LOG_GROUPS, NMS_GROUPS, Autotuner
+    plan = plan_f32()
+    imgs = small_mixed(9, 6)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "tune.json")
+        tuner = Autotuner(plan, path)
+        classes = sorted(set(tuple(t.shape) for t in imgs))
+        rep = tuner.tune(classes, reps=2)
+        for c in classes:
+            best, times = rep[c]
+            assert best in CANDIDATES and 0 in times and times[best] <= min(times.values()) + 1e-9
+        lt = tuner.tune_launch(imgs, reps=1)
+        b = lt["best"]
+        assert b["log_groups_per_cu"] in LOG_GROUPS and b["nms_groups_per_cu"] in NMS_GROUPS
+        assert b["lanes"] in LANES and lt["best_ms"] <= lt["default_ms"] + 1e-9
+        again = Autotuner(plan, path)          # the cache gives the same choices
+        assert again.table == tuner.table and again.launch == tuner.launch
+        r = tuner.runner(len(imgs), sum(t.numel() for t in imgs), 1 << 14)
+        r.set_tiles(imgs, [tuner.seg_rows_for(*t.shape) for t in imgs])
+        r.run()
+        torch.cuda.synchronize()
+        for dd, t in zip(r.detections(), imgs):
+            same(dd, plan.detect(t))
+
+
+def test_batch_options_are_checked():
+    import ctypes as C
+    from paper_2108_12050_amd import _lib
+    plan = plan_f32(max_hw=128)
+    L = _lib.load()
+    bad = _lib.BatchOpts(9, 8)
+    assert L.mhfd_detect_batched(plan._handle, 1, 1 << 20, 100, C.byref(bad), 1 << 20, 1 << 20,
+                                 None) == 1
