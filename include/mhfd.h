@@ -124,6 +124,25 @@ typedef struct mhfd_result {
 #define MHFD_CRITERION_LOG 0
 #define MHFD_CRITERION_DOG 1
 
+/*
+ * How a plan computes the stack (the convolution of section 3).
+ *   DIRECT  separable convolution on the matrix cores (radius <= 56) or the
+ *           vector units (radius <= MHFD_MAX_RADIUS); cost grows with sigma.
+ *   FFT     products of transforms: the image's 2-D DCT-II (the Fourier
+ *           transform of its half-sample symmetric extension) times each
+ *           scale's kernel spectrum, then the inverse DCT; cost independent
+ *           of sigma, radius up to MHFD_MAX_FFT_RADIUS.  Images must have
+ *           power-of-two sides of at most MHFD_MAX_FFT_SIZE
+ *           (MHFD_ERR_UNSUPPORTED otherwise); the LoG criterion only, no
+ *           stretch; detection only (batched and focus-score calls refuse
+ *           such plans).  FP32 arithmetic, twiddles and spectra built in
+ *           FP64.
+ */
+#define MHFD_BLUR_DIRECT 0
+#define MHFD_BLUR_FFT 1
+#define MHFD_MAX_FFT_SIZE 4096
+#define MHFD_MAX_FFT_RADIUS 2048
+
 typedef struct mhfd_config {
     int32_t n_scales;        /* K, 1..MHFD_MAX_SCALES */
     float sigma_min;         /* linear grid sigma_k = min + k (max - min)/(K - 1), */
@@ -153,6 +172,7 @@ typedef struct mhfd_config {
                                 halo is its plan radius rounded up to a
                                 multiple of 4, and a sigma may move while its
                                 radius stays within that                       */
+    int32_t blur;            /* MHFD_BLUR_DIRECT (0) or MHFD_BLUR_FFT (1)       */
 } mhfd_config;
 
 typedef struct mhfd_plan_s *mhfd_plan;

@@ -17,6 +17,9 @@ MHFD_MAX_RADIUS = 64
 MHFD_F32, MHFD_U8 = 0, 1
 MHFD_BRIGHT, MHFD_DARK = 0, 1
 MHFD_CRITERION_LOG, MHFD_CRITERION_DOG = 0, 1
+MHFD_BLUR_DIRECT, MHFD_BLUR_FFT = 0, 1
+MHFD_MAX_FFT_SIZE = 4096
+MHFD_MAX_FFT_RADIUS = 2048
 MHFD_FLAG_BLOB_OVERFLOW = 1
 MHFD_FLAG_CAND_OVERFLOW = 2
 MHFD_FLAG_INVALID_TILE = 4
@@ -53,7 +56,7 @@ class Config(C.Structure):
                 ("threshold", C.c_float), ("overlap", C.c_float), ("polarity", C.c_int32),
                 ("in_dtype", C.c_int32), ("max_h", C.c_int32), ("max_w", C.c_int32),
                 ("max_candidates", C.c_int64), ("stretch", C.c_int32), ("criterion", C.c_int32),
-                ("sigma_cap", C.c_float)]
+                ("sigma_cap", C.c_float), ("blur", C.c_int32)]
 
 
 class Blob(C.Structure):

@@ -61,13 +61,15 @@ class Plan:
     Scales follow section 2.2's linear grid (sigma_min .. sigma_max, K = n+1
     values) unless ``sigmas`` is given.  ``threshold`` is the strict lower
     bound on the response of a candidate, ``overlap`` the pruning threshold
-    (>= 1 disables pruning)."""
+    (>= 1 disables pruning).  ``blur="fft"`` computes the scale space in
+    the frequency domain (power-of-two tiles, radii up to 2048)."""
 
     def __init__(self, n_scales: int = 10, sigma_min: float = 1.0, sigma_max: float = 10.0,
                  sigmas=None, truncate: float = 4.0, threshold: float = 0.1,
                  overlap: float = 0.5, polarity: str = "bright", dtype: str = "f32",
                  max_h: int = 4096, max_w: int = 4096, max_candidates: int = 0,
-                 stretch: bool = False, criterion: str = "log", sigma_cap: float | None = None):
+                 stretch: bool = False, criterion: str = "log", sigma_cap: float | None = None,
+                 blur: str = "direct"):
         self._L = _lib.load()
         self._handle = None
         cfg = _lib.Config()
@@ -88,6 +90,7 @@ class Plan:
         cfg.stretch = 1 if stretch else 0
         cfg.criterion = {"log": _lib.MHFD_CRITERION_LOG, "dog": _lib.MHFD_CRITERION_DOG}[criterion]
         cfg.sigma_cap = 0.0 if sigma_cap is None else float(sigma_cap)
+        cfg.blur = {"direct": _lib.MHFD_BLUR_DIRECT, "fft": _lib.MHFD_BLUR_FFT}[blur]
         h = C.c_void_p()
         _lib.check(self._L.mhfd_create_plan(C.byref(cfg), C.byref(h)), "mhfd_create_plan")
         self._handle = h
@@ -104,6 +107,7 @@ class Plan:
         self.max_h, self.max_w = int(max_h), int(max_w)
         self.stretch = bool(stretch)
         self.criterion = criterion
+        self.blur = blur
         # None / 0: each scale may move while its radius stays within its
         # plan radius rounded up to a multiple of 4
         self.sigma_cap = float(sigma_cap) if sigma_cap else None

@@ -74,6 +74,11 @@ struct mhfd_plan_s {
     float sigma_cap = 0.0f;
     std::vector<int> focus_padded;
     uint32_t* d_scratch = nullptr;  // this device's static scratch (mhfd_log_stack_static)
+    int blur = MHFD_BLUR_DIRECT;
+    // MHFD_BLUR_FFT: device tables (taps in double, radii, normalisations,
+    // twiddles), one allocation
+    void* d_fft = nullptr;
+    mhfd::FftTables fft{};
 };
 
 namespace {
@@ -166,7 +171,8 @@ int max_overlapping_d2(double ra, double rb, double theta) {
     return static_cast<int>(lo);
 }
 
-size_t log_stack_scratch_bytes(const mhfd_plan_s* p) {
+size_t log_stack_scratch_bytes(const mhfd_plan_s* p, int h, int w) {
+    if (p->blur == MHFD_BLUR_FFT) return sizeof(float) * mhfd::fft_workspace_floats(p->K, h, w);
     if (p->stretch) return sizeof(int32_t) * (256 + 2);
     return (p->d_frags && p->dtype == MHFD_F32) ? sizeof(uint32_t) : 0;
 }
@@ -184,7 +190,9 @@ struct DetectLayout {
 // the whole stack.
 bool sparse_stack(const mhfd_plan_s* p) {
     // the maxima pass reads unwritten groups as 0, which must not exceed tau
-    if (p->criterion != MHFD_CRITERION_LOG || !p->d_frags || !(p->threshold >= 0.0f)) return false;
+    if (p->criterion != MHFD_CRITERION_LOG || p->blur != MHFD_BLUR_DIRECT || !p->d_frags ||
+        !(p->threshold >= 0.0f))
+        return false;
     for (int k = 0; k < p->K; ++k)
         if (p->mfma_off[k] < 0) return false;
     return true;
@@ -212,7 +220,7 @@ DetectLayout detect_layout(const mhfd_plan_s* p, int h, int w) {
     const int64_t longest = static_cast<int64_t>(cap) > L.n_blk ? static_cast<int64_t>(cap) : L.n_blk;
     L.scan_sums = take(sizeof(int32_t) * mhfd::scan_sums_ints(longest));
     L.ctr = take(sizeof(mhfd::DetectCounters));
-    L.maxbits = take(log_stack_scratch_bytes(p));
+    L.maxbits = take(log_stack_scratch_bytes(p, h, w));
     const bool dog = p->criterion == MHFD_CRITERION_DOG;
     L.dog_max = take(dog ? sizeof(float) * static_cast<size_t>(h) * w : 0);
     L.dog_arg = take(dog ? static_cast<size_t>(h) * w : 0);
@@ -222,6 +230,67 @@ DetectLayout detect_layout(const mhfd_plan_s* p, int h, int w) {
     L.act = take(sizeof(uint64_t) * static_cast<size_t>(p->K) * L.act_bx * L.act_by);
     L.total = off;
     return L;
+}
+
+// FFT plan tables in one device block: the one-sided taps g_0..g_R, h_0..h_R
+// of every scale and the normalisations s sigma^2 (double), tap offsets and
+// radii (int), twiddles e^{-2 pi i k / nmax} (k < nmax / 2) and
+// e^{-i pi k / (2 nmax)} (k < nmax) (float2 from double).
+hipError_t build_fft_tables(mhfd_plan_s* p) {
+    int nmax = 1;
+    while (nmax < p->max_h || nmax < p->max_w) nmax <<= 1;
+    std::vector<double> taps, norm(p->K);
+    std::vector<int> off(p->K), rad(p->K);
+    for (int k = 0; k < p->K; ++k) {
+        std::vector<double> g, h;
+        gauss_taps(static_cast<double>(p->sigmas[k]), p->radii[k], g, h);
+        off[k] = static_cast<int>(taps.size());
+        rad[k] = p->radii[k];
+        taps.insert(taps.end(), g.begin(), g.end());
+        taps.insert(taps.end(), h.begin(), h.end());
+        norm[k] = polarity_norm(static_cast<double>(p->sigmas[k]), p->polarity);
+    }
+    std::vector<float2> tw(nmax / 2 > 0 ? nmax / 2 : 1), q(nmax);
+    for (int k = 0; k < nmax / 2; ++k) {
+        const double a = -2.0 * M_PI * k / nmax;
+        tw[k] = make_float2(static_cast<float>(cos(a)), static_cast<float>(sin(a)));
+    }
+    for (int k = 0; k < nmax; ++k) {
+        const double a = -M_PI * k / (2.0 * nmax);
+        q[k] = make_float2(static_cast<float>(cos(a)), static_cast<float>(sin(a)));
+    }
+    size_t o = 0;
+    auto place = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    const size_t o_taps = place(sizeof(double) * taps.size());
+    const size_t o_norm = place(sizeof(double) * norm.size());
+    const size_t o_off = place(sizeof(int) * off.size());
+    const size_t o_rad = place(sizeof(int) * rad.size());
+    const size_t o_tw = place(sizeof(float2) * tw.size());
+    const size_t o_q = place(sizeof(float2) * q.size());
+    std::vector<char> blob(o, 0);
+    memcpy(blob.data() + o_taps, taps.data(), sizeof(double) * taps.size());
+    memcpy(blob.data() + o_norm, norm.data(), sizeof(double) * norm.size());
+    memcpy(blob.data() + o_off, off.data(), sizeof(int) * off.size());
+    memcpy(blob.data() + o_rad, rad.data(), sizeof(int) * rad.size());
+    memcpy(blob.data() + o_tw, tw.data(), sizeof(float2) * tw.size());
+    memcpy(blob.data() + o_q, q.data(), sizeof(float2) * q.size());
+    hipError_t e = hipMalloc(&p->d_fft, o);
+    if (e == hipSuccess) e = hipMemcpy(p->d_fft, blob.data(), o, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return e;
+    const char* b = static_cast<const char*>(p->d_fft);
+    p->fft.taps = reinterpret_cast<const double*>(b + o_taps);
+    p->fft.norm = reinterpret_cast<const double*>(b + o_norm);
+    p->fft.tap_off = reinterpret_cast<const int*>(b + o_off);
+    p->fft.radii = reinterpret_cast<const int*>(b + o_rad);
+    p->fft.tw = reinterpret_cast<const float2*>(b + o_tw);
+    p->fft.q = reinterpret_cast<const float2*>(b + o_q);
+    p->fft.K = p->K;
+    p->fft.nmax = nmax;
+    return hipSuccess;
 }
 
 mhfd_status check_device(const mhfd_plan_s* p) {
@@ -284,6 +353,14 @@ mhfd_status mhfd_create_plan(const mhfd_config* cfg, mhfd_plan* out) {
         return fail(MHFD_ERR_UNSUPPORTED, "the histogram stretch is built for 8-bit plans");
     if (!(cfg->sigma_cap >= 0.0f) || !isfinite(cfg->sigma_cap))
         return fail(MHFD_ERR_INVALID_ARG, "sigma_cap must be >= 0 and finite");
+    if (cfg->blur != MHFD_BLUR_DIRECT && cfg->blur != MHFD_BLUR_FFT)
+        return fail(MHFD_ERR_INVALID_ARG, "unknown blur %d", cfg->blur);
+    const bool fft = cfg->blur == MHFD_BLUR_FFT;
+    if (fft && (cfg->criterion != MHFD_CRITERION_LOG || cfg->stretch))
+        return fail(MHFD_ERR_UNSUPPORTED, "the FFT blur takes LoG plans without the stretch");
+    if (fft && (cfg->max_h > MHFD_MAX_FFT_SIZE || cfg->max_w > MHFD_MAX_FFT_SIZE))
+        return fail(MHFD_ERR_UNSUPPORTED, "the FFT blur takes tiles up to %d x %d",
+                    MHFD_MAX_FFT_SIZE, MHFD_MAX_FFT_SIZE);
 
     std::vector<float> sig(K);
     if (cfg->sigmas) {
@@ -317,6 +394,7 @@ mhfd_status mhfd_create_plan(const mhfd_config* cfg, mhfd_plan* out) {
     p->max_w = cfg->max_w;
     p->stretch = cfg->stretch;
     p->criterion = cfg->criterion;
+    p->blur = cfg->blur;
     int64_t dc = static_cast<int64_t>(cfg->max_h) * cfg->max_w / 64;
     p->max_cand = cfg->max_candidates > 0 ? cfg->max_candidates : (dc > 65536 ? dc : 65536);
     if (p->max_cand > (int64_t(1) << 30)) {
@@ -326,10 +404,11 @@ mhfd_status mhfd_create_plan(const mhfd_config* cfg, mhfd_plan* out) {
     size_t off = 0;
     for (int k = 0; k < K; ++k) {
         const int R = static_cast<int>(floor(static_cast<double>(p->truncate) * sig[k] + 0.5));
-        if (R > MHFD_MAX_RADIUS) {
+        const int rmax = fft ? MHFD_MAX_FFT_RADIUS : MHFD_MAX_RADIUS;
+        if (R > rmax) {
             delete p;
             return fail(MHFD_ERR_UNSUPPORTED, "radius %d of sigma %g exceeds %d", R,
-                        static_cast<double>(sig[k]), MHFD_MAX_RADIUS);
+                        static_cast<double>(sig[k]), rmax);
         }
         if ((cfg->stretch || cfg->criterion == MHFD_CRITERION_DOG) && !mhfd::mfma_radius_ok(R)) {
             delete p;
@@ -391,7 +470,7 @@ mhfd_status mhfd_create_plan(const mhfd_config* cfg, mhfd_plan* out) {
     {
         for (int k = 0; k < K; ++k) {
             const int R = p->radii[k];
-            if (!mhfd::mfma_radius_ok(R)) continue;
+            if (!mhfd::mfma_radius_ok(R) || p->blur == MHFD_BLUR_FFT) continue;
             std::vector<double> g, h;
             gauss_taps(static_cast<double>(sig[k]), R, g, h);
             const size_t at = frags.size();
@@ -445,6 +524,10 @@ mhfd_status mhfd_create_plan(const mhfd_config* cfg, mhfd_plan* out) {
         delete p;
         return hip_fail(e, "copy of the plan tables");
     }
+    if (p->blur == MHFD_BLUR_FFT && (e = build_fft_tables(p)) != hipSuccess) {
+        mhfd_destroy_plan(p);
+        return hip_fail(e, "FFT plan tables");
+    }
     *out = p;
     return MHFD_OK;
 }
@@ -455,6 +538,7 @@ mhfd_status mhfd_destroy_plan(mhfd_plan p) {
     hipFree(p->d_sigmas);
     hipFree(p->d_d2max);
     hipFree(p->d_frags);
+    hipFree(p->d_fft);
     delete p;
     return MHFD_OK;
 }
@@ -488,6 +572,9 @@ mhfd_status check_image(const mhfd_plan_s* p, const void* d_img, int32_t h, int3
     if (pitch < w) return fail(MHFD_ERR_INVALID_ARG, "pitch %lld < width %d", (long long)pitch, w);
     if (p->dtype == MHFD_F32 && reinterpret_cast<uintptr_t>(d_img) % 4)
         return fail(MHFD_ERR_INVALID_ARG, "float image not 4-byte aligned");
+    if (p->blur == MHFD_BLUR_FFT && (!mhfd::fft_size_ok(h) || !mhfd::fft_size_ok(w)))
+        return fail(MHFD_ERR_UNSUPPORTED, "the FFT blur takes power-of-two sides (image %d x %d)",
+                    h, w);
     return MHFD_OK;
 }
 
@@ -658,11 +745,19 @@ std::vector<std::pair<std::pair<int, int>, mhfd::MfmaLaunch>> mfma_launches(cons
 // Bytes of scratch the stack needs: the max |I| word of fp32 plans with
 // matrix-core scales; the 256-bin histogram and the two levels of stretch
 // plans.
-size_t log_stack_scratch(const mhfd_plan_s* p) { return log_stack_scratch_bytes(p); }
+size_t log_stack_scratch(const mhfd_plan_s* p, int h, int w) {
+    return log_stack_scratch_bytes(p, h, w);
+}
 
 mhfd_status enqueue_log_stack(const mhfd_plan_s* p, const void* d_img, int h, int w,
                               int64_t pitch, float* stack, uint32_t* maxbits, hipStream_t s,
                               const mhfd::ActOut& act = mhfd::ActOut{nullptr, 0, 0, 0.0f}) {
+    if (p->blur == MHFD_BLUR_FFT) {
+        hipError_t e = mhfd::launch_fft_log_stack(p->fft, p->dtype, d_img, h, w, pitch, stack,
+                                                  reinterpret_cast<float*>(maxbits), s);
+        if (e != hipSuccess) return hip_fail(e, "LoG stack (FFT) launch");
+        return MHFD_OK;
+    }
     std::vector<int> strip_scales;
     for (int k = 0; k < p->K; ++k)
         if (p->mfma_off.empty() || p->mfma_off[k] < 0) strip_scales.push_back(k);
@@ -785,7 +880,7 @@ mhfd_status check_focus(const mhfd_plan_s* p, const float* d_imgs, int b, int h,
                         const float* d_sigmas, float beta, float tau, const void* d_ws,
                         size_t ws_bytes) {
     if (!p) return fail(MHFD_ERR_INVALID_ARG, "null plan");
-    if (p->stretch || p->criterion != MHFD_CRITERION_LOG)
+    if (p->stretch || p->criterion != MHFD_CRITERION_LOG || p->blur != MHFD_BLUR_DIRECT)
         return fail(MHFD_ERR_UNSUPPORTED, "the focus score takes plain LoG plans only");
     if (!d_imgs || !d_sigmas || !d_ws) return fail(MHFD_ERR_INVALID_ARG, "null pointer argument");
     if (b < 1 || h < 1 || w < 1) return fail(MHFD_ERR_INVALID_ARG, "empty batch %d x %d x %d", b, h, w);
@@ -850,7 +945,7 @@ extern "C" {
 
 size_t mhfd_log_stack_workspace_size(mhfd_plan p, int32_t h, int32_t w) {
     if (!p || h < 1 || w < 1 || h > p->max_h || w > p->max_w) return 0;
-    return log_stack_scratch(p);
+    return log_stack_scratch(p, h, w);
 }
 
 mhfd_status mhfd_log_stack(mhfd_plan p, const void* d_img, int32_t h, int32_t w, int64_t pitch,
@@ -859,7 +954,7 @@ mhfd_status mhfd_log_stack(mhfd_plan p, const void* d_img, int32_t h, int32_t w,
     mhfd_status st = check_image(p, d_img, h, w, pitch);
     if (st != MHFD_OK) return st;
     if (!d_stack) return fail(MHFD_ERR_INVALID_ARG, "null stack");
-    const size_t need = log_stack_scratch(p);
+    const size_t need = log_stack_scratch(p, h, w);
     if (need) {
         if (!d_ws) return fail(MHFD_ERR_INVALID_ARG, "null workspace (this plan needs %zu bytes)", need);
         if (reinterpret_cast<uintptr_t>(d_ws) % 4)
@@ -878,7 +973,7 @@ mhfd_status mhfd_log_stack_static(mhfd_plan p, const void* d_img, int32_t h, int
     mhfd_status st = check_image(p, d_img, h, w, pitch);
     if (st != MHFD_OK) return st;
     if (!d_stack) return fail(MHFD_ERR_INVALID_ARG, "null stack");
-    const size_t need = log_stack_scratch(p);
+    const size_t need = log_stack_scratch(p, h, w);
     if (need > MHFD_STATIC_SCRATCH_BYTES)
         return fail(MHFD_ERR_UNSUPPORTED, "the plan needs %zu bytes of scratch, the static array "
                     "holds %d", need, MHFD_STATIC_SCRATCH_BYTES);
@@ -938,7 +1033,7 @@ mhfd_status mhfd_log_stack_sparse(mhfd_plan p, const void* d_img, int32_t h, int
     if (!d_stack || !d_act) return fail(MHFD_ERR_INVALID_ARG, "null stack or activity words");
     if (reinterpret_cast<uintptr_t>(d_act) % 8)
         return fail(MHFD_ERR_INVALID_ARG, "activity words not 8-byte aligned");
-    const size_t need = log_stack_scratch(p);
+    const size_t need = log_stack_scratch(p, h, w);
     if (need) {
         if (!d_ws) return fail(MHFD_ERR_INVALID_ARG, "null workspace (this plan needs %zu bytes)", need);
         if (reinterpret_cast<uintptr_t>(d_ws) % 4)
@@ -1012,7 +1107,7 @@ mhfd_status mhfd_detect_batched(mhfd_plan p, int32_t n, const mhfd_tile* d_tiles
     if (log_per_cu < 1 || log_per_cu > 8 || nms_per_cu < 1 || nms_per_cu > 32)
         return fail(MHFD_ERR_INVALID_ARG, "batch options out of range (log %d of 1..8, maxima %d "
                     "of 1..32 workgroups per compute unit)", log_per_cu, nms_per_cu);
-    if (p->stretch || p->criterion != MHFD_CRITERION_LOG)
+    if (p->stretch || p->criterion != MHFD_CRITERION_LOG || p->blur != MHFD_BLUR_DIRECT)
         return fail(MHFD_ERR_UNSUPPORTED, "batched detection takes plain LoG plans only");
     if (!d_tiles || !d_ws) return fail(MHFD_ERR_INVALID_ARG, "null tiles or workspace");
     BatchLayout L;

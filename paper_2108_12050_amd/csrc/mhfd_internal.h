@@ -165,6 +165,25 @@ hipError_t launch_stretch_levels(const uint8_t* img, int h, int w, long long pit
 hipError_t launch_absmax(const float* img, int h, int w, int64_t pitch, uint32_t* bits,
                          hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// Frequency-domain scale-space operator (plan mode MHFD_BLUR_FFT), fft_blur.hip.
+constexpr int FFT_MAX_N = MHFD_MAX_FFT_SIZE;  // longest transform (power of two)
+struct FftTables {      // device pointers, owned by the plan
+    const double* taps;     // per scale: g_0..g_R then h_0..h_R (one-sided)
+    const int* tap_off;     // first double of scale k
+    const int* radii;
+    const double* norm;     // s sigma_k^2
+    int K;
+    const float2* tw;       // e^{-2 pi i k / nmax}, k < nmax / 2
+    const float2* q;        // e^{-i pi k / (2 nmax)}, k < nmax
+    int nmax;
+};
+bool fft_size_ok(int n);
+// floats of scratch per call for an h x w tile
+size_t fft_workspace_floats(int K, int h, int w);
+hipError_t launch_fft_log_stack(const FftTables& T, int in_dtype, const void* img, int h, int w,
+                                int64_t pitch, float* stack, float* ws, hipStream_t s);
+
 // Detection tail: stack -> candidates -> canonical order -> prune -> blobs.
 struct DetectWorkspace {
     const float* stack;      // K x h x w
