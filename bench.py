@@ -191,6 +191,9 @@ def bench_dog(imgs, cap: int, warmup: int) -> dict:
     from paper_2108_12050_amd import Plan, _lib
     plan = Plan(n_scales=K, sigma_min=1.0, sigma_max=10.0, threshold=0.02, overlap=1.0,
                 dtype="u8", max_h=H, max_w=W, criterion="dog")
+    # the criterion looks for dark blobs (a minimum of the DoG): the tiles are
+    # inverted so that the features, not the background between them, are dark
+    imgs = [255 - t for t in imgs]
     L = _lib.load()
     ws = torch.empty(plan.detect_workspace_bytes(H, W), dtype=torch.uint8, device="cuda")
     stack = torch.empty((K, H, W), dtype=torch.float32, device="cuda")
@@ -223,11 +226,54 @@ def bench_dog(imgs, cap: int, warmup: int) -> dict:
     for i in range(len(imgs)):
         detect(i)
         counts.append(int(res[0].item()))
-    return {"workload": "4096x4096 u8 SEM tiles as above (bright texture, so the dark-blob "
-                        "DoG counts the background between features), sigma 1..10, "
-                        "threshold 0.02, no pruning",
+    return {"workload": "4096x4096 u8 SEM tiles as above, inverted (dark features), "
+                        "sigma 1..10, threshold 0.02, no pruning",
             "detector_ms_per_tile": round(det_ms, 4), "gaussian_planes_ms": round(pl_ms, 4),
             "mpix_s": round(H * W / 1e6 / (det_ms * 1e-3), 1), "count": counts}
+
+
+def bench_fft_blur(imgs, cap: int, warmup: int) -> dict:
+    """The detector with the frequency-domain scale space (blur="fft") beside
+    the direct one on the same 4096^2 u8 tiles, one stream, for scale ranges
+    of growing width (K = 10 linear scales each): per-tile milliseconds.
+    The direct form's radius limit is 64 (sigma 16); wider ranges are FFT
+    only."""
+    import numpy as np
+    import torch
+
+    from paper_2108_12050_amd import Plan, _lib
+    L = _lib.load()
+    raw = torch.empty((cap, 5), dtype=torch.int32, device="cuda")
+    res = torch.zeros(_lib.RESULT_WORDS, dtype=torch.int64, device="cuda")
+    sptr = int(torch.cuda.current_stream().cuda_stream)
+    out = {"workload": "4096x4096 u8 SEM tiles, K = 10 linear scales over each range, "
+                       "threshold 0.05, overlap 0.5", "ms_per_tile": {}}
+    for lo, hi in ((1.0, 10.0), (1.0, 14.0), (2.0, 16.0), (4.0, 64.0)):
+        row = {}
+        for blur in ("direct", "fft"):
+            if blur == "direct" and hi > 16.0:
+                continue
+            plan = Plan(sigmas=list(np.linspace(lo, hi, K)), threshold=TAU, overlap=OVERLAP,
+                        dtype="u8", max_h=H, max_w=W, blur=blur)
+            ws = torch.empty(plan.detect_workspace_bytes(H, W), dtype=torch.uint8, device="cuda")
+
+            def detect(i):
+                _lib.check(L.mhfd_detect(plan._handle, imgs[i % len(imgs)].data_ptr(), H, W, W,
+                                         raw.data_ptr(), cap, res.data_ptr(), None, ws.data_ptr(),
+                                         ws.numel(), sptr), "mhfd_detect")
+            for i in range(warmup):
+                detect(i)
+            n = 20
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for i in range(n):
+                detect(i)
+            e1.record()
+            e1.synchronize()
+            row[blur] = round(e0.elapsed_time(e1) / n, 4)
+            del ws, plan
+        out["ms_per_tile"][f"sigma {lo:g}..{hi:g}"] = row
+    return out
 
 
 def bench_batched(warmup: int) -> dict:
@@ -722,6 +768,7 @@ def main() -> int:
     if not a.no_forms:
         out["stretch"] = bench_stretch(imgs, nbytes, cap, a.warmup)
         out["paper_criterion"] = bench_dog(imgs, cap, a.warmup)
+        out["fft_blur"] = bench_fft_blur(imgs, cap, a.warmup)
     if not a.no_forms:
         del bufs
         torch.cuda.empty_cache()

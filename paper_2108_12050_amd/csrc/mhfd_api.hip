@@ -75,8 +75,8 @@ struct mhfd_plan_s {
     std::vector<int> focus_padded;
     uint32_t* d_scratch = nullptr;  // this device's static scratch (mhfd_log_stack_static)
     int blur = MHFD_BLUR_DIRECT;
-    // MHFD_BLUR_FFT: device tables (taps in double, radii, normalisations,
-    // twiddles), one allocation
+    // MHFD_BLUR_FFT: device tables (taps in double, radii, twiddles, the
+    // spectral weights of every scale), one allocation
     void* d_fft = nullptr;
     mhfd::FftTables fft{};
 };
@@ -172,7 +172,7 @@ int max_overlapping_d2(double ra, double rb, double theta) {
 }
 
 size_t log_stack_scratch_bytes(const mhfd_plan_s* p, int h, int w) {
-    if (p->blur == MHFD_BLUR_FFT) return sizeof(float) * mhfd::fft_workspace_floats(p->K, h, w);
+    if (p->blur == MHFD_BLUR_FFT) return sizeof(float) * mhfd::fft_workspace_floats(h, w);
     if (p->stretch) return sizeof(int32_t) * (256 + 2);
     return (p->d_frags && p->dtype == MHFD_F32) ? sizeof(uint32_t) : 0;
 }
@@ -233,13 +233,13 @@ DetectLayout detect_layout(const mhfd_plan_s* p, int h, int w) {
 }
 
 // FFT plan tables in one device block: the one-sided taps g_0..g_R, h_0..h_R
-// of every scale and the normalisations s sigma^2 (double), tap offsets and
-// radii (int), twiddles e^{-2 pi i k / nmax} (k < nmax / 2) and
-// e^{-i pi k / (2 nmax)} (k < nmax) (float2 from double).
+// of every scale (double), their offsets and radii (int), twiddles
+// e^{-2 pi i k / nmax} and e^{-i pi k / (2 nmax)} (k < nmax; float2 from
+// double), and the spectral weights the device computes from the taps once.
 hipError_t build_fft_tables(mhfd_plan_s* p) {
     int nmax = 1;
     while (nmax < p->max_h || nmax < p->max_w) nmax <<= 1;
-    std::vector<double> taps, norm(p->K);
+    std::vector<double> taps;
     std::vector<int> off(p->K), rad(p->K);
     for (int k = 0; k < p->K; ++k) {
         std::vector<double> g, h;
@@ -248,16 +248,15 @@ hipError_t build_fft_tables(mhfd_plan_s* p) {
         rad[k] = p->radii[k];
         taps.insert(taps.end(), g.begin(), g.end());
         taps.insert(taps.end(), h.begin(), h.end());
-        norm[k] = polarity_norm(static_cast<double>(p->sigmas[k]), p->polarity);
+        p->fft.norm[k] =
+            static_cast<float>(polarity_norm(static_cast<double>(p->sigmas[k]), p->polarity));
     }
-    std::vector<float2> tw(nmax / 2 > 0 ? nmax / 2 : 1), q(nmax);
-    for (int k = 0; k < nmax / 2; ++k) {
+    std::vector<float2> tw(nmax), q(nmax);
+    for (int k = 0; k < nmax; ++k) {
         const double a = -2.0 * M_PI * k / nmax;
         tw[k] = make_float2(static_cast<float>(cos(a)), static_cast<float>(sin(a)));
-    }
-    for (int k = 0; k < nmax; ++k) {
-        const double a = -M_PI * k / (2.0 * nmax);
-        q[k] = make_float2(static_cast<float>(cos(a)), static_cast<float>(sin(a)));
+        const double b = -M_PI * k / (2.0 * nmax);
+        q[k] = make_float2(static_cast<float>(cos(b)), static_cast<float>(sin(b)));
     }
     size_t o = 0;
     auto place = [&](size_t bytes) {
@@ -266,26 +265,28 @@ hipError_t build_fft_tables(mhfd_plan_s* p) {
         return at;
     };
     const size_t o_taps = place(sizeof(double) * taps.size());
-    const size_t o_norm = place(sizeof(double) * norm.size());
     const size_t o_off = place(sizeof(int) * off.size());
     const size_t o_rad = place(sizeof(int) * rad.size());
     const size_t o_tw = place(sizeof(float2) * tw.size());
     const size_t o_q = place(sizeof(float2) * q.size());
-    std::vector<char> blob(o, 0);
+    const size_t o_lam = place(sizeof(float) * 2 * static_cast<size_t>(nmax) * p->K);
+    std::vector<char> blob(o_lam, 0);
     memcpy(blob.data() + o_taps, taps.data(), sizeof(double) * taps.size());
-    memcpy(blob.data() + o_norm, norm.data(), sizeof(double) * norm.size());
     memcpy(blob.data() + o_off, off.data(), sizeof(int) * off.size());
     memcpy(blob.data() + o_rad, rad.data(), sizeof(int) * rad.size());
     memcpy(blob.data() + o_tw, tw.data(), sizeof(float2) * tw.size());
     memcpy(blob.data() + o_q, q.data(), sizeof(float2) * q.size());
     hipError_t e = hipMalloc(&p->d_fft, o);
-    if (e == hipSuccess) e = hipMemcpy(p->d_fft, blob.data(), o, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_fft, blob.data(), o_lam, hipMemcpyHostToDevice);
     if (e != hipSuccess) return e;
-    const char* b = static_cast<const char*>(p->d_fft);
-    p->fft.taps = reinterpret_cast<const double*>(b + o_taps);
-    p->fft.norm = reinterpret_cast<const double*>(b + o_norm);
-    p->fft.tap_off = reinterpret_cast<const int*>(b + o_off);
-    p->fft.radii = reinterpret_cast<const int*>(b + o_rad);
+    char* b = static_cast<char*>(p->d_fft);
+    float* lam = reinterpret_cast<float*>(b + o_lam);
+    e = mhfd::build_fft_spectra(reinterpret_cast<const double*>(b + o_taps),
+                                reinterpret_cast<const int*>(b + o_off),
+                                reinterpret_cast<const int*>(b + o_rad), p->K, nmax, lam, nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) return e;
+    p->fft.lam = lam;
     p->fft.tw = reinterpret_cast<const float2*>(b + o_tw);
     p->fft.q = reinterpret_cast<const float2*>(b + o_q);
     p->fft.K = p->K;

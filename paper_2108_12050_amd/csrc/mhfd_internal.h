@@ -169,18 +169,20 @@ hipError_t launch_absmax(const float* img, int h, int w, int64_t pitch, uint32_t
 // Frequency-domain scale-space operator (plan mode MHFD_BLUR_FFT), fft_blur.hip.
 constexpr int FFT_MAX_N = MHFD_MAX_FFT_SIZE;  // longest transform (power of two)
 struct FftTables {      // device pointers, owned by the plan
-    const double* taps;     // per scale: g_0..g_R then h_0..h_R (one-sided)
-    const int* tap_off;     // first double of scale k
-    const int* radii;
-    const double* norm;     // s sigma_k^2
-    int K;
-    const float2* tw;       // e^{-2 pi i k / nmax}, k < nmax / 2
+    const float* lam;       // [k][g, h][nmax] spectral weights at nmax
+    const float2* tw;       // e^{-2 pi i k / nmax}, k < nmax
     const float2* q;        // e^{-i pi k / (2 nmax)}, k < nmax
+    int K;
     int nmax;
+    float norm[MHFD_MAX_SCALES];  // s sigma_k^2 (host copy)
 };
 bool fft_size_ok(int n);
 // floats of scratch per call for an h x w tile
-size_t fft_workspace_floats(int K, int h, int w);
+size_t fft_workspace_floats(int h, int w);
+// Spectral weights of every scale (one-sided double taps g_0..g_R, h_0..h_R
+// per scale at taps + tap_off[k]) into lam, once per plan.
+hipError_t build_fft_spectra(const double* taps, const int* tap_off, const int* radii, int K,
+                             int nmax, float* lam, hipStream_t s);
 hipError_t launch_fft_log_stack(const FftTables& T, int in_dtype, const void* img, int h, int w,
                                 int64_t pitch, float* stack, float* ws, hipStream_t s);
 
