@@ -10,7 +10,7 @@
 //              arithmetic as the single-tile path; scales above the
 //              matrix-core radius: persistent strip workgroups per radius
 //              class (log_strip.hip);
-//   nms        persistent waves over every tile's (32-row run, strip) items,
+//   nms        persistent waves over every tile's (16-row run, strip) items,
 //              the per-wave body of the single-tile path (nms_wave.h); the
 //              tile index rides in the upper bits of k;
 //   scan       over all cells, tile-major: the canonical list of every tile

@@ -1,7 +1,7 @@
 // Scale-space operator on the matrix cores (u8 codes or fp32 values).
 //
 // The operator of one scale (the sigma^2-normalised Laplacian of the Gaussian
-// of section 3, computed separably as in the strip kernel) is a pair of banded
+// of section 2.2, computed separably as in the strip kernel) is a pair of banded
 // Toeplitz products, so it maps onto gfx950's 16x16x32 FP16 MFMA:
 //
 //   row pass     A = I * Tg, B = I * Th: M = 16 image rows, N = 16 output
@@ -108,7 +108,17 @@ struct WaveJob {
     uint64_t* act;
     int act_bx;
     float tau;
+    // Softplus-sum epilogue (EPI_SOFTSUM): the wave's sum of
+    // softplus(sp_beta (|R| - sp_tau)) goes to *partial.
+    double* partial;
+    float sp_beta, sp_tau;
 };
+
+// softplus(z) = max(z, 0) + log(1 + e^{-|z|}) on the hardware exp2 / log2
+// (absolute error a few 1e-8 per value, against summands of order 0.1).
+__device__ __forceinline__ float softplus_f(float z) {
+    return fmaxf(z, 0.0f) + __logf(1.0f + __expf(-fabsf(z)));
+}
 
 // 8-bit input with the histogram stretch applied as it is read (stretch.hip):
 // codes clamped to [low, high], minus low.
@@ -276,7 +286,7 @@ __device__ __forceinline__ Input<float>::Raw select_raw<float>(bool c, Input<flo
 // value above J.tau, and every 16 x 16 output block's groups are marked in
 // one activity word (bit 16 g + r: row r, columns 4 g ... 4 g + 3 of the
 // block), which the maxima pass reads instead of the unwritten groups.
-template <typename T, int NKR, int NKC, bool EDGE, bool CTL, bool SPARSE>
+template <typename T, int NKR, int NKC, bool EDGE, bool CTL, bool SPARSE, int EPI = EPI_STORE>
 __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __restrict__ fr,
                                          const half8_t* cl, int lane) {
     typedef Input<T> In;
@@ -379,8 +389,17 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
     };
 
     const bool vec = !EDGE || (J.out_vec && x0 + 16 <= w);
+    float tsum = 0.0f;  // EPI_SOFTSUM: this lane's softplus sum
     auto store = [&](int t, float4_t v) {
         const int y = y0 + 16 * t + c;
+        if constexpr (EPI == EPI_SOFTSUM) {
+            if (!EDGE || y < y1) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (!EDGE || x0 + 4 * g + i < w) tsum += softplus_f(J.sp_beta * (fabsf(v[i]) - J.sp_tau));
+            }
+            return;
+        }
         if constexpr (SPARSE) {
             bool a = false;
 #pragma unroll
@@ -393,6 +412,16 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
         }
         if (EDGE && y >= y1) return;
         float* o = J.plane + static_cast<long long>(y) * w + x0 + 4 * g;
+        if constexpr (EPI == EPI_ACCUM) {  // o += v
+            if (vec) {
+                *reinterpret_cast<float4_t*>(o) = *reinterpret_cast<const float4_t*>(o) + v;
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (x0 + 4 * g + i < w) o[i] += v[i];
+            }
+            return;
+        }
         if (!EDGE) {
             // Streaming store: the stack is read once, by the maxima pass, and
             // measured end to end it is faster when the stores do not stay
@@ -470,15 +499,21 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
             }
         }
     }
+    if constexpr (EPI == EPI_SOFTSUM) {
+        double t = tsum;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) t += __shfl_xor(t, o, 64);
+        if (lane == 0) *J.partial = t;
+    }
 }
 
-template <typename T, int NKR, int NKC, bool CTL = false, bool SPARSE = false>
+template <typename T, int NKR, int NKC, bool CTL = false, bool SPARSE = false, int EPI = EPI_STORE>
 __device__ __forceinline__ void run_job(const WaveJob& J, const half8_t* __restrict__ fr,
                                         int lane, const half8_t* cl = nullptr) {
     if (regular_job<T, NKR, NKC>(J))
-        wave_job<T, NKR, NKC, false, CTL, SPARSE>(J, fr, cl, lane);
+        wave_job<T, NKR, NKC, false, CTL, SPARSE, EPI>(J, fr, cl, lane);
     else
-        wave_job<T, NKR, NKC, true, CTL, SPARSE>(J, fr, cl, lane);
+        wave_job<T, NKR, NKC, true, CTL, SPARSE, EPI>(J, fr, cl, lane);
 }
 
 // Kernels of shapes with nkc >= 3 read their column taps from LDS: the
@@ -493,7 +528,9 @@ constexpr bool mfma_cols_in_lds() { return NKC >= 3; }
 template <typename T, int NKC>
 constexpr int mfma_waves() { return NKC <= (sizeof(typename Elem<T>::type) == 1 ? 3 : 2) ? 2 : 1; }
 
-template <typename T, int NKR, int NKC, bool SPARSE>
+// blockIdx.y: the image of a batch (L.img_stride, L.out_stride apart; fp32
+// input: its own max |I| word maxbits[blockIdx.y]).
+template <typename T, int NKR, int NKC, bool SPARSE, int EPI = EPI_STORE>
 __global__ __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(mfma_waves<T, NKC>(), 2)))
 void log_mfma_kernel(const typename Elem<T>::type* __restrict__ img, int h, int w,
                      long long pitch, int aligned, int out_vec,
@@ -501,6 +538,9 @@ void log_mfma_kernel(const typename Elem<T>::type* __restrict__ img, int h, int 
                      const half8_t* __restrict__ frags, MfmaLaunch L, float* __restrict__ out,
                      long long plane_stride, ActOut act) {
     const int bid = blockIdx.x;
+    const int bimg = blockIdx.y;
+    img += bimg * L.img_stride;
+    out += bimg * L.out_stride;
     int si = 0;
     while (si + 1 < L.n && bid >= L.sc[si + 1].block_begin) ++si;
     const MfmaScale& sc = L.sc[si];
@@ -514,7 +554,14 @@ void log_mfma_kernel(const typename Elem<T>::type* __restrict__ img, int h, int 
         for (int i = threadIdx.x; i < NKC * 4 * 64; i += 64 * MW) cl[i] = src[i];
         __syncthreads();
     }
-    if (wcol >= L.tiles_x) return;
+    double* partial = nullptr;  // EPI_SOFTSUM: one double per wave of the launch and image
+    if constexpr (EPI == EPI_SOFTSUM)
+        partial = L.partial + (static_cast<long long>(bimg) * gridDim.x + bid) * MW + (threadIdx.x >> 6);
+    if (wcol >= L.tiles_x) {
+        if constexpr (EPI == EPI_SOFTSUM)
+            if ((threadIdx.x & 63) == 0) *partial = 0.0;
+        return;
+    }
     // fp32: maxbits = max |I| bits; stretched u8: maxbits = {low, high}
     float in_s = 1.0f, stretch = 1.0f;
     WaveJob J;
@@ -528,7 +575,7 @@ void log_mfma_kernel(const typename Elem<T>::type* __restrict__ img, int h, int 
         J.s_nlo = (0xE400u + static_cast<uint32_t>(lo)) * 0x10001u;  // sign bit set
         stretch = hi > lo ? 255.0f / static_cast<float>(hi - lo) : 0.0f;
     } else if (maxbits) {
-        in_s = input_scale(*maxbits);
+        in_s = input_scale(maxbits[bimg]);
     }
     J.img = img;
     J.pitch = pitch;
@@ -543,11 +590,14 @@ void log_mfma_kernel(const typename Elem<T>::type* __restrict__ img, int h, int 
     J.aligned = aligned;
     J.out_vec = out_vec;
     J.in_scale = in_s;
-    J.out_scale = sc.out_scale / in_s * stretch;
+    J.out_scale = (L.dev_scale ? L.dev_scale[sc.dev_scale_idx] : sc.out_scale) / in_s * stretch;
     J.act = act.mask + static_cast<long long>(sc.plane) * act.by * act.bx;
     J.act_bx = act.bx;
     J.tau = act.tau;
-    run_job<T, NKR, NKC, CTL, SPARSE>(J, frags + sc.frag_off, threadIdx.x & 63, cl);
+    J.partial = partial;
+    J.sp_beta = L.beta;
+    J.sp_tau = L.tau;
+    run_job<T, NKR, NKC, CTL, SPARSE, EPI>(J, frags + sc.frag_off, threadIdx.x & 63, cl);
 }
 
 // Persistent form over a batch of tiles: every workgroup pulls items (scale j
@@ -906,6 +956,55 @@ hipError_t launch_log_mfma(int in_dtype, int stretch, int nkr, int nkc, const vo
     }
 #undef MHFD_MFMA_CASE
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_log_mfma_soft(int epi, int nkr, int nkc, const float* img, int h, int w,
+                                int batch, const uint32_t* maxbits, const uint16_t* frags,
+                                const MfmaLaunch& L, float* out, hipStream_t s) {
+    int blocks = 0;
+    for (int i = 0; i < L.n; ++i) blocks += L.sc[i].n_blocks;
+    if (blocks == 0 || batch == 0) return hipSuccess;
+    const int aligned = (w % 8 == 0) && (reinterpret_cast<uintptr_t>(img) % 32 == 0) &&
+                        (L.img_stride % 8 == 0);
+    const int out_vec = (w % 4 == 0) && (L.out_stride % 4 == 0) &&
+                        (reinterpret_cast<uintptr_t>(out) % 16 == 0);
+    const half8_t* f = reinterpret_cast<const half8_t*>(frags);
+    const dim3 grid(blocks, batch);
+#define MHFD_SOFT_CASE(A, E)                                                                  \
+    if (nkr == A && nkc == A && epi == E) {                                                   \
+        log_mfma_kernel<float, A, A, false, E><<<grid, 64 * MW, 0, s>>>(                      \
+            img, h, w, static_cast<long long>(w), aligned, out_vec, maxbits, f, L, out, 0,    \
+            ActOut{nullptr, 0, 0, 0.0f});                                                     \
+        return hipGetLastError();                                                             \
+    }
+#define MHFD_SOFT_SHAPE(A)         \
+    MHFD_SOFT_CASE(A, EPI_STORE)   \
+    MHFD_SOFT_CASE(A, EPI_ACCUM)   \
+    MHFD_SOFT_CASE(A, EPI_SOFTSUM)
+    MHFD_SOFT_SHAPE(1)
+    MHFD_SOFT_SHAPE(2)
+    MHFD_SOFT_SHAPE(3)
+    MHFD_SOFT_SHAPE(4)
+#undef MHFD_SOFT_SHAPE
+#undef MHFD_SOFT_CASE
+    return hipErrorInvalidValue;
+}
+
+// max |I| of each image of a batch of b dense h x w fp32 images (bits[i]).
+__global__ __launch_bounds__(256) void absmax_images_kernel(const float* __restrict__ imgs, int h,
+                                                            int w, uint32_t* __restrict__ bits) {
+    const int b = blockIdx.y;
+    const float m = block_max256(rows_absmax(imgs + static_cast<long long>(b) * h * w, h, w,
+                                             static_cast<long long>(w), blockIdx.x, gridDim.x));
+    if (threadIdx.x == 0 && m > 0.0f) atomicMax(bits + b, __float_as_uint(m));
+}
+
+hipError_t launch_absmax_images(const float* imgs, int batch, int h, int w, uint32_t* bits,
+                                hipStream_t s) {
+    zero_words_kernel<<<(batch + 255) / 256, 256, 0, s>>>(bits, batch);
+    const int blocks = (h + 3) / 4 < 128 ? (h + 3) / 4 : 128;
+    absmax_images_kernel<<<dim3(blocks, batch), 256, 0, s>>>(imgs, h, w, bits);
+    return hipGetLastError();
 }
 
 hipError_t launch_absmax(const float* img, int h, int w, int64_t pitch, uint32_t* bits,

@@ -841,10 +841,77 @@ mhfd_status enqueue_tail(const mhfd_plan_s* p, const float* stack, int h, int w,
 }
 
 struct FocusLayout {
-    size_t taps, partial, rplane, dplane, cot, total;
+    size_t taps, partial, rplane, dplane, cot, frags, scales, maxbits, total;
     mhfd::SoftTapLayout lay;
-    int fwd_blocks;  // workgroups per image over every class launch
+    int fwd_blocks;  // workgroups per image over every class launch (strip form)
+    bool mfma;       // matrix-core form
+    mhfd::SoftFragLayout fl;
 };
+
+// The soft score runs on the matrix cores when every scale's launch radius
+// is within their limit (else on the strip kernel).
+bool soft_mfma_ok(const mhfd_plan_s* p) {
+    for (int k = 0; k < p->K; ++k) {
+        const int P = p->focus_padded[k];
+        if (!mhfd::mfma_radius_ok(P)) return false;
+        const mhfd::MfmaShape m = mhfd::mfma_shape(P);
+        if (m.nkr != m.nkc || m.nkr < 1 || m.nkr > mhfd::MFMA_SHAPES) return false;
+    }
+    return true;
+}
+
+// Matrix-core launches of tap set `set` over scales ks for a batch of b
+// images, one per shape: (nkr, launch).
+std::vector<std::pair<int, mhfd::MfmaLaunch>> soft_mfma_launches(const mhfd_plan_s* p,
+                                                                 const mhfd::SoftFragLayout& fl,
+                                                                 int b, int h, int w,
+                                                                 const std::vector<int>& ks,
+                                                                 int set) {
+    std::vector<std::pair<int, mhfd::MfmaLaunch>> out;
+    const int tiles_x = mhfd::mfma_wave_tiles(w);
+    const int mw = mhfd::mfma_waves_per_block();
+    const int groups_x = (tiles_x + mw - 1) / mw;
+    const long long target = 8LL * (p->n_cu > 0 ? p->n_cu : 256);
+    const int hr = (h + 15) / 16 * 16;
+    for (int a = 1; a <= mhfd::MFMA_SHAPES; ++a) {
+        std::vector<int> sel;
+        for (int k : ks)
+            if (fl.nkr[k] == a) sel.push_back(k);
+        if (sel.empty()) continue;
+        int seg = 1024 < hr ? 1024 : hr;
+        auto waves = [&]() {
+            return static_cast<long long>(sel.size()) * b * tiles_x * ((h + seg - 1) / seg);
+        };
+        while (waves() < target && seg > 16) seg = (seg / 2 + 15) / 16 * 16;
+        mhfd::MfmaLaunch L{};
+        L.tiles_x = tiles_x;
+        L.groups_x = groups_x;
+        L.img_stride = static_cast<long long>(h) * w;
+        L.out_stride = static_cast<long long>(h) * w;
+        int begin = 0;
+        for (int k : sel) {
+            mhfd::MfmaScale& sc = L.sc[L.n++];
+            sc.rw8 = fl.rw8[k];
+            sc.rwc = fl.rwc[k];
+            sc.frag_off = static_cast<int>((fl.off[k] + static_cast<long long>(set) * fl.halves[k]) / 8);
+            sc.plane = 0;
+            sc.seg_rows = seg;
+            sc.block_begin = begin;
+            sc.n_blocks = groups_x * ((h + seg - 1) / seg);
+            sc.out_scale = 0.0f;
+            sc.dev_scale_idx = 4 * k + set;
+            begin += sc.n_blocks;
+        }
+        out.emplace_back(a, L);
+    }
+    return out;
+}
+
+int mfma_launch_blocks(const mhfd::MfmaLaunch& L) {
+    int n = 0;
+    for (int i = 0; i < L.n; ++i) n += L.sc[i].n_blocks;
+    return n;
+}
 
 FocusLayout focus_layout(const mhfd_plan_s* p, int b, int h, int w) {
     FocusLayout F{};
@@ -862,6 +929,27 @@ FocusLayout focus_layout(const mhfd_plan_s* p, int b, int h, int w) {
         [&](int k) { return p->focus_padded[k]; });
     F.fwd_blocks = 0;
     for (auto& cl : launches) F.fwd_blocks += launch_blocks(cl.second);
+    size_t partials = static_cast<size_t>(F.fwd_blocks) * b;
+    long long frag_halves = 0;
+    F.mfma = soft_mfma_ok(p);
+    if (F.mfma) {
+        F.fl.K = p->K;
+        for (int k = 0; k < p->K; ++k) {
+            const mhfd::MfmaShape m = mhfd::mfma_shape(p->focus_padded[k]);
+            F.fl.nkr[k] = m.nkr;
+            F.fl.nkc[k] = m.nkc;
+            F.fl.rw8[k] = m.rw8;
+            F.fl.rwc[k] = m.rwc;
+            F.fl.halves[k] = static_cast<int>(mhfd::mfma_frag_halves(p->focus_padded[k]));
+            F.fl.off[k] = frag_halves;
+            frag_halves += static_cast<long long>(mhfd::SOFT_SETS) * F.fl.halves[k];
+        }
+        size_t waves = 0;
+        for (auto& ml : soft_mfma_launches(p, F.fl, b, h, w, all_scales(p), mhfd::SOFT_FWD))
+            waves += static_cast<size_t>(mfma_launch_blocks(ml.second)) *
+                     mhfd::mfma_waves_per_block() * b;
+        if (waves > partials) partials = waves;
+    }
     size_t o = 0;
     auto take = [&](size_t bytes) {
         const size_t r = o;
@@ -869,10 +957,13 @@ FocusLayout focus_layout(const mhfd_plan_s* p, int b, int h, int w) {
         return r;
     };
     F.taps = take(sizeof(float) * off);
-    F.partial = take(sizeof(double) * static_cast<size_t>(F.fwd_blocks) * b);
+    F.partial = take(sizeof(double) * partials);
     F.rplane = take(sizeof(float) * static_cast<size_t>(b) * h * w);
     F.dplane = take(sizeof(float) * static_cast<size_t>(b) * h * w);
-    F.cot = take(sizeof(double) * static_cast<size_t>(p->K) * mhfd::soft_cotangent_blocks());
+    F.cot = take(sizeof(double) * static_cast<size_t>(p->K) * mhfd::soft_cotangent_blocks(b));
+    F.frags = take(sizeof(uint16_t) * static_cast<size_t>(frag_halves));
+    F.scales = take(sizeof(float) * 4 * p->K);
+    F.maxbits = take(sizeof(uint32_t) * 2 * static_cast<size_t>(b));
     F.total = o;
     return F;
 }
@@ -1234,12 +1325,39 @@ mhfd_status mhfd_focus_score(mhfd_plan p, const float* d_imgs, int32_t b, int32_
     hipError_t e = mhfd::launch_soft_taps(d_sigmas, F.lay, taps, d_error, s);
     if (e != hipSuccess) return hip_fail(e, "soft tap synthesis");
     const std::vector<int>& P = p->focus_padded;
+    mhfd::SoftPartials sp{};
+    long long done = 0;
+    if (F.mfma) {
+        uint16_t* frags = reinterpret_cast<uint16_t*>(base + F.frags);
+        float* scales = reinterpret_cast<float*>(base + F.scales);
+        uint32_t* maxbits = reinterpret_cast<uint32_t*>(base + F.maxbits);
+        if ((e = mhfd::launch_soft_frags(taps, F.lay, F.fl, frags, scales, s)) != hipSuccess ||
+            (e = mhfd::launch_absmax_images(d_imgs, b, h, w, maxbits, s)) != hipSuccess)
+            return hip_fail(e, "soft score set-up");
+        for (auto& ml : soft_mfma_launches(p, F.fl, b, h, w, all_scales(p), mhfd::SOFT_FWD)) {
+            mhfd::MfmaLaunch L = ml.second;
+            L.dev_scale = scales;
+            L.partial = partial + done;
+            L.beta = beta;
+            L.tau = tau;
+            e = mhfd::launch_log_mfma_soft(mhfd::EPI_SOFTSUM, ml.first, ml.first, d_imgs, h, w, b,
+                                           maxbits, frags, L, nullptr, s);
+            if (e != hipSuccess) return hip_fail(e, "soft score launch");
+            const int per_image = mfma_launch_blocks(L) * mhfd::mfma_waves_per_block();
+            sp.base[sp.n] = done;
+            sp.blocks[sp.n] = per_image;
+            ++sp.n;
+            done += static_cast<long long>(per_image) * b;
+        }
+        e = mhfd::launch_soft_finish(partial, sp, b, 1.0 / (static_cast<double>(p->K) * h * w),
+                                     d_scores, s);
+        if (e != hipSuccess) return hip_fail(e, "soft score finish");
+        return MHFD_OK;
+    }
     auto launches = make_launches(
         p, h, w, all_scales(p),
         [&](int k) { return F.lay.offset[k] + mhfd::SOFT_FWD * 4 * (P[k] + 1); },
         [](int k) { return k; }, [&](int k) { return P[k]; });
-    mhfd::SoftPartials sp{};
-    long long done = 0;
     for (auto& cl : launches) {
         mhfd::StackIO io{};
         io.img_batch = static_cast<long long>(h) * w;
@@ -1284,10 +1402,29 @@ mhfd_status mhfd_focus_score_backward(mhfd_plan p, const float* d_imgs, int32_t 
     if (e != hipSuccess) return hip_fail(e, "soft tap synthesis");
     const long long npix = static_cast<long long>(h) * w;
     const double inv_khw = 1.0 / (static_cast<double>(p->K) * h * w);
-    const int ncb = mhfd::soft_cotangent_blocks();
+    const int ncb = mhfd::soft_cotangent_blocks(b);
+    uint16_t* frags = reinterpret_cast<uint16_t*>(base + F.frags);
+    float* scales = reinterpret_cast<float*>(base + F.scales);
+    uint32_t* maxbits = reinterpret_cast<uint32_t*>(base + F.maxbits);
+    if (F.mfma) {
+        if ((e = mhfd::launch_soft_frags(taps, F.lay, F.fl, frags, scales, s)) != hipSuccess ||
+            (e = mhfd::launch_absmax_images(d_imgs, b, h, w, maxbits, s)) != hipSuccess)
+            return hip_fail(e, "soft score backward set-up");
+    }
     for (int k = 0; k < p->K; ++k) {
         const std::vector<int> one{k};
         auto run = [&](int set, int epi, const float* src, float* dst) -> hipError_t {
+            if (F.mfma) {  // src: the images, or the cotangent planes (range words b .. 2b-1)
+                const uint32_t* range = src == d_imgs ? maxbits : maxbits + b;
+                for (auto& ml : soft_mfma_launches(p, F.fl, b, h, w, one, set)) {
+                    mhfd::MfmaLaunch L = ml.second;
+                    L.dev_scale = scales;
+                    hipError_t err = mhfd::launch_log_mfma_soft(epi, ml.first, ml.first, src, h, w,
+                                                                b, range, frags, L, dst, s);
+                    if (err != hipSuccess) return err;
+                }
+                return hipSuccess;
+            }
             auto launches = make_launches(
                 p, h, w, one, [&](int kk) { return F.lay.offset[kk] + set * 4 * (P[kk] + 1); },
                 [](int) { return 0; }, [&](int kk) { return P[kk]; });
@@ -1309,7 +1446,8 @@ mhfd_status mhfd_focus_score_backward(mhfd_plan p, const float* d_imgs, int32_t 
             (e = run(mhfd::SOFT_D2, mhfd::EPI_ACCUM, d_imgs, dpl)) != hipSuccess)
             return hip_fail(e, "soft score backward recompute");
         e = mhfd::launch_soft_cotangent(rpl, dpl, npix, b, d_sigmas, k, d_grad_scores, inv_khw,
-                                        beta, tau, cot + static_cast<long long>(k) * ncb, s);
+                                        beta, tau, cot + static_cast<long long>(k) * ncb,
+                                        F.mfma ? maxbits + b : nullptr, s);
         if (e != hipSuccess) return hip_fail(e, "soft score cotangent");
         // dI (+)= Lap^T c = Lap c
         if ((e = run(mhfd::SOFT_ADJ, k == 0 ? mhfd::EPI_STORE : mhfd::EPI_ACCUM, rpl,

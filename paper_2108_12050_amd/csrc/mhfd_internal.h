@@ -121,6 +121,7 @@ struct MfmaScale {
     int n_blocks;     // groups_x * segments
     int seg_rows;     // rows per wave segment (multiple of 16)
     float out_scale;  // exact power of two
+    int dev_scale_idx;  // MfmaLaunch::dev_scale: index of the scale's output factor
 };
 
 // Scales sharing one (nkr, nkc) instantiation.
@@ -130,6 +131,15 @@ struct MfmaLaunch {
     int groups_x;     // workgroups across a row: ceil(tiles_x / waves per block)
     int pad;
     MfmaScale sc[MHFD_MAX_SCALES];
+    // Batched fp32 launches (launch_log_mfma_soft; zero elsewhere): images
+    // img_stride elements apart, outputs out_stride apart; non-null
+    // dev_scale: output factors on the device (fragments built there);
+    // EPI_SOFTSUM: one double per wave and image at partial, softplus of
+    // beta (|R| - tau).
+    long long img_stride, out_stride;
+    const float* dev_scale;
+    double* partial;
+    float beta, tau;
 };
 
 // Threshold-sparse stack output (mask null: the dense stack): only the
@@ -164,6 +174,15 @@ hipError_t launch_stretch_levels(const uint8_t* img, int h, int w, long long pit
 // *bits = float bits of max |I| over an fp32 image (zeroed first).
 hipError_t launch_absmax(const float* img, int h, int w, int64_t pitch, uint32_t* bits,
                          hipStream_t s);
+// max |I| word of each of `batch` dense h x w fp32 images
+hipError_t launch_absmax_images(const float* imgs, int batch, int h, int w, uint32_t* bits,
+                                hipStream_t s);
+// The matrix-core operator over a batch of dense fp32 images (gridDim.y =
+// batch) with epilogue epi (EPI_STORE / EPI_ACCUM into out, plane stride 0,
+// or EPI_SOFTSUM into L.partial); maxbits[b]: max |I| word of image b.
+hipError_t launch_log_mfma_soft(int epi, int nkr, int nkc, const float* img, int h, int w,
+                                int batch, const uint32_t* maxbits, const uint16_t* frags,
+                                const MfmaLaunch& L, float* out, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Frequency-domain scale-space operator (plan mode MHFD_BLUR_FFT), fft_blur.hip.
@@ -360,15 +379,31 @@ hipError_t launch_soft_taps(const float* sigmas, const SoftTapLayout& lay, float
 // (blocks[c] per image) starting at partial + base[c].
 struct SoftPartials {
     int n;
-    long long base[3];
-    int blocks[3];
+    long long base[4];
+    int blocks[4];
 };
+// Matrix-core form of the soft score: fragment tables of every (scale, tap
+// set) built on the device from the synthesised taps, at the shape of the
+// scale's launch radius; set s of scale k at frag + off[k] + s * halves[k]
+// (FP16 halves), output factor at scales[4 k + s].
+struct SoftFragLayout {
+    int K;
+    int nkr[MHFD_MAX_SCALES], nkc[MHFD_MAX_SCALES], rw8[MHFD_MAX_SCALES], rwc[MHFD_MAX_SCALES];
+    long long off[MHFD_MAX_SCALES];
+    int halves[MHFD_MAX_SCALES];
+};
+hipError_t launch_soft_frags(const float* taps, const SoftTapLayout& lay, const SoftFragLayout& fl,
+                             uint16_t* frags, float* scales, hipStream_t s);
 hipError_t launch_soft_finish(const double* partial, const SoftPartials& sp, int batch,
                               double inv_khw, float* scores, hipStream_t s);
-int soft_cotangent_blocks();
+// Sigma-gradient partials per scale of the cotangent pass ([image][workgroup]).
+int soft_cotangent_blocks(int batch);
+// r <- c = w sigma^2 (per pixel of each image), partial[] <- the sigma
+// partials; cmax (optional, `batch` words): max |c| of each image.
 hipError_t launch_soft_cotangent(float* r, const float* d, long long n_per_image, int batch,
                                  const float* sigmas, int k, const float* gbar, double inv_khw,
-                                 float beta, float tau, double* partial, hipStream_t s);
+                                 float beta, float tau, double* partial, uint32_t* cmax,
+                                 hipStream_t s);
 hipError_t launch_sigma_grad_finish(const double* partial, int nb, int K, float* dsig,
                                     hipStream_t s);
 

@@ -94,6 +94,87 @@ __global__ void soft_taps_kernel(const float* __restrict__ sigmas, SoftTapLayout
     }
 }
 
+// Largest integer S with m 2^S <= limit (m > 0).
+__device__ int pow2_fit_dev(double m, double limit) {
+    int S = static_cast<int>(floor(log2(limit / m)));
+    while (ldexp(m, S + 1) <= limit) ++S;
+    while (ldexp(m, S) > limit) --S;
+    return S;
+}
+
+__device__ __forceinline__ uint16_t half_of(float v) {
+    return __builtin_bit_cast(uint16_t, static_cast<_Float16>(v));
+}
+
+// Matrix-core fragments of one (scale, tap set) per workgroup (blockIdx.x =
+// scale, blockIdx.y = set) from the float tap runs grow, hrow, gcol, hcol of
+// the strip layout, whose operator is hcol (*)_y (grow (*)_x I) +
+// gcol (*)_y (hrow (*)_x I): row taps (grow, hrow), column taps (hcol for
+// the grow intermediate, gcol for the hrow one).  The power-of-two factors
+// follow the plan tables: fp32 input below 2^14, row intermediates at or
+// below 2^15, the largest column tap at or below 2^14; each tap as an FP16
+// pair hi + lo.  Fragment layout as the kernel reads it: row K-block kb,
+// part t (0/1: grow hi/lo, 2/3: hrow hi/lo), lane (column n = lane & 15,
+// group lane >> 4), 8 halves; then the column K-blocks likewise.
+__global__ __launch_bounds__(256) void soft_frags_kernel(const float* __restrict__ taps,
+                                                         SoftTapLayout lay, SoftFragLayout fl,
+                                                         uint16_t* __restrict__ frags,
+                                                         float* __restrict__ scales) {
+    const int k = blockIdx.x, set = blockIdx.y;
+    const int P = lay.padded[k];
+    const float* base = taps + lay.offset[k] + set * 4 * (P + 1);
+    const float* grow = base;
+    const float* hrow = base + (P + 1);
+    const float* gcol = base + 2 * (P + 1);
+    const float* hcol = base + 3 * (P + 1);
+    __shared__ int sS[3];
+    if (threadIdx.x == 0) {
+        constexpr double in_max = 16384.0;
+        double sg = 0.0, sh = 0.0;
+        for (int j = 0; j <= P; ++j) {
+            sg += (j ? 2.0 : 1.0) * fabs(static_cast<double>(grow[j]));
+            sh += (j ? 2.0 : 1.0) * fabs(static_cast<double>(hrow[j]));
+        }
+        const int Sg = sg > 0.0 ? pow2_fit_dev(in_max * sg, 32768.0) : 0;
+        const int Sh = sh > 0.0 ? pow2_fit_dev(in_max * sh, 32768.0) : 0;
+        double cmax = 0.0;
+        for (int j = 0; j <= P; ++j)
+            cmax = fmax(cmax, fmax(fabs(ldexp(static_cast<double>(hcol[j]), -Sg)),
+                                   fabs(ldexp(static_cast<double>(gcol[j]), -Sh))));
+        const int Sc = cmax > 0.0 ? pow2_fit_dev(cmax, 16384.0) : 0;
+        sS[0] = Sg;
+        sS[1] = Sh;
+        sS[2] = Sc;
+        scales[4 * k + set] = ldexpf(1.0f, -Sc);
+    }
+    __syncthreads();
+    const int Sg = sS[0], Sh = sS[1], Sc = sS[2];
+    const int nkr = fl.nkr[k], nkc = fl.nkc[k], rw8 = fl.rw8[k], rwc = fl.rwc[k];
+    uint16_t* dst = frags + fl.off[k] + static_cast<long long>(set) * fl.halves[k];
+    const int nrow = nkr * 4 * 64 * 8, ntot = (nkr + nkc) * 4 * 64 * 8;
+    for (int e = threadIdx.x; e < ntot; e += blockDim.x) {
+        const bool col = e >= nrow;
+        const int f = col ? e - nrow : e;
+        const int i = f & 7, lane = (f >> 3) & 63, t = (f >> 9) & 3, kb = f >> 11;
+        const int n = lane & 15, gq = lane >> 4;
+        int j;
+        if (!col)
+            j = 32 * kb + 8 * gq + i - rw8 - n;
+        else
+            j = 32 * kb + (i < 4 ? 4 * gq + i : 16 + 4 * gq + (i - 4)) - rwc - n;
+        const int a = j < 0 ? -j : j;
+        float v = 0.0f;
+        if (a <= P) {
+            if (!col)
+                v = t < 2 ? ldexpf(grow[a], Sg) : ldexpf(hrow[a], Sh);
+            else
+                v = t < 2 ? ldexpf(ldexpf(hcol[a], -Sg), Sc) : ldexpf(ldexpf(gcol[a], -Sh), Sc);
+        }
+        const uint16_t hi = half_of(v);
+        dst[e] = (t & 1) ? half_of(v - static_cast<float>(__builtin_bit_cast(_Float16, hi))) : hi;
+    }
+}
+
 // S_b = sum of the softplus partials of image b / (K H W), in a fixed order.
 // Partials are laid out per class launch c as [image][block] from base[c].
 __global__ void soft_finish_kernel(const double* __restrict__ partial, SoftPartials sp, int batch,
@@ -120,37 +201,58 @@ __global__ void soft_finish_kernel(const double* __restrict__ partial, SoftParti
 // cotangent c = w sigma^2.  One double partial per workgroup.
 constexpr int COT_T = 256;
 
+// Workgroup row blockIdx.y is image b; the gridDim.x workgroups of the row
+// stride over its pixels.  Partials laid out [image][workgroup]; with
+// `cmax`, max |c| of image b as float bits (zero on entry) for the input
+// scale of the adjoint on the matrix cores.
 __global__ __launch_bounds__(COT_T) void soft_cotangent_kernel(
-    float* __restrict__ r, const float* __restrict__ d, long long n_per_image, int batch,
+    float* __restrict__ r, const float* __restrict__ d, long long n_per_image,
     const float* __restrict__ sigmas, int k, const float* __restrict__ gbar, double inv_khw,
-    float beta, float tau, double* __restrict__ partial) {
+    float beta, float tau, double* __restrict__ partial, uint32_t* __restrict__ cmax) {
     __shared__ double sh[COT_T / 64];
+    __shared__ float shm[COT_T / 64];
+    const int b = blockIdx.y;
     const double sg = static_cast<double>(sigmas[k]);
     const float sgf = sigmas[k];
     const float s2 = sgf * sgf;
-    const long long n = n_per_image * batch;
+    const float wb = static_cast<float>(gbar[b] * inv_khw) * beta;
+    float* rb = r + static_cast<long long>(b) * n_per_image;
+    const float* db = d + static_cast<long long>(b) * n_per_image;
     double acc = 0.0;
-    for (long long i = blockIdx.x * static_cast<long long>(COT_T) + threadIdx.x; i < n;
+    float m = 0.0f;
+    for (long long i = blockIdx.x * static_cast<long long>(COT_T) + threadIdx.x; i < n_per_image;
          i += static_cast<long long>(gridDim.x) * COT_T) {
-        const int b = static_cast<int>(i / n_per_image);
-        const float rv = r[i];
+        const float rv = rb[i];
         const float z = beta * (fabsf(rv) - tau);
-        const float sig = 1.0f / (1.0f + expf(-z));
+        const float sig = 1.0f / (1.0f + __expf(-z));
         const float sgn = rv > 0.0f ? 1.0f : (rv < 0.0f ? -1.0f : 0.0f);
-        const float w = static_cast<float>(gbar[b] * inv_khw) * beta * sig * sgn;
+        const float w = wb * sig * sgn;
         acc += static_cast<double>(w) * (2.0 * static_cast<double>(rv) / sg +
-                                         static_cast<double>(s2) * static_cast<double>(d[i]));
-        r[i] = w * s2;
+                                         static_cast<double>(s2) * static_cast<double>(db[i]));
+        const float c = w * s2;
+        rb[i] = c;
+        m = fmaxf(m, fabsf(c));
     }
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) acc += __shfl_down(acc, o, 64);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    for (int o = 32; o >= 1; o >>= 1) {
+        acc += __shfl_down(acc, o, 64);
+        m = fmaxf(m, __shfl_down(m, o, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        sh[threadIdx.x >> 6] = acc;
+        shm[threadIdx.x >> 6] = m;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         double t = 0.0;
+        float mm = 0.0f;
 #pragma unroll
-        for (int w = 0; w < COT_T / 64; ++w) t += sh[w];
-        partial[blockIdx.x] = t;
+        for (int w = 0; w < COT_T / 64; ++w) {
+            t += sh[w];
+            mm = fmaxf(mm, shm[w]);
+        }
+        partial[static_cast<long long>(b) * gridDim.x + blockIdx.x] = t;
+        if (cmax && mm > 0.0f) atomicMax(cmax + b, __float_as_uint(mm));
     }
 }
 
@@ -172,12 +274,25 @@ __global__ void sigma_grad_finish_kernel(const double* __restrict__ partial, int
 
 }  // namespace
 
-int soft_cotangent_blocks() { return 2048; }
+__global__ void zero_u32_kernel(uint32_t* __restrict__ p, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+// Workgroups per image of the cotangent pass (about 2048 in all).
+int cotangent_blocks_per_image(int batch) { return batch >= 2048 ? 1 : 2048 / batch; }
+
+int soft_cotangent_blocks(int batch) { return cotangent_blocks_per_image(batch) * batch; }
 
 hipError_t launch_soft_taps(const float* sigmas, const SoftTapLayout& lay, float* taps,
                             int32_t* err, hipStream_t s) {
     static_assert(MHFD_MAX_SCALES <= 64, "one thread per scale");
     soft_taps_kernel<<<1, 64, 0, s>>>(sigmas, lay, taps, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_soft_frags(const float* taps, const SoftTapLayout& lay, const SoftFragLayout& fl,
+                             uint16_t* frags, float* scales, hipStream_t s) {
+    soft_frags_kernel<<<dim3(fl.K, SOFT_SETS), 256, 0, s>>>(taps, lay, fl, frags, scales);
     return hipGetLastError();
 }
 
@@ -189,9 +304,11 @@ hipError_t launch_soft_finish(const double* partial, const SoftPartials& sp, int
 
 hipError_t launch_soft_cotangent(float* r, const float* d, long long n_per_image, int batch,
                                  const float* sigmas, int k, const float* gbar, double inv_khw,
-                                 float beta, float tau, double* partial, hipStream_t s) {
-    soft_cotangent_kernel<<<soft_cotangent_blocks(), COT_T, 0, s>>>(
-        r, d, n_per_image, batch, sigmas, k, gbar, inv_khw, beta, tau, partial);
+                                 float beta, float tau, double* partial, uint32_t* cmax,
+                                 hipStream_t s) {
+    if (cmax) zero_u32_kernel<<<(batch + 255) / 256, 256, 0, s>>>(cmax, batch);
+    soft_cotangent_kernel<<<dim3(cotangent_blocks_per_image(batch), batch), COT_T, 0, s>>>(
+        r, d, n_per_image, sigmas, k, gbar, inv_khw, beta, tau, partial, cmax);
     return hipGetLastError();
 }
 

@@ -52,7 +52,11 @@ def test_constant_batch_closed_form():
     plan = make_plan([1.0, 2.0, 4.0], 64, 64)
     imgs = to_dev(np.full((2, 64, 50), 0.3))
     s = plan.focus_score(imgs, to_dev(np.float32([1.0, 2.0, 4.0])), BETA, TAU).cpu().numpy()
-    np.testing.assert_allclose(s, np.log1p(np.exp(-BETA * TAU)), rtol=1e-6)
+    # r = 0 exactly in real arithmetic; computed, it is the rounding of the
+    # taps (FP16 pairs on the matrix cores: |r| <= 1e-7 of the image value),
+    # which the softplus slope beta sigmoid(-beta tau) ~ 3.8 turns into
+    # ~1e-6 of the score
+    np.testing.assert_allclose(s, np.log1p(np.exp(-BETA * TAU)), rtol=4e-6)
     dI, ds = plan.focus_score_backward(imgs, to_dev(np.float32([1.0, 2.0, 4.0])),
                                        torch.ones(2, device="cuda"), BETA, TAU)
     # In exact arithmetic r = 0, so sgn(r) = 0 and both gradients vanish.  In
