@@ -112,6 +112,10 @@ struct WaveJob {
     // softplus(sp_beta (|R| - sp_tau)) goes to *partial.
     double* partial;
     float sp_beta, sp_tau;
+    // Cotangent epilogue (EPI_COTAN): r plane, sigma, w factor of the image.
+    float* aux;
+    float sigma, wb;
+    uint32_t* cmax_word;
 };
 
 // softplus(z) = max(z, 0) + log(1 + e^{-|z|}) on the hardware exp2 / log2
@@ -390,8 +394,42 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
 
     const bool vec = !EDGE || (J.out_vec && x0 + 16 <= w);
     float tsum = 0.0f;  // EPI_SOFTSUM: this lane's softplus sum
+    double gsum = 0.0;  // EPI_COTAN: this lane's sigma-gradient sum
+    float cmx = 0.0f;   // EPI_COTAN: this lane's max |c|
     auto store = [&](int t, float4_t v) {
         const int y = y0 + 16 * t + c;
+        if constexpr (EPI == EPI_COTAN) {
+            if (EDGE && y >= y1) return;
+            const long long at = static_cast<long long>(y) * w + x0 + 4 * g;
+            const float s2 = J.sigma * J.sigma;
+            const double inv_s = 1.0 / static_cast<double>(J.sigma);
+            auto one = [&](float dv, float& rv) {  // rv: r in, c out
+                const float z = J.sp_beta * (fabsf(rv) - J.sp_tau);
+                const float sig = 1.0f / (1.0f + __expf(-z));
+                const float sgn = rv > 0.0f ? 1.0f : (rv < 0.0f ? -1.0f : 0.0f);
+                const float wv = J.wb * sig * sgn;
+                gsum += static_cast<double>(wv) * (2.0 * static_cast<double>(rv) * inv_s +
+                                                   static_cast<double>(s2) * static_cast<double>(dv));
+                rv = wv * s2;
+                cmx = fmaxf(cmx, fabsf(rv));
+            };
+            if (vec) {
+                const float4_t d1 = *reinterpret_cast<const float4_t*>(J.plane + at);
+                float4_t r = *reinterpret_cast<const float4_t*>(J.aux + at);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    float rv = r[i];
+                    one(d1[i] + v[i], rv);
+                    r[i] = rv;
+                }
+                *reinterpret_cast<float4_t*>(J.aux + at) = r;
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (x0 + 4 * g + i < w) one(J.plane[at + i] + v[i], J.aux[at + i]);
+            }
+            return;
+        }
         if constexpr (EPI == EPI_SOFTSUM) {
             if (!EDGE || y < y1) {
 #pragma unroll
@@ -505,6 +543,17 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
         for (int o = 32; o >= 1; o >>= 1) t += __shfl_xor(t, o, 64);
         if (lane == 0) *J.partial = t;
     }
+    if constexpr (EPI == EPI_COTAN) {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            gsum += __shfl_xor(gsum, o, 64);
+            cmx = fmaxf(cmx, __shfl_xor(cmx, o, 64));
+        }
+        if (lane == 0) {
+            *J.partial = gsum;
+            if (cmx > 0.0f) atomicMax(J.cmax_word, __float_as_uint(cmx));
+        }
+    }
 }
 
 template <typename T, int NKR, int NKC, bool CTL = false, bool SPARSE = false, int EPI = EPI_STORE>
@@ -554,11 +603,13 @@ void log_mfma_kernel(const typename Elem<T>::type* __restrict__ img, int h, int 
         for (int i = threadIdx.x; i < NKC * 4 * 64; i += 64 * MW) cl[i] = src[i];
         __syncthreads();
     }
-    double* partial = nullptr;  // EPI_SOFTSUM: one double per wave of the launch and image
-    if constexpr (EPI == EPI_SOFTSUM)
+    // EPI_SOFTSUM, EPI_COTAN: one double per wave of the launch and image
+    constexpr bool WAVE_SUM = EPI == EPI_SOFTSUM || EPI == EPI_COTAN;
+    double* partial = nullptr;
+    if constexpr (WAVE_SUM)
         partial = L.partial + (static_cast<long long>(bimg) * gridDim.x + bid) * MW + (threadIdx.x >> 6);
     if (wcol >= L.tiles_x) {
-        if constexpr (EPI == EPI_SOFTSUM)
+        if constexpr (WAVE_SUM)
             if ((threadIdx.x & 63) == 0) *partial = 0.0;
         return;
     }
@@ -597,6 +648,12 @@ void log_mfma_kernel(const typename Elem<T>::type* __restrict__ img, int h, int 
     J.partial = partial;
     J.sp_beta = L.beta;
     J.sp_tau = L.tau;
+    if constexpr (EPI == EPI_COTAN) {
+        J.aux = L.aux + bimg * L.out_stride;
+        J.sigma = L.sigmas[L.soft_k];
+        J.wb = static_cast<float>(static_cast<double>(L.gbar[bimg]) * L.inv_khw) * L.beta;
+        J.cmax_word = L.cmax + bimg;
+    }
     run_job<T, NKR, NKC, CTL, SPARSE, EPI>(J, frags + sc.frag_off, threadIdx.x & 63, cl);
 }
 
@@ -970,6 +1027,7 @@ hipError_t launch_log_mfma_soft(int epi, int nkr, int nkc, const float* img, int
                         (reinterpret_cast<uintptr_t>(out) % 16 == 0);
     const half8_t* f = reinterpret_cast<const half8_t*>(frags);
     const dim3 grid(blocks, batch);
+    if (epi == EPI_COTAN) zero_words_kernel<<<(batch + 255) / 256, 256, 0, s>>>(L.cmax, batch);
 #define MHFD_SOFT_CASE(A, E)                                                                  \
     if (nkr == A && nkc == A && epi == E) {                                                   \
         log_mfma_kernel<float, A, A, false, E><<<grid, 64 * MW, 0, s>>>(                      \
@@ -980,7 +1038,8 @@ hipError_t launch_log_mfma_soft(int epi, int nkr, int nkc, const float* img, int
 #define MHFD_SOFT_SHAPE(A)         \
     MHFD_SOFT_CASE(A, EPI_STORE)   \
     MHFD_SOFT_CASE(A, EPI_ACCUM)   \
-    MHFD_SOFT_CASE(A, EPI_SOFTSUM)
+    MHFD_SOFT_CASE(A, EPI_SOFTSUM) \
+    MHFD_SOFT_CASE(A, EPI_COTAN)
     MHFD_SOFT_SHAPE(1)
     MHFD_SOFT_SHAPE(2)
     MHFD_SOFT_SHAPE(3)

@@ -842,6 +842,7 @@ mhfd_status enqueue_tail(const mhfd_plan_s* p, const float* stack, int h, int w,
 
 struct FocusLayout {
     size_t taps, partial, rplane, dplane, cot, frags, scales, maxbits, total;
+    int cot_stride;  // sigma-gradient partials per scale
     mhfd::SoftTapLayout lay;
     int fwd_blocks;  // workgroups per image over every class launch (strip form)
     bool mfma;       // matrix-core form
@@ -950,6 +951,14 @@ FocusLayout focus_layout(const mhfd_plan_s* p, int b, int h, int w) {
                      mhfd::mfma_waves_per_block() * b;
         if (waves > partials) partials = waves;
     }
+    F.cot_stride = mhfd::soft_cotangent_blocks(b);
+    if (F.mfma) {  // the cotangent epilogue: one partial per wave of each scale's launch
+        F.cot_stride = 0;
+        for (int k = 0; k < p->K; ++k)
+            for (auto& ml : soft_mfma_launches(p, F.fl, b, h, w, {k}, mhfd::SOFT_D2))
+                F.cot_stride = std::max(F.cot_stride, mfma_launch_blocks(ml.second) *
+                                                          mhfd::mfma_waves_per_block() * b);
+    }
     size_t o = 0;
     auto take = [&](size_t bytes) {
         const size_t r = o;
@@ -960,7 +969,7 @@ FocusLayout focus_layout(const mhfd_plan_s* p, int b, int h, int w) {
     F.partial = take(sizeof(double) * partials);
     F.rplane = take(sizeof(float) * static_cast<size_t>(b) * h * w);
     F.dplane = take(sizeof(float) * static_cast<size_t>(b) * h * w);
-    F.cot = take(sizeof(double) * static_cast<size_t>(p->K) * mhfd::soft_cotangent_blocks(b));
+    F.cot = take(sizeof(double) * static_cast<size_t>(p->K) * F.cot_stride);
     F.frags = take(sizeof(uint16_t) * static_cast<size_t>(frag_halves));
     F.scales = take(sizeof(float) * 4 * p->K);
     F.maxbits = take(sizeof(uint32_t) * 2 * static_cast<size_t>(b));
@@ -1402,13 +1411,15 @@ mhfd_status mhfd_focus_score_backward(mhfd_plan p, const float* d_imgs, int32_t 
     if (e != hipSuccess) return hip_fail(e, "soft tap synthesis");
     const long long npix = static_cast<long long>(h) * w;
     const double inv_khw = 1.0 / (static_cast<double>(p->K) * h * w);
-    const int ncb = mhfd::soft_cotangent_blocks(b);
+    const int ncb = F.cot_stride;
     uint16_t* frags = reinterpret_cast<uint16_t*>(base + F.frags);
     float* scales = reinterpret_cast<float*>(base + F.scales);
     uint32_t* maxbits = reinterpret_cast<uint32_t*>(base + F.maxbits);
     if (F.mfma) {
+        // the partial slots a scale's launch does not reach stay zero
         if ((e = mhfd::launch_soft_frags(taps, F.lay, F.fl, frags, scales, s)) != hipSuccess ||
-            (e = mhfd::launch_absmax_images(d_imgs, b, h, w, maxbits, s)) != hipSuccess)
+            (e = mhfd::launch_absmax_images(d_imgs, b, h, w, maxbits, s)) != hipSuccess ||
+            (e = mhfd::launch_zero_f64(cot, static_cast<long long>(p->K) * ncb, s)) != hipSuccess)
             return hip_fail(e, "soft score backward set-up");
     }
     for (int k = 0; k < p->K; ++k) {
@@ -1442,13 +1453,35 @@ mhfd_status mhfd_focus_score_backward(mhfd_plan p, const float* d_imgs, int32_t 
         };
         // r = sigma^2 Lap I, d = D1 I + D2 I (the sigma-derivative of Lap I)
         if ((e = run(mhfd::SOFT_FWD, mhfd::EPI_STORE, d_imgs, rpl)) != hipSuccess ||
-            (e = run(mhfd::SOFT_D1, mhfd::EPI_STORE, d_imgs, dpl)) != hipSuccess ||
-            (e = run(mhfd::SOFT_D2, mhfd::EPI_ACCUM, d_imgs, dpl)) != hipSuccess)
+            (e = run(mhfd::SOFT_D1, mhfd::EPI_STORE, d_imgs, dpl)) != hipSuccess)
             return hip_fail(e, "soft score backward recompute");
-        e = mhfd::launch_soft_cotangent(rpl, dpl, npix, b, d_sigmas, k, d_grad_scores, inv_khw,
-                                        beta, tau, cot + static_cast<long long>(k) * ncb,
-                                        F.mfma ? maxbits + b : nullptr, s);
-        if (e != hipSuccess) return hip_fail(e, "soft score cotangent");
+        if (F.mfma) {
+            // D2 on the matrix cores with the cotangent as its epilogue: r <- c
+            // in place, sigma partials, max |c| per image for the adjoint
+            for (auto& ml : soft_mfma_launches(p, F.fl, b, h, w, one, mhfd::SOFT_D2)) {
+                mhfd::MfmaLaunch L = ml.second;
+                L.dev_scale = scales;
+                L.partial = cot + static_cast<long long>(k) * ncb;
+                L.beta = beta;
+                L.tau = tau;
+                L.aux = rpl;
+                L.sigmas = d_sigmas;
+                L.soft_k = k;
+                L.gbar = d_grad_scores;
+                L.inv_khw = inv_khw;
+                L.cmax = maxbits + b;
+                e = mhfd::launch_log_mfma_soft(mhfd::EPI_COTAN, ml.first, ml.first, d_imgs, h, w,
+                                               b, maxbits, frags, L, dpl, s);
+                if (e != hipSuccess) return hip_fail(e, "soft score cotangent");
+            }
+        } else {
+            if ((e = run(mhfd::SOFT_D2, mhfd::EPI_ACCUM, d_imgs, dpl)) != hipSuccess)
+                return hip_fail(e, "soft score backward recompute");
+            e = mhfd::launch_soft_cotangent(rpl, dpl, npix, b, d_sigmas, k, d_grad_scores,
+                                            inv_khw, beta, tau,
+                                            cot + static_cast<long long>(k) * ncb, nullptr, s);
+            if (e != hipSuccess) return hip_fail(e, "soft score cotangent");
+        }
         // dI (+)= Lap^T c = Lap c
         if ((e = run(mhfd::SOFT_ADJ, k == 0 ? mhfd::EPI_STORE : mhfd::EPI_ACCUM, rpl,
                      d_grad_imgs)) != hipSuccess)

@@ -70,7 +70,7 @@ int log_chunk_rows();
 
 // Where a stack launch writes.  Plane k of image b is at
 // out + b * out_batch + k * plane_stride (row pitch = image width).
-enum { EPI_STORE = 0, EPI_ACCUM = 1, EPI_SOFTSUM = 2 };
+enum { EPI_STORE = 0, EPI_ACCUM = 1, EPI_SOFTSUM = 2, EPI_COTAN = 3 };
 struct StackIO {
     long long img_batch;     // elements between consecutive images of a batch
     float* out;              // EPI_STORE: out = R; EPI_ACCUM: out += R
@@ -140,6 +140,17 @@ struct MfmaLaunch {
     const float* dev_scale;
     double* partial;
     float beta, tau;
+    // EPI_COTAN (the soft score's backward, on the last sigma-derivative
+    // term): with d = out + R and r = aux at each pixel, the cotangent
+    // c = w sigma^2, w = gbar[b] inv_khw beta sigmoid(beta (|r| - tau)) sgn r,
+    // replaces r in aux; the wave's sum of w (2 r / sigma + sigma^2 d) goes
+    // to partial and max |c| of image b to cmax[b] (float bits).
+    float* aux;
+    const float* sigmas;
+    int soft_k;
+    const float* gbar;
+    double inv_khw;
+    uint32_t* cmax;
 };
 
 // Threshold-sparse stack output (mask null: the dense stack): only the
@@ -179,7 +190,8 @@ hipError_t launch_absmax_images(const float* imgs, int batch, int h, int w, uint
                                 hipStream_t s);
 // The matrix-core operator over a batch of dense fp32 images (gridDim.y =
 // batch) with epilogue epi (EPI_STORE / EPI_ACCUM into out, plane stride 0,
-// or EPI_SOFTSUM into L.partial); maxbits[b]: max |I| word of image b.
+// EPI_SOFTSUM into L.partial, EPI_COTAN as MfmaLaunch describes); maxbits[b]:
+// max |I| word of image b.
 hipError_t launch_log_mfma_soft(int epi, int nkr, int nkc, const float* img, int h, int w,
                                 int batch, const uint32_t* maxbits, const uint16_t* frags,
                                 const MfmaLaunch& L, float* out, hipStream_t s);
@@ -404,6 +416,8 @@ hipError_t launch_soft_cotangent(float* r, const float* d, long long n_per_image
                                  const float* sigmas, int k, const float* gbar, double inv_khw,
                                  float beta, float tau, double* partial, uint32_t* cmax,
                                  hipStream_t s);
+// p[0 .. n) = 0 (a fill kernel, safe under graph capture)
+hipError_t launch_zero_f64(double* p, long long n, hipStream_t s);
 hipError_t launch_sigma_grad_finish(const double* partial, int nb, int K, float* dsig,
                                     hipStream_t s);
 

@@ -29,36 +29,61 @@ namespace mhfd {
 
 namespace {
 
-__global__ void soft_taps_kernel(const float* __restrict__ sigmas, SoftTapLayout lay,
-                                 float* __restrict__ taps, int32_t* __restrict__ err) {
-    const int k = threadIdx.x;
-    const double s = k < lay.K ? static_cast<double>(sigmas[k]) : 1.0;
-    const int P = k < lay.K ? lay.padded[k] : 1;
-    // radius from the current sigma; accepted within (0, sigma_cap] and the
-    // launch radius (comparisons are false for NaN)
-    const double rr = floor(static_cast<double>(lay.truncate) * s + 0.5);
-    const bool ok = k >= lay.K || (s > 0.0 && s <= static_cast<double>(lay.sigma_cap) && rr <= P);
-    const int bad = __syncthreads_or(!ok);
-    if (err && threadIdx.x == 0) *err = bad ? MHFD_FOCUS_BAD_SIGMA : 0;
-    if (k >= lay.K) return;
-    const int R = ok ? static_cast<int>(rr) : 0;
+// One workgroup per scale k (64 threads over the taps j = 0 .. P); workgroup
+// 0 also writes the error word from every scale's acceptance.
+__device__ __forceinline__ bool sigma_ok(double s, double truncate, double cap, int P) {
+    // radius from the current sigma; accepted within (0, cap] and the launch
+    // radius (comparisons are false for NaN)
+    const double rr = floor(truncate * s + 0.5);
+    return s > 0.0 && s <= cap && rr <= P;
+}
+
+// sum over the 64 lanes of the wave (the workgroup is one wave)
+__device__ __forceinline__ double sum64(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__global__ __launch_bounds__(64) void soft_taps_kernel(const float* __restrict__ sigmas,
+                                                       SoftTapLayout lay, float* __restrict__ taps,
+                                                       int32_t* __restrict__ err) {
+    const int k = blockIdx.x;
+    const int tid = threadIdx.x;
+    const double trunc = static_cast<double>(lay.truncate);
+    const double cap = static_cast<double>(lay.sigma_cap);
+    if (k == 0 && err) {
+        bool bad = false;
+        for (int q = tid; q < lay.K; q += 64)
+            bad |= !sigma_ok(static_cast<double>(sigmas[q]), trunc, cap, lay.padded[q]);
+        bad = __any(bad);
+        if (tid == 0) *err = bad ? MHFD_FOCUS_BAD_SIGMA : 0;
+    }
+    const double s = static_cast<double>(sigmas[k]);
+    const int P = lay.padded[k];
+    const bool ok = sigma_ok(s, trunc, cap, P);
+    const int R = ok ? static_cast<int>(floor(trunc * s + 0.5)) : 0;
     float* base = taps + lay.offset[k];
     const int run = P + 1;  // floats per tap run
     const int blk = 4 * run;  // floats per tap set
     double z = 0.0, V = 0.0, M4 = 0.0;
-    for (int j = 0; j <= R; ++j) {
+    for (int j = tid; j <= R; j += 64) {
         const double e = exp(-static_cast<double>(j) * j / (2.0 * s * s));
         z += j == 0 ? e : 2.0 * e;
     }
-    for (int j = 1; j <= R; ++j) {
+    z = sum64(z);
+    for (int j = tid; j <= R; j += 64) {
+        if (j == 0) continue;
         const double gj = exp(-static_cast<double>(j) * j / (2.0 * s * s)) / z;
         const double j2 = static_cast<double>(j) * j;
         V += 2.0 * j2 * gj;
         M4 += 2.0 * j2 * j2 * gj;
     }
+    V = sum64(V);
+    M4 = sum64(M4);
     const double s2 = s * s, s3 = s2 * s, s4 = s3 * s, s5 = s4 * s;
     const double Vd = (M4 - V * V) / s3;
-    for (int j = 0; j <= P; ++j) {
+    for (int j = tid; j <= P; j += 64) {
         double g = 0.0, h = 0.0, gd = 0.0, hd = 0.0;
         if (j <= R) {
             const double j2 = static_cast<double>(j) * j;
@@ -120,7 +145,7 @@ __global__ __launch_bounds__(256) void soft_frags_kernel(const float* __restrict
                                                          SoftTapLayout lay, SoftFragLayout fl,
                                                          uint16_t* __restrict__ frags,
                                                          float* __restrict__ scales) {
-    const int k = blockIdx.x, set = blockIdx.y;
+    const int k = blockIdx.x, set = blockIdx.y;  // blockIdx.z: slice of the table
     const int P = lay.padded[k];
     const float* base = taps + lay.offset[k] + set * 4 * (P + 1);
     const float* grow = base;
@@ -145,14 +170,14 @@ __global__ __launch_bounds__(256) void soft_frags_kernel(const float* __restrict
         sS[0] = Sg;
         sS[1] = Sh;
         sS[2] = Sc;
-        scales[4 * k + set] = ldexpf(1.0f, -Sc);
+        if (blockIdx.z == 0) scales[4 * k + set] = ldexpf(1.0f, -Sc);
     }
     __syncthreads();
     const int Sg = sS[0], Sh = sS[1], Sc = sS[2];
     const int nkr = fl.nkr[k], nkc = fl.nkc[k], rw8 = fl.rw8[k], rwc = fl.rwc[k];
     uint16_t* dst = frags + fl.off[k] + static_cast<long long>(set) * fl.halves[k];
     const int nrow = nkr * 4 * 64 * 8, ntot = (nkr + nkc) * 4 * 64 * 8;
-    for (int e = threadIdx.x; e < ntot; e += blockDim.x) {
+    for (int e = blockIdx.z * blockDim.x + threadIdx.x; e < ntot; e += gridDim.z * blockDim.x) {
         const bool col = e >= nrow;
         const int f = col ? e - nrow : e;
         const int i = f & 7, lane = (f >> 3) & 63, t = (f >> 9) & 3, kb = f >> 11;
@@ -278,6 +303,12 @@ __global__ void zero_u32_kernel(uint32_t* __restrict__ p, int n) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
 }
 
+__global__ void zero_f64_kernel(double* __restrict__ p, long long n) {
+    for (long long i = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<long long>(gridDim.x) * blockDim.x)
+        p[i] = 0.0;
+}
+
 // Workgroups per image of the cotangent pass (about 2048 in all).
 int cotangent_blocks_per_image(int batch) { return batch >= 2048 ? 1 : 2048 / batch; }
 
@@ -285,14 +316,13 @@ int soft_cotangent_blocks(int batch) { return cotangent_blocks_per_image(batch) 
 
 hipError_t launch_soft_taps(const float* sigmas, const SoftTapLayout& lay, float* taps,
                             int32_t* err, hipStream_t s) {
-    static_assert(MHFD_MAX_SCALES <= 64, "one thread per scale");
-    soft_taps_kernel<<<1, 64, 0, s>>>(sigmas, lay, taps, err);
+    soft_taps_kernel<<<lay.K, 64, 0, s>>>(sigmas, lay, taps, err);
     return hipGetLastError();
 }
 
 hipError_t launch_soft_frags(const float* taps, const SoftTapLayout& lay, const SoftFragLayout& fl,
                              uint16_t* frags, float* scales, hipStream_t s) {
-    soft_frags_kernel<<<dim3(fl.K, SOFT_SETS), 256, 0, s>>>(taps, lay, fl, frags, scales);
+    soft_frags_kernel<<<dim3(fl.K, SOFT_SETS, 8), 256, 0, s>>>(taps, lay, fl, frags, scales);
     return hipGetLastError();
 }
 
@@ -309,6 +339,13 @@ hipError_t launch_soft_cotangent(float* r, const float* d, long long n_per_image
     if (cmax) zero_u32_kernel<<<(batch + 255) / 256, 256, 0, s>>>(cmax, batch);
     soft_cotangent_kernel<<<dim3(cotangent_blocks_per_image(batch), batch), COT_T, 0, s>>>(
         r, d, n_per_image, sigmas, k, gbar, inv_khw, beta, tau, partial, cmax);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_f64(double* p, long long n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const long long blocks = (n + 255) / 256;
+    zero_f64_kernel<<<static_cast<unsigned>(blocks < 1024 ? blocks : 1024), 256, 0, s>>>(p, n);
     return hipGetLastError();
 }
 
