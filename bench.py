@@ -297,6 +297,7 @@ def bench_batched(warmup: int) -> dict:
     tuner = Autotuner(plan)
     classes = sorted(set((h, w) for h, w, _ in shapes))
     report = tuner.tune(classes, reps=3)
+    rule = tuner.tune_batch_segments(imgs, reps=3)
     segs = [tuner.seg_rows_for(*t.shape) for t in imgs]
     launch = tuner.tune_launch(imgs, reps=2)
     r = tuner.runner(64, px, 1 << 17)
@@ -362,6 +363,8 @@ def bench_batched(warmup: int) -> dict:
                     f"{h}x{w}": [round(report[(h, w)][1][0], 3),
                                  round(report[(h, w)][1][report[(h, w)][0]], 3)]
                     for (h, w) in classes},
+                "batch_segment_rule": rule["best"],
+                "batch_ms_per_segment_rule": rule["times"],
                 "launch": launch["best"],
                 "batch_ms_default_vs_tuned_launch": [round(launch["default_ms"], 3),
                                                      round(launch["best_ms"], 3)]}}
@@ -479,8 +482,9 @@ def traffic_run() -> int:
     return 0
 
 
-def _pmc_per_kernel(path: str) -> dict:
-    """Mean counter value per dispatch of each kernel in a rocprofv3 --pmc CSV."""
+def _pmc_per_kernel(path: str, counter: str | None = None) -> dict:
+    """Mean value per dispatch of each kernel in a rocprofv3 --pmc CSV, for
+    one counter (`counter`, or the only one the run collected)."""
     import csv
     import glob
     import os
@@ -489,9 +493,30 @@ def _pmc_per_kernel(path: str) -> dict:
     for fn in files:
         with open(fn) as f:
             for row in csv.DictReader(f):
+                if counter is not None and row["Counter_Name"] != counter:
+                    continue
                 name = row["Kernel_Name"]
                 acc.setdefault(name, []).append(float(row["Counter_Value"]))
     return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
+def _pmc_counters(path: str) -> list:
+    import csv
+    import glob
+    import os
+    names = set()
+    for fn in glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True):
+        with open(fn) as f:
+            for row in csv.DictReader(f):
+                names.add(row["Counter_Name"])
+    return sorted(names)
+
+
+# SIMDs per shader engine (the SQ counters are summed per engine; busy cycles
+# per SIMD = SQ_BUSY_CYCLES / SE count, so the MFMA pipes' busy fraction is
+# SQ_VALU_MFMA_BUSY_CYCLES / (SQ_BUSY_CYCLES * SIMDs per SE)): 256 CUs in 32
+# engines, 4 SIMDs per CU.
+SIMDS_PER_SE = 32
 
 
 def _short(name: str) -> str:
@@ -500,13 +525,15 @@ def _short(name: str) -> str:
     return n.split("(")[0][:60]
 
 
-def traffic_summarize(fetch_dir: str, write_dir: str, mfma_dir: str) -> int:
-    """Write profiles/log_mfma_4096_u8_counters.json from three counter runs
+def traffic_summarize(fetch_dir: str, write_dir: str, mfma_dir: str,
+                      sq2_dir: str | None = None) -> int:
+    """Write profiles/log_mfma_4096_u8_counters.json from the counter runs
     of --traffic-run: FETCH_SIZE, WRITE_SIZE (KiB per dispatch, scaled by
-    what they read for the 256 MiB copy) and SQ_INSTS_VALU_MFMA_MOPS_F16
-    (512 FLOP per count)."""
+    what they read for the 256 MiB copy), SQ_INSTS_VALU_MFMA_MOPS_F16 (512
+    FLOP per count) with the other SQ counters of its run, and optionally a
+    second SQ run: per-tile sums over the LoG launches and the maxima pass."""
     fetch, write = _pmc_per_kernel(fetch_dir), _pmc_per_kernel(write_dir)
-    mops = _pmc_per_kernel(mfma_dir)
+    mops = _pmc_per_kernel(mfma_dir, "SQ_INSTS_VALU_MFMA_MOPS_F16")
     cal = [k for k in fetch if "elementwise" in k and "neg" in k.lower()] or \
           [k for k in fetch if "elementwise" in k]
     expect_kib = (256 << 20) / 1024.0
@@ -528,6 +555,19 @@ def traffic_summarize(fetch_dir: str, write_dir: str, mfma_dir: str) -> int:
            "mfma_flop_per_tile": round(mfma_flop),
            "tail_kernels_fetch_kib": {_short(k): round(fetch[k], 1) for k in tail},
            "tail_kernels_write_kib": {_short(k): round(write.get(k, 0.0), 1) for k in tail}}
+    sq = {}
+    for d in [mfma_dir] + ([sq2_dir] if sq2_dir else []):
+        for c in _pmc_counters(d):
+            per = _pmc_per_kernel(d, c)
+            sq.setdefault("log_mfma", {})[c] = round(sum(v for k, v in per.items() if LOG_KERNEL in k))
+            sq.setdefault("nms", {})[c] = round(sum(v for k, v in per.items() if "nms_kernel" in k))
+    for fam, v in sq.items():
+        if v.get("SQ_BUSY_CYCLES"):
+            v["mfma_busy_frac"] = round(v.get("SQ_VALU_MFMA_BUSY_CYCLES", 0) /
+                                        (v["SQ_BUSY_CYCLES"] * SIMDS_PER_SE), 4)
+        if v.get("SQ_INSTS_MFMA"):
+            v["valu_insts_per_mfma"] = round(v.get("SQ_INSTS_VALU", 0) / v["SQ_INSTS_MFMA"], 2)
+    out["sq_per_tile"] = sq
     with open(COUNTER_FILE, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out, indent=1))
@@ -536,9 +576,11 @@ def traffic_summarize(fetch_dir: str, write_dir: str, mfma_dir: str) -> int:
 
 def profile_run(kind: str) -> int:
     """Fixed workloads for kernel traces (run under rocprofv3): `batch` tunes
-    the 64-tile fp32 batch, captures it into a HIP graph and replays it six
-    times; `stretch` and `dog` run 23 detections of the 4096^2 u8 SEM tile
-    with a stretch plan / the paper's criterion."""
+    the 64-tile fp32 batch (segment heights per class, then the batch's
+    segment rule), captures it into a HIP graph and replays it six times; `plain_f32` runs the same tiles through single-tile calls;
+    `stretch` and `dog` run 23 detections of the 4096^2 u8 SEM tile with a
+    stretch plan / the paper's criterion; `soft` runs the soft focus score
+    forward and backward; `fft` the frequency-domain scale space."""
     import torch
 
     from paper_2108_12050_amd import Plan, synth
@@ -556,7 +598,8 @@ def profile_run(kind: str) -> int:
                     max_h=4096, max_w=4096)
         tuner = Autotuner(plan)
         tuner.tune(sorted(set((h, w) for h, w, _ in shapes)), reps=1)
-        tuner.launch = {"log_groups_per_cu": 2, "nms_groups_per_cu": 8, "lanes": BATCH_LANES}
+        tuner.tune_batch_segments(imgs, reps=1)
+        tuner.launch = {"log_groups_per_cu": 2, "nms_groups_per_cu": 16, "lanes": BATCH_LANES}
         r = tuner.runner(64, sum(t.numel() for t in imgs), 1 << 17)
         r.set_tiles(imgs, [tuner.seg_rows_for(*t.shape) for t in imgs])
         g = r.capture()
@@ -591,6 +634,28 @@ def profile_run(kind: str) -> int:
                         dtype="u8", max_h=H, max_w=W, criterion="dog")
         for _ in range(23):
             plan.detect(img)
+    elif kind == "soft":
+        # the soft focus score on 8 x 2048^2 fp32, K = 10: three forward and
+        # three backward calls
+        B, Hs, Ws = 8, 2048, 2048
+        imgs = torch.from_numpy(synth.grad_batch(0, B, Hs, Ws)).cuda()
+        plan = Plan(n_scales=K, sigma_min=1.0, sigma_max=10.0, max_h=Hs, max_w=Ws)
+        sig = torch.arange(1, K + 1, dtype=torch.float32, device="cuda")
+        gb = torch.ones(B, device="cuda")
+        for _ in range(3):
+            plan.focus_score(imgs, sig, check=False)
+            plan.focus_score_backward(imgs, sig, gb, check=False)
+    elif kind == "fft":
+        # the frequency-domain scale space: 23 detections of the 4096^2 u8
+        # tile, sigma 4..64 (radii up to 256)
+        import numpy as np
+        img = torch.from_numpy(synth.sem_tile(0, psf_sigma=0.0)).cuda()
+        plan = Plan(sigmas=list(np.linspace(4.0, 64.0, K)), threshold=TAU, overlap=OVERLAP,
+                    dtype="u8", max_h=H, max_w=W, blur="fft")
+        raw = torch.empty((1 << 17, 5), dtype=torch.int32, device="cuda")
+        res = torch.zeros(4, dtype=torch.int64, device="cuda")
+        for _ in range(23):
+            plan.detect_into(img, raw, res)
     else:
         print(f"unknown profile run {kind!r}", file=sys.stderr)
         return 2
@@ -599,13 +664,18 @@ def profile_run(kind: str) -> int:
     return 0
 
 
+def _phase(name: str) -> None:
+    """One progress line per phase on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench] {time.strftime('%H:%M:%S')} {name}", file=sys.stderr, flush=True)
+
+
 def main() -> int:
     if len(sys.argv) > 2 and sys.argv[1] == "--profile-run":
         return profile_run(sys.argv[2])
     if len(sys.argv) > 1 and sys.argv[1] == "--traffic-run":
         return traffic_run()
     if len(sys.argv) > 1 and sys.argv[1] == "--traffic-summarize":
-        return traffic_summarize(sys.argv[2], sys.argv[3], sys.argv[4])
+        return traffic_summarize(*sys.argv[2:6])
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
@@ -633,6 +703,8 @@ def main() -> int:
     torch.cuda.set_device(dev)
     imgs_np = [synth.sem_tile(0, psf_sigma=p) for p in PSF]
     imgs = [torch.from_numpy(x).to(dev) for x in imgs_np]
+    _phase(f"plain detector: {a.warmup} warmup + {a.steps} timed tiles on {a.streams} streams, "
+           "then one stream")
     plan = Plan(n_scales=K, sigma_min=1.0, sigma_max=10.0, threshold=TAU, overlap=OVERLAP,
                 dtype="u8", max_h=H, max_w=W)
     L = _lib.load()
@@ -705,12 +777,13 @@ def main() -> int:
     mpix = H * W / 1e6
     value = a.steps * mpix / elapsed
     achieved = FLOP_PER_PX * H * W / (log_ms.mean() * 1e-3)
-    traffic = mfma_flop = None
+    traffic = mfma_flop = sq = None
     if os.path.exists(COUNTER_FILE):
         tr = json.load(open(COUNTER_FILE))
         if tr.get("kernel_source_sha256_16") == kernel_source_hash():
             traffic = tr.get("bytes_per_tile")
             mfma_flop = tr.get("mfma_flop_per_tile")
+            sq = tr.get("sq_per_tile")
     log_s = log_ms.mean() * 1e-3
     out = {
         "metric": "MPix/s, 10-scale LoG detect+NMS (plain vs batched); p99 latency/4096² tile",
@@ -749,7 +822,13 @@ def main() -> int:
                      "executed_mfma": None if mfma_flop is None else {
                          "flop_per_tile": mfma_flop,
                          "tflops": round(mfma_flop / log_s / 1e12, 2),
-                         "frac": round(mfma_flop / log_s / PEAK_FP16_MFMA, 4)}},
+                         "frac": round(mfma_flop / log_s / PEAK_FP16_MFMA, 4)},
+                     # from the committed SQ counter runs of the same kernels
+                     "counters": None if not sq else {
+                         "log_mfma_busy_frac": sq["log_mfma"].get("mfma_busy_frac"),
+                         "log_valu_insts_per_mfma": sq["log_mfma"].get("valu_insts_per_mfma"),
+                         "log_valu_insts_per_tile": sq["log_mfma"].get("SQ_INSTS_VALU"),
+                         "nms_valu_insts_per_tile": sq["nms"].get("SQ_INSTS_VALU")}},
         "focus": {"psf_sigma": list(PSF), "blobs": counts, "candidates": cands},
     }
     # The LoG stack and the detector against the HBM roof: algorithmic bytes
@@ -766,16 +845,24 @@ def main() -> int:
         "detector_bytes": 81 * H * W, "detector_gbs": round(81 * H * W / det_s / 1e9, 1),
         "detector_frac": round(81 * H * W / det_s / PEAK_HBM, 4)}
     if not a.no_forms:
+        _phase("stretched detector")
         out["stretch"] = bench_stretch(imgs, nbytes, cap, a.warmup)
+        _phase("paper criterion")
         out["paper_criterion"] = bench_dog(imgs, cap, a.warmup)
+        _phase("frequency-domain scale space")
         out["fft_blur"] = bench_fft_blur(imgs, cap, a.warmup)
     if not a.no_forms:
         del bufs
         torch.cuda.empty_cache()
-        out["forms"] = {"batched": bench_batched(a.warmup),
-                        "soft_score": bench_soft(),
+        _phase("batched form")
+        batched = bench_batched(a.warmup)
+        _phase("soft score")
+        soft = bench_soft()
+        _phase(f"serving ({a.serve_seconds:g} s trace, then saturation)")
+        out["forms"] = {"batched": batched, "soft_score": soft,
                         "serving": bench_serving(a.serve_seconds)}
     if not a.no_cpu:
+        _phase("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(imgs_np[0], a.cpu_rows)
     print(json.dumps(out), flush=True)
     return 0

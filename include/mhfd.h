@@ -135,8 +135,11 @@ typedef struct mhfd_result {
  *           power-of-two sides of at most MHFD_MAX_FFT_SIZE
  *           (MHFD_ERR_UNSUPPORTED otherwise); the LoG criterion only, no
  *           stretch; detection only (batched and focus-score calls refuse
- *           such plans).  FP32 arithmetic, twiddles and spectra built in
- *           FP64.
+ *           such plans; no threshold-sparse stack).  FP32 arithmetic,
+ *           twiddles and spectra built in FP64 (the spectra once per plan,
+ *           on the device, at the plan's largest power-of-two side).
+ *           Measured error against the FP64 direct convolution: about 3e-7
+ *           of each plane's maximum.
  */
 #define MHFD_BLUR_DIRECT 0
 #define MHFD_BLUR_FFT 1
@@ -218,7 +221,8 @@ mhfd_status mhfd_detect(mhfd_plan plan, const void *d_img, int32_t h, int32_t w,
  * input, and for 8-bit plans without the stretch, which need none).  fp32
  * plans keep one word: the image's max |I|, from which the matrix-core
  * kernels take an exact power-of-two input scale.  Stretch plans keep the
- * 256-bin histogram and the two levels (258 words).
+ * 256-bin histogram and the two levels (258 words).  FFT plans keep three
+ * h x w float transform buffers.
  */
 size_t mhfd_log_stack_workspace_size(mhfd_plan plan, int32_t h, int32_t w);
 

@@ -23,9 +23,14 @@ scale-major, so a workgroup keeps its taps over consecutive items).
 candidate height (HIP events, median of repeats) beside the library default
 (0), keeps the fastest, and caches the choice in a JSON file keyed by GPU
 architecture, library build and plan (scales, radii, dtype).
-`tune_launch` times a representative batch over the launch shapes and
-lanes.  `seg_rows_for` returns the tuned height for a tile (nearest size
-class by pixel count), or 0 -- the library default -- when nothing was tuned.
+`tune_batch_segments` then times a representative batch under each
+segment-height rule (the per-class table, the library default, uniform
+heights, whole-tile items) and keeps the fastest: in a batch of many tiles
+the parallelism comes from the tiles, so the per-class heights, tuned on one
+tile alone, are often too short.  `tune_launch` times the batch over the
+launch shapes and lanes.  `seg_rows_for` returns the height the kept rule
+gives a tile (per class: the nearest size class by pixel count), or 0 -- the
+library default -- when nothing was tuned.
 """
 from __future__ import annotations
 
@@ -46,6 +51,9 @@ LOG_GROUPS = (1, 2, 4)
 NMS_GROUPS = (4, 8, 16)
 LANES = (1, 2, 3)
 DEFAULT_LAUNCH = {"log_groups_per_cu": 2, "nms_groups_per_cu": 8, "lanes": 1}
+# segment-height rules for a whole batch: the per-class table, uniform
+# heights, whole-tile items (height rounded up to 32 rows)
+BATCH_RULES = ("per_class", "default", "uniform_1024", "uniform_2048", "whole_tile")
 
 
 def _lib_hash() -> str:
@@ -76,6 +84,7 @@ class Autotuner:
         self.cache_path = cache_path
         self.table: dict[tuple[int, int], int] = {}
         self.launch = dict(DEFAULT_LAUNCH)
+        self.batch_rule = "per_class"
         self.key = json.dumps({"arch": _arch(), "lib": _lib_hash(), "sigmas": plan.sigmas,
                                "radii": plan.radii, "dtype": plan.dtype}, sort_keys=True)
         if cache_path and os.path.exists(cache_path):
@@ -85,6 +94,7 @@ class Autotuner:
                 self.table = {tuple(map(int, k.split("x"))): int(v)
                               for k, v in entry.get("seg_rows", {}).items()}
                 self.launch.update(entry.get("launch", {}))
+                self.batch_rule = entry.get("batch_rule", self.batch_rule)
 
     def _tile(self, h: int, w: int, seed: int) -> torch.Tensor:
         from . import synth
@@ -115,6 +125,29 @@ class Autotuner:
             report[(int(h), int(w))] = (best, t)
         self._save()
         return report
+
+    def tune_batch_segments(self, imgs, reps: int = 3) -> dict:
+        """Segment heights for a whole batch: a height tuned on one tile of a
+        class trades warm-up work for parallelism that a batch of many tiles
+        does not need, so the batch `imgs` is timed (default launch shape)
+        with the per-class table, with uniform heights and with whole-tile
+        items, and the fastest rule is kept for `seg_rows_for`.  Returns
+        {"best": rule, "times": {rule: ms}}."""
+        px = sum(t.numel() for t in imgs)
+        saved = self.batch_rule
+        times = {}
+        for rule in BATCH_RULES:
+            self.batch_rule = rule
+            if rule == "per_class" and not self.table:
+                continue
+            r = BatchRunner(self.plan, len(imgs), px, 1 << 12)
+            r.set_tiles(imgs, [self.seg_rows_for(*t.shape) for t in imgs])
+            r.run()
+            times[rule] = _median_ms(r.run, reps)
+            del r
+        self.batch_rule = min(times, key=times.get) if times else saved
+        self._save()
+        return {"best": self.batch_rule, "times": {k: round(v, 3) for k, v in times.items()}}
 
     def tune_launch(self, imgs, reps: int = 3) -> dict:
         """Time the batch `imgs` (device tiles, tuned segment heights) for
@@ -148,11 +181,17 @@ class Autotuner:
             with open(self.cache_path) as f:
                 data = json.load(f)
         data[self.key] = {"seg_rows": {f"{h}x{w}": s for (h, w), s in self.table.items()},
-                          "launch": self.launch}
+                          "launch": self.launch, "batch_rule": self.batch_rule}
         with open(self.cache_path, "w") as f:
             json.dump(data, f, indent=1)
 
     def seg_rows_for(self, h: int, w: int) -> int:
+        if self.batch_rule == "default":
+            return 0
+        if self.batch_rule.startswith("uniform_"):
+            return min(int(self.batch_rule.split("_")[1]), max(32, (h + 31) // 32 * 32))
+        if self.batch_rule == "whole_tile":
+            return min(4096, max(32, (h + 31) // 32 * 32))
         if not self.table:
             return 0
         if (h, w) in self.table:

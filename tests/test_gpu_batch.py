@@ -259,7 +259,8 @@ def test_autotuner_choices_keep_results():
     single-tile path's (launch parameters change the time only)."""
     import os
     import tempfile
-    from paper_2108_12050_amd.autotune import CANDIDATES, LANES, LOG_GROUPS, NMS_GROUPS, Autotuner
+    from paper_2108_12050_amd.autotune import (BATCH_RULES, CANDIDATES, LANES, LOG_GROUPS,
+                                               NMS_GROUPS, Autotuner)
     plan = plan_f32()
     imgs = small_mixed(9, 6)
     with tempfile.TemporaryDirectory() as d:
@@ -270,12 +271,19 @@ def test_autotuner_choices_keep_results():
         for c in classes:
             best, times = rep[c]
             assert best in CANDIDATES and 0 in times and times[best] <= min(times.values()) + 1e-9
+        br = tuner.tune_batch_segments(imgs, reps=1)
+        assert br["best"] in BATCH_RULES and set(br["times"]) == set(BATCH_RULES)
+        assert br["times"][br["best"]] <= min(br["times"].values()) + 1e-9
+        for t in imgs:
+            sr = tuner.seg_rows_for(*t.shape)
+            assert sr == 0 or (sr % 32 == 0 and 32 <= sr <= 4096)
         lt = tuner.tune_launch(imgs, reps=1)
         b = lt["best"]
         assert b["log_groups_per_cu"] in LOG_GROUPS and b["nms_groups_per_cu"] in NMS_GROUPS
         assert b["lanes"] in LANES and lt["best_ms"] <= lt["default_ms"] + 1e-9
         again = Autotuner(plan, path)          # the cache gives the same choices
         assert again.table == tuner.table and again.launch == tuner.launch
+        assert again.batch_rule == tuner.batch_rule
         r = tuner.runner(len(imgs), sum(t.numel() for t in imgs), 1 << 14)
         r.set_tiles(imgs, [tuner.seg_rows_for(*t.shape) for t in imgs])
         r.run()
