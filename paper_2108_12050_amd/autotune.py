@@ -17,7 +17,7 @@ Fixed by the kernels and therefore not tuned: the 16-column wave tile and
 the 32-row K-block of the MFMA operands, the per-scale halo (the exact
 column window, R rows above the block), and the scales a workgroup holds
 (one per item: its column taps in LDS, a ring per wave; items are numbered
-scale-major, so a workgroup keeps its taps over consecutive items).
+tile-major, so a tile's scales share its image in the caches).
 
 `Autotuner.tune` times one-tile batches of each size class for each
 candidate height (HIP events, median of repeats) beside the library default

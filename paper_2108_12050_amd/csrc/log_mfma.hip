@@ -657,13 +657,13 @@ void log_mfma_kernel(const typename Elem<T>::type* __restrict__ img, int h, int 
     run_job<T, NKR, NKC, CTL, SPARSE, EPI>(J, frags + sc.frag_off, threadIdx.x & 63, cl);
 }
 
-// Persistent form over a batch of tiles: every workgroup pulls items (scale j
-// of the launch, tile, row segment, group of MW adjacent wave columns) from a
-// counter, and its waves run the single-tile path's per-wave body on them.
-// Items are numbered scale-major, so a launch finishes its scales in order
-// and a workgroup mostly keeps its scale from one item to the next; for
-// nkc >= 3 the scale's column taps sit in LDS as in the single-tile kernel,
-// copied again only when the scale changes.
+// Persistent form over a batch of tiles: every workgroup pulls items (tile,
+// scale j of the launch, row segment, group of MW adjacent wave columns) from
+// a counter, and its waves run the single-tile path's per-wave body on them.
+// Items are numbered tile-major, so the scales of a tile run together and
+// re-read its image from the caches; for nkc >= 3 the scale's column taps
+// sit in LDS as in the single-tile kernel, copied again when the scale
+// changes.
 template <typename T, int NKR, int NKC, bool SPARSE>
 __global__ __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(mfma_waves<T, NKC>(), 2)))
 void log_mfma_batch_kernel(int n_tiles, const BatchTile* __restrict__ tiles,
@@ -684,8 +684,23 @@ void log_mfma_batch_kernel(int n_tiles, const BatchTile* __restrict__ tiles,
         __syncthreads();
         const int item = s_item;
         if (item >= total) break;
-        const int j = item / per_scale;
-        const int rem = item - j * per_scale;
+        // Tile-major: tile t owns items [S base_t, S base_t+1) (base: its
+        // items per scale before it), scale-major inside, so the scales of
+        // a tile run close together in time and re-read its image from the
+        // caches rather than HBM.
+        const int S = sc.n;
+        int lo = 0, hi = n_tiles;  // last tile with S mitem_base <= item
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (S * tiles[mid].mitem_base <= item)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const BatchTile& t = tiles[lo];
+        const int n_t = (lo + 1 < n_tiles ? tiles[lo + 1].mitem_base : per_scale) - t.mitem_base;
+        const int r = item - S * t.mitem_base;
+        const int j = r / n_t;
         if constexpr (CTL) {
             if (j != loaded) {
                 const half8_t* src = frags + sc.frag_off[j] + NKR * 4 * 64;
@@ -694,16 +709,7 @@ void log_mfma_batch_kernel(int n_tiles, const BatchTile* __restrict__ tiles,
                 loaded = j;
             }
         }
-        int lo = 0, hi = n_tiles;  // last tile with mitem_base <= rem
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (tiles[mid].mitem_base <= rem)
-                lo = mid;
-            else
-                hi = mid;
-        }
-        const BatchTile& t = tiles[lo];
-        const int local = rem - t.mitem_base;
+        const int local = r - j * n_t;
         const int seg = local / t.mgroups_x;
         const int wcol = (local - seg * t.mgroups_x) * MW + wv;
         if (wcol >= t.mtiles_x) continue;
