@@ -290,7 +290,11 @@ __device__ __forceinline__ Input<float>::Raw select_raw<float>(bool c, Input<flo
 // value above J.tau, and every 16 x 16 output block's groups are marked in
 // one activity word (bit 16 g + r: row r, columns 4 g ... 4 g + 3 of the
 // block), which the maxima pass reads instead of the unwritten groups.
-template <typename T, int NKR, int NKC, bool EDGE, bool CTL, bool SPARSE, int EPI = EPI_STORE>
+// INNER (regular jobs only): every row-pass window column lies inside the
+// image, so no group is mirrored and the groups of a row are one base
+// address plus constant offsets.
+template <typename T, int NKR, int NKC, bool EDGE, bool CTL, bool SPARSE, int EPI = EPI_STORE,
+          bool INNER = false>
 __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __restrict__ fr,
                                          const half8_t* cl, int lane) {
     typedef Input<T> In;
@@ -325,7 +329,7 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
     // Regular items: source column and order of each 8-element group.
     int src[NKR];
     bool rev[NKR] = {};
-    if (!EDGE) {
+    if (!EDGE && !INNER) {
 #pragma unroll
         for (int kb = 0; kb < NKR; ++kb) {
             const int gs = xw + 32 * kb + 8 * g;
@@ -346,7 +350,11 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
             r = min(r0, 2 * h - 1 - r0);
         }
         const E* row = img + static_cast<long long>(r) * J.pitch;
-        if (!EDGE) {
+        if (INNER) {
+            const E* base = row + xw + 8 * g;
+#pragma unroll
+            for (int kb = 0; kb < NKR; ++kb) raw[kb] = In::load(base + 32 * kb);
+        } else if (!EDGE) {
 #pragma unroll
             for (int kb = 0; kb < NKR; ++kb) {
                 const RawGroup v = In::load(row + src[kb]);
@@ -371,8 +379,9 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
         half8_t in_hi[NKR], in_lo[NKR];
 #pragma unroll
         for (int kb = 0; kb < NKR; ++kb) {
-            const RawGroup v = (EDGE || !LATE_REV) ? rw[kb]
-                                                   : select_raw<T>(rev[kb], In::reverse(rw[kb]), rw[kb]);
+            const RawGroup v = (EDGE || INNER || !LATE_REV)
+                                   ? rw[kb]
+                                   : select_raw<T>(rev[kb], In::reverse(rw[kb]), rw[kb]);
             In::convert(v, J, in_hi[kb], in_lo[kb]);
         }
         fetch(hb + D, rw);
@@ -559,10 +568,15 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
 template <typename T, int NKR, int NKC, bool CTL = false, bool SPARSE = false, int EPI = EPI_STORE>
 __device__ __forceinline__ void run_job(const WaveJob& J, const half8_t* __restrict__ fr,
                                         int lane, const half8_t* cl = nullptr) {
-    if (regular_job<T, NKR, NKC>(J))
-        wave_job<T, NKR, NKC, false, CTL, SPARSE, EPI>(J, fr, cl, lane);
-    else
+    if (regular_job<T, NKR, NKC>(J)) {
+        const int xw = J.x0 - J.rw8;
+        if (xw >= 0 && xw + 32 * NKR <= J.w)
+            wave_job<T, NKR, NKC, false, CTL, SPARSE, EPI, true>(J, fr, cl, lane);
+        else
+            wave_job<T, NKR, NKC, false, CTL, SPARSE, EPI, false>(J, fr, cl, lane);
+    } else {
         wave_job<T, NKR, NKC, true, CTL, SPARSE, EPI>(J, fr, cl, lane);
+    }
 }
 
 // Kernels of shapes with nkc >= 3 read their column taps from LDS: the
