@@ -195,15 +195,22 @@ __global__ __launch_bounds__(64 * NMS_WAVES) void nms_batch_kernel(
     const uint64_t* __restrict__ act) {
     const int total = ctr->nms_items;
     const int n_waves = gridDim.x * NMS_WAVES;
-    for (int item = blockIdx.x * NMS_WAVES + (threadIdx.x >> 6); item < total; item += n_waves) {
-        int lo = 0, hi = n_tiles;  // last t with nitem_base <= item
+    // A wave's items increase, so its tile (the last t with nitem_base <=
+    // item) only moves forward: one binary search, then a cursor.
+    int lo = 0;
+    {
+        const int first = blockIdx.x * NMS_WAVES + (threadIdx.x >> 6);
+        int hi = n_tiles;
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
-            if (tiles[mid].nitem_base <= item)
+            if (tiles[mid].nitem_base <= first)
                 lo = mid;
             else
                 hi = mid;
         }
+    }
+    for (int item = blockIdx.x * NMS_WAVES + (threadIdx.x >> 6); item < total; item += n_waves) {
+        while (lo + 1 < n_tiles && tiles[lo + 1].nitem_base <= item) ++lo;
         const BatchTile& T = tiles[lo];
         const int local = item - T.nitem_base;
         const int run = local / T.bpr, strip = local - run * T.bpr;

@@ -692,6 +692,7 @@ void log_mfma_batch_kernel(int n_tiles, const BatchTile* __restrict__ tiles,
     const int per_scale = ctr->mitems_per_scale;
     const int total = ctr->valid ? per_scale * sc.n : 0;
     int loaded = -1;  // scale whose column taps are in LDS (uniform)
+    int lo = 0;       // tile of the last item (uniform)
     for (;;) {
         __syncthreads();  // every wave is done with s_item and the LDS taps
         if (threadIdx.x == 0) s_item = atomicAdd(&ctr->mwork[slot], 1);
@@ -702,15 +703,10 @@ void log_mfma_batch_kernel(int n_tiles, const BatchTile* __restrict__ tiles,
         // items per scale before it), scale-major inside, so the scales of
         // a tile run close together in time and re-read its image from the
         // caches rather than HBM.
+        // The workgroup's items increase (one counter), so its tile only
+        // moves forward: a cursor from the last item's tile.
         const int S = sc.n;
-        int lo = 0, hi = n_tiles;  // last tile with S mitem_base <= item
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (S * tiles[mid].mitem_base <= item)
-                lo = mid;
-            else
-                hi = mid;
-        }
+        while (lo + 1 < n_tiles && S * tiles[lo + 1].mitem_base <= item) ++lo;
         const BatchTile& t = tiles[lo];
         const int n_t = (lo + 1 < n_tiles ? tiles[lo + 1].mitem_base : per_scale) - t.mitem_base;
         const int r = item - S * t.mitem_base;
