@@ -187,7 +187,12 @@ __global__ __launch_bounds__(SETUP_T) void batch_setup_kernel(
 // Persistent maxima waves over every tile's (run of nms::ROWS rows, strip of
 // 64 nms_cw columns) items, the per-wave body of the single-tile pass; the
 // tile index rides in the upper bits of every record's k.
-template <int K, bool SPARSE>
+//
+// One kernel per lane width CW: each takes the items of the tiles with
+// nms_cw == CW and skips the others, so each is compiled for its own width
+// alone (one kernel holding both needed more registers than either, and ran
+// fewer waves per SIMD).
+template <int K, int CW, bool SPARSE>
 __global__ __launch_bounds__(64 * NMS_WAVES) void nms_batch_kernel(
     const float* __restrict__ stack, const BatchTile* __restrict__ tiles, int n_tiles, float tau,
     int n_blk_bound, int32_t* __restrict__ blk_n, int32_t* __restrict__ blk_o,
@@ -195,11 +200,14 @@ __global__ __launch_bounds__(64 * NMS_WAVES) void nms_batch_kernel(
     const uint64_t* __restrict__ act) {
     const int total = ctr->nms_items;
     const int n_waves = gridDim.x * NMS_WAVES;
+    // wave-uniform (readfirstlane), so the tile fields come in scalar
+    // registers rather than in every lane's
+    const int wave0 = __builtin_amdgcn_readfirstlane(blockIdx.x * NMS_WAVES + (threadIdx.x >> 6));
     // A wave's items increase, so its tile (the last t with nitem_base <=
     // item) only moves forward: one binary search, then a cursor.
     int lo = 0;
     {
-        const int first = blockIdx.x * NMS_WAVES + (threadIdx.x >> 6);
+        const int first = wave0;
         int hi = n_tiles;
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
@@ -209,9 +217,10 @@ __global__ __launch_bounds__(64 * NMS_WAVES) void nms_batch_kernel(
                 hi = mid;
         }
     }
-    for (int item = blockIdx.x * NMS_WAVES + (threadIdx.x >> 6); item < total; item += n_waves) {
+    for (int item = wave0; item < total; item += n_waves) {
         while (lo + 1 < n_tiles && tiles[lo + 1].nitem_base <= item) ++lo;
         const BatchTile& T = tiles[lo];
+        if (T.nms_cw != CW) continue;
         const int local = item - T.nitem_base;
         const int run = local / T.bpr, strip = local - run * T.bpr;
         nms::Sink out;
@@ -225,13 +234,7 @@ __global__ __launch_bounds__(64 * NMS_WAVES) void nms_batch_kernel(
         out.k_tag = lo << TILE_SHIFT;
         const float* st = stack + T.stack_off;
         const nms::Active a{SPARSE ? act + T.act_off : nullptr, (T.w + 15) / 16, (T.h + 15) / 16};
-        if constexpr (2 * K <= 32) {
-            if (T.nms_cw == 2) {
-                nms::wave<K, 2, SLOT, SPARSE>(st, T.h, T.w, tau, T.bpr, strip, run, out, a);
-                continue;
-            }
-        }
-        nms::wave<K, 1, SLOT, SPARSE>(st, T.h, T.w, tau, T.bpr, strip, run, out, a);
+        nms::wave<K, CW, SLOT, SPARSE>(st, T.h, T.w, tau, T.bpr, strip, run, out, a);
     }
 }
 
@@ -359,16 +362,24 @@ __global__ void results_batch_kernel(const int32_t* __restrict__ blk_off,
     }
 }
 
-template <int K>
-void launch_nms_batch_k(const BatchLaunchArgs& a, hipStream_t s) {
+template <int K, int CW>
+void launch_nms_batch_cw(const BatchLaunchArgs& a, hipStream_t s) {
     if (a.act)
-        nms_batch_kernel<K, true><<<a.nms_grid, 64 * NMS_WAVES, 0, s>>>(
+        nms_batch_kernel<K, CW, true><<<a.nms_grid, 64 * NMS_WAVES, 0, s>>>(
             a.stack, a.tiles, a.n_tiles, a.tau, a.n_blk_bound, a.blk_n, a.blk_o, a.pool, a.cap,
             a.ctr, a.act);
     else
-        nms_batch_kernel<K, false><<<a.nms_grid, 64 * NMS_WAVES, 0, s>>>(
+        nms_batch_kernel<K, CW, false><<<a.nms_grid, 64 * NMS_WAVES, 0, s>>>(
             a.stack, a.tiles, a.n_tiles, a.tau, a.n_blk_bound, a.blk_n, a.blk_o, a.pool, a.cap,
             a.ctr, a.act);
+}
+
+// Two columns per lane for the tiles that allow it (even widths, K <= 16),
+// then one for the rest (an empty pass when there is none).
+template <int K>
+void launch_nms_batch_k(const BatchLaunchArgs& a, hipStream_t s) {
+    if constexpr (K <= 16) launch_nms_batch_cw<K, 2>(a, s);
+    launch_nms_batch_cw<K, 1>(a, s);
 }
 
 template <int... Ks>

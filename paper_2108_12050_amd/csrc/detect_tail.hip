@@ -54,7 +54,9 @@ __global__ __launch_bounds__(64 * NMS_WAVES) void nms_kernel(
     const float* __restrict__ st, int H, int W, float tau, int bpr, int n_runs,
     int32_t* __restrict__ blk_n, int32_t* __restrict__ blk_o, Cand* __restrict__ pool,
     int64_t n_cells, int64_t cap, DetectCounters* __restrict__ ctr, nms::Active act) {
-    const int wid = blockIdx.x * NMS_WAVES + (threadIdx.x >> 6);  // (run, strip), strip fastest
+    // (run, strip), strip fastest; wave-uniform (readfirstlane), so the row
+    // and column bookkeeping stays in scalar registers
+    const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * NMS_WAVES + (threadIdx.x >> 6));
     if (wid >= n_runs * bpr) return;
     nms::Sink out;
     out.blk_n = blk_n;

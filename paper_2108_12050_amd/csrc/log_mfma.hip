@@ -697,7 +697,7 @@ void log_mfma_batch_kernel(int n_tiles, const BatchTile* __restrict__ tiles,
         __syncthreads();  // every wave is done with s_item and the LDS taps
         if (threadIdx.x == 0) s_item = atomicAdd(&ctr->mwork[slot], 1);
         __syncthreads();
-        const int item = s_item;
+        const int item = __builtin_amdgcn_readfirstlane(s_item);  // uniform: scalar registers
         if (item >= total) break;
         // Tile-major: tile t owns items [S base_t, S base_t+1) (base: its
         // items per scale before it), scale-major inside, so the scales of
