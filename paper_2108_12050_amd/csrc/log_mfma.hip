@@ -116,6 +116,9 @@ struct WaveJob {
     float* aux;
     float sigma, wb;
     uint32_t* cmax_word;
+    // Second column-tap set (EPI_DUAL): output plane and factor.
+    float* plane2;
+    float out_scale2;
 };
 
 // softplus(z) = max(z, 0) + log(1 + e^{-|z|}) on the hardware exp2 / log2
@@ -293,10 +296,13 @@ __device__ __forceinline__ Input<float>::Raw select_raw<float>(bool c, Input<flo
 // INNER (regular jobs only): every row-pass window column lies inside the
 // image, so no group is mirrored and the groups of a row are one base
 // address plus constant offsets.
+// EPI_DUAL: a second set of column taps (cl2, always in LDS) applied to the
+// same ring, its result stored (dense) to J.plane2.
 template <typename T, int NKR, int NKC, bool EDGE, bool CTL, bool SPARSE, int EPI = EPI_STORE,
           bool INNER = false>
 __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __restrict__ fr,
-                                         const half8_t* cl, int lane) {
+                                         const half8_t* cl, int lane,
+                                         const half8_t* cl2 = nullptr) {
     typedef Input<T> In;
     typedef typename In::Raw RawGroup;
     constexpr int NS = mfma_ring<T, NKC>();   // ring of intermediate blocks
@@ -402,6 +408,19 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
     };
 
     const bool vec = !EDGE || (J.out_vec && x0 + 16 <= w);
+    // dense store of one output block row to `plane` (EPI_DUAL)
+    auto put = [&](float* plane, int t, float4_t v) {
+        const int y = y0 + 16 * t + c;
+        if (EDGE && y >= y1) return;
+        float* o = plane + static_cast<long long>(y) * w + x0 + 4 * g;
+        if (vec) {
+            *reinterpret_cast<float4_t*>(o) = v;
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (x0 + 4 * g + i < w) o[i] = v[i];
+        }
+    };
     float tsum = 0.0f;  // EPI_SOFTSUM: this lane's softplus sum
     double gsum = 0.0;  // EPI_COTAN: this lane's sigma-gradient sum
     float cmx = 0.0f;   // EPI_COTAN: this lane's max |c|
@@ -495,7 +514,7 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
         // LDS form: an opaque lane offset per block keeps the reads in the
         // loop (hoisted, they would be the registers this form saves)
         int lo = lane;
-        if constexpr (CTL) asm volatile("" : "+v"(lo));
+        if constexpr (CTL || EPI == EPI_DUAL) asm volatile("" : "+v"(lo));
         auto tap = [&](int kb, int t) -> half8_t {
             if constexpr (CTL)
                 return cl[(kb * 4 + t) * 64 + lo];
@@ -516,7 +535,27 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
             ra = mfma16(xl, c0, ra);
             rb = mfma16(yl, c2, rb);
         }
-        store(t, (ra + rb) * J.out_scale);
+        if constexpr (EPI == EPI_DUAL) {
+            float4_t ra2 = {0.f, 0.f, 0.f, 0.f}, rb2 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kb = 0; kb < NKC; ++kb) {
+                const Slot& sa = ring[(p + 2 * kb) % NS];
+                const Slot& sb = ring[(p + 2 * kb + 1) % NS];
+                const half8_t xh = cat(sa.ah, sb.ah), xl = cat(sa.al, sb.al);
+                const half8_t yh = cat(sa.bh, sb.bh), yl = cat(sa.bl, sb.bl);
+                const half8_t d0 = cl2[(kb * 4 + 0) * 64 + lo], d2 = cl2[(kb * 4 + 2) * 64 + lo];
+                ra2 = mfma16(xh, d0, ra2);
+                rb2 = mfma16(yh, d2, rb2);
+                ra2 = mfma16(xh, cl2[(kb * 4 + 1) * 64 + lo], ra2);
+                rb2 = mfma16(yh, cl2[(kb * 4 + 3) * 64 + lo], rb2);
+                ra2 = mfma16(xl, d0, ra2);
+                rb2 = mfma16(yl, d2, rb2);
+            }
+            put(J.plane, t, (ra + rb) * J.out_scale);
+            put(J.plane2, t, (ra2 + rb2) * J.out_scale2);
+        } else {
+            store(t, (ra + rb) * J.out_scale);
+        }
     };
     if constexpr (mfma_peel<T, NKC>()) {
         // Whole ring turns without exits, the first one peeled, then the
@@ -567,15 +606,16 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
 
 template <typename T, int NKR, int NKC, bool CTL = false, bool SPARSE = false, int EPI = EPI_STORE>
 __device__ __forceinline__ void run_job(const WaveJob& J, const half8_t* __restrict__ fr,
-                                        int lane, const half8_t* cl = nullptr) {
+                                        int lane, const half8_t* cl = nullptr,
+                                        const half8_t* cl2 = nullptr) {
     if (regular_job<T, NKR, NKC>(J)) {
         const int xw = J.x0 - J.rw8;
         if (xw >= 0 && xw + 32 * NKR <= J.w)
-            wave_job<T, NKR, NKC, false, CTL, SPARSE, EPI, true>(J, fr, cl, lane);
+            wave_job<T, NKR, NKC, false, CTL, SPARSE, EPI, true>(J, fr, cl, lane, cl2);
         else
-            wave_job<T, NKR, NKC, false, CTL, SPARSE, EPI, false>(J, fr, cl, lane);
+            wave_job<T, NKR, NKC, false, CTL, SPARSE, EPI, false>(J, fr, cl, lane, cl2);
     } else {
-        wave_job<T, NKR, NKC, true, CTL, SPARSE, EPI>(J, fr, cl, lane);
+        wave_job<T, NKR, NKC, true, CTL, SPARSE, EPI>(J, fr, cl, lane, cl2);
     }
 }
 
@@ -611,10 +651,18 @@ void log_mfma_kernel(const typename Elem<T>::type* __restrict__ img, int h, int 
     const int seg = local / L.groups_x;
     const int wcol = (local - seg * L.groups_x) * MW + (threadIdx.x >> 6);
     constexpr bool CTL = mfma_cols_in_lds<NKC>();
+    constexpr bool DUAL = EPI == EPI_DUAL;
     __shared__ half8_t cl[CTL ? NKC * 4 * 64 : 1];
-    if constexpr (CTL) {  // the block's scale's column fragments, before any wave leaves
-        const half8_t* src = frags + sc.frag_off + NKR * 4 * 64;
-        for (int i = threadIdx.x; i < NKC * 4 * 64; i += 64 * MW) cl[i] = src[i];
+    __shared__ half8_t cl2[DUAL ? NKC * 4 * 64 : 1];
+    if constexpr (CTL || DUAL) {  // the block's column fragments, before any wave leaves
+        if constexpr (CTL) {
+            const half8_t* src = frags + sc.frag_off + NKR * 4 * 64;
+            for (int i = threadIdx.x; i < NKC * 4 * 64; i += 64 * MW) cl[i] = src[i];
+        }
+        if constexpr (DUAL) {
+            const half8_t* src2 = frags + sc.frag_off2 + NKR * 4 * 64;
+            for (int i = threadIdx.x; i < NKC * 4 * 64; i += 64 * MW) cl2[i] = src2[i];
+        }
         __syncthreads();
     }
     // EPI_SOFTSUM, EPI_COTAN: one double per wave of the launch and image
@@ -662,13 +710,17 @@ void log_mfma_kernel(const typename Elem<T>::type* __restrict__ img, int h, int 
     J.partial = partial;
     J.sp_beta = L.beta;
     J.sp_tau = L.tau;
+    if constexpr (DUAL) {
+        J.plane2 = L.aux + bimg * L.out_stride;
+        J.out_scale2 = L.dev_scale[sc.dev_scale_idx2] / in_s;
+    }
     if constexpr (EPI == EPI_COTAN) {
         J.aux = L.aux + bimg * L.out_stride;
         J.sigma = L.sigmas[L.soft_k];
         J.wb = static_cast<float>(static_cast<double>(L.gbar[bimg]) * L.inv_khw) * L.beta;
         J.cmax_word = L.cmax + bimg;
     }
-    run_job<T, NKR, NKC, CTL, SPARSE, EPI>(J, frags + sc.frag_off, threadIdx.x & 63, cl);
+    run_job<T, NKR, NKC, CTL, SPARSE, EPI>(J, frags + sc.frag_off, threadIdx.x & 63, cl, cl2);
 }
 
 // Persistent form over a batch of tiles: every workgroup pulls items (tile,
@@ -1055,7 +1107,8 @@ hipError_t launch_log_mfma_soft(int epi, int nkr, int nkc, const float* img, int
     MHFD_SOFT_CASE(A, EPI_STORE)   \
     MHFD_SOFT_CASE(A, EPI_ACCUM)   \
     MHFD_SOFT_CASE(A, EPI_SOFTSUM) \
-    MHFD_SOFT_CASE(A, EPI_COTAN)
+    MHFD_SOFT_CASE(A, EPI_COTAN)   \
+    MHFD_SOFT_CASE(A, EPI_DUAL)
     MHFD_SOFT_SHAPE(1)
     MHFD_SOFT_SHAPE(2)
     MHFD_SOFT_SHAPE(3)

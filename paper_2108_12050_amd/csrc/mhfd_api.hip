@@ -867,7 +867,7 @@ std::vector<std::pair<int, mhfd::MfmaLaunch>> soft_mfma_launches(const mhfd_plan
                                                                  const mhfd::SoftFragLayout& fl,
                                                                  int b, int h, int w,
                                                                  const std::vector<int>& ks,
-                                                                 int set) {
+                                                                 int set, int set2 = -1) {
     std::vector<std::pair<int, mhfd::MfmaLaunch>> out;
     const int tiles_x = mhfd::mfma_wave_tiles(w);
     const int mw = mhfd::mfma_waves_per_block();
@@ -901,6 +901,11 @@ std::vector<std::pair<int, mhfd::MfmaLaunch>> soft_mfma_launches(const mhfd_plan
             sc.n_blocks = groups_x * ((h + seg - 1) / seg);
             sc.out_scale = 0.0f;
             sc.dev_scale_idx = 4 * k + set;
+            if (set2 >= 0) {  // EPI_DUAL: the second set's columns on the same row pass
+                sc.frag_off2 =
+                    static_cast<int>((fl.off[k] + static_cast<long long>(set2) * fl.halves[k]) / 8);
+                sc.dev_scale_idx2 = 4 * k + set2;
+            }
             begin += sc.n_blocks;
         }
         out.emplace_back(a, L);
@@ -1452,9 +1457,21 @@ mhfd_status mhfd_focus_score_backward(mhfd_plan p, const float* d_imgs, int32_t 
             return hipSuccess;
         };
         // r = sigma^2 Lap I, d = D1 I + D2 I (the sigma-derivative of Lap I)
-        if ((e = run(mhfd::SOFT_FWD, mhfd::EPI_STORE, d_imgs, rpl)) != hipSuccess ||
-            (e = run(mhfd::SOFT_D1, mhfd::EPI_STORE, d_imgs, dpl)) != hipSuccess)
+        if (F.mfma) {
+            // r and D1 from one row pass (same row taps g, h)
+            for (auto& ml : soft_mfma_launches(p, F.fl, b, h, w, one, mhfd::SOFT_FWD,
+                                               mhfd::SOFT_D1)) {
+                mhfd::MfmaLaunch L = ml.second;
+                L.dev_scale = scales;
+                L.aux = dpl;
+                e = mhfd::launch_log_mfma_soft(mhfd::EPI_DUAL, ml.first, ml.first, d_imgs, h, w,
+                                               b, maxbits, frags, L, rpl, s);
+                if (e != hipSuccess) return hip_fail(e, "soft score backward recompute");
+            }
+        } else if ((e = run(mhfd::SOFT_FWD, mhfd::EPI_STORE, d_imgs, rpl)) != hipSuccess ||
+                   (e = run(mhfd::SOFT_D1, mhfd::EPI_STORE, d_imgs, dpl)) != hipSuccess) {
             return hip_fail(e, "soft score backward recompute");
+        }
         if (F.mfma) {
             // D2 on the matrix cores with the cotangent as its epilogue: r <- c
             // in place, sigma partials, max |c| per image for the adjoint

@@ -70,7 +70,7 @@ int log_chunk_rows();
 
 // Where a stack launch writes.  Plane k of image b is at
 // out + b * out_batch + k * plane_stride (row pitch = image width).
-enum { EPI_STORE = 0, EPI_ACCUM = 1, EPI_SOFTSUM = 2, EPI_COTAN = 3 };
+enum { EPI_STORE = 0, EPI_ACCUM = 1, EPI_SOFTSUM = 2, EPI_COTAN = 3, EPI_DUAL = 4 };
 struct StackIO {
     long long img_batch;     // elements between consecutive images of a batch
     float* out;              // EPI_STORE: out = R; EPI_ACCUM: out += R
@@ -122,6 +122,10 @@ struct MfmaScale {
     int seg_rows;     // rows per wave segment (multiple of 16)
     float out_scale;  // exact power of two
     int dev_scale_idx;  // MfmaLaunch::dev_scale: index of the scale's output factor
+    // EPI_DUAL: a second column-tap set on the same row pass (same row
+    // taps), its table and output factor
+    int frag_off2;
+    int dev_scale_idx2;
 };
 
 // Scales sharing one (nkr, nkc) instantiation.
@@ -145,6 +149,8 @@ struct MfmaLaunch {
     // c = w sigma^2, w = gbar[b] inv_khw beta sigmoid(beta (|r| - tau)) sgn r,
     // replaces r in aux; the wave's sum of w (2 r / sigma + sigma^2 d) goes
     // to partial and max |c| of image b to cmax[b] (float bits).
+    // EPI_DUAL: the second column set's output, plane stride 0, images
+    // out_stride apart
     float* aux;
     const float* sigmas;
     int soft_k;
@@ -190,7 +196,8 @@ hipError_t launch_absmax_images(const float* imgs, int batch, int h, int w, uint
                                 hipStream_t s);
 // The matrix-core operator over a batch of dense fp32 images (gridDim.y =
 // batch) with epilogue epi (EPI_STORE / EPI_ACCUM into out, plane stride 0,
-// EPI_SOFTSUM into L.partial, EPI_COTAN as MfmaLaunch describes); maxbits[b]:
+// EPI_SOFTSUM into L.partial, EPI_COTAN as MfmaLaunch describes, EPI_DUAL:
+// the first column set into out and the second into L.aux); maxbits[b]:
 // max |I| word of image b.
 hipError_t launch_log_mfma_soft(int epi, int nkr, int nkc, const float* img, int h, int w,
                                 int batch, const uint32_t* maxbits, const uint16_t* frags,

@@ -1,5 +1,5 @@
-// Soft focus score and its gradient: the kernels around the shared strip
-// kernel.
+// Soft focus score and its gradient: the kernels around the matrix-core
+// (or, for launch radii above its limit, the strip) operator.
 //
 //   S_b = 1/(K H W) sum_k sum_{y,x} softplus(beta (|r_k| - tau)),
 //   r_k = sigma_k^2 Lap(G_sigma_k * I_b).
@@ -8,12 +8,15 @@
 // synthesised here in double (no host round trip), each scale's kernel radius
 // floor(truncate sigma + 0.5) taken from its current sigma, and launched at
 // the padded radius of the plan's sigma cap (taps beyond the radius are
-// zero).  Four tap sets per scale feed the strip
-// kernel, whose operator is hcol (*)_y (grow (*)_x I) + gcol (*)_y (hrow (*)_x I):
+// zero).  Four tap sets per scale, each (grow, hrow, gcol, hcol) for the
+// operator hcol (*)_y (grow (*)_x I) + gcol (*)_y (hrow (*)_x I):
 //   FWD  (g, h, sigma^2 g, sigma^2 h)   r = sigma^2 Lap
-//   D1   (g, h', g, h')                 the sigma-derivative of the Laplacian
-//   D2   (g', h, g', h)                   is D1 + D2 (product rule on
-//                                         h(y) g(x) + g(y) h(x))
+//   D1   (g, h, g', h')                 the sigma-derivative of the Laplacian
+//   D2   (g', h', g, h)                   is D1 + D2 (product rule on
+//                                         h(y) g(x) + g(y) h(x): D1 holds
+//                                         h'(y) g(x) + g'(y) h(x), D2
+//                                         h(y) g'(x) + g(y) h'(x)); D1 has
+//                                         the row taps of FWD
 //   ADJ  (g, h, g, h)                   the Laplacian operator itself, which is
 //                                       its own adjoint under half-sample
 //                                       reflection (each 1-D border-handled
@@ -103,13 +106,13 @@ __global__ __launch_bounds__(64) void soft_taps_kernel(const float* __restrict__
         put(0, 3, s2 * h);
         // D1
         put(1, 0, g);
-        put(1, 1, hd);
-        put(1, 2, g);
+        put(1, 1, h);
+        put(1, 2, gd);
         put(1, 3, hd);
         // D2
         put(2, 0, gd);
-        put(2, 1, h);
-        put(2, 2, gd);
+        put(2, 1, hd);
+        put(2, 2, g);
         put(2, 3, h);
         // ADJ
         put(3, 0, g);

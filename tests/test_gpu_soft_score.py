@@ -249,3 +249,25 @@ def test_default_halos_follow_the_plan_radii():
     np.testing.assert_allclose(ds.cpu().numpy(), ds_o, rtol=0, atol=1e-4 * np.abs(ds_o).max())
     with pytest.raises(MHFDError):   # radius 5 > halo 4
         plan.focus_score(to_dev(img), to_dev(np.float32([1.2, 2.0, 3.0])), BETA, TAU)
+
+
+def test_vector_path_beyond_the_matrix_core_radius():
+    """A sigma cap whose radius (60) exceeds the matrix cores' limit (56)
+    sends every scale to the vector strip kernel with the same four tap sets:
+    score, sigma gradient and image gradient against the oracle, at sigmas
+    off the plan grid."""
+    B, H, W = 2, 70, 66
+    sig0 = [2.0, 5.0, 9.0]
+    plan = make_plan(sig0, H, W, sigma_cap=15.0)
+    sig32 = np.float32([2.3, 4.6, 9.7])
+    imgs = np.stack([synth.blob_field(30 + b, H, W, n_blobs=5) for b in range(B)])
+    gbar = np.float32([1.0, -0.7])
+    g = plan.focus_score(to_dev(imgs), to_dev(sig32), BETA, TAU).cpu().numpy()
+    np.testing.assert_allclose(g, oracle.soft_score(imgs.astype(np.float64), np.float64(sig32),
+                                                    BETA, TAU), rtol=1e-5, atol=0)
+    dI, ds = plan.focus_score_backward(to_dev(imgs), to_dev(sig32), to_dev(gbar), BETA, TAU)
+    dI, ds = dI.cpu().numpy().astype(np.float64), ds.cpu().numpy().astype(np.float64)
+    dI_o, ds_o = oracle.soft_score_grad(imgs.astype(np.float64), np.float64(sig32), BETA, TAU,
+                                        gbar.astype(np.float64))
+    np.testing.assert_allclose(ds, ds_o, rtol=0, atol=1e-4 * np.abs(ds_o).max())
+    check_image_grad(dI, dI_o, imgs, np.float64(sig32), gbar)
