@@ -88,7 +88,7 @@ __global__ __launch_bounds__(SETUP_T) void batch_setup_kernel(
     __syncthreads();
     const int per = (n + SETUP_T - 1) / SETUP_T;
     const int t0 = min(n, static_cast<int>(threadIdx.x) * per), t1 = min(n, t0 + per);
-    long long items = 0, nms = 0, pix = 0, mitems = 0, nitems = 0, sfl = 0, acw = 0;
+    long long items = 0, nms = 0, pix = 0, mitems = 0, nitems = 0, sfl = 0, acw = 0, nitems1 = 0;
     for (int t = t0; t < t1; ++t) {
         const mhfd_tile d = in[t];
         bool ok = d.img && d.result && d.h >= 1 && d.w >= 1 && d.h <= max_h && d.w <= max_w &&
@@ -121,6 +121,7 @@ __global__ __launch_bounds__(SETUP_T) void batch_setup_kernel(
         items += static_cast<long long>(bt.strips) * bt.segs;
         nms += static_cast<long long>(bt.h) * bt.bpr;
         nitems += static_cast<long long>(nms_runs(bt.h)) * bt.bpr;
+        if (bt.nms_cw == 1) nitems1 += static_cast<long long>(nms_runs(bt.h)) * bt.bpr;
         pix += static_cast<long long>(bt.h) * bt.w;
         sfl += stack_floats(bt.h, bt.w, K);
         acw += act_words(bt.h, bt.w, K);
@@ -132,8 +133,9 @@ __global__ __launch_bounds__(SETUP_T) void batch_setup_kernel(
     const long long b_mitems = block_exclusive_scan(mitems, shl, &tot_mitems);
     const long long b_nitems = block_exclusive_scan(nitems, shl, &tot_nitems);
     const long long b_sfl = block_exclusive_scan(sfl, shl, &tot_sfl);
-    long long tot_acw;
+    long long tot_acw, tot_nitems1;
     const long long b_acw = block_exclusive_scan(acw, shl, &tot_acw);
+    (void)block_exclusive_scan(nitems1, shl, &tot_nitems1);
     (void)b_pix;
     (void)tot_sfl;
     (void)tot_acw;
@@ -161,6 +163,7 @@ __global__ __launch_bounds__(SETUP_T) void batch_setup_kernel(
         ctr->items_per_scale = valid ? static_cast<int>(tot_items) : 0;
         ctr->nms_blocks = valid ? static_cast<int>(tot_nms) : 0;
         ctr->nms_items = valid ? static_cast<int>(tot_nitems) : 0;
+        ctr->nms_items1 = valid ? static_cast<int>(tot_nitems1) : 0;
         ctr->valid = valid ? 1 : 0;
         ctr->pool_used = 0;
         ctr->flags = 0;
@@ -200,6 +203,10 @@ __global__ __launch_bounds__(64 * NMS_WAVES) void nms_batch_kernel(
     const uint64_t* __restrict__ act) {
     const int total = ctr->nms_items;
     const int n_waves = gridDim.x * NMS_WAVES;
+    // nothing for this width: leave at once (the pass for the other width,
+    // or both when the batch is invalid)
+    const int mine = CW == 1 ? ctr->nms_items1 : total - ctr->nms_items1;
+    if (mine == 0) return;
     // wave-uniform (readfirstlane), so the tile fields come in scalar
     // registers rather than in every lane's
     const int wave0 = __builtin_amdgcn_readfirstlane(blockIdx.x * NMS_WAVES + (threadIdx.x >> 6));

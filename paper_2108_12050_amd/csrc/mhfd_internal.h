@@ -305,7 +305,8 @@ inline long long batch_act_words(int K, int n, long long max_pixels, int max_h, 
 struct BatchCounters {
     int32_t items_per_scale;  // sum over tiles of strips * segs
     int32_t nms_blocks;       // sum over tiles of h * bpr (maxima cells)
-    int32_t nms_items;        // sum over tiles of ceil(h / 32) * bpr (maxima waves)
+    int32_t nms_items;        // sum over tiles of ceil(h / 16) * bpr (maxima waves)
+    int32_t nms_items1;       // the part of nms_items from tiles with one column per lane
     int32_t valid;            // 1 when every descriptor passed the checks
     int32_t pool_used;
     int32_t flags;
