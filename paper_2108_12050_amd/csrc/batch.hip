@@ -88,7 +88,7 @@ __global__ __launch_bounds__(SETUP_T) void batch_setup_kernel(
     __syncthreads();
     const int per = (n + SETUP_T - 1) / SETUP_T;
     const int t0 = min(n, static_cast<int>(threadIdx.x) * per), t1 = min(n, t0 + per);
-    long long items = 0, nms = 0, pix = 0, mitems = 0, nitems = 0, sfl = 0, acw = 0, nitems1 = 0;
+    long long items = 0, nms = 0, pix = 0, mitems = 0, nitems = 0, sfl = 0, acw = 0;
     for (int t = t0; t < t1; ++t) {
         const mhfd_tile d = in[t];
         bool ok = d.img && d.result && d.h >= 1 && d.w >= 1 && d.h <= max_h && d.w <= max_w &&
@@ -121,7 +121,6 @@ __global__ __launch_bounds__(SETUP_T) void batch_setup_kernel(
         items += static_cast<long long>(bt.strips) * bt.segs;
         nms += static_cast<long long>(bt.h) * bt.bpr;
         nitems += static_cast<long long>(nms_runs(bt.h)) * bt.bpr;
-        if (bt.nms_cw == 1) nitems1 += static_cast<long long>(nms_runs(bt.h)) * bt.bpr;
         pix += static_cast<long long>(bt.h) * bt.w;
         sfl += stack_floats(bt.h, bt.w, K);
         acw += act_words(bt.h, bt.w, K);
@@ -133,9 +132,8 @@ __global__ __launch_bounds__(SETUP_T) void batch_setup_kernel(
     const long long b_mitems = block_exclusive_scan(mitems, shl, &tot_mitems);
     const long long b_nitems = block_exclusive_scan(nitems, shl, &tot_nitems);
     const long long b_sfl = block_exclusive_scan(sfl, shl, &tot_sfl);
-    long long tot_acw, tot_nitems1;
+    long long tot_acw;
     const long long b_acw = block_exclusive_scan(acw, shl, &tot_acw);
-    (void)block_exclusive_scan(nitems1, shl, &tot_nitems1);
     (void)b_pix;
     (void)tot_sfl;
     (void)tot_acw;
@@ -163,7 +161,6 @@ __global__ __launch_bounds__(SETUP_T) void batch_setup_kernel(
         ctr->items_per_scale = valid ? static_cast<int>(tot_items) : 0;
         ctr->nms_blocks = valid ? static_cast<int>(tot_nms) : 0;
         ctr->nms_items = valid ? static_cast<int>(tot_nitems) : 0;
-        ctr->nms_items1 = valid ? static_cast<int>(tot_nitems1) : 0;
         ctr->valid = valid ? 1 : 0;
         ctr->pool_used = 0;
         ctr->flags = 0;
@@ -190,12 +187,10 @@ __global__ __launch_bounds__(SETUP_T) void batch_setup_kernel(
 // Persistent maxima waves over every tile's (run of nms::ROWS rows, strip of
 // 64 nms_cw columns) items, the per-wave body of the single-tile pass; the
 // tile index rides in the upper bits of every record's k.
-//
-// One kernel per lane width CW: each takes the items of the tiles with
-// nms_cw == CW and skips the others, so each is compiled for its own width
-// alone (one kernel holding both needed more registers than either, and ran
-// fewer waves per SIMD).
-template <int K, int CW, bool SPARSE>
+// Every index a wave derives its tile and cell from is wave-uniform
+// (readfirstlane), so that bookkeeping stays in scalar registers: without it
+// the kernel held 190 vector registers, with it 149 (three waves per SIMD).
+template <int K, bool SPARSE>
 __global__ __launch_bounds__(64 * NMS_WAVES) void nms_batch_kernel(
     const float* __restrict__ stack, const BatchTile* __restrict__ tiles, int n_tiles, float tau,
     int n_blk_bound, int32_t* __restrict__ blk_n, int32_t* __restrict__ blk_o,
@@ -203,10 +198,7 @@ __global__ __launch_bounds__(64 * NMS_WAVES) void nms_batch_kernel(
     const uint64_t* __restrict__ act) {
     const int total = ctr->nms_items;
     const int n_waves = gridDim.x * NMS_WAVES;
-    // nothing for this width: leave at once (the pass for the other width,
-    // or both when the batch is invalid)
-    const int mine = CW == 1 ? ctr->nms_items1 : total - ctr->nms_items1;
-    if (mine == 0) return;
+
     // wave-uniform (readfirstlane), so the tile fields come in scalar
     // registers rather than in every lane's
     const int wave0 = __builtin_amdgcn_readfirstlane(blockIdx.x * NMS_WAVES + (threadIdx.x >> 6));
@@ -227,7 +219,7 @@ __global__ __launch_bounds__(64 * NMS_WAVES) void nms_batch_kernel(
     for (int item = wave0; item < total; item += n_waves) {
         while (lo + 1 < n_tiles && tiles[lo + 1].nitem_base <= item) ++lo;
         const BatchTile& T = tiles[lo];
-        if (T.nms_cw != CW) continue;
+
         const int local = item - T.nitem_base;
         const int run = local / T.bpr, strip = local - run * T.bpr;
         nms::Sink out;
@@ -241,7 +233,13 @@ __global__ __launch_bounds__(64 * NMS_WAVES) void nms_batch_kernel(
         out.k_tag = lo << TILE_SHIFT;
         const float* st = stack + T.stack_off;
         const nms::Active a{SPARSE ? act + T.act_off : nullptr, (T.w + 15) / 16, (T.h + 15) / 16};
-        nms::wave<K, CW, SLOT, SPARSE>(st, T.h, T.w, tau, T.bpr, strip, run, out, a);
+        if constexpr (2 * K <= 32) {
+            if (T.nms_cw == 2) {
+                nms::wave<K, 2, SLOT, SPARSE>(st, T.h, T.w, tau, T.bpr, strip, run, out, a);
+                continue;
+            }
+        }
+        nms::wave<K, 1, SLOT, SPARSE>(st, T.h, T.w, tau, T.bpr, strip, run, out, a);
     }
 }
 
@@ -369,24 +367,16 @@ __global__ void results_batch_kernel(const int32_t* __restrict__ blk_off,
     }
 }
 
-template <int K, int CW>
-void launch_nms_batch_cw(const BatchLaunchArgs& a, hipStream_t s) {
+template <int K>
+void launch_nms_batch_k(const BatchLaunchArgs& a, hipStream_t s) {
     if (a.act)
-        nms_batch_kernel<K, CW, true><<<a.nms_grid, 64 * NMS_WAVES, 0, s>>>(
+        nms_batch_kernel<K, true><<<a.nms_grid, 64 * NMS_WAVES, 0, s>>>(
             a.stack, a.tiles, a.n_tiles, a.tau, a.n_blk_bound, a.blk_n, a.blk_o, a.pool, a.cap,
             a.ctr, a.act);
     else
-        nms_batch_kernel<K, CW, false><<<a.nms_grid, 64 * NMS_WAVES, 0, s>>>(
+        nms_batch_kernel<K, false><<<a.nms_grid, 64 * NMS_WAVES, 0, s>>>(
             a.stack, a.tiles, a.n_tiles, a.tau, a.n_blk_bound, a.blk_n, a.blk_o, a.pool, a.cap,
             a.ctr, a.act);
-}
-
-// Two columns per lane for the tiles that allow it (even widths, K <= 16),
-// then one for the rest (an empty pass when there is none).
-template <int K>
-void launch_nms_batch_k(const BatchLaunchArgs& a, hipStream_t s) {
-    if constexpr (K <= 16) launch_nms_batch_cw<K, 2>(a, s);
-    launch_nms_batch_cw<K, 1>(a, s);
 }
 
 template <int... Ks>

@@ -306,7 +306,6 @@ struct BatchCounters {
     int32_t items_per_scale;  // sum over tiles of strips * segs
     int32_t nms_blocks;       // sum over tiles of h * bpr (maxima cells)
     int32_t nms_items;        // sum over tiles of ceil(h / 16) * bpr (maxima waves)
-    int32_t nms_items1;       // the part of nms_items from tiles with one column per lane
     int32_t valid;            // 1 when every descriptor passed the checks
     int32_t pool_used;
     int32_t flags;
