@@ -220,9 +220,9 @@ mhfd_status mhfd_detect(mhfd_plan plan, const void *d_img, int32_t h, int32_t w,
  * Bytes of device scratch mhfd_log_stack needs for an h x w image (0 on bad
  * input, and for 8-bit plans without the stretch, which need none).  fp32
  * plans keep one word: the image's max |I|, from which the matrix-core
- * kernels take an exact power-of-two input scale.  Stretch plans keep the
- * 256-bin histogram and the two levels (258 words).  FFT plans keep three
- * h x w float transform buffers.
+ * kernels take an exact power-of-two input scale.  Stretch plans keep eight
+ * copies of the 256-bin histogram and the two levels (2050 words).  FFT plans
+ * keep three h x w float transform buffers.
  */
 size_t mhfd_log_stack_workspace_size(mhfd_plan plan, int32_t h, int32_t w);
 
@@ -242,7 +242,8 @@ mhfd_status mhfd_log_stack(mhfd_plan plan, const void *d_img, int32_t h, int32_t
  * mhfd_log_stack without a workspace, for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc).  The call's scratch (the fp32 range word,
- * or the stretch histogram and levels: at most MHFD_STATIC_SCRATCH_BYTES) is
+ * or the stretch histogram copies and levels, 8200 bytes: at most
+ * MHFD_STATIC_SCRATCH_BYTES) is
  * a static array of the library, one per device, kept until the process
  * ends; the call allocates nothing.  Every call on a device shares that
  * array: calls that overlap in time on one device (on different streams, or
@@ -251,7 +252,7 @@ mhfd_status mhfd_log_stack(mhfd_plan plan, const void *d_img, int32_t h, int32_t
  * mhfd_log_stack, plus MHFD_ERR_UNSUPPORTED if the plan needed more scratch
  * than the array holds.
  */
-#define MHFD_STATIC_SCRATCH_BYTES 2048
+#define MHFD_STATIC_SCRATCH_BYTES 16384
 mhfd_status mhfd_log_stack_static(mhfd_plan plan, const void *d_img, int32_t h, int32_t w,
                                   int64_t pitch, float *d_stack, void *stream);
 
@@ -267,7 +268,9 @@ mhfd_status mhfd_log_stack_static(mhfd_plan plan, const void *d_img, int32_t h, 
  *   d_levels  2 int32, receives {low, high}.
  * Device pointers, caller-owned; enqueued on `stream` (the current device's
  * compute units size the launch).  No plan and no workspace: the outputs are
- * the scratch.  Errors: MHFD_ERR_INVALID_ARG for null pointers or bad sizes,
+ * the scratch, so every workgroup adds its counts to the one d_hist (the
+ * detector's own stretch pass spreads them over eight copies in its
+ * workspace, a few microseconds faster on a 4096 x 4096 tile).  Errors: MHFD_ERR_INVALID_ARG for null pointers or bad sizes,
  * MHFD_ERR_UNSUPPORTED above 2^31 - 1 pixels, MHFD_ERR_HIP for launch
  * failures; nothing is enqueued on error.
  */

@@ -20,6 +20,8 @@
 // hipGetSymbolAddress returns for the current device (looked up once per
 // device when a plan is created there).
 static __device__ __align__(256) uint32_t scratch[MHFD_STATIC_SCRATCH_BYTES / sizeof(uint32_t)];
+static_assert(sizeof(int32_t) * (256 * mhfd::STRETCH_COPIES + 2) <= MHFD_STATIC_SCRATCH_BYTES,
+              "the stretch histogram copies fit the static scratch");
 
 namespace {
 
@@ -173,7 +175,7 @@ int max_overlapping_d2(double ra, double rb, double theta) {
 
 size_t log_stack_scratch_bytes(const mhfd_plan_s* p, int h, int w) {
     if (p->blur == MHFD_BLUR_FFT) return sizeof(float) * mhfd::fft_workspace_floats(h, w);
-    if (p->stretch) return sizeof(int32_t) * (256 + 2);
+    if (p->stretch) return sizeof(int32_t) * (256 * mhfd::STRETCH_COPIES + 2);
     return (p->d_frags && p->dtype == MHFD_F32) ? sizeof(uint32_t) : 0;
 }
 
@@ -744,8 +746,8 @@ std::vector<std::pair<std::pair<int, int>, mhfd::MfmaLaunch>> mfma_launches(cons
 }
 
 // Bytes of scratch the stack needs: the max |I| word of fp32 plans with
-// matrix-core scales; the 256-bin histogram and the two levels of stretch
-// plans.
+// matrix-core scales; the global copies of the 256-bin histogram and the two
+// levels of stretch plans.
 size_t log_stack_scratch(const mhfd_plan_s* p, int h, int w) {
     return log_stack_scratch_bytes(p, h, w);
 }
@@ -763,7 +765,7 @@ mhfd_status enqueue_log_stack(const mhfd_plan_s* p, const void* d_img, int h, in
     for (int k = 0; k < p->K; ++k)
         if (p->mfma_off.empty() || p->mfma_off[k] < 0) strip_scales.push_back(k);
     const auto mls = mfma_launches(p, h, w);
-    // fp32: max |I| word; stretch: histogram (256 counts), then {low, high}
+    // fp32: max |I| word; stretch: histogram copies (8 x 256 counts), then {low, high}
     const uint32_t* range = nullptr;
     if (!mls.empty() && p->dtype == MHFD_F32) {
         hipError_t e = mhfd::launch_absmax(static_cast<const float*>(d_img), h, w, pitch, maxbits, s);
@@ -771,11 +773,13 @@ mhfd_status enqueue_log_stack(const mhfd_plan_s* p, const void* d_img, int h, in
         range = maxbits;
     }
     if (p->stretch) {
-        int32_t* hist = reinterpret_cast<int32_t*>(maxbits);
+        int32_t* copies = reinterpret_cast<int32_t*>(maxbits);
+        int32_t* levels = copies + 256 * mhfd::STRETCH_COPIES;
         hipError_t e = mhfd::launch_stretch_levels(static_cast<const uint8_t*>(d_img), h, w, pitch,
-                                                   hist, hist + 256, p->n_cu, s);
+                                                   copies, mhfd::STRETCH_COPIES, nullptr, levels,
+                                                   p->n_cu, s);
         if (e != hipSuccess) return hip_fail(e, "histogram stretch levels");
-        range = reinterpret_cast<const uint32_t*>(hist + 256);
+        range = reinterpret_cast<const uint32_t*>(levels);
     }
     for (const auto& ml : mls) {
         hipError_t e = mhfd::launch_log_mfma(p->dtype, p->stretch, ml.first.first, ml.first.second,
@@ -1102,7 +1106,7 @@ mhfd_status mhfd_stretch_levels(const uint8_t* d_img, int32_t h, int32_t w, int6
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess)
-        e = mhfd::launch_stretch_levels(d_img, h, w, pitch, d_hist, d_levels, n_cu,
+        e = mhfd::launch_stretch_levels(d_img, h, w, pitch, d_hist, 1, nullptr, d_levels, n_cu,
                                         static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "histogram stretch levels");
     return MHFD_OK;

@@ -184,10 +184,15 @@ hipError_t launch_dog(const float* L, int K, const float* sigmas_dev, int h, int
                       uint8_t* arg, hipStream_t s);
 hipError_t launch_dog_label(mhfd_blob* blobs, int capacity, const mhfd_result* result,
                             const uint8_t* arg, int w, const float* sigmas_dev, hipStream_t s);
-// Histogram stretch of an 8-bit image: hist[256] counts (zeroed first), then
-// levels[0] = low, levels[1] = high.
+// Histogram stretch of an 8-bit image: the counts go to n_copies global
+// histograms copies[n_copies][256] (zeroed first, 1 <= n_copies <=
+// STRETCH_MAX_COPIES), then levels[0] = low, levels[1] = high and, when hist
+// is not null, hist[256] = the summed counts (hist may not alias copies).
+constexpr int STRETCH_COPIES = 8;
+constexpr int STRETCH_MAX_COPIES = 64;
 hipError_t launch_stretch_levels(const uint8_t* img, int h, int w, long long pitch,
-                                 int32_t* hist, int32_t* levels, int n_cu, hipStream_t s);
+                                 int32_t* copies, int n_copies, int32_t* hist, int32_t* levels,
+                                 int n_cu, hipStream_t s);
 // *bits = float bits of max |I| over an fp32 image (zeroed first).
 hipError_t launch_absmax(const float* img, int h, int w, int64_t pitch, uint32_t* bits,
                          hipStream_t s);
