@@ -62,10 +62,16 @@ struct Slot {
     half4_t ah, al, bh, bl;
 };
 
-__device__ __forceinline__ void split(float4_t v, half4_t& hi, half4_t& lo) {
+// lo = the FP16 rounding of v - hi, formed as one mixed-precision FMA per
+// value (hi * neg1 + v with hi read as FP16, rounded once), which is the
+// rounding of the exact remainder.  neg1 = -1 arrives as an opaque register:
+// with a literal -1 the product folds into a subtraction and the FMA is lost
+// (two conversions and a subtraction per value).
+__device__ __forceinline__ void split(float4_t v, half4_t& hi, half4_t& lo, float neg1) {
     hi = __builtin_convertvector(v, half4_t);
-    const float4_t r = v - __builtin_convertvector(hi, float4_t);  // exact in FP32
-    lo = __builtin_convertvector(r, half4_t);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        lo[i] = static_cast<_Float16>(__builtin_fmaf(static_cast<float>(hi[i]), neg1, v[i]));
 }
 
 __device__ __forceinline__ half8_t cat(half4_t a, half4_t b) {
@@ -100,6 +106,7 @@ struct WaveJob {
     int aligned;      // rows aligned for whole 8-element group loads
     int out_vec;      // 16-byte aligned output rows and w % 4 == 0
     float in_scale;   // fp32 input: exact power of two applied before the split
+    float neg1;       // -1, opaque to the compiler (split)
     float out_scale;  // exact power of two (times 255 / (high - low) when stretched)
     uint32_t s_lo, s_hi, s_nlo;  // stretched u8 input: 1024 + low, 1024 + high,
                                  // -(1024 + low), each as an FP16 pair
@@ -164,11 +171,15 @@ __device__ __forceinline__ float input_scale(uint32_t maxbits) {
 // and ring length NS (intermediate blocks held: at least the 2 nkc the
 // column pass reads, rounded up to a multiple of D so that ring and prefetch
 // slots repeat together).
-// Measured on 4096^2 u8 tiles: depth 4 with the peeled loop below pays for
-// nkc = 1 (11% faster); for nkc = 2 it was 10% slower, and for nkc >= 3 the
-// extra registers spill.
+// Measured on 4096^2 tiles: depth 4 with the peeled loop below pays for
+// nkc = 1 (11% faster); for 8-bit inputs with nkc = 2, depth 4 (4 more
+// registers per block of rows) is 4-5% faster than 2, for fp32 inputs 3%
+// slower; for nkc = 3 depth 3 (ring unchanged) was no faster, and depth 4
+// (ring of 8) spills.
 template <typename T, int NKC>
-constexpr int mfma_depth() { return NKC == 1 ? 4 : 2; }
+constexpr int mfma_depth() {
+    return NKC == 1 ? 4 : (NKC == 2 && sizeof(typename Elem<T>::type) == 1 ? 4 : 2);
+}
 // Whether the first ring turn is peeled off the main loop.
 template <typename T, int NKC>
 constexpr bool mfma_peel() { return NKC == 1; }
@@ -183,9 +194,12 @@ __device__ __forceinline__ bool regular_job(const WaveJob& J) {
     const int xw = J.x0 - J.rw8;
     // rows touched: y0 - rwc ... y1 - rwc + 16 (NS - 1 + D) (ring and
     // prefetch overrun), reflected once at most
+    // offsets formed with 24-bit multiplies: rows, widths and pitches below
+    // 2^24, every input offset below 2^32 (output planes hold < 2^29 pixels)
     return J.aligned && J.out_vec && (J.w & 7) == 0 && J.x0 + 16 <= J.w && xw >= -J.w &&
            xw + 32 * NKR <= 2 * J.w && J.h >= J.rwc + 16 * (NS + D + 1) &&
-           ((J.y1 - J.y0) & 15) == 0;
+           ((J.y1 - J.y0) & 15) == 0 && J.h < (1 << 24) && J.w < (1 << 24) &&
+           J.pitch < (1 << 24) && static_cast<long long>(J.h) * J.pitch <= 0xFFFFFFFFLL;
 }
 
 // Input group of 8 elements per lane and K-block: the raw registers and
@@ -260,8 +274,8 @@ struct Input<float> {
     }
     __device__ static void convert(Raw v, const WaveJob& J, half8_t& hi, half8_t& lo) {
         half4_t h0, l0, h1, l1;
-        split(v.a * J.in_scale, h0, l0);
-        split(v.b * J.in_scale, h1, l1);
+        split(v.a * J.in_scale, h0, l0, J.neg1);
+        split(v.b * J.in_scale, h1, l1, J.neg1);
         hi = cat(h0, h1);
         lo = cat(l0, l1);
     }
@@ -355,7 +369,9 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
             const int r0 = yr ^ (yr >> 31);
             r = min(r0, 2 * h - 1 - r0);
         }
-        const E* row = img + static_cast<long long>(r) * J.pitch;
+        const E* row = EDGE ? img + static_cast<long long>(r) * J.pitch
+                            : img + __umul24(static_cast<unsigned>(r),
+                                             static_cast<unsigned>(J.pitch));
         if (INNER) {
             const E* base = row + xw + 8 * g;
 #pragma unroll
@@ -403,16 +419,25 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
                 b = mfma16(in_lo[kb], rt[kb][2], b);
             }
         }
-        split(a, out.ah, out.al);
-        split(b, out.bh, out.bl);
+        split(a, out.ah, out.al, J.neg1);
+        split(b, out.bh, out.bl, J.neg1);
     };
 
     const bool vec = !EDGE || (J.out_vec && x0 + 16 <= w);
+    // element offset of (y, x0 + 4 g) in an output plane (regular jobs: a
+    // full-rate 24-bit multiply instead of 64-bit arithmetic)
+    auto opix = [&](int y) -> long long {
+        if constexpr (EDGE)
+            return static_cast<long long>(y) * w + x0 + 4 * g;
+        else
+            return __umul24(static_cast<unsigned>(y), static_cast<unsigned>(w)) +
+                   static_cast<unsigned>(x0 + 4 * g);
+    };
     // dense store of one output block row to `plane` (EPI_DUAL)
     auto put = [&](float* plane, int t, float4_t v) {
         const int y = y0 + 16 * t + c;
         if (EDGE && y >= y1) return;
-        float* o = plane + static_cast<long long>(y) * w + x0 + 4 * g;
+        float* o = plane + opix(y);
         if (vec) {
             *reinterpret_cast<float4_t*>(o) = v;
         } else {
@@ -428,7 +453,7 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
         const int y = y0 + 16 * t + c;
         if constexpr (EPI == EPI_COTAN) {
             if (EDGE && y >= y1) return;
-            const long long at = static_cast<long long>(y) * w + x0 + 4 * g;
+            const long long at = opix(y);
             const float s2 = J.sigma * J.sigma;
             const double inv_s = 1.0 / static_cast<double>(J.sigma);
             auto one = [&](float dv, float& rv) {  // rv: r in, c out
@@ -477,7 +502,7 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
             if (!a) return;
         }
         if (EDGE && y >= y1) return;
-        float* o = J.plane + static_cast<long long>(y) * w + x0 + 4 * g;
+        float* o = J.plane + opix(y);
         if constexpr (EPI == EPI_ACCUM) {  // o += v
             if (vec) {
                 *reinterpret_cast<float4_t*>(o) = *reinterpret_cast<const float4_t*>(o) + v;
@@ -678,6 +703,8 @@ void log_mfma_kernel(const typename Elem<T>::type* __restrict__ img, int h, int 
     // fp32: maxbits = max |I| bits; stretched u8: maxbits = {low, high}
     float in_s = 1.0f, stretch = 1.0f;
     WaveJob J;
+    J.neg1 = -1.0f;
+    asm volatile("" : "+s"(J.neg1));
     J.s_lo = J.s_hi = 0x64006400u;
     J.s_nlo = 0xE400E400u;
     if constexpr (std::is_same<T, U8Stretch>::value) {
@@ -777,6 +804,8 @@ void log_mfma_batch_kernel(int n_tiles, const BatchTile* __restrict__ tiles,
         if (wcol >= t.mtiles_x) continue;
         const float in_s = maxbits ? input_scale(maxbits[lo]) : 1.0f;
         WaveJob J;
+        J.neg1 = -1.0f;
+        asm volatile("" : "+s"(J.neg1));
         J.img = t.img;
         J.pitch = t.pitch;
         J.h = t.h;
