@@ -449,26 +449,49 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
     float tsum = 0.0f;  // EPI_SOFTSUM: this lane's softplus sum
     double gsum = 0.0;  // EPI_COTAN: this lane's sigma-gradient sum
     float cmx = 0.0f;   // EPI_COTAN: this lane's max |c|
-    auto store = [&](int t, float4_t v) {
+    const float cot_s2 = J.sigma * J.sigma, cot_2is = 2.0f / J.sigma;  // EPI_COTAN
+    // Inputs of the read-modify-write epilogues (EPI_COTAN: the D1 plane and
+    // r; EPI_ACCUM: the plane), loaded when the block's step starts so that
+    // the block's MFMA work covers their latency (vector rows only; the
+    // general path reads them at the store).
+    struct EpiIn {
+        float4_t a, b;
+    };
+    auto epi_load = [&](int t) {
+        EpiIn e;
+        if constexpr (EPI == EPI_COTAN || EPI == EPI_ACCUM) {
+            const int y = y0 + 16 * t + c;
+            if (vec && (!EDGE || y < y1)) {
+                const long long at = opix(y);
+                e.a = *reinterpret_cast<const float4_t*>(J.plane + at);
+                if constexpr (EPI == EPI_COTAN) e.b = *reinterpret_cast<const float4_t*>(J.aux + at);
+            }
+        }
+        return e;
+    };
+    auto store = [&](int t, float4_t v, const EpiIn& e) {
         const int y = y0 + 16 * t + c;
         if constexpr (EPI == EPI_COTAN) {
             if (EDGE && y >= y1) return;
             const long long at = opix(y);
-            const float s2 = J.sigma * J.sigma;
-            const double inv_s = 1.0 / static_cast<double>(J.sigma);
+            // Per value: w = wb sigmoid(z) sgn(r) (sigmoid through the hardware
+            // exp and reciprocal, about 1 ulp each), the sigma partial
+            // w (2 r / sigma + sigma^2 d) in FP32, summed over the lane's four
+            // values and added to the FP64 sum once per block.  The partials'
+            // inputs r and d carry FP32 rounding already, so FP64 arithmetic
+            // per value (twice the issue cost) would add no accuracy.
+            float part = 0.0f;
             auto one = [&](float dv, float& rv) {  // rv: r in, c out
                 const float z = J.sp_beta * (fabsf(rv) - J.sp_tau);
-                const float sig = 1.0f / (1.0f + __expf(-z));
-                const float sgn = rv > 0.0f ? 1.0f : (rv < 0.0f ? -1.0f : 0.0f);
-                const float wv = J.wb * sig * sgn;
-                gsum += static_cast<double>(wv) * (2.0 * static_cast<double>(rv) * inv_s +
-                                                   static_cast<double>(s2) * static_cast<double>(dv));
-                rv = wv * s2;
+                const float m = J.wb * __builtin_amdgcn_rcpf(1.0f + __expf(-z));
+                const float wv = rv > 0.0f ? m : (rv < 0.0f ? -m : 0.0f);
+                part += wv * (cot_2is * rv + cot_s2 * dv);
+                rv = wv * cot_s2;
                 cmx = fmaxf(cmx, fabsf(rv));
             };
             if (vec) {
-                const float4_t d1 = *reinterpret_cast<const float4_t*>(J.plane + at);
-                float4_t r = *reinterpret_cast<const float4_t*>(J.aux + at);
+                const float4_t d1 = e.a;
+                float4_t r = e.b;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     float rv = r[i];
@@ -481,6 +504,7 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
                 for (int i = 0; i < 4; ++i)
                     if (x0 + 4 * g + i < w) one(J.plane[at + i] + v[i], J.aux[at + i]);
             }
+            gsum += static_cast<double>(part);
             return;
         }
         if constexpr (EPI == EPI_SOFTSUM) {
@@ -505,7 +529,7 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
         float* o = J.plane + opix(y);
         if constexpr (EPI == EPI_ACCUM) {  // o += v
             if (vec) {
-                *reinterpret_cast<float4_t*>(o) = *reinterpret_cast<const float4_t*>(o) + v;
+                *reinterpret_cast<float4_t*>(o) = e.a + v;
             } else {
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
@@ -534,6 +558,7 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
     for (int p = 0; p < NS - 1; ++p) rowpass(p, raw[p % D], ring[p]);
     // Output block t at ring position p (= t mod NS).
     auto step = [&](int t, int p) {
+        const EpiIn ein = epi_load(t);
         rowpass(t + NS - 1, raw[(p + NS - 1) % D], ring[(p + NS - 1) % NS]);
         float4_t ra = {0.f, 0.f, 0.f, 0.f}, rb = {0.f, 0.f, 0.f, 0.f};
         // LDS form: an opaque lane offset per block keeps the reads in the
@@ -579,7 +604,7 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
             put(J.plane, t, (ra + rb) * J.out_scale);
             put(J.plane2, t, (ra2 + rb2) * J.out_scale2);
         } else {
-            store(t, (ra + rb) * J.out_scale);
+            store(t, (ra + rb) * J.out_scale, ein);
         }
     };
     if constexpr (mfma_peel<T, NKC>()) {
