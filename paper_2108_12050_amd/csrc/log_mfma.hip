@@ -128,12 +128,6 @@ struct WaveJob {
     float out_scale2;
 };
 
-// softplus(z) = max(z, 0) + log(1 + e^{-|z|}) on the hardware exp2 / log2
-// (absolute error a few 1e-8 per value, against summands of order 0.1).
-__device__ __forceinline__ float softplus_f(float z) {
-    return fmaxf(z, 0.0f) + __logf(1.0f + __expf(-fabsf(z)));
-}
-
 // 8-bit input with the histogram stretch applied as it is read (stretch.hip):
 // codes clamped to [low, high], minus low.
 struct U8Stretch {};
@@ -508,10 +502,21 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
             return;
         }
         if constexpr (EPI == EPI_SOFTSUM) {
+            // softplus(z) = max(z, 0) + log(1 + e^{-|z|}); the lane's four
+            // log terms as one logarithm of their product (each factor in
+            // (1, 2], the product at most 16): one hardware log2 instead of
+            // four (quarter-rate instructions)
             if (!EDGE || y < y1) {
+                float lin = 0.0f, prod = 1.0f;
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    if (!EDGE || x0 + 4 * g + i < w) tsum += softplus_f(J.sp_beta * (fabsf(v[i]) - J.sp_tau));
+                for (int i = 0; i < 4; ++i) {
+                    if (!EDGE || x0 + 4 * g + i < w) {
+                        const float z = J.sp_beta * (fabsf(v[i]) - J.sp_tau);
+                        lin += fmaxf(z, 0.0f);
+                        prod *= 1.0f + __expf(-fabsf(z));
+                    }
+                }
+                tsum += lin + __logf(prod);
             }
             return;
         }
