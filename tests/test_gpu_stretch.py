@@ -73,6 +73,20 @@ def test_stretched_stack_and_candidates():
     assert plain.detect(torch.from_numpy(img).to(plain.device)).count < d.count
 
 
+@pytest.mark.parametrize("name", ["skewed", "bimodal", "odd_row", "sem_low_contrast"])
+def test_plan_levels_through_the_stack(name):
+    """The detector's own stretch pass (histogram spread over several global
+    copies, then summed) against the oracle: the stack scales with
+    255 / (high - low), so a level off by one code moves it far outside the
+    1e-5 bound.  Heights of 1 to 300 rows leave some copies unused."""
+    img = images()[name]
+    print(f"stretch plan levels {name} {img.shape}", flush=True)
+    plan = stretch_plan(1024)
+    d = plan.detect(torch.from_numpy(img).to(plan.device), return_stack=True)
+    ora = oracle.log_stack(oracle.stretch(img), SIG10)
+    assert plane_rel_err(d.stack.cpu().numpy(), ora).max() <= STACK_TOL
+
+
 def test_constant_image_gives_empty_stack():
     img = images()["constant"]
     plan = stretch_plan(64)
