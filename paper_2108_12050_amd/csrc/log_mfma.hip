@@ -443,7 +443,11 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
     float tsum = 0.0f;  // EPI_SOFTSUM: this lane's softplus sum
     double gsum = 0.0;  // EPI_COTAN: this lane's sigma-gradient sum
     float cmx = 0.0f;   // EPI_COTAN: this lane's max |c|
-    const float cot_s2 = J.sigma * J.sigma, cot_2is = 2.0f / J.sigma;  // EPI_COTAN
+    float cot_s2 = 0.0f, cot_2is = 0.0f;  // EPI_COTAN: sigma^2 and 2 / sigma
+    if constexpr (EPI == EPI_COTAN) {
+        cot_s2 = J.sigma * J.sigma;
+        cot_2is = 2.0f / J.sigma;
+    }
     // Inputs of the read-modify-write epilogues (EPI_COTAN: the D1 plane and
     // r; EPI_ACCUM: the plane), loaded when the block's step starts so that
     // the block's MFMA work covers their latency (vector rows only; the
@@ -452,7 +456,7 @@ __device__ __forceinline__ void wave_job(const WaveJob& J, const half8_t* __rest
         float4_t a, b;
     };
     auto epi_load = [&](int t) {
-        EpiIn e;
+        EpiIn e{};
         if constexpr (EPI == EPI_COTAN || EPI == EPI_ACCUM) {
             const int y = y0 + 16 * t + c;
             if (vec && (!EDGE || y < y1)) {
