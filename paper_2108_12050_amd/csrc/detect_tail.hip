@@ -90,7 +90,7 @@ template <int... Ks>
 void launch_nms(int K, int cw, const DetectWorkspace& ws, int h, int w, float tau, hipStream_t s,
                 std::integer_sequence<int, Ks...>) {
     if (cw == 4) {
-        ((K == Ks + 1 && Ks + 1 <= 4 ? launch_nms_k<Ks + 1, (Ks + 1 <= 4 ? 4 : 1)>(ws, h, w, tau, s)
+        ((K == Ks + 1 && Ks + 1 <= 10 ? launch_nms_k<Ks + 1, (Ks + 1 <= 10 ? 4 : 1)>(ws, h, w, tau, s)
                                      : void()), ...);
     } else if (cw == 2) {
         ((K == Ks + 1 && Ks + 1 <= 16 ? launch_nms_k<Ks + 1, (Ks + 1 <= 16 ? 2 : 1)>(ws, h, w, tau, s)
@@ -394,12 +394,15 @@ hipError_t launch_detect_tail(const DetectWorkspace& ws, int K, int h, int w, fl
                               const float* sigmas_dev, mhfd_blob* blobs, int capacity,
                               mhfd_result* result, hipStream_t s) {
     init_counters_kernel<<<1, 64, 0, s>>>(ws.ctr);
-    // Two columns per lane when the planes allow aligned float2 loads; four
-    // (float4) for up to four planes, whose rows are otherwise too short a
-    // load to keep the memory busy.
+    // Four columns per lane (float4 loads) for up to ten planes: per voxel
+    // the strip-end exchange and the row bookkeeping cost half of what they
+    // cost at two columns, and a wave keeps twice the bytes in flight
+    // (K = 10: 219 registers, two waves per SIMD, 9% faster than two columns
+    // at four waves; K = 1: 44 -> 36 us); two (float2) for 11 to 16 planes,
+    // where four columns take 247 to 340 registers per lane (not measured).
     DetectWorkspace wk = ws;
     const uintptr_t sa = reinterpret_cast<uintptr_t>(ws.stack);
-    const int cw = (K <= 4 && w % 4 == 0 && sa % 16 == 0) ? 4
+    const int cw = (K <= 10 && w % 4 == 0 && sa % 16 == 0) ? 4
                    : (K <= 16 && w % 2 == 0 && sa % 8 == 0) ? 2 : 1;
     wk.blk_per_row = (w + 64 * cw - 1) / (64 * cw);
     wk.n_blk = h * wk.blk_per_row;

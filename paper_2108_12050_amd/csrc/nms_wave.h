@@ -5,6 +5,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "mhfd_internal.h"
 
 namespace mhfd {
@@ -104,7 +106,9 @@ template <int K, int CW, int SLOTS, bool SPARSE = false>
 __device__ __forceinline__ void wave(const float* __restrict__ st, int H, int W, float tau,
                                      int bpr, int strip, int run, const Sink& out,
                                      const Active& act = Active{nullptr, 0, 0}) {
-    static_assert(CW * K <= 32, "candidate mask is 32 bits");
+    static_assert(CW * K <= 64, "candidate mask is 64 bits");
+    // a lane's (column, plane) hits, bit c K + k
+    typedef typename std::conditional<(CW * K > 32), unsigned long long, unsigned>::type Mask;
     typedef float Vec __attribute__((ext_vector_type(CW)));
     typedef Vec Row[K];
     const int lane = threadIdx.x & 63;
@@ -198,7 +202,7 @@ __device__ __forceinline__ void wave(const float* __restrict__ st, int H, int W,
             return m;
         };
         // planes k - 1, k, k + 1 in a rolling window
-        unsigned mask = 0u;
+        Mask mask = 0u;
         Vec mp = static_cast<Vec>(-INFINITY), mk = plane_max(0);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -207,12 +211,12 @@ __device__ __forceinline__ void wave(const float* __restrict__ st, int H, int W,
             for (int c = 0; c < CW; ++c) {
                 const float v = cur[k][c];
                 const bool hit = (v > tau) & (v >= fmax3(mp[c], mk[c], mn[c]));
-                mask |= static_cast<unsigned>(hit) << (c * K + k);
+                mask |= static_cast<Mask>(hit) << (c * K + k);
             }
             mp = mk;
             mk = mn;
         }
-        mask = col_ok ? mask : 0u;
+        mask = col_ok ? mask : Mask(0);
         const int64_t cell = static_cast<int64_t>(y) * bpr + strip;
         if (__ballot(mask != 0u) == 0ull) {  // wave-uniform: no candidate in the cell
             if (lane == 0) {
@@ -221,7 +225,7 @@ __device__ __forceinline__ void wave(const float* __restrict__ st, int H, int W,
             }
             return;
         }
-        const int cnt = __popc(mask);
+        const int cnt = static_cast<int>(__popcll(static_cast<unsigned long long>(mask)));
         int n;
         const int pre = wave_exclusive_prefix<6>(cnt, &n);
         int o = 0;
@@ -240,10 +244,10 @@ __device__ __forceinline__ void wave(const float* __restrict__ st, int H, int W,
         if (cnt > 0) {
             int j = pre;
             Cand* own = out.slots + cell * SLOTS;
-            unsigned m = mask;
+            Mask m = mask;
             do {
-                const int bit = __builtin_ctz(m);
-                m &= m - 1u;
+                const int bit = __builtin_ctzll(static_cast<unsigned long long>(m));
+                m &= m - 1;
                 const int c = bit / K;
                 const int k = bit - c * K;
                 Cand rec;

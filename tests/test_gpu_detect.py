@@ -176,10 +176,11 @@ def test_single_scale():
     compare_candidates(g["stack"], as_set(g["yxk"]), ora, as_set(ykx), TAU)
 
 
-@pytest.mark.parametrize("K,w", [(3, 300), (4, 516), (2, 260)])
+@pytest.mark.parametrize("K,w", [(3, 300), (4, 516), (2, 260), (7, 372), (10, 516)])
 def test_four_columns_per_lane(K, w):
-    """Up to four planes the maxima pass reads four columns per lane (strips of
-    256 columns): widths past one strip, with a ragged last strip."""
+    """Up to ten planes the maxima pass reads four columns per lane (strips of
+    256 columns, a 64-bit hit mask beyond 32 (column, plane) pairs): widths
+    past one strip, with a ragged last strip."""
     plan = make_plan(n_scales=K, sigma_min=1.5, sigma_max=3.5, overlap=1.0, max_h=160,
                      max_w=520)
     sig = oracle.linear_sigmas(K, 1.5, 3.5)
