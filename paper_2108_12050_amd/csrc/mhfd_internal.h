@@ -289,7 +289,7 @@ struct BatchTile {
     int bpr;                // maxima cells per row (strips of 64 nms_cw columns)
     int item_base;          // prefix of strips * segs over earlier tiles
     int nms_base;           // prefix of h * bpr over earlier tiles
-    int nms_cw;             // columns per maxima lane (1 or 2)
+    int nms_cw;             // columns per maxima lane (1, 2 or 4)
     int nitem_base;         // prefix of ceil(h / 32) * bpr (maxima wave items)
     // matrix-core items: workgroups of MFMA_GROUP_WAVES wave columns x row
     // segments
