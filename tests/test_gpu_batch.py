@@ -211,11 +211,13 @@ def test_u8_graph_replay_and_full_size_batch():
 def test_odd_shapes_and_one_column_lanes(K):
     """Odd widths (one column per maxima lane) and odd pixel counts (tile
     stack extents padded to whole float4s), and K = 20 (more than 16 scales:
-    one column per lane at every width); widths around the 64- and
-    128-column strips.  Every tile's list equals the single-tile path's."""
+    one column per lane at every width); widths around the 64-, 128- and
+    256-column strips (two and four columns per lane at K = 10).  Every
+    tile's list equals the single-tile path's."""
     from paper_2108_12050_amd import detect_batched
-    plan = plan_f32(max_hw=320, n_scales=K)
-    shapes = [(65, 63), (1, 1), (130, 129), (97, 128), (3, 257), (200, 66), (33, 191)]
+    plan = plan_f32(max_hw=520, n_scales=K)
+    shapes = [(65, 63), (1, 1), (130, 129), (97, 128), (3, 257), (200, 66), (33, 191),
+              (40, 260), (21, 516), (70, 254)]
     imgs = [torch.from_numpy(synth.blob_field(40 + i, h, w, psf_sigma=1.0)).cuda()
             for i, (h, w) in enumerate(shapes)]
     print(f"batch K={K} shapes {shapes}", flush=True)
